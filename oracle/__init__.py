@@ -1,0 +1,247 @@
+"""Python front end of the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+CPU-baseline leg of the benchmark. The product path never imports it.
+
+Functions take and return plain numpy arrays in input (generator) order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+F32, F16, BF16, F64 = 0, 1, 2, 3
+DTYPE_CODES = {"f32": F32, "f16": F16, "bf16": BF16, "f64": F64}
+
+# Constants of the method (paper Sec. 2.1 names the cubic spline; the values
+# are the readings listed in the design notes).
+GAMMA_K = 1.825742      # H / h for the 3D cubic spline
+GAMMA = 5.0 / 3.0       # ideal-gas adiabatic index
+ALPHA = 0.8             # artificial-viscosity strength
+BETA = 3.0              # signal-velocity coefficient
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no fast-math, no FP contraction)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    src = os.path.join(HERE, "oracle.c")
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+           "-D_DEFAULT_SOURCE", "-Wall", "-fPIC", "-shared", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma_k", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gradh", C.c_int32)]
+
+
+def params(gamma_k=GAMMA_K, gamma=GAMMA, alpha=ALPHA, beta=BETA, gradh=True) -> Params:
+    return Params(gamma_k, gamma, alpha, beta, 1 if gradh else 0)
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        d, i32, i64, u16, f32 = (C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                                 C.c_int64, C.POINTER(C.c_uint16), C.POINTER(C.c_float))
+        L.orc_w_hat.restype = C.c_double
+        L.orc_w_hat.argtypes = [C.c_double]
+        L.orc_dw_hat.restype = C.c_double
+        L.orc_dw_hat.argtypes = [C.c_double]
+        L.orc_W.restype = C.c_double
+        L.orc_W.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_dWdh.restype = C.c_double
+        L.orc_dWdh.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_bin.argtypes = [C.c_int, d, C.c_int, i32, i32, i32, d]
+        L.orc_density.argtypes = [C.c_int, d, d, d, d, C.POINTER(Params), C.c_int, C.c_int,
+                                  i32, C.c_int, d, d, d, d, d, d, i32]
+        L.orc_force.argtypes = [C.c_int, d, d, d, d, d, d, d, d, C.POINTER(Params), C.c_int,
+                                C.c_int, i32, C.c_int, d, d, d, i32]
+        L.orc_kick_drift.argtypes = [C.c_int, d, d, d, d, d, C.c_double, C.c_double]
+        L.orc_kick_drift.restype = None
+        L.orc_reduce.argtypes = [C.c_int, d, d, d, d, d]
+        L.orc_reduce.restype = None
+        L.orc_count32.argtypes = [C.c_int, d, d, C.c_int, C.c_double, C.c_int, C.c_int,
+                                  C.c_int, C.c_int, i32, i32]
+        L.orc_f32_to_f16.restype = C.c_uint16
+        L.orc_f32_to_f16.argtypes = [C.c_float]
+        L.orc_f16_to_f32.restype = C.c_float
+        L.orc_f16_to_f32.argtypes = [C.c_uint16]
+        L.orc_f32_to_bf16.restype = C.c_uint16
+        L.orc_f32_to_bf16.argtypes = [C.c_float]
+        L.orc_bf16_to_f32.restype = C.c_float
+        L.orc_bf16_to_f32.argtypes = [C.c_uint16]
+        L.orc_quant_array.argtypes = [i64, f32, u16, C.c_int]
+        L.orc_quant_array.restype = None
+        L.orc_dequant_array.argtypes = [i64, u16, f32, C.c_int]
+        L.orc_dequant_array.restype = None
+        L.orc_roundtrip.restype = C.c_double
+        L.orc_roundtrip.argtypes = [C.c_double, C.c_int, C.c_int]
+        L.orc_dequantise_set.argtypes = [C.c_int, d, d, d, d, d, C.c_int, C.c_int, C.c_int,
+                                         C.c_int, i32, d, d, d, d, d]
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t)) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def w_hat(u: float) -> float:
+    return lib().orc_w_hat(float(u))
+
+
+def dw_hat(u: float) -> float:
+    return lib().orc_dw_hat(float(u))
+
+
+def W(r, h, gamma_k=GAMMA_K):
+    return lib().orc_W(float(r), float(h), float(gamma_k))
+
+
+def dWdh(r, h, gamma_k=GAMMA_K):
+    return lib().orc_dWdh(float(r), float(h), float(gamma_k))
+
+
+def bin_cells(x, n_c):
+    """-> (cell[N], cell_start[C+1], perm[N], off[N,3])"""
+    x = _f64(x)
+    n = x.shape[0]
+    cell = np.empty(n, np.int32)
+    start = np.empty(n_c ** 3 + 1, np.int32)
+    perm = np.empty(n, np.int32)
+    off = np.empty((n, 3), np.float64)
+    rc = lib().orc_bin(n, _p(x, C.c_double), n_c, _p(cell, C.c_int32), _p(start, C.c_int32),
+                       _p(perm, C.c_int32), _p(off, C.c_double))
+    assert rc == 0
+    return cell, start, perm, off
+
+
+def density(ps, prm=None, mode="cells", n_c=None, sel=None):
+    """FP64 density loop. Returns a dict of arrays (length N, or len(sel))."""
+    prm = prm or params()
+    x, m, h, u = _f64(ps.x), _f64(ps.m), _f64(ps.h), _f64(ps.u)
+    n = x.shape[0]
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+    cnt = n if sel is None else sel.shape[0]
+    out = {k: np.empty(cnt) for k in ("rho", "wcount", "rho_dh", "f", "P", "c")}
+    out["nngb"] = np.empty(cnt, np.int32)
+    md = 0 if mode == "brute" else 1
+    rc = lib().orc_density(n, _p(x, C.c_double), _p(m, C.c_double), _p(h, C.c_double),
+                           _p(u, C.c_double), C.byref(prm), md, int(n_c or 0),
+                           _p(sel, C.c_int32), cnt,
+                           *[_p(out[k], C.c_double) for k in ("rho", "wcount", "rho_dh", "f",
+                                                               "P", "c")],
+                           _p(out["nngb"], C.c_int32))
+    if rc != 0:
+        raise ValueError(f"orc_density failed ({rc}): cell side must be >= max H and n_c >= 3")
+    return out
+
+
+def force(ps, dens, prm=None, mode="cells", n_c=None, sel=None):
+    """FP64 force loop; ``dens`` holds rho, f, P, c over all particles."""
+    prm = prm or params()
+    x, v, m, h = _f64(ps.x), _f64(ps.v), _f64(ps.m), _f64(ps.h)
+    n = x.shape[0]
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+    cnt = n if sel is None else sel.shape[0]
+    a = np.empty((cnt, 3))
+    du = np.empty(cnt)
+    vsig = np.empty(cnt)
+    nf = np.empty(cnt, np.int32)
+    arr = [_f64(dens[k]) for k in ("rho", "f", "P", "c")]
+    md = 0 if mode == "brute" else 1
+    rc = lib().orc_force(n, _p(x, C.c_double), _p(v, C.c_double), _p(m, C.c_double),
+                         _p(h, C.c_double), *[_p(t, C.c_double) for t in arr], C.byref(prm),
+                         md, int(n_c or 0), _p(sel, C.c_int32), cnt, _p(a, C.c_double),
+                         _p(du, C.c_double), _p(vsig, C.c_double), _p(nf, C.c_int32))
+    if rc != 0:
+        raise ValueError(f"orc_force failed ({rc})")
+    return {"a": a, "du": du, "vsig": vsig, "nforce": nf}
+
+
+def kick_drift(x, v, u, a, du, dt_kick, dt_drift):
+    x, v, u = _f64(x).copy(), _f64(v).copy(), _f64(u).copy()
+    a, du = _f64(a), _f64(du)
+    lib().orc_kick_drift(x.shape[0], _p(x, C.c_double), _p(v, C.c_double), _p(u, C.c_double),
+                         _p(a, C.c_double), _p(du, C.c_double), float(dt_kick), float(dt_drift))
+    return x, v, u
+
+
+def reduce(m, v, a, du):
+    out = np.empty(6)
+    m, v, a, du = _f64(m), _f64(v), _f64(a), _f64(du)
+    lib().orc_reduce(m.shape[0], _p(m, C.c_double), _p(v, C.c_double), _p(a, C.c_double),
+                     _p(du, C.c_double), _p(out, C.c_double))
+    return out
+
+
+def count32(ps, n_c, pos="f32", hdt="f32", h_scale=0, mode="cells", gamma_k=GAMMA_K):
+    """Neighbour counts with the support test in FP32 -> (n_density, n_force)."""
+    x, h = _f64(ps.x), _f64(ps.h)
+    n = x.shape[0]
+    nd = np.empty(n, np.int32)
+    nf = np.empty(n, np.int32)
+    rc = lib().orc_count32(n, _p(x, C.c_double), _p(h, C.c_double), int(n_c), float(gamma_k),
+                           DTYPE_CODES[pos], DTYPE_CODES[hdt], int(h_scale),
+                           0 if mode == "brute" else 1, _p(nd, C.c_int32), _p(nf, C.c_int32))
+    assert rc == 0
+    return nd, nf
+
+
+def quant(a32, dtype):
+    a32 = np.ascontiguousarray(a32, dtype=np.float32)
+    out = np.empty(a32.shape, np.uint16)
+    lib().orc_quant_array(a32.size, _p(a32, C.c_float), _p(out, C.c_uint16), DTYPE_CODES[dtype])
+    return out
+
+
+def dequant(bits, dtype):
+    bits = np.ascontiguousarray(bits, dtype=np.uint16)
+    out = np.empty(bits.shape, np.float32)
+    lib().orc_dequant_array(bits.size, _p(bits, C.c_uint16), _p(out, C.c_float),
+                            DTYPE_CODES[dtype])
+    return out
+
+
+def roundtrip(v, dtype, scale=0):
+    return lib().orc_roundtrip(float(v), DTYPE_CODES[dtype], int(scale))
+
+
+def dequantise_set(ps, n_c, pos="f32", vel="f32", mhu="f32", scales=(0, 0, 0)):
+    """The particle set as an SoA view of the given storage formats holds it,
+    read back into FP64 (positions = cell origin + stored offset)."""
+    from paper_2512_05516_amd.inputs import ParticleSet
+    x, v, m, h, u = (_f64(ps.x), _f64(ps.v), _f64(ps.m), _f64(ps.h), _f64(ps.u))
+    n = x.shape[0]
+    xq, vq = np.empty_like(x), np.empty_like(v)
+    mq, hq, uq = np.empty_like(m), np.empty_like(h), np.empty_like(u)
+    sc = np.ascontiguousarray(scales, dtype=np.int32)
+    lib().orc_dequantise_set(n, _p(x, C.c_double), _p(v, C.c_double), _p(m, C.c_double),
+                             _p(h, C.c_double), _p(u, C.c_double), int(n_c), DTYPE_CODES[pos],
+                             DTYPE_CODES[vel], DTYPE_CODES[mhu], _p(sc, C.c_int32),
+                             _p(xq, C.c_double), _p(vq, C.c_double), _p(mq, C.c_double),
+                             _p(hq, C.c_double), _p(uq, C.c_double))
+    return ParticleSet(xq, vq, mq, hq, uq, ps.name + "_dq")

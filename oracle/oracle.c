@@ -1,0 +1,568 @@
+/* FP64 CPU oracle of the SPH hot path (paper Sec. 2.1, Sec. 3.2, Sec. 4).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product path. It shares
+ * no code, header, table or constant with the HIP library.
+ *
+ * Everything here is the plain definition, written for a reader to check by
+ * eye: every neighbour sum is taken over an explicit, ascending list of
+ * neighbour indices, so the brute-force and cell-list modes produce
+ * bit-identical results (the cell list only restricts candidates).
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math: the
+ * FP32 support-test replica relies on unfused float arithmetic).
+ *
+ * Readings where the paper is silent (listed in the design notes):
+ *  - kernel: cubic-spline M4 with support radius H = gamma_k h (Sec. 2.1
+ *    names the cubic spline; gamma_k = 1.825742 makes (4 pi/3)(gamma_k eta)^3
+ *    about 48 neighbours at eta = 1.2348).
+ *  - h_ij: density uses h_i (gather); the force uses the grad-h form with
+ *    separate W(h_i) and W(h_j) terms; gradh = 0 with uniform h reduces it to
+ *    the momentum equation of Sec. 2.1 as printed.
+ *  - the momentum equation's "grad rho / rho" is read as "grad P / rho".
+ *  - viscosity: signal-velocity artificial viscosity, no limiter.
+ *  - the self pair is in the density sums and out of the force sums.
+ *  - support test is strict: r < H.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Kernel (Sec. 2.1: cubic spline, compact support)                          */
+/* ------------------------------------------------------------------------ */
+
+/* Normalised 3D M4 cubic spline on the unit support, u = r / H. */
+double orc_w_hat(double u) {
+  if (u < 0.5) return (8.0 / ORC_PI) * (1.0 - 6.0 * u * u + 6.0 * u * u * u);
+  if (u < 1.0) {
+    double t = 1.0 - u;
+    return (16.0 / ORC_PI) * t * t * t;
+  }
+  return 0.0;
+}
+
+/* d(w_hat)/du */
+double orc_dw_hat(double u) {
+  if (u < 0.5) return (8.0 / ORC_PI) * (-12.0 * u + 18.0 * u * u);
+  if (u < 1.0) {
+    double t = 1.0 - u;
+    return -(48.0 / ORC_PI) * t * t;
+  }
+  return 0.0;
+}
+
+/* W(r, h) = w_hat(r / H) / H^3 with H = gamma_k h (Eq. interpolant, Eq. density) */
+double orc_W(double r, double h, double gamma_k) {
+  double H = gamma_k * h;
+  return orc_w_hat(r / H) / (H * H * H);
+}
+
+/* dW/dh at fixed r: -gamma_k (3 w_hat(u) + u w_hat'(u)) / H^4 */
+double orc_dWdh(double r, double h, double gamma_k) {
+  double H = gamma_k * h;
+  double u = r / H;
+  return -gamma_k * (3.0 * orc_w_hat(u) + u * orc_dw_hat(u)) / (H * H * H * H);
+}
+
+/* |grad_i W(r_ij, h)| along e_ij = (x_i - x_j)/r: w_hat'(u) / H^4 (Eq. gradient) */
+static double orc_gradW(double r, double h, double gamma_k) {
+  double H = gamma_k * h;
+  if (!(r < H)) return 0.0;
+  return orc_dw_hat(r / H) / (H * H * H * H);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Binning (the cell list of Sec. 2.2's spatial search structures)           */
+/* ------------------------------------------------------------------------ */
+
+static int cell_axis(double xw, int n_c) {
+  double t = floor(xw * (double)n_c);
+  int c = (t != t) ? 0 : (int)t;          /* NaN -> 0: inputs are validated */
+  if (c > n_c - 1) c = n_c - 1;
+  if (c < 0) c = 0;
+  return c;
+}
+
+/* wrap into the periodic unit box */
+static double wrap01(double x) { return x - floor(x); }
+
+/* cell[i]: linear cell id cx + n_c (cy + n_c cz) of particle i (input order);
+ * cell_start[C+1], perm[N]: particles of cell c are perm[cell_start[c] ..
+ * cell_start[c+1]-1], in increasing input index; off[3i+k]: x_k - c_k / n_c
+ * in FP64 after wrapping. Any output pointer may be NULL. */
+int orc_bin(int n, const double *x, int n_c, int32_t *cell, int32_t *cell_start,
+            int32_t *perm, double *off) {
+  if (n < 0 || n_c < 1) return -1;
+  int C = n_c * n_c * n_c;
+  int32_t *cid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *start = (int32_t *)calloc((size_t)C + 1, sizeof(int32_t));
+  for (int i = 0; i < n; ++i) {
+    int cc[3];
+    for (int k = 0; k < 3; ++k) {
+      double xw = wrap01(x[3 * i + k]);
+      cc[k] = cell_axis(xw, n_c);
+      if (off) off[3 * i + k] = xw - (double)cc[k] / (double)n_c;
+    }
+    cid[i] = cc[0] + n_c * (cc[1] + n_c * cc[2]);
+    start[cid[i] + 1] += 1;
+  }
+  for (int c = 0; c < C; ++c) start[c + 1] += start[c];
+  if (perm) {
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)C);
+    memcpy(fill, start, sizeof(int32_t) * (size_t)C);
+    for (int i = 0; i < n; ++i) perm[fill[cid[i]]++] = i;   /* stable */
+    free(fill);
+  }
+  if (cell) memcpy(cell, cid, sizeof(int32_t) * (size_t)n);
+  if (cell_start) memcpy(cell_start, start, sizeof(int32_t) * ((size_t)C + 1));
+  free(cid);
+  free(start);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour lists                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* minimum-image separation x_i - x_j in the periodic unit box */
+static double sep2(const double *x, int i, int j, double d[3]) {
+  for (int k = 0; k < 3; ++k) {
+    double t = x[3 * i + k] - x[3 * j + k];
+    d[k] = t - nearbyint(t);
+  }
+  return d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+}
+
+typedef struct { int32_t *idx; int n, cap; } nlist;
+
+static void nl_push(nlist *l, int j) {
+  if (l->n == l->cap) {
+    l->cap = l->cap ? 2 * l->cap : 128;
+    l->idx = (int32_t *)realloc(l->idx, sizeof(int32_t) * (size_t)l->cap);
+  }
+  l->idx[l->n++] = j;
+}
+
+static int cmp_i32(const void *a, const void *b) {
+  int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  int n, n_c;
+  int32_t *cell, *start, *perm;
+} cellgrid;
+
+static int grid_build(cellgrid *g, int n, const double *x, int n_c) {
+  g->n = n;
+  g->n_c = n_c;
+  int C = n_c * n_c * n_c;
+  g->cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  g->start = (int32_t *)malloc(sizeof(int32_t) * ((size_t)C + 1));
+  g->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  return orc_bin(n, x, n_c, g->cell, g->start, g->perm, NULL);
+}
+
+static void grid_free(cellgrid *g) {
+  free(g->cell);
+  free(g->start);
+  free(g->perm);
+}
+
+/* kind 0: density list {j : r_ij < H_i}, self included.
+ * kind 1: force list {j != i : r_ij < max(H_i, H_j)}.
+ * The list comes back sorted by ascending j. */
+static void neighbours(int kind, int i, int n, const double *x, const double *h,
+                       double gamma_k, int mode, const cellgrid *g, nlist *out) {
+  out->n = 0;
+  double Hi = gamma_k * h[i];
+  double d[3];
+  if (mode == 0) {
+    for (int j = 0; j < n; ++j) {
+      double r2 = sep2(x, i, j, d);
+      double r = sqrt(r2);
+      if (kind == 0) {
+        if (r < Hi) nl_push(out, j);
+      } else {
+        double Hj = gamma_k * h[j];
+        if (j != i && (r < Hi || r < Hj)) nl_push(out, j);
+      }
+    }
+  } else {
+    int n_c = g->n_c;
+    int ci = g->cell[i];
+    int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int nx = (cx + dx + n_c) % n_c, ny = (cy + dy + n_c) % n_c,
+              nz = (cz + dz + n_c) % n_c;
+          int cn = nx + n_c * (ny + n_c * nz);
+          for (int t = g->start[cn]; t < g->start[cn + 1]; ++t) {
+            int j = g->perm[t];
+            double r2 = sep2(x, i, j, d);
+            double r = sqrt(r2);
+            if (kind == 0) {
+              if (r < Hi) nl_push(out, j);
+            } else {
+              double Hj = gamma_k * h[j];
+              if (j != i && (r < Hi || r < Hj)) nl_push(out, j);
+            }
+          }
+        }
+    qsort(out->idx, (size_t)out->n, sizeof(int32_t), cmp_i32);
+  }
+}
+
+/* the cell list finds every neighbour only if the cell side is >= max H */
+static int grid_ok(int n, const double *h, double gamma_k, int n_c) {
+  if (n_c < 3) return 0;
+  double side = 1.0 / (double)n_c;
+  for (int i = 0; i < n; ++i)
+    if (!(gamma_k * h[i] <= side)) return 0;
+  return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density loop (Eq. density) with dRho/dh, weighted neighbour number,       */
+/* grad-h factor, pressure and sound speed                                   */
+/* ------------------------------------------------------------------------ */
+
+int orc_density(int n, const double *x, const double *m, const double *h,
+                const double *u, const orc_params *p, int mode, int n_c,
+                const int32_t *sel, int nsel, double *rho, double *wcount,
+                double *rho_dh, double *f, double *P, double *c, int32_t *nngb) {
+  cellgrid g;
+  memset(&g, 0, sizeof g);
+  if (mode == 1) {
+    if (!grid_ok(n, h, p->gamma_k, n_c)) return -2;
+    grid_build(&g, n, x, n_c);
+  }
+  int cnt = sel ? nsel : n;
+#pragma omp parallel
+  {
+    nlist l = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+    for (int s = 0; s < cnt; ++s) {
+      int i = sel ? sel[s] : s;
+      neighbours(0, i, n, x, h, p->gamma_k, mode, &g, &l);
+      double rho_i = 0.0, S = 0.0, dh = 0.0, d[3];
+      for (int t = 0; t < l.n; ++t) {
+        int j = l.idx[t];
+        double r = sqrt(sep2(x, i, j, d));
+        double Hi = p->gamma_k * h[i];
+        rho_i += m[j] * orc_W(r, h[i], p->gamma_k);
+        S += orc_w_hat(r / Hi);
+        dh += m[j] * orc_dWdh(r, h[i], p->gamma_k);
+      }
+      /* grad-h term Omega_i = 1 + (h_i / (3 rho_i)) d rho_i / d h_i,
+       * from h = eta (m / rho)^(1/3) */
+      double omega = 1.0 + h[i] * dh / (3.0 * rho_i);
+      rho[s] = rho_i;
+      if (wcount) wcount[s] = (4.0 * ORC_PI / 3.0) * S;
+      if (rho_dh) rho_dh[s] = dh;
+      if (f) f[s] = p->gradh ? 1.0 / omega : 1.0;
+      /* ideal gas: P = (gamma - 1) rho u, c = sqrt(gamma P / rho) */
+      if (P) P[s] = (p->gamma - 1.0) * rho_i * u[i];
+      if (c) c[s] = sqrt(p->gamma * (p->gamma - 1.0) * u[i]);
+      if (nngb) nngb[s] = l.n;
+    }
+    free(l.idx);
+  }
+  if (mode == 1) grid_free(&g);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Force loop (Eq. momentum and Eq. energy of Sec. 2.1, discrete form):      */
+/*   dv_i/dt = -sum_j m_j (A_i g_i + A_j g_j + Pi_ij gbar_ij) e_ij           */
+/*   du_i/dt =  sum_j m_j (A_i g_i + Pi_ij gbar_ij / 2) (v_ij . e_ij)        */
+/* with A_k = f_k P_k / rho_k^2, g_k = |grad W(r_ij, h_k)| (signed),         */
+/* gbar = (g_i + g_j) / 2, Pi_ij the signal-velocity viscosity.              */
+/* rho, f, P, c are arrays over all particles (input order).                 */
+/* ------------------------------------------------------------------------ */
+
+int orc_force(int n, const double *x, const double *v, const double *m,
+              const double *h, const double *rho, const double *f,
+              const double *P, const double *c, const orc_params *p, int mode,
+              int n_c, const int32_t *sel, int nsel, double *a, double *du,
+              double *vsig, int32_t *nforce) {
+  cellgrid g;
+  memset(&g, 0, sizeof g);
+  if (mode == 1) {
+    if (!grid_ok(n, h, p->gamma_k, n_c)) return -2;
+    grid_build(&g, n, x, n_c);
+  }
+  int cnt = sel ? nsel : n;
+#pragma omp parallel
+  {
+    nlist l = {0, 0, 0};
+#pragma omp for schedule(dynamic, 64)
+    for (int s = 0; s < cnt; ++s) {
+      int i = sel ? sel[s] : s;
+      neighbours(1, i, n, x, h, p->gamma_k, mode, &g, &l);
+      double ai[3] = {0.0, 0.0, 0.0}, dui = 0.0, vs = 0.0, d[3];
+      double fi = p->gradh ? f[i] : 1.0;
+      double Ai = fi * P[i] / (rho[i] * rho[i]);
+      for (int t = 0; t < l.n; ++t) {
+        int j = l.idx[t];
+        double r = sqrt(sep2(x, i, j, d));
+        double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+        double fj = p->gradh ? f[j] : 1.0;
+        double Aj = fj * P[j] / (rho[j] * rho[j]);
+        double gi = orc_gradW(r, h[i], p->gamma_k);
+        double gj = orc_gradW(r, h[j], p->gamma_k);
+        double w = (v[3 * i + 0] - v[3 * j + 0]) * e[0] +
+                   (v[3 * i + 1] - v[3 * j + 1]) * e[1] +
+                   (v[3 * i + 2] - v[3 * j + 2]) * e[2];
+        double mu = w < 0.0 ? w : 0.0;
+        double vsig_ij = c[i] + c[j] - p->beta * mu;
+        double Pi = -p->alpha * vsig_ij * mu / (rho[i] + rho[j]);
+        double gbar = 0.5 * (gi + gj);
+        double K = Ai * gi + Aj * gj + Pi * gbar;
+        for (int k = 0; k < 3; ++k) ai[k] -= m[j] * K * e[k];
+        dui += m[j] * (Ai * gi * w + 0.5 * Pi * gbar * w);
+        if (vsig_ij > vs) vs = vsig_ij;
+      }
+      for (int k = 0; k < 3; ++k) a[3 * s + k] = ai[k];
+      du[s] = dui;
+      if (vsig) vsig[s] = vs;
+      if (nforce) nforce[s] = l.n;
+    }
+    free(l.idx);
+  }
+  if (mode == 1) grid_free(&g);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kick and drift (linear kernels, Alg. 1 CallLinear): kick v and u, then    */
+/* drift x with the kicked velocity and wrap into the periodic box.          */
+/* ------------------------------------------------------------------------ */
+
+void orc_kick_drift(int n, double *x, double *v, double *u, const double *a,
+                    const double *du, double dt_kick, double dt_drift) {
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) v[3 * i + k] = v[3 * i + k] + a[3 * i + k] * dt_kick;
+    u[i] = u[i] + du[i] * dt_kick;
+    for (int k = 0; k < 3; ++k) {
+      double xn = x[3 * i + k] + v[3 * i + k] * dt_drift;
+      x[3 * i + k] = xn - floor(xn);
+    }
+  }
+}
+
+void orc_reduce(int n, const double *m, const double *v, const double *a,
+                const double *du, double *out) {
+  for (int k = 0; k < 6; ++k) out[k] = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double va = 0.0, an = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      out[k] += m[i] * a[3 * i + k];
+      va += v[3 * i + k] * a[3 * i + k];
+      an += a[3 * i + k] * a[3 * i + k];
+    }
+    out[3] += m[i] * (va + du[i]);
+    out[4] += m[i] * sqrt(an);
+    out[5] += m[i] * (fabs(va) + fabs(du[i]));
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quantisers (Sec. 3.2, Table 2: the 32- and 16-bit rows are IEEE single    */
+/* and half; bfloat16 keeps single's 8-bit exponent). Round to nearest,      */
+/* ties to even, written from the IEEE-754 encodings.                        */
+/* ------------------------------------------------------------------------ */
+
+static uint32_t f32_bits(float v) {
+  uint32_t b;
+  memcpy(&b, &v, 4);
+  return b;
+}
+
+static float bits_f32(uint32_t b) {
+  float v;
+  memcpy(&v, &b, 4);
+  return v;
+}
+
+/* round the integer sig right by s bits, ties to even */
+static uint32_t rne_shift(uint32_t sig, int s) {
+  if (s <= 0) return sig;
+  if (s >= 32) return 0;
+  uint32_t q = sig >> s;
+  uint32_t rem = sig & ((1u << s) - 1u);
+  uint32_t half = 1u << (s - 1);
+  if (rem > half || (rem == half && (q & 1u))) q += 1u;
+  return q;
+}
+
+uint16_t orc_f32_to_f16(float v) {
+  uint32_t b = f32_bits(v);
+  uint16_t sign = (uint16_t)((b >> 16) & 0x8000u);
+  uint32_t E = (b >> 23) & 0xffu, M = b & 0x7fffffu;
+  if (E == 0xffu) return (uint16_t)(sign | (M ? 0x7e00u : 0x7c00u));  /* NaN, Inf */
+  if (E == 0u) return sign;   /* FP32 subnormals are below half of 2^-24 */
+  int e = (int)E - 127;       /* value = 1.M * 2^e */
+  uint32_t sig = (1u << 23) | M;
+  if (e >= -14) {             /* normal half: 10 fraction bits */
+    uint32_t q = rne_shift(sig, 13);          /* 11 bits incl. hidden one */
+    int he = e + 15;
+    if (q == (1u << 11)) { q >>= 1; he += 1; }
+    if (he >= 31) return (uint16_t)(sign | 0x7c00u);
+    return (uint16_t)(sign | ((uint32_t)he << 10) | (q & 0x3ffu));
+  }
+  /* subnormal half: value / 2^-24 = sig * 2^(e + 1 - 23 + 23) */
+  int s = -(e + 1);           /* sig * 2^(e+1) = sig >> s */
+  uint32_t q = rne_shift(sig, s);
+  return (uint16_t)(sign | q); /* q == 0x400 encodes the smallest normal */
+}
+
+float orc_f16_to_f32(uint16_t h) {
+  uint32_t sign = ((uint32_t)h & 0x8000u) << 16;
+  uint32_t E = (h >> 10) & 0x1fu, M = h & 0x3ffu;
+  if (E == 0x1fu) return bits_f32(sign | 0x7f800000u | (M << 13));
+  if (E == 0u) {
+    float mag = (float)M * 0x1p-24f;          /* exact */
+    return sign ? -mag : mag;
+  }
+  return bits_f32(sign | ((E - 15u + 127u) << 23) | (M << 13));
+}
+
+uint16_t orc_f32_to_bf16(float v) {
+  uint32_t b = f32_bits(v);
+  uint32_t E = (b >> 23) & 0xffu, M = b & 0x7fffffu;
+  if (E == 0xffu && M) return (uint16_t)(((b >> 16) & 0x8000u) | 0x7fc0u);
+  /* keep the top 16 bits, round the low 16 to nearest even; a carry into
+   * the exponent (up to infinity) is the correct rounding */
+  uint32_t q = rne_shift(b & 0x7fffffffu, 16);
+  return (uint16_t)(((b >> 16) & 0x8000u) | q);
+}
+
+float orc_bf16_to_f32(uint16_t h) { return bits_f32((uint32_t)h << 16); }
+
+void orc_quant_array(int64_t n, const float *in, uint16_t *out, int dtype) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = dtype == ORC_BF16 ? orc_f32_to_bf16(in[i]) : orc_f32_to_f16(in[i]);
+}
+
+void orc_dequant_array(int64_t n, const uint16_t *in, float *out, int dtype) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    out[i] = dtype == ORC_BF16 ? orc_bf16_to_f32(in[i]) : orc_f16_to_f32(in[i]);
+}
+
+/* stored value of v: RNE to FP32, times 2^scale (exact), RNE to the storage
+ * format; read back: widen to FP32, times 2^-scale. FP64 storage is exact. */
+static float roundtrip32(double v, int dtype, int scale) {
+  float q32 = (float)v;
+  if (dtype == ORC_F32) return q32;
+  float s = ldexpf(q32, scale);
+  float back = dtype == ORC_BF16 ? orc_bf16_to_f32(orc_f32_to_bf16(s))
+                                 : orc_f16_to_f32(orc_f32_to_f16(s));
+  return ldexpf(back, -scale);
+}
+
+double orc_roundtrip(double v, int dtype, int scale) {
+  if (dtype == ORC_F64) return v;
+  return (double)roundtrip32(v, dtype, scale);
+}
+
+int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
+                       const double *h, const double *u, int n_c, int pos_dt,
+                       int vel_dt, int mhu_dt, const int32_t *scales,
+                       double *xq, double *vq, double *mq, double *hq, double *uq) {
+  int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  orc_bin(n, x, n_c, cell, NULL, NULL, off);
+  int s_m = scales ? scales[0] : 0, s_h = scales ? scales[1] : 0, s_u = scales ? scales[2] : 0;
+  for (int i = 0; i < n; ++i) {
+    int c3[3] = {cell[i] % n_c, (cell[i] / n_c) % n_c, cell[i] / (n_c * n_c)};
+    for (int k = 0; k < 3; ++k) {
+      xq[3 * i + k] = (double)c3[k] / (double)n_c + orc_roundtrip(off[3 * i + k], pos_dt, 0);
+      vq[3 * i + k] = orc_roundtrip(v[3 * i + k], vel_dt, 0);
+    }
+    mq[i] = orc_roundtrip(m[i], mhu_dt, s_m);
+    hq[i] = orc_roundtrip(h[i], mhu_dt, s_h);
+    uq[i] = orc_roundtrip(u[i], mhu_dt, s_u);
+  }
+  free(cell);
+  free(off);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour counts with the support test taken in FP32.                     */
+/* A floating-point decision that produces an integer is taken in the        */
+/* kernel's precision on both sides. The FP32 test for particle i in cell    */
+/* c_i and j in cell c_i + delta (delta in {-1,0,1}^3, periodic):            */
+/*   s      = FP32(1 / n_c)                                                  */
+/*   xr_k   = off_j,k + delta_k s          (one FP32 add; delta s exact)     */
+/*   d_k    = off_i,k - xr_k               (FP32)                            */
+/*   r2     = fma(d_z, d_z, fma(d_y, d_y, d_x * d_x))                        */
+/*   H_i    = FP32(gamma_k) * h_i, H2_i = H_i * H_i (FP32)                   */
+/* density: r2 < H2_i (self included); force: j != i and r2 < max(H2_i,H2_j) */
+/* off and h are the stored values (pos_dtype, h_dtype) read back as FP32.   */
+/* ------------------------------------------------------------------------ */
+
+int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
+                int pos_dtype, int h_dtype, int h_scale, int mode,
+                int32_t *nd, int32_t *nf) {
+  if (n_c < 3) return -1;
+  cellgrid g;
+  double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  float *o32 = (float *)malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
+  float *H2 = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+  grid_build(&g, n, x, n_c);
+  orc_bin(n, x, n_c, NULL, NULL, NULL, off);
+  float gk = (float)gamma_k;
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < 3; ++k) o32[3 * i + k] = roundtrip32(off[3 * i + k], pos_dtype, 0);
+    float hi = roundtrip32(h[i], h_dtype, h_scale);
+    float Hi = gk * hi;
+    H2[i] = Hi * Hi;
+  }
+  float s = (float)(1.0 / (double)n_c);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int i = 0; i < n; ++i) {
+    int ci = g.cell[i];
+    int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
+    int cnt_d = 0, cnt_f = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int cn = ((cx + dx + n_c) % n_c) +
+                   n_c * (((cy + dy + n_c) % n_c) + n_c * ((cz + dz + n_c) % n_c));
+          float sh[3] = {dx < 0 ? -s : (dx > 0 ? s : 0.0f),
+                         dy < 0 ? -s : (dy > 0 ? s : 0.0f),
+                         dz < 0 ? -s : (dz > 0 ? s : 0.0f)};
+          int lo = 0, hi = n;
+          if (mode == 1) { lo = g.start[cn]; hi = g.start[cn + 1]; }
+          for (int t = lo; t < hi; ++t) {
+            int j = (mode == 1) ? g.perm[t] : t;
+            if (mode == 0 && g.cell[j] != cn) continue;
+            float dd[3];
+            for (int k = 0; k < 3; ++k) {
+              float xr = o32[3 * j + k] + sh[k];
+              dd[k] = o32[3 * i + k] - xr;
+            }
+            float r2 = fmaf(dd[2], dd[2], fmaf(dd[1], dd[1], dd[0] * dd[0]));
+            if (r2 < H2[i]) cnt_d++;
+            if (j != i && (r2 < H2[i] || r2 < H2[j])) cnt_f++;
+          }
+        }
+    if (nd) nd[i] = cnt_d;
+    if (nf) nf[i] = cnt_f;
+  }
+  grid_free(&g);
+  free(off);
+  free(o32);
+  free(H2);
+  return 0;
+}

@@ -1,0 +1,96 @@
+/* FP64 CPU oracle of the SPH hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path (the HIP library and
+ * its Python binding) includes, links or calls this code; only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark do. It shares no code
+ * with the HIP path.
+ *
+ * What it computes (paper Sec. 2.1):
+ *   * the density sum rho_i = sum_j m_j W(r_ij, h_i)            (Eq. density)
+ *   * the discrete momentum equation with pressure gradient and
+ *     artificial viscosity, and the matching internal-energy rate
+ *                                                   (Eq. momentum, Eq. energy)
+ *   * the linear kick/drift update                        (Alg. 1, CallLinear)
+ *   * the AoS->SoA quantisers of Table 2 for the 32- and 16-bit rows and for
+ *     bfloat16                                         (Sec. 3.2, Table 2)
+ * The cubic-spline M4 kernel is the kernel family the paper names in Sec. 2.1.
+ * Readings where the paper is silent are listed in the design notes and in
+ * the comments of oracle.c.
+ */
+#ifndef SPH_ORACLE_H
+#define SPH_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double gamma_k;   /* support radius over smoothing length, H = gamma_k h  */
+  double gamma;     /* adiabatic index of the ideal gas                     */
+  double alpha;     /* artificial-viscosity strength                        */
+  double beta;      /* signal-velocity coefficient of the viscosity         */
+  int32_t gradh;    /* 1: grad-h correction factor f_i; 0: f_i = 1          */
+} orc_params;
+
+/* dtype codes shared with the quantiser entry points */
+enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_F64 = 3 };
+
+/* kernel */
+double orc_w_hat(double u);
+double orc_dw_hat(double u);
+double orc_W(double r, double h, double gamma_k);
+double orc_dWdh(double r, double h, double gamma_k);
+
+/* binning: wrap, integer cell, stable order by (cell, input index) */
+int orc_bin(int n, const double *x, int n_c, int32_t *cell, int32_t *cell_start,
+            int32_t *perm, double *off);
+
+/* density; mode 0 = brute force over all pairs, 1 = own cell list.
+ * sel (nsel entries) selects which i to evaluate; sel == NULL means all. */
+int orc_density(int n, const double *x, const double *m, const double *h,
+                const double *u, const orc_params *p, int mode, int n_c,
+                const int32_t *sel, int nsel, double *rho, double *wcount,
+                double *rho_dh, double *f, double *P, double *c, int32_t *nngb);
+
+int orc_force(int n, const double *x, const double *v, const double *m,
+              const double *h, const double *rho, const double *f,
+              const double *P, const double *c, const orc_params *p, int mode,
+              int n_c, const int32_t *sel, int nsel, double *a, double *du,
+              double *vsig, int32_t *nforce);
+
+void orc_kick_drift(int n, double *x, double *v, double *u, const double *a,
+                    const double *du, double dt_kick, double dt_drift);
+
+/* out[0..2] = sum m a; out[3] = sum m (v.a + du); out[4] = sum m |a|;
+ * out[5] = sum m (|v.a| + |du|) */
+void orc_reduce(int n, const double *m, const double *v, const double *a,
+                const double *du, double *out);
+
+/* neighbour counts with the support test taken in FP32, as the GPU takes it */
+int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
+                int pos_dtype, int h_dtype, int h_scale, int mode,
+                int32_t *nd, int32_t *nf);
+
+/* quantisers (RNE), FP32 -> {FP16, BF16} bits and back */
+uint16_t orc_f32_to_f16(float v);
+float orc_f16_to_f32(uint16_t b);
+uint16_t orc_f32_to_bf16(float v);
+float orc_bf16_to_f32(uint16_t b);
+void orc_quant_array(int64_t n, const float *in, uint16_t *out, int dtype);
+void orc_dequant_array(int64_t n, const uint16_t *in, float *out, int dtype);
+
+/* FP64 value -> stored value -> FP64 (the value a kernel reads back) */
+double orc_roundtrip(double v, int dtype, int scale);
+
+/* Dequantised copy of a particle set as stored in an SoA view:
+ * positions become cell origin + stored offset, other fields round-trip. */
+int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
+                       const double *h, const double *u, int n_c, int pos_dt,
+                       int vel_dt, int mhu_dt, const int32_t *scales,
+                       double *xq, double *vq, double *mq, double *hq, double *uq);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
