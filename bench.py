@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPH hot path on one MI355X.
+
+Workload: 2,097,152 particles on a jittered 128^3 lattice in the periodic unit
+box (seeded), FP32 AoS records of 128 bytes (FP64 positions), resident in HBM.
+One step = bin -> AoS->SoA convert (GPU) -> density -> force -> FP64
+reductions -> kick/drift -> SoA->AoS writeback, all through the C ABI on one
+stream. The headline value is in-support pair interactions (density pairs
+incl. self + force pairs) per second over whole steps.
+
+Beside it: per-kernel times (HIP events on the launch stream), HBM GB/s of
+convert / kick-drift / writeback at algorithmic bytes, the plain-AoS step and
+the reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) on the same
+particles, the host-side convert variant, and the FP64 CPU oracle timed on a
+bounded sample (rank 0, N = 1).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pair-interactions/s (density, force) + HBM GB/s; FP16-store vs FP32 AoS"
+N_SIDE = 128
+N_C = 32
+SEED = 2
+DT = 1e-4
+
+# Algorithmic work per unit (counted from the pair expressions; FMA = 2 flops,
+# sqrt / reciprocal = 1): per in-support density pair and force pair.
+FLOP_DENSITY_PAIR = 34
+FLOP_FORCE_PAIR = 72
+# Algorithmic bytes per particle (FP32 record, FP32 storage):
+BYTES_CONVERT_FULL = 56 + 8 + 76     # record fields x,v,m,h,u + perm,cell; SoA writes
+BYTES_KICK = 96                      # x(24) v(12) u(4) a(12) du(4) read; x v u written
+BYTES_WRITEBACK_FULL = 104 + 96      # SoA reads (incl. perm, cell); record field writes
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_list(pipe, kind):
+    if kind == "soa":
+        return [("bin", pipe.bin), ("convert", lambda: pipe.convert("full")),
+                ("density", pipe.density), ("force", pipe.force), ("reduce", pipe.reduce),
+                ("kick_drift", lambda: pipe.kick_drift(DT, DT)),
+                ("writeback", lambda: pipe.writeback("full"))]
+    return [("bin", pipe.bin), ("density", pipe.density_aos), ("force", pipe.force_aos),
+            ("kick_drift", lambda: pipe.kick_drift_aos(DT, DT))]
+
+
+def timed_steps(torch, pipe, kind, steps, warmup):
+    """Run warmup + steps whole steps; events bracket every stage of every
+    timed step on the launch stream. Returns (seconds, per-stage ms)."""
+    stages = stage_list(pipe, kind)
+    for _ in range(warmup):
+        for _, fn in stages:
+            fn()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s in range(steps):
+        evs[s][0].record()
+        for q, (_, fn) in enumerate(stages):
+            fn()
+            evs[s][q + 1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {}
+    for q, (name, _) in enumerate(stages):
+        per[name] = float(np.mean([evs[s][q].elapsed_time(evs[s][q + 1]) for s in range(steps)]))
+    return t1 - t0, per
+
+
+def cpu_baseline(ps):
+    """FP64 oracle (cells mode, OpenMP) on a bounded sample of the workload:
+    density over all particles and force over every 8th particle."""
+    import oracle
+    oracle.lib()
+    n = ps.n
+    t0 = time.perf_counter()
+    d = oracle.density(ps, n_c=N_C)
+    t1 = time.perf_counter()
+    sel = np.arange(0, n, 8, dtype=np.int32)
+    f = oracle.force(ps, d, n_c=N_C, sel=sel)
+    t2 = time.perf_counter()
+    pairs = float(d["nngb"].sum() + f["nforce"].sum())
+    return {"value": pairs / (t2 - t0), "unit": "pair-interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, cell-list mode: density over all {n} particles "
+                      f"({t1 - t0:.2f} s) + force over {len(sel)} (every 8th) "
+                      f"({t2 - t1:.2f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="time only the FP32 SoA step (profiling runs)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the halo-exchange design is documented, not built). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_05516_amd import inputs, sphmi
+    from paper_2512_05516_amd.pipeline import Pipeline
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    sphmi.lib()
+    torch.cuda.set_device(0)
+    log("generating 128^3 jittered lattice")
+    ps = inputs.medium_set(SEED)
+    rec = inputs.pack_aos(ps, "f32")
+    n = ps.n
+
+    # ---- headline: FP32 SoA step, GPU-side convert ---------------------------
+    log("FP32 SoA step")
+    pipe = Pipeline(rec, N_C)
+    secs, per = timed_steps(torch, pipe, "soa", args.steps, args.warmup)
+    red = pipe.red_out.cpu().numpy()
+    pairs_d, pairs_f = float(red[6]), float(red[7])
+    pairs = pairs_d + pairs_f
+    ms_step = 1e3 * secs / args.steps
+    value = pairs * args.steps / secs
+    status = pipe.status()
+    if status:
+        log(f"WARNING: kernel status flags {status}")
+
+    force_s = per["force"] * 1e-3
+    achieved = FLOP_FORCE_PAIR * pairs_f / force_s / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None, "kernel": "k_force (FP32 SoA)",
+                "flop_per_unit": FLOP_FORCE_PAIR, "units_per_launch": pairs_f}
+    dens_tf = FLOP_DENSITY_PAIR * pairs_d / (per["density"] * 1e-3) / 1e12
+    gbs = lambda b, ms: b * n / (ms * 1e-3) / 1e9
+    hbm = {"convert_full": round(gbs(BYTES_CONVERT_FULL, per["convert"]), 1),
+           "kick_drift": round(gbs(BYTES_KICK, per["kick_drift"]), 1),
+           "writeback_full": round(gbs(BYTES_WRITEBACK_FULL, per["writeback"]), 1)}
+    result = {
+        "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "jittered 128^3 lattice, 2,097,152 particles, FP32 AoS records "
+                               "(128 B, FP64 x) resident in HBM, GPU-side AoS->SoA convert",
+                   "particles": n, "n_c": N_C, "cells": N_C ** 3, "dt": DT,
+                   "step": "bin+convert+density+force+reduce+kick_drift+writeback",
+                   "tile": "64x4"},
+        "roofline": roofline,
+        "pairs_per_step": {"density": pairs_d, "force": pairs_f},
+        "kernels_ms": {k: round(v, 4) for k, v in per.items()},
+        "density_tflops": round(dens_tf, 3),
+        "hbm_gbs": hbm,
+        "hbm_frac": {k: round(v / PEAK_HBM_GBS, 4) for k, v in hbm.items()},
+        "status_flags": status,
+    }
+    del pipe
+    torch.cuda.empty_cache()
+
+    if not args.no_variants:
+        # ---- plain AoS step (Eq. gpu_native) ---------------------------------
+        log("plain AoS step")
+        pa = Pipeline(rec, N_C)
+        s_aos, per_aos = timed_steps(torch, pa, "aos", args.steps, args.warmup)
+        del pa
+        # ---- reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) -----
+        log("FP16-store SoA step")
+        prec = sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
+        pr = Pipeline(rec, N_C, prec=prec)
+        s_r, per_r = timed_steps(torch, pr, "soa", args.steps, args.warmup)
+        del pr
+        torch.cuda.empty_cache()
+        ms_aos = 1e3 * s_aos / args.steps
+        ms_r = 1e3 * s_r / args.steps
+        result["aos_plain"] = {"ms_per_step": ms_aos, "value": pairs * args.steps / s_aos,
+                               "kernels_ms": {k: round(v, 4) for k, v in per_aos.items()}}
+        result["fp16_store"] = {"ms_per_step": ms_r, "value": pairs * args.steps / s_r,
+                                "precision": "pos f16 offsets, v bf16, m/h/u f16 (scales 21/7/0)",
+                                "kernels_ms": {k: round(v, 4) for k, v in per_r.items()}}
+        result["speedup_vs_fp32_aos"] = {
+            "fp32_soa_step": round(ms_aos / ms_step, 3),
+            "fp16_store_step": round(ms_aos / ms_r, 3),
+            "density_fp16_store": round(per_aos["density"] / per_r["density"], 3),
+            "force_fp16_store": round(per_aos["force"] / per_r["force"], 3),
+            "kick_drift_fp16_store": round(per_aos["kick_drift"] / per_r["kick_drift"], 3),
+        }
+        # ---- host-side convert (CPU data management) vs GPU convert + copy ----
+        log("host-convert variant")
+        ph = Pipeline(rec, N_C)
+        prec32 = sphmi.precision()
+        nbytes = sphmi.host_staging_size(n, N_C, "full", prec32)
+        staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        host_aos = torch.from_numpy(rec.view(np.uint8).reshape(-1)).pin_memory()
+        variants = {}
+        for threads in (0, 16):
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sphmi.convert_host(rec, ph.layout, ph.cells, "full", ph.soa, staging, threads)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            variants[f"host_convert_full_ms_threads_{threads or 'all'}"] = 1e3 * min(ts)
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ph.aos.copy_(host_aos, non_blocking=True)
+            ph.bin()
+            ph.convert("full")
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        variants["gpu_convert_full_incl_h2d_ms"] = 1e3 * min(ts)
+        variants["host_cores"] = os.cpu_count()
+        result["convert_placement"] = variants
+        del ph, staging
+        torch.cuda.empty_cache()
+
+    if args.copy_probe_mib:
+        log("device copy probe")
+        nb = args.copy_probe_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = nb
+
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(ps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

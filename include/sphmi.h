@@ -1,0 +1,283 @@
+/* sphmi.h: C ABI of the MI355X (gfx950) SPH hot-path library libsphmi.so.
+ *
+ * The library implements the per-particle compute kernels of the SPH code
+ * studied in "Compiler-supported reduced precision and AoS-SoA
+ * transformations for heterogeneous hardware" (Radtke & Weinzierl):
+ *   - cell binning of an array-of-structs particle set,
+ *   - the AoS->SoA gather with narrowing and storage below IEEE double
+ *     (operators N, C, U of Sec. 4.1) and its inverse,
+ *   - the quadratic density and force kernels (Sec. 2.1, Eq. density and
+ *     Eq. momentum; Alg. 1 CallQuadratic),
+ *   - the linear kick/drift kernel (Alg. 1 CallLinear),
+ *   - plain-AoS forms of the three kernels (the GPU-native variant of
+ *     Sec. 4.3, Eq. gpu_native),
+ *   - FP64 conservation reductions.
+ *
+ * Conventions
+ *   - Every entry point returns sph_status: 0 (SPH_OK) or a negative error.
+ *     sph_last_error() returns a thread-local message describing the last
+ *     failure on the calling thread; it stays valid until the next call on
+ *     that thread. No C++ exception and no HIP error crosses this boundary.
+ *   - Pointers are device pointers unless a parameter says "host". The
+ *     caller allocates and owns every buffer, including workspaces; the
+ *     library allocates no persistent device memory and keeps no global
+ *     mutable state.
+ *   - Device work is enqueued on the caller's stream and the call returns
+ *     without waiting. Kernel-side conditions (NaN positions, smoothing
+ *     lengths too large for the cell list) are OR-ed into the optional
+ *     device word sph_cells.status; the caller reads it after the stream
+ *     has reached the call. Argument errors are detected on the host before
+ *     anything is enqueued.
+ *   - Particle arrays in an sph_soa are indexed by sorted slot k
+ *     (0 <= k < n): slot k holds input particle perm[k], and slots of one
+ *     cell are contiguous.
+ *   - Floating-point arithmetic and accumulation in the pair kernels is
+ *     FP32; positions are FP64 in the AoS record and in the kick view.
+ */
+#ifndef SPHMI_H
+#define SPHMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1
+
+typedef int32_t sph_status;
+enum {
+  SPH_OK = 0,
+  SPH_E_INVALID = -1,      /* bad pointer, enum, size or layout            */
+  SPH_E_RANGE = -2,        /* n_c < 3, cell count overflow                 */
+  SPH_E_NOMEM = -3,        /* workspace smaller than required              */
+  SPH_E_HIP = -4,          /* HIP runtime error (message has the details)  */
+  SPH_E_UNSUPPORTED = -5   /* valid but unsupported combination            */
+};
+
+/* bits OR-ed into *sph_cells.status by kernels */
+enum {
+  SPH_FLAG_BAD_POSITION = 1,   /* a position was NaN or infinite            */
+  SPH_FLAG_H_TOO_LARGE = 2     /* some H_i exceeded the cell side: neighbour
+                                  sums may miss particles                   */
+};
+
+/* storage formats (Table 2: 64, 32 and 16 total bits; plus bfloat16) */
+typedef enum {
+  SPH_F64 = 0, SPH_F32 = 1, SPH_F16 = 2, SPH_BF16 = 3, SPH_I32 = 4
+} sph_dtype;
+
+/* ------------------------------------------------------------------ */
+/* AoS record description (Table 1 fields; "all variants derive from   */
+/* one struct declaration", Sec. 4.1). X, V, A are 3 consecutive        */
+/* elements. X must be SPH_F64; the other floating fields SPH_F32 or    */
+/* SPH_F64; NNGB, NFORCE, CELL are SPH_I32. Unused fields: offset       */
+/* SPH_ABSENT. Every present field must lie inside the stride and be    */
+/* aligned to its element size.                                         */
+/* ------------------------------------------------------------------ */
+enum {
+  SPH_A_X = 0, SPH_A_V, SPH_A_A, SPH_A_M, SPH_A_H, SPH_A_U, SPH_A_RHO, SPH_A_P,
+  SPH_A_C, SPH_A_DU, SPH_A_RHO_DH, SPH_A_WCOUNT, SPH_A_F, SPH_A_VSIG,
+  SPH_A_NNGB, SPH_A_NFORCE, SPH_A_CELL, SPH_A_NFIELDS
+};
+#define SPH_ABSENT 0xffffffffu
+
+typedef struct {
+  uint32_t stride;                     /* bytes per record, multiple of 8 */
+  uint32_t offset[SPH_A_NFIELDS];      /* byte offset or SPH_ABSENT      */
+  int32_t dtype[SPH_A_NFIELDS];        /* sph_dtype of each element      */
+} sph_aos_layout;
+
+/* ------------------------------------------------------------------ */
+/* Cell list (uniform grid over the periodic unit box)                  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t n;              /* particles                                   */
+  int32_t n_c;            /* cells per axis, >= 3; cell side 1/n_c must   */
+                          /* be >= every support radius H = gamma_k h     */
+  int32_t *cell_start;    /* [n_c^3 + 1] slots of cell c: [start[c],     */
+                          /* start[c+1])                                  */
+  int32_t *perm;          /* [n] input index of sorted slot k             */
+  int32_t *cell;          /* [n] cell id cx + n_c (cy + n_c cz) of slot k */
+  int32_t *status;        /* [1] optional (may be NULL) SPH_FLAG_* word   */
+} sph_cells;
+
+/* ------------------------------------------------------------------ */
+/* SoA buffers (sorted-slot order). One struct names every array a       */
+/* kernel may touch; each entry point lists the ones it reads/writes,   */
+/* the rest may be NULL.                                                */
+/* ------------------------------------------------------------------ */
+enum {
+  /* narrowed views for the pair kernels, stored in sph_precision formats */
+  SPH_S_OFF_X = 0, SPH_S_OFF_Y, SPH_S_OFF_Z,  /* x - cell origin  (pos)   */
+  SPH_S_VQ_X, SPH_S_VQ_Y, SPH_S_VQ_Z,         /* velocity         (vel)   */
+  SPH_S_M, SPH_S_H, SPH_S_U,                  /* m, h, u          (mhu)   */
+  /* kick view: absolute FP64 positions, FP32 velocity and energy        */
+  SPH_S_X_X, SPH_S_X_Y, SPH_S_X_Z,            /* double                   */
+  SPH_S_V_X, SPH_S_V_Y, SPH_S_V_Z, SPH_S_UK,  /* float                    */
+  /* density outputs (float; NNGB int32)                                  */
+  SPH_S_RHO, SPH_S_WCOUNT, SPH_S_RHO_DH, SPH_S_F, SPH_S_P, SPH_S_C, SPH_S_NNGB,
+  /* force outputs (float; NFORCE int32)                                  */
+  SPH_S_A_X, SPH_S_A_Y, SPH_S_A_Z, SPH_S_DU, SPH_S_VSIG, SPH_S_NFORCE,
+  SPH_S_NFIELDS
+};
+
+typedef struct {
+  void *f[SPH_S_NFIELDS];
+} sph_soa;
+
+/* storage precision of the narrowed views. pos: SPH_F32 | SPH_F16 |
+ * SPH_BF16; vel and mhu: SPH_F32 | SPH_F16 | SPH_BF16. A field with scale
+ * s is stored as RNE(RNE32(v) * 2^s) and read back as stored * 2^-s
+ * (|s| <= 64; exact power-of-two scaling keeps small masses and
+ * smoothing lengths in the normal range of FP16). */
+typedef struct {
+  int32_t pos, vel, mhu;
+  int32_t scale_m, scale_h, scale_u;
+} sph_precision;
+
+/* which fields a convert or writeback moves (operator N of Sec. 4.1) */
+typedef enum {
+  SPH_VIEW_DENSITY = 0,   /* OFF, M, H, U                                 */
+  SPH_VIEW_FORCE = 1,     /* OFF, VQ, M, H                                */
+  SPH_VIEW_KICK = 2,      /* X, V, UK                                     */
+  SPH_VIEW_FULL = 3       /* all of the above                             */
+} sph_view;
+
+/* physics constants: H = gamma_k h; P = (gamma - 1) rho u; viscosity
+ * strength alpha and signal-velocity coefficient beta; gradh = 1 applies
+ * the grad-h factor f_i, 0 sets f_i = 1. */
+typedef struct {
+  double gamma_k, gamma, alpha, beta;
+  int32_t gradh;
+} sph_params;
+
+/* pair-kernel tiling: ti particles i per work item, k lanes per particle
+ * (ti * k threads per workgroup). {0, 0} picks the default. Supported
+ * combinations are listed by sph_tile_supported. */
+typedef struct {
+  int32_t ti, k;
+} sph_tile;
+
+/* ------------------------------------------------------------------ */
+/* Entry points                                                        */
+/* ------------------------------------------------------------------ */
+
+int32_t sph_abi_version(void);
+const char *sph_last_error(void);
+
+/* 1 if the tiling is compiled in, else 0. */
+int32_t sph_tile_supported(sph_tile tile);
+
+/* Workspace bytes sph_bin needs for n particles and n_c cells per axis. */
+sph_status sph_bin_workspace_size(int32_t n, int32_t n_c, size_t *bytes);
+
+/* Cell binning (spatial buffers of co-located particles, Sec. 6 setup).
+ * For every record i of the AoS (device pointer aos, layout->stride bytes
+ * apart, X read as FP64): wrap x into [0,1) as x - floor(x); per axis
+ * c = min(floor(x * n_c), n_c - 1) in FP64; id = cx + n_c (cy + n_c cz).
+ * Writes cells->cell_start, cells->perm and cells->cell (stable order by
+ * (cell id, input index): bit-identical on every run). cells->n and
+ * cells->n_c are inputs. Raises SPH_FLAG_BAD_POSITION for non-finite x
+ * (such particles are put in cell 0). */
+sph_status sph_bin(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* AoS->SoA gather U o N o C (Sec. 4.1; Eq. gpu_soa_conversion): for every
+ * sorted slot k, read record perm[k] and write the view's fields at k.
+ * OFF = FP32(x_wrapped - c / n_c) (FP64 difference, one rounding), then
+ * the pos format; VQ, M, H, U: RNE to FP32, scale, RNE to the format;
+ * X: wrapped FP64 position; V, UK: FP32. */
+sph_status sph_convert(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                       int32_t view, const sph_precision *prec, const sph_soa *out,
+                       hipStream_t stream);
+
+/* Host-side variant (Eq. gpu_soa_conversion_cpu_datamanagement; the
+ * soa_conversion_handler(host) semantics of Sec. 3.1): the host bins the
+ * host AoS (aos_host, n records) with nthreads OpenMP threads and gathers
+ * the view into pinned host staging (staging_host, at least
+ * sph_host_staging_size bytes, allocated with hipHostMalloc), then copies
+ * the cell list and the view to the device buffers of cells / out on
+ * stream. Returns after the copies are enqueued; staging must stay alive
+ * until the stream reaches them. */
+sph_status sph_host_staging_size(int32_t n, int32_t n_c, int32_t view,
+                                 const sph_precision *prec, size_t *bytes);
+sph_status sph_convert_host(const void *aos_host, const sph_aos_layout *layout,
+                            const sph_cells *cells, int32_t view, const sph_precision *prec,
+                            const sph_soa *out, void *staging_host, size_t staging_bytes,
+                            int32_t nthreads, hipStream_t stream);
+
+/* SoA->AoS writeback C^AoS_SoA o N^T o U^T (Sec. 4.1): writes the view's
+ * state (KICK: X, V, UK -> x, v, u) and the kernel outputs present in soa
+ * (DENSITY: rho, wcount, rho_dh, f, P, c, nngb; FORCE: a, du, vsig,
+ * nforce; FULL: all plus the cell id) into record perm[k]. */
+sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t view,
+                         void *aos, const sph_aos_layout *layout, hipStream_t stream);
+
+/* Density loop (Eq. density; Alg. 1 CallQuadratic over the 27 cells
+ * around each particle's cell). For every slot i, over every j with
+ * r_ij < H_i, the self pair included (support test in FP32:
+ * r2 = fma(dz,dz,fma(dy,dy,dx*dx)) < (gamma_k h_i)^2 with d the difference
+ * of the stored offsets shifted by the cell separation):
+ *   rho_i = sum m_j W(r_ij, h_i)      wcount_i = (4 pi/3) sum w(r_ij/H_i)
+ *   rho_dh_i = sum m_j dW/dh          nngb_i = #j
+ *   f_i = 1 / (1 + h_i rho_dh_i / (3 rho_i))   (1 if gradh = 0)
+ *   P_i = (gamma-1) rho_i u_i         c_i = sqrt(gamma (gamma-1) u_i)
+ * Reads OFF, M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB. */
+sph_status sph_density(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                       const sph_params *params, sph_tile tile, hipStream_t stream);
+
+/* Force loop (Eq. momentum and Eq. energy, discrete grad-h form with
+ * signal-velocity artificial viscosity). For every slot i, over j != i with
+ * r_ij < max(H_i, H_j) (FP32 test as above against both radii):
+ *   A = f P / rho^2,  g_k = w'(r/H_k)/H_k^4 if r < H_k else 0,
+ *   w = (v_i - v_j).e,  mu = min(w, 0),  vsig_ij = c_i + c_j - beta mu,
+ *   Pi = -alpha vsig_ij mu / (rho_i + rho_j),  gbar = (g_i + g_j)/2,
+ *   a_i   -= m_j (A_i g_i + A_j g_j + Pi gbar) e
+ *   du_i  += m_j (A_i g_i + Pi gbar / 2) w
+ *   vsig_i = max_j vsig_ij,  nforce_i = #j
+ * Reads OFF, VQ, M, H and RHO, F, P, C; writes A_*, DU, VSIG, NFORCE. */
+sph_status sph_force(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                     const sph_params *params, sph_tile tile, hipStream_t stream);
+
+/* Kick and drift (Alg. 1 CallLinear): v += a dt_kick, u += du dt_kick
+ * (FP32), then x += v dt_drift in FP64 with the kicked v and wrap into
+ * [0,1). Reads/writes X, V, UK; reads A_*, DU. If moved (device int32)
+ * is non-NULL, adds the number of particles whose cell changed. */
+sph_status sph_kick_drift(const sph_soa *soa, const sph_cells *cells, double dt_kick,
+                          double dt_drift, int32_t *moved, hipStream_t stream);
+
+/* FP64 reductions over the slots (deterministic order):
+ * out[0..2] = sum m a, out[3] = sum m (v.a + du), out[4] = sum m |a|,
+ * out[5] = sum m (|v.a| + |du|), out[6] = sum nngb, out[7] = sum nforce.
+ * Reads M (with its scale) or, if NULL, nothing for m (m = 1), V, A, DU,
+ * NNGB, NFORCE. out: 8 doubles on the device. workspace: at least
+ * sph_reduce_workspace_size bytes. */
+sph_status sph_reduce_workspace_size(int32_t n, size_t *bytes);
+sph_status sph_reduce(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                      double *out, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Plain-AoS forms (Eq. gpu_native): the same kernels reading and writing
+ * the AoS records through the cell list (record perm[k] for slot k),
+ * with the identical loop order and arithmetic, so FP32 records give
+ * bit-identical results to the FP32 SoA path. */
+sph_status sph_density_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                           const sph_params *params, sph_tile tile, hipStream_t stream);
+sph_status sph_force_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                         const sph_params *params, sph_tile tile, hipStream_t stream);
+/* kick/drift over records 0..n-1 (no cell list needed; cells->n_c is used
+ * for the moved count when moved != NULL) */
+sph_status sph_kick_drift_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                              double dt_kick, double dt_drift, int32_t *moved,
+                              hipStream_t stream);
+
+/* hipStreamSynchronize with the error mapped to sph_status */
+sph_status sph_sync(hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPHMI_H */

@@ -95,8 +95,13 @@ def lib():
         L.orc_roundtrip.argtypes = [C.c_double, C.c_int, C.c_int]
         L.orc_dequantise_set.argtypes = [C.c_int, d, d, d, d, d, C.c_int, C.c_int, C.c_int,
                                          C.c_int, i32, d, d, d, d, d]
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _p(a, t):

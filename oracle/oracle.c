@@ -29,6 +29,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846
 
@@ -565,4 +568,13 @@ int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k
   free(o32);
   free(H2);
   return 0;
+}
+
+/* threads an OpenMP parallel region of the oracle uses */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

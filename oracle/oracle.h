@@ -90,6 +90,9 @@ int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
                        int vel_dt, int mhu_dt, const int32_t *scales,
                        double *xq, double *vq, double *mq, double *hq, double *uq);
 
+/* threads the OpenMP regions use */
+int orc_num_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

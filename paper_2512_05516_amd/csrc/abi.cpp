@@ -1,0 +1,399 @@
+// Host entry points of libsphmi: argument validation, conversion of the ABI
+// structs to the kernels' parameter blocks, HIP error mapping and the
+// thread-local last-error message. Nothing here allocates device memory.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sph_internal.h"
+
+using namespace sph;
+
+namespace {
+
+thread_local std::string g_err;
+
+sph_status fail(sph_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+sph_status fail(sph_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+sph_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SPH_OK;
+  return fail(SPH_E_HIP, "%s: HIP error %d (%s)", what, (int)e, hipGetErrorString(e));
+}
+
+bool is_float_dt(int dt) { return dt == SPH_F32 || dt == SPH_F64; }
+bool is_store_dt(int dt) { return dt == SPH_F32 || dt == SPH_F16 || dt == SPH_BF16; }
+
+int elem_size(int dt) {
+  switch (dt) {
+    case SPH_F64: return 8;
+    case SPH_F32: return 4;
+    case SPH_F16:
+    case SPH_BF16: return 2;
+    case SPH_I32: return 4;
+    default: return 0;
+  }
+}
+
+int field_comps(int f) { return (f == SPH_A_X || f == SPH_A_V || f == SPH_A_A) ? 3 : 1; }
+bool field_is_int(int f) { return f == SPH_A_NNGB || f == SPH_A_NFORCE || f == SPH_A_CELL; }
+
+const char* aos_field_name(int f) {
+  static const char* names[SPH_A_NFIELDS] = {"X", "V", "A", "M", "H", "U", "RHO", "P", "C",
+                                             "DU", "RHO_DH", "WCOUNT", "F", "VSIG", "NNGB",
+                                             "NFORCE", "CELL"};
+  return (f >= 0 && f < SPH_A_NFIELDS) ? names[f] : "?";
+}
+
+// Validate the layout; `need` is a bitmask of fields that must be present.
+sph_status check_layout(const sph_aos_layout* l, uint32_t need, AosLayout& out) {
+  if (!l) return fail(SPH_E_INVALID, "layout is NULL");
+  if (l->stride == 0 || l->stride % 8 != 0)
+    return fail(SPH_E_INVALID, "layout stride %u must be a positive multiple of 8", l->stride);
+  out.stride = l->stride;
+  for (int f = 0; f < SPH_A_NFIELDS; ++f) {
+    out.off[f] = l->offset[f];
+    out.dt[f] = l->dtype[f];
+    if (l->offset[f] == SPH_ABSENT) {
+      if (need & (1u << f)) return fail(SPH_E_INVALID, "layout lacks field %s", aos_field_name(f));
+      continue;
+    }
+    int dt = l->dtype[f];
+    if (f == SPH_A_X && dt != SPH_F64)
+      return fail(SPH_E_INVALID, "layout field X must be SPH_F64");
+    if (field_is_int(f) ? dt != SPH_I32 : !is_float_dt(dt))
+      return fail(SPH_E_INVALID, "layout field %s has unsupported dtype %d", aos_field_name(f), dt);
+    uint64_t size = (uint64_t)elem_size(dt) * (uint64_t)field_comps(f);
+    if ((uint64_t)l->offset[f] + size > l->stride)
+      return fail(SPH_E_INVALID, "layout field %s exceeds the stride", aos_field_name(f));
+    if (l->offset[f] % (uint32_t)elem_size(dt) != 0)
+      return fail(SPH_E_INVALID, "layout field %s is misaligned", aos_field_name(f));
+  }
+  return SPH_OK;
+}
+
+constexpr uint32_t bit(int f) { return 1u << f; }
+
+sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
+  if (!c) return fail(SPH_E_INVALID, "cells is NULL");
+  if (c->n < 0) return fail(SPH_E_INVALID, "cells->n = %d is negative", c->n);
+  if (c->n_c < 3) return fail(SPH_E_RANGE, "cells->n_c = %d must be >= 3", c->n_c);
+  if (c->n_c > 1290) return fail(SPH_E_RANGE, "cells->n_c = %d: n_c^3 overflows int32", c->n_c);
+  if (need_lists && (!c->cell_start || !c->perm || !c->cell))
+    return fail(SPH_E_INVALID, "cells->cell_start, perm and cell must be device pointers");
+  out.n = c->n;
+  out.n_c = c->n_c;
+  out.start = c->cell_start;
+  out.perm = c->perm;
+  out.cell = c->cell;
+  out.status = c->status;
+  return SPH_OK;
+}
+
+sph_status check_prec(const sph_precision* p, Prec& out) {
+  if (!p) return fail(SPH_E_INVALID, "precision is NULL");
+  if (!is_store_dt(p->pos) || !is_store_dt(p->vel) || !is_store_dt(p->mhu))
+    return fail(SPH_E_INVALID, "precision formats must be SPH_F32, SPH_F16 or SPH_BF16");
+  const int32_t sc[3] = {p->scale_m, p->scale_h, p->scale_u};
+  for (int q = 0; q < 3; ++q)
+    if (sc[q] < -64 || sc[q] > 64) return fail(SPH_E_INVALID, "precision scale %d out of range", sc[q]);
+  out.pos = p->pos;
+  out.vel = p->vel;
+  out.mhu = p->mhu;
+  out.store_m = std::ldexp(1.0f, p->scale_m);
+  out.store_h = std::ldexp(1.0f, p->scale_h);
+  out.store_u = std::ldexp(1.0f, p->scale_u);
+  out.load_m = std::ldexp(1.0f, -p->scale_m);
+  out.load_h = std::ldexp(1.0f, -p->scale_h);
+  out.load_u = std::ldexp(1.0f, -p->scale_u);
+  return SPH_OK;
+}
+
+sph_status check_params(const sph_params* p, Phys& out) {
+  if (!p) return fail(SPH_E_INVALID, "params is NULL");
+  const double v[4] = {p->gamma_k, p->gamma, p->alpha, p->beta};
+  for (double x : v)
+    if (!std::isfinite(x)) return fail(SPH_E_INVALID, "params must be finite");
+  if (!(p->gamma_k > 0.0)) return fail(SPH_E_INVALID, "params->gamma_k must be positive");
+  out.gamma_k = (float)p->gamma_k;
+  out.gamma = (float)p->gamma;
+  out.alpha = (float)p->alpha;
+  out.beta = (float)p->beta;
+  out.gradh = p->gradh ? 1 : 0;
+  return SPH_OK;
+}
+
+sph_status check_soa(const sph_soa* s, const int* fields, int nf, const char* what) {
+  if (!s) return fail(SPH_E_INVALID, "%s: soa is NULL", what);
+  for (int q = 0; q < nf; ++q)
+    if (!s->f[fields[q]]) return fail(SPH_E_INVALID, "%s: soa field %d is NULL", what, fields[q]);
+  return SPH_OK;
+}
+
+sph_status resolve_tile(sph_tile t, int& ti, int& k) {
+  ti = t.ti;
+  k = t.k;
+  if (ti == 0 && k == 0) {
+    ti = 64;
+    k = 4;
+  }
+  if (!tile_supported(ti, k)) return fail(SPH_E_UNSUPPORTED, "tile {%d, %d} is not compiled in", ti, k);
+  return SPH_OK;
+}
+
+#define SPH_TRY(x)                  \
+  do {                              \
+    sph_status _st = (x);           \
+    if (_st != SPH_OK) return _st;  \
+  } while (0)
+
+const int kDensIn[] = {SPH_S_OFF_X, SPH_S_OFF_Y, SPH_S_OFF_Z, SPH_S_M, SPH_S_H, SPH_S_U,
+                       SPH_S_RHO, SPH_S_WCOUNT, SPH_S_RHO_DH, SPH_S_F, SPH_S_P, SPH_S_C,
+                       SPH_S_NNGB};
+const int kForceIn[] = {SPH_S_OFF_X, SPH_S_OFF_Y, SPH_S_OFF_Z, SPH_S_VQ_X, SPH_S_VQ_Y, SPH_S_VQ_Z,
+                        SPH_S_M, SPH_S_H, SPH_S_RHO, SPH_S_F, SPH_S_P, SPH_S_C, SPH_S_A_X,
+                        SPH_S_A_Y, SPH_S_A_Z, SPH_S_DU, SPH_S_VSIG};
+const int kKickIn[] = {SPH_S_X_X, SPH_S_X_Y, SPH_S_X_Z, SPH_S_V_X, SPH_S_V_Y, SPH_S_V_Z, SPH_S_UK,
+                       SPH_S_A_X, SPH_S_A_Y, SPH_S_A_Z, SPH_S_DU};
+const int kReduceIn[] = {SPH_S_VQ_X, SPH_S_VQ_Y, SPH_S_VQ_Z, SPH_S_A_X, SPH_S_A_Y, SPH_S_A_Z,
+                         SPH_S_DU};
+const int kViewDens[] = {SPH_S_OFF_X, SPH_S_OFF_Y, SPH_S_OFF_Z, SPH_S_M, SPH_S_H, SPH_S_U};
+const int kViewForce[] = {SPH_S_OFF_X, SPH_S_OFF_Y, SPH_S_OFF_Z, SPH_S_VQ_X, SPH_S_VQ_Y,
+                          SPH_S_VQ_Z, SPH_S_M, SPH_S_H};
+const int kViewKick[] = {SPH_S_X_X, SPH_S_X_Y, SPH_S_X_Z, SPH_S_V_X, SPH_S_V_Y, SPH_S_V_Z,
+                         SPH_S_UK};
+
+template <size_t N>
+constexpr int len(const int (&)[N]) { return (int)N; }
+
+sph_status check_view_soa(const sph_soa* s, int view, const char* what) {
+  switch (view) {
+    case SPH_VIEW_DENSITY: return check_soa(s, kViewDens, len(kViewDens), what);
+    case SPH_VIEW_FORCE: return check_soa(s, kViewForce, len(kViewForce), what);
+    case SPH_VIEW_KICK: return check_soa(s, kViewKick, len(kViewKick), what);
+    case SPH_VIEW_FULL:
+      SPH_TRY(check_soa(s, kViewDens, len(kViewDens), what));
+      SPH_TRY(check_soa(s, kViewForce, len(kViewForce), what));
+      return check_soa(s, kViewKick, len(kViewKick), what);
+    default: return fail(SPH_E_INVALID, "%s: unknown view %d", what, view);
+  }
+}
+
+uint32_t view_aos_fields(int view) {
+  uint32_t need = bit(SPH_A_X);
+  if (view == SPH_VIEW_DENSITY || view == SPH_VIEW_FULL)
+    need |= bit(SPH_A_M) | bit(SPH_A_H) | bit(SPH_A_U);
+  if (view == SPH_VIEW_FORCE || view == SPH_VIEW_FULL)
+    need |= bit(SPH_A_V) | bit(SPH_A_M) | bit(SPH_A_H);
+  if (view == SPH_VIEW_KICK || view == SPH_VIEW_FULL) need |= bit(SPH_A_V) | bit(SPH_A_U);
+  return need;
+}
+
+}  // namespace
+
+namespace sph {
+sph_status host_fail(sph_status code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace sph
+
+extern "C" {
+
+int32_t sph_abi_version(void) { return SPH_ABI_VERSION; }
+
+const char* sph_last_error(void) { return g_err.c_str(); }
+
+int32_t sph_tile_supported(sph_tile tile) { return tile_supported(tile.ti, tile.k) ? 1 : 0; }
+
+sph_status sph_bin_workspace_size(int32_t n, int32_t n_c, size_t* bytes) {
+  if (!bytes) return fail(SPH_E_INVALID, "bytes is NULL");
+  if (n < 0) return fail(SPH_E_INVALID, "n = %d is negative", n);
+  if (n_c < 3 || n_c > 1290) return fail(SPH_E_RANGE, "n_c = %d out of range [3, 1290]", n_c);
+  *bytes = bin_workspace_bytes(n, n_c);
+  return SPH_OK;
+}
+
+sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                   void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  SPH_TRY(check_layout(layout, bit(SPH_A_X), L));
+  SPH_TRY(check_cells(cells, true, c));
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  size_t need = bin_workspace_bytes(c.n, c.n_c);
+  if (!workspace) return fail(SPH_E_INVALID, "workspace is NULL");
+  if (workspace_bytes < need)
+    return fail(SPH_E_NOMEM, "workspace has %zu bytes, sph_bin needs %zu", workspace_bytes, need);
+  return hip_status(launch_bin(aos, L, c, cells->cell_start, cells->perm, cells->cell, workspace,
+                               stream),
+                    "sph_bin");
+}
+
+sph_status sph_convert(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                       int32_t view, const sph_precision* prec, const sph_soa* out,
+                       hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  Prec p;
+  SPH_TRY(check_view_soa(out, view, "sph_convert"));
+  SPH_TRY(check_layout(layout, view_aos_fields(view), L));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  return hip_status(launch_convert(aos, L, c, view, p, *out, stream), "sph_convert");
+}
+
+sph_status sph_writeback(const sph_soa* soa, const sph_cells* cells, int32_t view, void* aos,
+                         const sph_aos_layout* layout, hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  if (!soa) return fail(SPH_E_INVALID, "sph_writeback: soa is NULL");
+  if (view < SPH_VIEW_DENSITY || view > SPH_VIEW_FULL)
+    return fail(SPH_E_INVALID, "sph_writeback: unknown view %d", view);
+  uint32_t need = bit(SPH_A_X);
+  if (view == SPH_VIEW_KICK || view == SPH_VIEW_FULL) {
+    SPH_TRY(check_view_soa(soa, SPH_VIEW_KICK, "sph_writeback"));
+    need |= bit(SPH_A_V) | bit(SPH_A_U);
+  }
+  bool dens = (view == SPH_VIEW_DENSITY || view == SPH_VIEW_FULL) && soa->f[SPH_S_RHO];
+  bool force = (view == SPH_VIEW_FORCE || view == SPH_VIEW_FULL) && soa->f[SPH_S_A_X];
+  if (dens) {
+    const int f[] = {SPH_S_RHO, SPH_S_WCOUNT, SPH_S_RHO_DH, SPH_S_F, SPH_S_P, SPH_S_C, SPH_S_NNGB};
+    SPH_TRY(check_soa(soa, f, len(f), "sph_writeback"));
+  }
+  if (force) {
+    const int f[] = {SPH_S_A_X, SPH_S_A_Y, SPH_S_A_Z, SPH_S_DU, SPH_S_VSIG};
+    SPH_TRY(check_soa(soa, f, len(f), "sph_writeback"));
+  }
+  SPH_TRY(check_layout(layout, need, L));
+  SPH_TRY(check_cells(cells, true, c));
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  return hip_status(launch_writeback(*soa, c, view, aos, L, stream), "sph_writeback");
+}
+
+sph_status sph_density(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                       const sph_params* params, sph_tile tile, hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  Phys ph;
+  int ti, k;
+  SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_density"));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_params(params, ph));
+  SPH_TRY(resolve_tile(tile, ti, k));
+  return hip_status(launch_density(*soa, p, c, ph, ti, k, stream), "sph_density");
+}
+
+sph_status sph_force(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                     const sph_params* params, sph_tile tile, hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  Phys ph;
+  int ti, k;
+  SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_force"));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_params(params, ph));
+  SPH_TRY(resolve_tile(tile, ti, k));
+  return hip_status(launch_force(*soa, p, c, ph, ti, k, stream), "sph_force");
+}
+
+sph_status sph_kick_drift(const sph_soa* soa, const sph_cells* cells, double dt_kick,
+                          double dt_drift, int32_t* moved, hipStream_t stream) {
+  CellsDev c;
+  SPH_TRY(check_soa(soa, kKickIn, len(kKickIn), "sph_kick_drift"));
+  SPH_TRY(check_cells(cells, false, c));
+  if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+    return fail(SPH_E_INVALID, "time steps must be finite");
+  return hip_status(launch_kick_drift(*soa, c, dt_kick, dt_drift, moved, stream), "sph_kick_drift");
+}
+
+sph_status sph_reduce_workspace_size(int32_t n, size_t* bytes) {
+  if (!bytes) return fail(SPH_E_INVALID, "bytes is NULL");
+  if (n < 0) return fail(SPH_E_INVALID, "n = %d is negative", n);
+  *bytes = reduce_workspace_bytes(n);
+  return SPH_OK;
+}
+
+sph_status sph_reduce(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                      double* out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  SPH_TRY(check_soa(soa, kReduceIn, len(kReduceIn), "sph_reduce"));
+  SPH_TRY(check_cells(cells, false, c));
+  SPH_TRY(check_prec(prec, p));
+  if (!out) return fail(SPH_E_INVALID, "sph_reduce: out is NULL");
+  if (!workspace) return fail(SPH_E_INVALID, "sph_reduce: workspace is NULL");
+  if (workspace_bytes < reduce_workspace_bytes(c.n))
+    return fail(SPH_E_NOMEM, "sph_reduce: workspace has %zu bytes, needs %zu", workspace_bytes,
+                reduce_workspace_bytes(c.n));
+  return hip_status(launch_reduce(*soa, p, c.n, out, workspace, stream), "sph_reduce");
+}
+
+sph_status sph_density_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                           const sph_params* params, sph_tile tile, hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  Phys ph;
+  int ti, k;
+  SPH_TRY(check_layout(layout,
+                       bit(SPH_A_X) | bit(SPH_A_M) | bit(SPH_A_H) | bit(SPH_A_U) | bit(SPH_A_RHO) |
+                           bit(SPH_A_WCOUNT) | bit(SPH_A_RHO_DH) | bit(SPH_A_F) | bit(SPH_A_P) |
+                           bit(SPH_A_C),
+                       L));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_params(params, ph));
+  SPH_TRY(resolve_tile(tile, ti, k));
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  return hip_status(launch_density_aos(aos, L, c, ph, ti, k, stream), "sph_density_aos");
+}
+
+sph_status sph_force_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                         const sph_params* params, sph_tile tile, hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  Phys ph;
+  int ti, k;
+  SPH_TRY(check_layout(layout,
+                       bit(SPH_A_X) | bit(SPH_A_V) | bit(SPH_A_A) | bit(SPH_A_M) | bit(SPH_A_H) |
+                           bit(SPH_A_RHO) | bit(SPH_A_F) | bit(SPH_A_P) | bit(SPH_A_C) |
+                           bit(SPH_A_DU) | bit(SPH_A_VSIG),
+                       L));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_params(params, ph));
+  SPH_TRY(resolve_tile(tile, ti, k));
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  return hip_status(launch_force_aos(aos, L, c, ph, ti, k, stream), "sph_force_aos");
+}
+
+sph_status sph_kick_drift_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                              double dt_kick, double dt_drift, int32_t* moved,
+                              hipStream_t stream) {
+  AosLayout L;
+  CellsDev c;
+  SPH_TRY(check_layout(layout,
+                       bit(SPH_A_X) | bit(SPH_A_V) | bit(SPH_A_A) | bit(SPH_A_U) | bit(SPH_A_DU), L));
+  SPH_TRY(check_cells(cells, false, c));
+  if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
+    return fail(SPH_E_INVALID, "time steps must be finite");
+  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  return hip_status(launch_kick_drift_aos(aos, L, c.n, c.n_c, dt_kick, dt_drift, moved, stream),
+                    "sph_kick_drift_aos");
+}
+
+sph_status sph_sync(hipStream_t stream) {
+  return hip_status(hipStreamSynchronize(stream), "sph_sync");
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+// Cell binning: FP64 cell ids, a stable LSD radix sort by cell id, and the
+// CSR cell_start table. The order is stable by (cell id, input index), so
+// the permutation is identical on every run and on every device.
+#include "sph_device.h"
+
+namespace sph {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kRounds = 8;
+constexpr int kTile = kThreads * kRounds;     // keys per radix block
+constexpr int kScanPer = 16;                  // elements per thread in scans
+constexpr int kScanTile = kThreads * kScanPer;
+
+__global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ aos,
+                                                        uint32_t stride, uint32_t offx, int n,
+                                                        int n_c, int32_t* __restrict__ keys,
+                                                        int32_t* __restrict__ vals,
+                                                        int32_t* status) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  const double* x = reinterpret_cast<const double*>(aos + (size_t)i * stride + offx);
+  bool bad = false;
+  int c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double xv = x[k];
+    bad |= !isfinite(xv);
+    c[k] = cell_axis(wrap01(xv), n_c);
+  }
+  keys[i] = c[0] + n_c * (c[1] + n_c * c[2]);
+  vals[i] = i;
+  if (bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restrict__ kin,
+                                                          int32_t* __restrict__ hist, int n,
+                                                          int nblk, int shift) {
+  __shared__ int h[256];
+  int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  int b = blockIdx.x;
+  for (int r = 0; r < kRounds; ++r) {
+    int idx = b * kTile + r * kThreads + tid;
+    if (idx < n) atomicAdd(&h[(kin[idx] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[tid * nblk + b] = h[tid];
+}
+
+// Stable scatter: in round r the block ranks keys b*kTile + r*256 + tid in
+// index order. Lanes with equal digits are found with 8 ballots; earlier
+// waves and earlier rounds are counted in LDS.
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
+    int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift) {
+  __shared__ int wcnt[kThreads / 64][256];
+  __shared__ int run[256];
+  __shared__ int base[256];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int b = blockIdx.x;
+  base[tid] = offsets[tid * nblk + b];
+  run[tid] = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  for (int r = 0; r < kRounds; ++r) {
+    int idx = b * kTile + r * kThreads + tid;
+    if (b * kTile + r * kThreads >= n) break;     // uniform over the block
+    bool valid = idx < n;
+    int key = valid ? kin[idx] : 0;
+    int val = valid ? vin[idx] : 0;
+    int d = (key >> shift) & 255;
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      uint64_t bl = __ballot((d >> bit) & 1);
+      m &= ((d >> bit) & 1) ? bl : ~bl;
+    }
+    int rank = __popcll(m & lanemask_lt());
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
+    __syncthreads();
+    if (valid) {
+      int pre = run[d];
+      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+      int pos = base[d] + pre + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      tot += wcnt[w][tid];
+      wcnt[w][tid] = 0;
+    }
+    run[tid] += tot;
+    __syncthreads();
+  }
+}
+
+// --- exclusive scan of int32 (three kernels: tile scan, partials, add) ---
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total) {
+  // Hillis-Steele over 256 threads in LDS
+  int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int t = tid >= off ? lds[tid - off] : 0;
+    __syncthreads();
+    lds[tid] += t;
+    __syncthreads();
+  }
+  int incl = lds[tid];
+  total = lds[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_tiles(int32_t* __restrict__ data, int len,
+                                                          int32_t* __restrict__ partials) {
+  __shared__ int lds[kThreads];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int s = 0;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) {
+    v[e] = (base + e < len) ? data[base + e] : 0;
+    s += v[e];
+  }
+  int total;
+  int run = block_exclusive_scan(s, lds, total);
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e) {
+    if (base + e < len) data[base + e] = run;
+    run += v[e];
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_partials(int32_t* __restrict__ partials,
+                                                             int np) {
+  __shared__ int lds[kThreads];
+  int carry = 0;
+  for (int base = 0; base < np; base += kThreads) {
+    int i = base + threadIdx.x;
+    int v = i < np ? partials[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, lds, total);
+    if (i < np) partials[i] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_add(int32_t* __restrict__ data, int len,
+                                                        const int32_t* __restrict__ partials) {
+  int add = partials[blockIdx.x];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+#pragma unroll
+  for (int e = 0; e < kScanPer; ++e)
+    if (base + e < len) data[base + e] += add;
+}
+
+__global__ __launch_bounds__(kThreads) void k_cell_start(const int32_t* __restrict__ skeys, int n,
+                                                          int C, int32_t* __restrict__ start) {
+  int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k > n) return;
+  int cur = k < n ? skeys[k] : C;
+  int prev = k > 0 ? skeys[k - 1] : -1;
+  for (int c = prev + 1; c <= cur; ++c) start[c] = k;
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+struct BinWs {
+  int32_t *ka, *va, *kb, *vb, *hist, *partials;
+};
+
+BinWs carve(void* ws, int n, int nblk) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  char* p = static_cast<char*>(ws);
+  BinWs w;
+  size_t nb = al(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  w.ka = reinterpret_cast<int32_t*>(p); p += nb;
+  w.va = reinterpret_cast<int32_t*>(p); p += nb;
+  w.kb = reinterpret_cast<int32_t*>(p); p += nb;
+  w.vb = reinterpret_cast<int32_t*>(p); p += nb;
+  size_t hl = (size_t)256 * (size_t)(nblk > 0 ? nblk : 1);
+  w.hist = reinterpret_cast<int32_t*>(p); p += al(sizeof(int32_t) * hl);
+  w.partials = reinterpret_cast<int32_t*>(p);
+  return w;
+}
+
+hipError_t scan(int32_t* data, int len, int32_t* partials, hipStream_t s) {
+  int nt = cdiv(len, kScanTile);
+  if (nt == 0) return hipSuccess;
+  k_scan_tiles<<<nt, kThreads, 0, s>>>(data, len, partials);
+  k_scan_partials<<<1, kThreads, 0, s>>>(partials, nt);
+  k_scan_add<<<nt, kThreads, 0, s>>>(data, len, partials);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t bin_workspace_bytes(int n, int n_c) {
+  (void)n_c;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  int nblk = cdiv(n, kTile);
+  size_t hl = (size_t)256 * (size_t)(nblk > 0 ? nblk : 1);
+  return 4 * al(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) + al(sizeof(int32_t) * hl) +
+         al(sizeof(int32_t) * ((size_t)cdiv((int64_t)hl, kScanTile) + 1));
+}
+
+hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
+                      int32_t* perm, int32_t* cell, void* ws, hipStream_t s) {
+  const int n = c.n, n_c = c.n_c;
+  const int C = n_c * n_c * n_c;
+  const int nblk = cdiv(n, kTile);
+  BinWs w = carve(ws, n, nblk);
+  if (n > 0) {
+    k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(static_cast<const char*>(aos), L.stride,
+                                                       L.off[SPH_A_X], n, n_c, w.ka, w.va,
+                                                       c.status);
+    int bits = 1;
+    while ((1 << bits) < C) ++bits;
+    int passes = (bits + 7) / 8;
+    int32_t *ks = w.ka, *vs = w.va;
+    for (int p = 0; p < passes; ++p) {
+      int32_t *kd, *vd;
+      if (p == passes - 1) {
+        kd = cell;
+        vd = perm;
+      } else {
+        kd = (ks == w.ka) ? w.kb : w.ka;
+        vd = (vs == w.va) ? w.vb : w.va;
+      }
+      k_radix_hist<<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p);
+      hipError_t e = scan(w.hist, 256 * nblk, w.partials, s);
+      if (e != hipSuccess) return e;
+      k_radix_scatter<<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p);
+      ks = kd;
+      vs = vd;
+    }
+  }
+  k_cell_start<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(cell, n, C, cell_start);
+  return hipGetLastError();
+}
+
+}  // namespace sph

@@ -1,0 +1,598 @@
+// Quadratic kernels: the density loop and the force loop over the cell list
+// (Alg. 1 CallQuadratic; Eq. density, Eq. momentum, Eq. energy).
+//
+// One workgroup per (cell, chunk of TI particles): the chunk's particles i
+// are held in registers, K lanes per particle. The workgroup gathers the
+// candidates j of the 27 surrounding cells into LDS, keeping only those whose
+// distance to the chunk's bounding box is below the largest support radius
+// (a conservative prune: every operation of the box distance is monotone in
+// the same inputs as the pair test, so no accepted pair is ever dropped).
+// Each lane then walks its share of the LDS list, applies the FP32 support
+// test and accumulates in FP32; the K partial sums of a particle are combined
+// with a fixed shuffle tree, so results are bit-identical run to run.
+//
+// The loaders (SoA views or AoS records) are the only difference between
+// the SoA kernels and the plain-AoS kernels.
+#include "sph_device.h"
+
+namespace sph {
+namespace {
+
+constexpr int kDensCap = 2048;   // LDS candidates per round, density
+constexpr int kForceCap = 1024;  // LDS candidates per round, force
+
+// --------------------------------------------------------------------------
+// Data sources
+// --------------------------------------------------------------------------
+struct SoaSrc {
+  const void* off[3];
+  const void* vq[3];
+  const void* m;
+  const void* h;
+  const void* u;
+  int pos_dt, vel_dt, mhu_dt;
+  float lm, lh, lu;
+  const float *rho, *f, *P, *c;
+  float *o_rho, *o_wcount, *o_rho_dh, *o_f, *o_P, *o_c;
+  int32_t* o_nngb;
+  float *o_ax, *o_ay, *o_az, *o_du, *o_vsig;
+  int32_t* o_nforce;
+
+  __device__ __forceinline__ void pos(int k, int cell, int n_c, float& x, float& y,
+                                      float& z) const {
+    (void)cell;
+    (void)n_c;
+    x = load_q(off[0], pos_dt, k, 1.0f);
+    y = load_q(off[1], pos_dt, k, 1.0f);
+    z = load_q(off[2], pos_dt, k, 1.0f);
+  }
+  __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
+    x = load_q(vq[0], vel_dt, k, 1.0f);
+    y = load_q(vq[1], vel_dt, k, 1.0f);
+    z = load_q(vq[2], vel_dt, k, 1.0f);
+  }
+  __device__ __forceinline__ float mass(int k) const { return load_q(m, mhu_dt, k, lm); }
+  __device__ __forceinline__ float hsml(int k) const { return load_q(h, mhu_dt, k, lh); }
+  __device__ __forceinline__ float uint(int k) const { return load_q(u, mhu_dt, k, lu); }
+  __device__ __forceinline__ void dens_in(int k, float& r, float& ff, float& p,
+                                          float& cs) const {
+    r = rho[k];
+    ff = f[k];
+    p = P[k];
+    cs = c[k];
+  }
+  __device__ __forceinline__ void dens_out(int k, float r, float wc, float dh, float ff, float p,
+                                           float cs, int nn) const {
+    o_rho[k] = r;
+    o_wcount[k] = wc;
+    o_rho_dh[k] = dh;
+    o_f[k] = ff;
+    o_P[k] = p;
+    o_c[k] = cs;
+    o_nngb[k] = nn;
+  }
+  __device__ __forceinline__ void force_out(int k, float ax, float ay, float az, float du,
+                                            float vs, int nf) const {
+    o_ax[k] = ax;
+    o_ay[k] = ay;
+    o_az[k] = az;
+    o_du[k] = du;
+    o_vsig[k] = vs;
+    if (o_nforce) o_nforce[k] = nf;
+  }
+};
+
+struct AosSrc {
+  char* base;
+  AosLayout L;
+  const int32_t* perm;
+
+  __device__ __forceinline__ char* rec(int k) const {
+    return base + (size_t)perm[k] * L.stride;
+  }
+  __device__ __forceinline__ void pos(int k, int cell, int n_c, float& x, float& y,
+                                      float& z) const {
+    const char* r = rec(k);
+    int cx, cy, cz;
+    cell_coords(cell, n_c, cx, cy, cz);
+    const double* xp = reinterpret_cast<const double*>(r + L.off[SPH_A_X]);
+    x = cell_offset(wrap01(xp[0]), cx, n_c);
+    y = cell_offset(wrap01(xp[1]), cy, n_c);
+    z = cell_offset(wrap01(xp[2]), cz, n_c);
+  }
+  __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
+    const char* r = rec(k);
+    x = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 0);
+    y = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 1);
+    z = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 2);
+  }
+  __device__ __forceinline__ float mass(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_M], L.dt[SPH_A_M]);
+  }
+  __device__ __forceinline__ float hsml(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_H], L.dt[SPH_A_H]);
+  }
+  __device__ __forceinline__ float uint(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_U], L.dt[SPH_A_U]);
+  }
+  __device__ __forceinline__ void dens_in(int k, float& rr, float& ff, float& p,
+                                          float& cs) const {
+    const char* r = rec(k);
+    rr = rec_load32(r, L.off[SPH_A_RHO], L.dt[SPH_A_RHO]);
+    ff = rec_load32(r, L.off[SPH_A_F], L.dt[SPH_A_F]);
+    p = rec_load32(r, L.off[SPH_A_P], L.dt[SPH_A_P]);
+    cs = rec_load32(r, L.off[SPH_A_C], L.dt[SPH_A_C]);
+  }
+  __device__ __forceinline__ void dens_out(int k, float rr, float wc, float dh, float ff,
+                                           float p, float cs, int nn) const {
+    char* r = rec(k);
+    rec_store32(r, L.off[SPH_A_RHO], L.dt[SPH_A_RHO], rr);
+    rec_store32(r, L.off[SPH_A_WCOUNT], L.dt[SPH_A_WCOUNT], wc);
+    rec_store32(r, L.off[SPH_A_RHO_DH], L.dt[SPH_A_RHO_DH], dh);
+    rec_store32(r, L.off[SPH_A_F], L.dt[SPH_A_F], ff);
+    rec_store32(r, L.off[SPH_A_P], L.dt[SPH_A_P], p);
+    rec_store32(r, L.off[SPH_A_C], L.dt[SPH_A_C], cs);
+    rec_store_i32(r, L.off[SPH_A_NNGB], nn);
+  }
+  __device__ __forceinline__ void force_out(int k, float ax, float ay, float az, float du,
+                                            float vs, int nf) const {
+    char* r = rec(k);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], ax, 0);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], ay, 1);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], az, 2);
+    rec_store32(r, L.off[SPH_A_DU], L.dt[SPH_A_DU], du);
+    rec_store32(r, L.off[SPH_A_VSIG], L.dt[SPH_A_VSIG], vs);
+    rec_store_i32(r, L.off[SPH_A_NFORCE], nf);
+  }
+};
+
+// Slot indices read from the cell table are clamped to [0, n], so a
+// corrupted table can never send a load outside the particle arrays.
+__device__ __forceinline__ int clamp_slot(int v, int n) { return min(max(v, 0), n); }
+
+// Spread consecutive workgroups over the 8 XCDs in contiguous ranges: block b
+// runs on XCD b % 8, so logical work item (b % 8) * per + b / 8 gives each
+// XCD a contiguous slab of cells (shared neighbour cells stay in one L2).
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  int per = G >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* lds) {
+  constexpr int NW = NT / 64;
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = fmaxf(r, lds[w]);
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ float block_min(float v, float* lds) {
+  return -block_max<NT>(-v, lds);
+}
+
+// Deterministic block-wide compaction: returns the LDS slot of this thread's
+// candidate (valid only if ok) and adds the block's count to nj.
+template <int NT>
+__device__ __forceinline__ int compact_slot(bool ok, int& nj, int* wtot) {
+  constexpr int NW = NT / 64;
+  const int wave = threadIdx.x >> 6;
+  uint64_t bal = __ballot(ok);
+  int wrank = __popcll(bal & lanemask_lt());
+  if ((threadIdx.x & 63) == 0) wtot[wave] = __popcll(bal);
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    int t = wtot[w];
+    pre += (w < wave) ? t : 0;
+    tot += t;
+  }
+  int slot = nj + pre + wrank;
+  nj += tot;
+  return slot;
+}
+
+template <int K>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int K>
+__device__ __forceinline__ int group_sum_i(int v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int K>
+__device__ __forceinline__ float group_max(float v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ void neighbour_cell(int nb, int cx, int cy, int cz, int n_c, float s,
+                                               int& cn, float& shx, float& shy, float& shz) {
+  int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+  int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+  nx += (nx < 0) ? n_c : ((nx >= n_c) ? -n_c : 0);
+  ny += (ny < 0) ? n_c : ((ny >= n_c) ? -n_c : 0);
+  nz += (nz < 0) ? n_c : ((nz >= n_c) ? -n_c : 0);
+  cn = nx + n_c * (ny + n_c * nz);
+  shx = dx < 0 ? -s : (dx > 0 ? s : 0.0f);
+  shy = dy < 0 ? -s : (dy > 0 ? s : 0.0f);
+  shz = dz < 0 ? -s : (dz > 0 ? s : 0.0f);
+}
+
+__device__ __forceinline__ float box_dist2(float x, float y, float z, float lox, float loy,
+                                           float loz, float hix, float hiy, float hiz) {
+#pragma clang fp contract(off)
+  float bx = fmaxf(fmaxf(lox - x, x - hix), 0.0f);
+  float by = fmaxf(fmaxf(loy - y, y - hiy), 0.0f);
+  float bz = fmaxf(fmaxf(loz - z, z - hiz), 0.0f);
+  float xx = bx * bx;
+  return __builtin_fmaf(bz, bz, __builtin_fmaf(by, by, xx));
+}
+
+// --------------------------------------------------------------------------
+// Density
+// --------------------------------------------------------------------------
+template <int TI, int K, class Src>
+__global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph, float s32) {
+  constexpr int NT = TI * K;
+  __shared__ float4 jl[kDensCap];
+  __shared__ int wtot[NT / 64];
+  __shared__ float red[NT / 64];
+
+  const int n_c = cd.n_c;
+  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  const int cs = clamp_slot(cd.start[cell], cd.n), ce = clamp_slot(cd.start[cell + 1], cd.n);
+  int cx, cy, cz;
+  cell_coords(cell, n_c, cx, cy, cz);
+  const int gi = threadIdx.x / K, kk = threadIdx.x % K;
+  const float gk = ph.gamma_k;
+
+  for (int base = cs; base < ce; base += TI) {
+    const int i = base + gi;
+    const bool vi = i < ce;
+    float xi = 0.f, yi = 0.f, zi = 0.f, hi = 0.f, ui = 0.f;
+    if (vi) {
+      src.pos(i, cell, n_c, xi, yi, zi);
+      hi = src.hsml(i);
+      ui = src.uint(i);
+    }
+    const float H2 = vi ? support2(gk, hi) : 0.0f;
+    const float Hinv = vi ? 1.0f / (gk * hi) : 0.0f;
+    const float inf = __builtin_inff();
+    const float lox = block_min<NT>(vi ? xi : inf, red);
+    const float loy = block_min<NT>(vi ? yi : inf, red);
+    const float loz = block_min<NT>(vi ? zi : inf, red);
+    const float hix = block_max<NT>(vi ? xi : -inf, red);
+    const float hiy = block_max<NT>(vi ? yi : -inf, red);
+    const float hiz = block_max<NT>(vi ? zi : -inf, red);
+    const float Hmax2 = block_max<NT>(H2, red);
+    if (vi && cd.status && H2 > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
+
+    float rho = 0.f, wsum = 0.f, dh = 0.f;
+    int nn = 0;
+    int nj = 0;
+    auto pair_loop = [&](int cnt) {
+      for (int t = kk; t < cnt; t += K) {
+        const float4 q = jl[t];
+        float dx, dy, dz;
+        const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
+        if (r2 < H2) {
+          const float u = fast_sqrt(r2) * Hinv;
+          float w, dw;
+          kernel_w_dw(u, w, dw);
+          rho = fmaf(q.w, w, rho);
+          wsum += w;
+          dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
+          ++nn;
+        }
+      }
+    };
+
+    for (int nb = 0; nb < 27; ++nb) {
+      int cn;
+      float shx, shy, shz;
+      neighbour_cell(nb, cx, cy, cz, n_c, s32, cn, shx, shy, shz);
+      const int js = clamp_slot(cd.start[cn], cd.n), je = clamp_slot(cd.start[cn + 1], cd.n);
+      for (int jb = js; jb < je; jb += NT) {
+        const int j = jb + threadIdx.x;
+        bool ok = j < je;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (ok) {
+          float ox, oy, oz;
+          src.pos(j, cn, n_c, ox, oy, oz);
+          q.x = shifted(ox, shx);
+          q.y = shifted(oy, shy);
+          q.z = shifted(oz, shz);
+          q.w = src.mass(j);
+          ok = box_dist2(q.x, q.y, q.z, lox, loy, loz, hix, hiy, hiz) < Hmax2;
+        }
+        const int slot = compact_slot<NT>(ok, nj, wtot);
+        if (ok) jl[slot] = q;
+        __syncthreads();
+        if (nj > kDensCap - NT) {
+          pair_loop(nj);
+          nj = 0;
+          __syncthreads();
+        }
+      }
+    }
+    pair_loop(nj);
+    __syncthreads();
+
+    rho = group_sum<K>(rho);
+    wsum = group_sum<K>(wsum);
+    dh = group_sum<K>(dh);
+    nn = group_sum_i<K>(nn);
+    if (vi && kk == 0) {
+      const float H = gk * hi;
+      const float Hinv = 1.0f / H;
+      const float Hinv3 = Hinv * Hinv * Hinv;
+      const float rho_i = rho * Hinv3;
+      const float rho_dh = -gk * dh * Hinv3 * Hinv;
+      const float omega = 1.0f + hi * rho_dh / (3.0f * rho_i);
+      const float f = ph.gradh ? 1.0f / omega : 1.0f;
+      const float P = (ph.gamma - 1.0f) * rho_i * ui;
+      const float c = sqrtf(ph.gamma * (ph.gamma - 1.0f) * ui);
+      src.dens_out(i, rho_i, kFourPiThird * wsum, rho_dh, f, P, c, nn);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Force
+// --------------------------------------------------------------------------
+template <int TI, int K, class Src>
+__global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, float s32) {
+  constexpr int NT = TI * K;
+  __shared__ float4 jp[kForceCap];   // x, y, z (relative to this cell), H_j^2
+  __shared__ float4 jv[kForceCap];   // v_j, m_j
+  __shared__ float4 js[kForceCap];   // 1/H_j, A_j, c_j, rho_j
+  __shared__ int jid[kForceCap];     // sorted slot of j
+  __shared__ int wtot[NT / 64];
+  __shared__ float red[NT / 64];
+
+  const int n_c = cd.n_c;
+  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  const int cs = clamp_slot(cd.start[cell], cd.n), ce = clamp_slot(cd.start[cell + 1], cd.n);
+  int cx, cy, cz;
+  cell_coords(cell, n_c, cx, cy, cz);
+  const int gi = threadIdx.x / K, kk = threadIdx.x % K;
+  const float gk = ph.gamma_k;
+
+  for (int base = cs; base < ce; base += TI) {
+    const int i = base + gi;
+    const bool vi = i < ce;
+    // lanes without a particle sit far outside the box and accept nothing
+    float xi = 1e30f, yi = 1e30f, zi = 1e30f, hi = 1.f, vxi = 0.f, vyi = 0.f, vzi = 0.f;
+    float rhoi = 1.f, fi = 1.f, Pi_ = 0.f, ci = 0.f;
+    if (vi) {
+      src.pos(i, cell, n_c, xi, yi, zi);
+      src.vel(i, vxi, vyi, vzi);
+      hi = src.hsml(i);
+      src.dens_in(i, rhoi, fi, Pi_, ci);
+    }
+    const float H2i = vi ? support2(gk, hi) : 0.0f;
+    const float Hinvi = 1.0f / (gk * hi);
+    const float Hinv2i = Hinvi * Hinvi;
+    const float Hinv4i = Hinv2i * Hinv2i;
+    const float Ai = (ph.gradh ? fi : 1.0f) * Pi_ / (rhoi * rhoi);
+    const float inf = __builtin_inff();
+    const float lox = block_min<NT>(vi ? xi : inf, red);
+    const float loy = block_min<NT>(vi ? yi : inf, red);
+    const float loz = block_min<NT>(vi ? zi : inf, red);
+    const float hix = block_max<NT>(vi ? xi : -inf, red);
+    const float hiy = block_max<NT>(vi ? yi : -inf, red);
+    const float hiz = block_max<NT>(vi ? zi : -inf, red);
+    const float Hmax2 = block_max<NT>(H2i, red);
+    if (vi && cd.status && H2i > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
+
+    float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
+    int nf = 0;
+    int nj = 0;
+    const float alpha = ph.alpha, beta = ph.beta;
+    auto pair_loop = [&](int cnt) {
+      for (int t = kk; t < cnt; t += K) {
+        const float4 q0 = jp[t];
+        float dx, dy, dz;
+        const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
+        if (r2 < fmaxf(H2i, q0.w) && jid[t] != i) {
+          const float4 q1 = jv[t];
+          const float4 q2 = js[t];
+          const float r = fast_sqrt(r2);
+          const float rinv = fast_rcp(r);
+          const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+          const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
+          const float hj2 = q2.x * q2.x;
+          const float gj_ = kernel_dw(r * q2.x) * (hj2 * hj2);
+          const float w = (vxi - q1.x) * ex + (vyi - q1.y) * ey + (vzi - q1.z) * ez;
+          const float mu = fminf(w, 0.0f);
+          const float vs = ci + q2.z - beta * mu;
+          const float visc = -alpha * vs * mu * fast_rcp(rhoi + q2.w);
+          const float gbar = 0.5f * (gi_ + gj_);
+          const float kc = q1.w * (Ai * gi_ + q2.y * gj_ + visc * gbar);
+          ax = fmaf(-kc, ex, ax);
+          ay = fmaf(-kc, ey, ay);
+          az = fmaf(-kc, ez, az);
+          du = fmaf(q1.w * (Ai * gi_ + 0.5f * visc * gbar), w, du);
+          vsig = fmaxf(vsig, vs);
+          ++nf;
+        }
+      }
+    };
+
+    for (int nb = 0; nb < 27; ++nb) {
+      int cn;
+      float shx, shy, shz;
+      neighbour_cell(nb, cx, cy, cz, n_c, s32, cn, shx, shy, shz);
+      const int jstart = clamp_slot(cd.start[cn], cd.n), jend = clamp_slot(cd.start[cn + 1], cd.n);
+      for (int jb = jstart; jb < jend; jb += NT) {
+        const int j = jb + threadIdx.x;
+        bool ok = j < jend;
+        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+        if (ok) {
+          float ox, oy, oz;
+          src.pos(j, cn, n_c, ox, oy, oz);
+          p0.x = shifted(ox, shx);
+          p0.y = shifted(oy, shy);
+          p0.z = shifted(oz, shz);
+          const float hj = src.hsml(j);
+          p0.w = support2(gk, hj);
+          ok = box_dist2(p0.x, p0.y, p0.z, lox, loy, loz, hix, hiy, hiz) < fmaxf(Hmax2, p0.w);
+          if (ok) {
+            src.vel(j, p1.x, p1.y, p1.z);
+            p1.w = src.mass(j);
+            float rj, fj, Pj, cj;
+            src.dens_in(j, rj, fj, Pj, cj);
+            p2.x = 1.0f / (gk * hj);
+            p2.y = (ph.gradh ? fj : 1.0f) * Pj / (rj * rj);
+            p2.z = cj;
+            p2.w = rj;
+          }
+        }
+        const int slot = compact_slot<NT>(ok, nj, wtot);
+        if (ok) {
+          jp[slot] = p0;
+          jv[slot] = p1;
+          js[slot] = p2;
+          jid[slot] = j;
+        }
+        __syncthreads();
+        if (nj > kForceCap - NT) {
+          pair_loop(nj);
+          nj = 0;
+          __syncthreads();
+        }
+      }
+    }
+    pair_loop(nj);
+    __syncthreads();
+
+    ax = group_sum<K>(ax);
+    ay = group_sum<K>(ay);
+    az = group_sum<K>(az);
+    du = group_sum<K>(du);
+    vsig = group_max<K>(vsig);
+    nf = group_sum_i<K>(nf);
+    if (vi && kk == 0) src.force_out(i, ax, ay, az, du, vsig, nf);
+  }
+}
+
+SoaSrc make_soa(const sph_soa& s, const Prec& p) {
+  SoaSrc r;
+  for (int k = 0; k < 3; ++k) {
+    r.off[k] = s.f[SPH_S_OFF_X + k];
+    r.vq[k] = s.f[SPH_S_VQ_X + k];
+  }
+  r.m = s.f[SPH_S_M];
+  r.h = s.f[SPH_S_H];
+  r.u = s.f[SPH_S_U];
+  r.pos_dt = p.pos;
+  r.vel_dt = p.vel;
+  r.mhu_dt = p.mhu;
+  r.lm = p.load_m;
+  r.lh = p.load_h;
+  r.lu = p.load_u;
+  r.rho = static_cast<const float*>(s.f[SPH_S_RHO]);
+  r.f = static_cast<const float*>(s.f[SPH_S_F]);
+  r.P = static_cast<const float*>(s.f[SPH_S_P]);
+  r.c = static_cast<const float*>(s.f[SPH_S_C]);
+  r.o_rho = static_cast<float*>(s.f[SPH_S_RHO]);
+  r.o_wcount = static_cast<float*>(s.f[SPH_S_WCOUNT]);
+  r.o_rho_dh = static_cast<float*>(s.f[SPH_S_RHO_DH]);
+  r.o_f = static_cast<float*>(s.f[SPH_S_F]);
+  r.o_P = static_cast<float*>(s.f[SPH_S_P]);
+  r.o_c = static_cast<float*>(s.f[SPH_S_C]);
+  r.o_nngb = static_cast<int32_t*>(s.f[SPH_S_NNGB]);
+  r.o_ax = static_cast<float*>(s.f[SPH_S_A_X]);
+  r.o_ay = static_cast<float*>(s.f[SPH_S_A_Y]);
+  r.o_az = static_cast<float*>(s.f[SPH_S_A_Z]);
+  r.o_du = static_cast<float*>(s.f[SPH_S_DU]);
+  r.o_vsig = static_cast<float*>(s.f[SPH_S_VSIG]);
+  r.o_nforce = static_cast<int32_t*>(s.f[SPH_S_NFORCE]);
+  return r;
+}
+
+template <class S>
+hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                       hipStream_t s) {
+  const int C = c.n_c * c.n_c * c.n_c;
+  const float s32 = (float)(1.0 / (double)c.n_c);
+#define SPH_DENS_CASE(TI_, K_)                                                   \
+  if (ti == TI_ && k == K_) {                                                    \
+    k_density<TI_, K_, S><<<C, TI_ * K_, 0, s>>>(src, c, ph, s32);                \
+    return hipGetLastError();                                                    \
+  }
+  SPH_DENS_CASE(64, 4)
+  SPH_DENS_CASE(32, 8)
+  SPH_DENS_CASE(128, 2)
+  SPH_DENS_CASE(64, 2)
+  SPH_DENS_CASE(64, 1)
+#undef SPH_DENS_CASE
+  return hipErrorInvalidValue;
+}
+
+template <class S>
+hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                     hipStream_t s) {
+  const int C = c.n_c * c.n_c * c.n_c;
+  const float s32 = (float)(1.0 / (double)c.n_c);
+#define SPH_FORCE_CASE(TI_, K_)                                                  \
+  if (ti == TI_ && k == K_) {                                                    \
+    k_force<TI_, K_, S><<<C, TI_ * K_, 0, s>>>(src, c, ph, s32);                  \
+    return hipGetLastError();                                                    \
+  }
+  SPH_FORCE_CASE(64, 4)
+  SPH_FORCE_CASE(32, 8)
+  SPH_FORCE_CASE(128, 2)
+  SPH_FORCE_CASE(64, 2)
+  SPH_FORCE_CASE(64, 1)
+#undef SPH_FORCE_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool tile_supported(int ti, int k) {
+  return (ti == 64 && (k == 4 || k == 2 || k == 1)) || (ti == 32 && k == 8) ||
+         (ti == 128 && k == 2);
+}
+
+hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
+                          int ti, int k, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  return run_density(make_soa(soa, p), c, ph, ti, k, s);
+}
+
+hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
+                        int ti, int k, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  return run_force(make_soa(soa, p), c, ph, ti, k, s);
+}
+
+hipError_t launch_density_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
+                              int ti, int k, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  AosSrc src{static_cast<char*>(aos), L, c.perm};
+  return run_density(src, c, ph, ti, k, s);
+}
+
+hipError_t launch_force_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
+                            int ti, int k, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  AosSrc src{static_cast<char*>(aos), L, c.perm};
+  return run_force(src, c, ph, ti, k, s);
+}
+
+}  // namespace sph

@@ -1,0 +1,165 @@
+// Device-side helpers shared by the HIP kernels of libsphmi: typed field
+// access, storage quantisers, cell arithmetic, the FP32 support test and the
+// cubic-spline kernel. Host code never includes this file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph_internal.h"
+
+namespace sph {
+
+// ---------------------------------------------------------------------------
+// Storage formats (Table 2 rows 32 and 16, plus bfloat16). Conversions use
+// the hardware RNE instructions: v_cvt_f32_f64, v_cvt_f16_f32,
+// v_cvt_pk_bf16_f32; widening is exact.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float v) {
+  return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t b) {
+  return (float)__builtin_bit_cast(_Float16, b);
+}
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float v) {
+  return __builtin_bit_cast(uint16_t, (__bf16)v);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
+  return __uint_as_float((uint32_t)b << 16);
+}
+
+// Read element k of an array stored in `dt`, widened to FP32, times `scale`
+// (an exact power of two, 1 when unscaled).
+__device__ __forceinline__ float load_q(const void* p, int dt, int64_t k, float scale) {
+  float v;
+  if (dt == DT_F32) v = static_cast<const float*>(p)[k];
+  else if (dt == DT_F16) v = f16_bits_to_f32(static_cast<const uint16_t*>(p)[k]);
+  else v = bf16_bits_to_f32(static_cast<const uint16_t*>(p)[k]);
+  return v * scale;
+}
+
+// Store FP64 value v as RNE(RNE32(v) * scale) in format dt.
+__device__ __forceinline__ void store_q(void* p, int dt, int64_t k, double v, float scale) {
+  float q = (float)v * scale;
+  if (dt == DT_F32) static_cast<float*>(p)[k] = q;
+  else if (dt == DT_F16) static_cast<uint16_t*>(p)[k] = f32_to_f16_bits(q);
+  else static_cast<uint16_t*>(p)[k] = f32_to_bf16_bits(q);
+}
+
+// Store an FP32 value (already in registers) in format dt.
+__device__ __forceinline__ void store_q32(void* p, int dt, int64_t k, float v, float scale) {
+  float q = v * scale;
+  if (dt == DT_F32) static_cast<float*>(p)[k] = q;
+  else if (dt == DT_F16) static_cast<uint16_t*>(p)[k] = f32_to_f16_bits(q);
+  else static_cast<uint16_t*>(p)[k] = f32_to_bf16_bits(q);
+}
+
+// AoS record fields: FP32 or FP64 floating elements, read as double.
+__device__ __forceinline__ double rec_load(const char* rec, uint32_t off, int dt, int c = 0) {
+  if (dt == DT_F64) return reinterpret_cast<const double*>(rec + off)[c];
+  return (double)reinterpret_cast<const float*>(rec + off)[c];
+}
+__device__ __forceinline__ float rec_load32(const char* rec, uint32_t off, int dt, int c = 0) {
+  if (dt == DT_F64) return (float)reinterpret_cast<const double*>(rec + off)[c];
+  return reinterpret_cast<const float*>(rec + off)[c];
+}
+__device__ __forceinline__ void rec_store32(char* rec, uint32_t off, int dt, float v, int c = 0) {
+  if (off == kAbsent) return;
+  if (dt == DT_F64) reinterpret_cast<double*>(rec + off)[c] = (double)v;
+  else reinterpret_cast<float*>(rec + off)[c] = v;
+}
+__device__ __forceinline__ void rec_store_i32(char* rec, uint32_t off, int32_t v) {
+  if (off == kAbsent) return;
+  *reinterpret_cast<int32_t*>(rec + off) = v;
+}
+
+// ---------------------------------------------------------------------------
+// Cells of the periodic unit box
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wrap01(double x) { return x - floor(x); }
+
+// per-axis cell index of a wrapped coordinate; NaN maps to 0 (flagged
+// separately by the binning kernel)
+__device__ __forceinline__ int cell_axis(double xw, int n_c) {
+  double t = floor(xw * (double)n_c);
+  int c = (t == t) ? (int)fmin(fmax(t, 0.0), (double)(n_c - 1)) : 0;
+  return c;
+}
+
+__device__ __forceinline__ void cell_coords(int c, int n_c, int& cx, int& cy, int& cz) {
+  cx = c % n_c;
+  cy = (c / n_c) % n_c;
+  cz = c / (n_c * n_c);
+}
+
+// FP32 offset of a wrapped coordinate from its cell origin c / n_c: the
+// FP64 difference rounded once.
+__device__ __forceinline__ float cell_offset(double xw, int c_axis, int n_c) {
+  return (float)(xw - (double)c_axis / (double)n_c);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 support test. With xr = off_j + shift (one FP32 add, shift in
+// {-s, 0, s}) and d = off_i - xr, the squared distance is
+// fma(dz, dz, fma(dy, dy, dx * dx)); the decision is r2 < (gamma_k h)^2
+// with H = gamma_k * h and H * H rounded in FP32. The arithmetic is spelled
+// out with contraction off so every build takes the same decisions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float shifted(float off, float shift) {
+#pragma clang fp contract(off)
+  return off + shift;
+}
+
+__device__ __forceinline__ float dist2(float xi, float yi, float zi, float xr, float yr,
+                                       float zr, float& dx, float& dy, float& dz) {
+#pragma clang fp contract(off)
+  dx = xi - xr;
+  dy = yi - yr;
+  dz = zi - zr;
+  float xx = dx * dx;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
+}
+
+__device__ __forceinline__ float support2(float gamma_k32, float h) {
+#pragma clang fp contract(off)
+  float H = gamma_k32 * h;
+  return H * H;
+}
+
+// ---------------------------------------------------------------------------
+// Cubic-spline M4 kernel (Sec. 2.1) on the unit support, FP32:
+// w(u) = 8/pi (1 - 6u^2 + 6u^3) for u < 1/2, 16/pi (1-u)^3 for u < 1.
+// ---------------------------------------------------------------------------
+constexpr float kC8 = 2.5464790894703255f;    // 8/pi
+constexpr float kC16 = 5.092958178940651f;    // 16/pi
+constexpr float kC48 = 15.278874536821952f;   // 48/pi
+constexpr float kFourPiThird = 4.1887902047863905f;
+
+__device__ __forceinline__ void kernel_w_dw(float u, float& w, float& dw) {
+  float t = 1.0f - u;
+  float wi = kC8 * (1.0f + u * u * (6.0f * u - 6.0f));
+  float dwi = kC8 * u * (18.0f * u - 12.0f);
+  float wo = kC16 * t * t * t;
+  float dwo = -kC48 * t * t;
+  bool inner = u < 0.5f;
+  w = inner ? wi : wo;
+  dw = inner ? dwi : dwo;
+}
+
+__device__ __forceinline__ float kernel_dw(float u) {
+  float t = 1.0f - u;
+  float dwi = kC8 * u * (18.0f * u - 12.0f);
+  float dwo = -kC48 * t * t;
+  float d = u < 0.5f ? dwi : dwo;
+  return u < 1.0f ? d : 0.0f;
+}
+
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// wave64 helpers
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  return (1ull << __lane_id()) - 1ull;
+}
+
+}  // namespace sph

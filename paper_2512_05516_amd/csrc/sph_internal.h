@@ -1,0 +1,73 @@
+// Internal declarations of libsphmi shared by the host entry points
+// (abi.cpp) and the HIP translation units that launch the kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/sphmi.h"
+
+namespace sph {
+
+enum : int { DT_F64 = SPH_F64, DT_F32 = SPH_F32, DT_F16 = SPH_F16, DT_BF16 = SPH_BF16,
+             DT_I32 = SPH_I32 };
+constexpr uint32_t kAbsent = SPH_ABSENT;
+
+// AoS layout as passed to kernels (by value)
+struct AosLayout {
+  uint32_t stride;
+  uint32_t off[SPH_A_NFIELDS];
+  int32_t dt[SPH_A_NFIELDS];
+};
+
+// Precision as passed to kernels: formats and exact power-of-two factors
+struct Prec {
+  int pos, vel, mhu;
+  float store_m, store_h, store_u;   // 2^scale (applied before storing)
+  float load_m, load_h, load_u;      // 2^-scale (applied after loading)
+};
+
+struct Phys {
+  float gamma_k, gamma, alpha, beta;
+  int gradh;
+};
+
+struct CellsDev {
+  int n, n_c;
+  const int32_t* start;
+  const int32_t* perm;
+  const int32_t* cell;
+  int32_t* status;
+};
+
+// --- launchers (return hipError_t of the launch) ---
+size_t bin_workspace_bytes(int n, int n_c);
+hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
+                      int32_t* perm, int32_t* cell, void* ws, hipStream_t s);
+
+hipError_t launch_convert(const void* aos, const AosLayout& L, const CellsDev& c, int view,
+                          const Prec& p, const sph_soa& out, hipStream_t s);
+hipError_t launch_writeback(const sph_soa& in, const CellsDev& c, int view, void* aos,
+                            const AosLayout& L, hipStream_t s);
+
+bool tile_supported(int ti, int k);
+hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
+                          int ti, int k, hipStream_t s);
+hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
+                        int ti, int k, hipStream_t s);
+hipError_t launch_density_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
+                              int ti, int k, hipStream_t s);
+hipError_t launch_force_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
+                            int ti, int k, hipStream_t s);
+
+hipError_t launch_kick_drift(const sph_soa& soa, const CellsDev& c, double dtk, double dtd,
+                             int32_t* moved, hipStream_t s);
+hipError_t launch_kick_drift_aos(void* aos, const AosLayout& L, int n, int n_c, double dtk,
+                                 double dtd, int32_t* moved, hipStream_t s);
+
+size_t reduce_workspace_bytes(int n);
+hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,
+                         hipStream_t s);
+
+}  // namespace sph

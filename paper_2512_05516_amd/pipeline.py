@@ -1,0 +1,108 @@
+"""Host orchestration of the hot path over the C ABI (no arithmetic here).
+
+``Pipeline`` keeps one particle set resident in HBM as AoS records and runs
+either the SoA path (bin, convert, density, force, reduce, kick/drift,
+writeback) or the plain-AoS path (bin, density, force, kick/drift on the
+records) on one HIP stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import sphmi
+
+
+class Pipeline:
+    def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
+                 prm=None, stream=None):
+        import torch
+        self.torch = torch
+        self.n = int(aos_np.shape[0])
+        self.n_c = int(n_c)
+        self.dtype = aos_np.dtype
+        self.layout = sphmi.layout_from_dtype(aos_np.dtype)
+        raw = np.ascontiguousarray(aos_np).view(np.uint8).reshape(-1)
+        self.aos = torch.from_numpy(raw.copy()).to(device)
+        self.prec = prec or sphmi.precision()
+        self.prm = prm or sphmi.params()
+        self.til = til or sphmi.tile()
+        self.stream = stream
+        self.cells = sphmi.DeviceCells(self.n, self.n_c, device)
+        self.bin_ws = torch.empty(sphmi.bin_workspace_size(self.n, self.n_c), dtype=torch.uint8,
+                                  device=device)
+        self.soa = sphmi.DeviceSoa(self.n, self.prec, device)
+        self.red_ws = torch.empty(sphmi.reduce_workspace_size(self.n), dtype=torch.uint8,
+                                  device=device)
+        self.red_out = torch.zeros(8, dtype=torch.float64, device=device)
+        self.moved = torch.zeros(1, dtype=torch.int32, device=device)
+
+    # --- individual stages -------------------------------------------------
+    def bin(self):
+        sphmi.bin(self.aos, self.layout, self.cells, self.bin_ws, self.stream)
+
+    def convert(self, view="full"):
+        sphmi.convert(self.aos, self.layout, self.cells, view, self.soa, self.stream)
+
+    def density(self):
+        sphmi.density(self.soa, self.cells, self.prm, self.til, self.stream)
+
+    def force(self):
+        sphmi.force(self.soa, self.cells, self.prm, self.til, self.stream)
+
+    def reduce(self):
+        sphmi.reduce(self.soa, self.cells, self.red_out, self.red_ws, self.stream)
+
+    def kick_drift(self, dt_kick, dt_drift):
+        sphmi.kick_drift(self.soa, self.cells, dt_kick, dt_drift, self.moved, self.stream)
+
+    def writeback(self, view="full"):
+        sphmi.writeback(self.soa, self.cells, view, self.aos, self.layout, self.stream)
+
+    def density_aos(self):
+        sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream)
+
+    def force_aos(self):
+        sphmi.force_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream)
+
+    def kick_drift_aos(self, dt_kick, dt_drift):
+        sphmi.kick_drift_aos(self.aos, self.layout, self.cells, dt_kick, dt_drift, self.moved,
+                             self.stream)
+
+    # --- whole steps ----------------------------------------------------------
+    def soa_step(self, dt_kick=1e-4, dt_drift=1e-4):
+        """bin -> convert(full) -> density -> force -> reduce -> kick/drift -> writeback"""
+        self.bin()
+        self.convert("full")
+        self.density()
+        self.force()
+        self.reduce()
+        self.kick_drift(dt_kick, dt_drift)
+        self.writeback("full")
+
+    def aos_step(self, dt_kick=1e-4, dt_drift=1e-4):
+        """bin -> density (AoS) -> force (AoS) -> kick/drift (AoS)"""
+        self.bin()
+        self.density_aos()
+        self.force_aos()
+        self.kick_drift_aos(dt_kick, dt_drift)
+
+    # --- readback ---------------------------------------------------------------
+    def records(self) -> np.ndarray:
+        self.torch.cuda.synchronize()
+        return self.aos.cpu().numpy().view(self.dtype).copy()
+
+    def slot(self, name) -> np.ndarray:
+        """SoA array in input order (slot k -> particle perm[k])."""
+        self.torch.cuda.synchronize()
+        t = self.soa[name]
+        if t.dtype in (self.torch.float16, self.torch.bfloat16):
+            t = t.float()
+        vals = t.cpu().numpy()
+        perm = self.cells.perm[: self.n].cpu().numpy()
+        out = np.empty_like(vals)
+        out[perm] = vals
+        return out
+
+    def status(self) -> int:
+        self.torch.cuda.synchronize()
+        return int(self.cells.status.item())

@@ -1,0 +1,324 @@
+"""ctypes binding of libsphmi (include/sphmi.h): argument marshalling only.
+
+Every step of the hot path runs in the HIP library; this module turns torch
+device tensors into raw pointers and ABI structs, calls the entry point of
+the same name and raises SphError on a non-zero status. PyTorch provides
+device memory and streams and nothing else. There is no fallback: if the
+library is missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsphmi.so")
+
+# --- constants mirrored from include/sphmi.h --------------------------------
+SPH_OK, SPH_E_INVALID, SPH_E_RANGE, SPH_E_NOMEM, SPH_E_HIP, SPH_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FLAG_BAD_POSITION, FLAG_H_TOO_LARGE = 1, 2
+F64, F32, F16, BF16, I32 = 0, 1, 2, 3, 4
+DT = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "i32": I32}
+ABSENT = 0xFFFFFFFF
+
+A_FIELDS = ["X", "V", "A", "M", "H", "U", "RHO", "P", "C", "DU", "RHO_DH", "WCOUNT", "F",
+            "VSIG", "NNGB", "NFORCE", "CELL"]
+A = {name: i for i, name in enumerate(A_FIELDS)}
+
+S_FIELDS = ["OFF_X", "OFF_Y", "OFF_Z", "VQ_X", "VQ_Y", "VQ_Z", "M", "H", "U",
+            "X_X", "X_Y", "X_Z", "V_X", "V_Y", "V_Z", "UK",
+            "RHO", "WCOUNT", "RHO_DH", "F", "P", "C", "NNGB",
+            "A_X", "A_Y", "A_Z", "DU", "VSIG", "NFORCE"]
+S = {name: i for i, name in enumerate(S_FIELDS)}
+
+VIEW_DENSITY, VIEW_FORCE, VIEW_KICK, VIEW_FULL = 0, 1, 2, 3
+VIEWS = {"density": VIEW_DENSITY, "force": VIEW_FORCE, "kick": VIEW_KICK, "full": VIEW_FULL}
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sph status {code}: {msg}")
+        self.code = code
+
+
+class AosLayout(C.Structure):
+    _fields_ = [("stride", C.c_uint32), ("offset", C.c_uint32 * len(A_FIELDS)),
+                ("dtype", C.c_int32 * len(A_FIELDS))]
+
+
+class Cells(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("cell_start", C.c_void_p),
+                ("perm", C.c_void_p), ("cell", C.c_void_p), ("status", C.c_void_p)]
+
+
+class Soa(C.Structure):
+    _fields_ = [("f", C.c_void_p * len(S_FIELDS))]
+
+
+class Precision(C.Structure):
+    _fields_ = [("pos", C.c_int32), ("vel", C.c_int32), ("mhu", C.c_int32),
+                ("scale_m", C.c_int32), ("scale_h", C.c_int32), ("scale_u", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma_k", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
+                ("beta", C.c_double), ("gradh", C.c_int32)]
+
+
+class Tile(C.Structure):
+    _fields_ = [("ti", C.c_int32), ("k", C.c_int32)]
+
+
+EXPORTS = [
+    "sph_abi_version", "sph_last_error", "sph_tile_supported", "sph_bin_workspace_size",
+    "sph_bin", "sph_convert", "sph_host_staging_size", "sph_convert_host", "sph_writeback",
+    "sph_density", "sph_force", "sph_kick_drift", "sph_reduce_workspace_size", "sph_reduce",
+    "sph_density_aos", "sph_force_aos", "sph_kick_drift_aos", "sph_sync",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libsphmi.so (built by ``python -m paper_2512_05516_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2512_05516_amd.build` (no fallback path exists)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, sz, st = C.c_void_p, C.c_int32, C.c_size_t, C.c_int32
+    P = C.POINTER
+    L.sph_abi_version.restype = i32
+    L.sph_last_error.restype = C.c_char_p
+    L.sph_tile_supported.argtypes = [Tile]
+    L.sph_tile_supported.restype = i32
+    L.sph_bin_workspace_size.argtypes = [i32, i32, P(sz)]
+    L.sph_bin.argtypes = [vp, P(AosLayout), P(Cells), vp, sz, vp]
+    L.sph_convert.argtypes = [vp, P(AosLayout), P(Cells), i32, P(Precision), P(Soa), vp]
+    L.sph_host_staging_size.argtypes = [i32, i32, i32, P(Precision), P(sz)]
+    L.sph_convert_host.argtypes = [vp, P(AosLayout), P(Cells), i32, P(Precision), P(Soa), vp, sz,
+                                   i32, vp]
+    L.sph_writeback.argtypes = [P(Soa), P(Cells), i32, vp, P(AosLayout), vp]
+    L.sph_density.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp]
+    L.sph_force.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp]
+    L.sph_kick_drift.argtypes = [P(Soa), P(Cells), C.c_double, C.c_double, vp, vp]
+    L.sph_reduce_workspace_size.argtypes = [i32, P(sz)]
+    L.sph_reduce.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp, sz, vp]
+    L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, vp]
+    L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, vp]
+    L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
+    L.sph_sync.argtypes = [vp]
+    for name in EXPORTS[3:]:
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _check(code):
+    if code != SPH_OK:
+        raise SphError(code, lib().sph_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().sph_last_error().decode()
+
+
+# --- struct builders ----------------------------------------------------------
+_NUMPY_FIELD = {"x": "X", "v": "V", "a": "A", "m": "M", "h": "H", "u": "U", "rho": "RHO",
+                "P": "P", "c": "C", "du": "DU", "rho_dh": "RHO_DH", "wcount": "WCOUNT",
+                "f": "F", "vsig": "VSIG", "nngb": "NNGB", "nforce": "NFORCE", "cell": "CELL"}
+
+
+def layout_from_dtype(dt: np.dtype) -> AosLayout:
+    """AoS layout struct from a numpy structured record dtype."""
+    lay = AosLayout()
+    lay.stride = dt.itemsize
+    for i in range(len(A_FIELDS)):
+        lay.offset[i] = ABSENT
+        lay.dtype[i] = 0
+    for name, fid in _NUMPY_FIELD.items():
+        if name not in dt.names:
+            continue
+        fdt, off = dt.fields[name][:2]
+        base = fdt.base if fdt.shape else fdt
+        code = {np.dtype("<f8"): F64, np.dtype("<f4"): F32, np.dtype("<i4"): I32}[np.dtype(base)]
+        lay.offset[A[fid]] = off
+        lay.dtype[A[fid]] = code
+    return lay
+
+
+def precision(pos="f32", vel="f32", mhu="f32", scale_m=0, scale_h=0, scale_u=0) -> Precision:
+    return Precision(DT[pos], DT[vel], DT[mhu], scale_m, scale_h, scale_u)
+
+
+def params(gamma_k=1.825742, gamma=5.0 / 3.0, alpha=0.8, beta=3.0, gradh=True) -> Params:
+    return Params(gamma_k, gamma, alpha, beta, 1 if gradh else 0)
+
+
+def tile(ti=0, k=0) -> Tile:
+    return Tile(ti, k)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# --- device buffers (torch allocations) --------------------------------------
+_TORCH_DT = {F32: "float32", F16: "float16", BF16: "bfloat16"}
+
+
+class DeviceCells:
+    """Cell list arrays on the device: cell_start[C+1], perm[n], cell[n], status[1]."""
+
+    def __init__(self, n: int, n_c: int, device="cuda"):
+        import torch
+        self.n, self.n_c = int(n), int(n_c)
+        C_ = self.n_c ** 3
+        self.cell_start = torch.zeros(C_ + 1, dtype=torch.int32, device=device)
+        self.perm = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.cell = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self._s = Cells(self.n, self.n_c, self.cell_start.data_ptr(), self.perm.data_ptr(),
+                        self.cell.data_ptr(), self.status.data_ptr())
+
+    @property
+    def struct(self) -> Cells:
+        return self._s
+
+
+class DeviceSoa:
+    """SoA arrays (sorted-slot order) for the given storage precision."""
+
+    def __init__(self, n: int, prec: Precision, device="cuda", fields=None):
+        import torch
+        self.n = int(n)
+        self.prec = prec
+        nn = max(self.n, 1)
+        dt = lambda code: getattr(torch, _TORCH_DT[code])
+        spec = {}
+        for a in ("X", "Y", "Z"):
+            spec["OFF_" + a] = dt(prec.pos)
+            spec["VQ_" + a] = dt(prec.vel)
+            spec["X_" + a] = torch.float64
+            spec["V_" + a] = torch.float32
+            spec["A_" + a] = torch.float32
+        for k in ("M", "H", "U"):
+            spec[k] = dt(prec.mhu)
+        for k in ("UK", "RHO", "WCOUNT", "RHO_DH", "F", "P", "C", "DU", "VSIG"):
+            spec[k] = torch.float32
+        spec["NNGB"] = torch.int32
+        spec["NFORCE"] = torch.int32
+        want = fields if fields is not None else S_FIELDS
+        self.t = {k: torch.zeros(nn, dtype=spec[k], device=device) for k in want}
+        self._s = Soa()
+        for k, v in self.t.items():
+            self._s.f[S[k]] = v.data_ptr()
+
+    def __getitem__(self, k):
+        return self.t[k][: self.n]
+
+    @property
+    def struct(self) -> Soa:
+        return self._s
+
+
+# --- entry points ------------------------------------------------------------
+def abi_version() -> int:
+    return lib().sph_abi_version()
+
+
+def tile_supported(ti, k) -> bool:
+    return bool(lib().sph_tile_supported(Tile(ti, k)))
+
+
+def bin_workspace_size(n, n_c) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_bin_workspace_size(n, n_c, C.byref(out)))
+    return out.value
+
+
+def reduce_workspace_size(n) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_reduce_workspace_size(n, C.byref(out)))
+    return out.value
+
+
+def host_staging_size(n, n_c, view, prec) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_host_staging_size(n, n_c, VIEWS.get(view, view), C.byref(prec), C.byref(out)))
+    return out.value
+
+
+def bin(aos, layout, cells: DeviceCells, workspace, stream=None):
+    _check(lib().sph_bin(_ptr(aos), C.byref(layout), C.byref(cells.struct), _ptr(workspace),
+                         workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def convert(aos, layout, cells: DeviceCells, view, soa: DeviceSoa, stream=None):
+    _check(lib().sph_convert(_ptr(aos), C.byref(layout), C.byref(cells.struct),
+                             VIEWS.get(view, view), C.byref(soa.prec), C.byref(soa.struct),
+                             _stream(stream)))
+
+
+def convert_host(aos_np: np.ndarray, layout, cells: DeviceCells, view, soa: DeviceSoa,
+                 staging, nthreads=0, stream=None):
+    """staging: pinned host uint8 tensor of at least host_staging_size bytes."""
+    _check(lib().sph_convert_host(C.c_void_p(aos_np.ctypes.data), C.byref(layout),
+                                  C.byref(cells.struct), VIEWS.get(view, view), C.byref(soa.prec),
+                                  C.byref(soa.struct), C.c_void_p(staging.data_ptr()),
+                                  staging.numel(), int(nthreads), _stream(stream)))
+
+
+def writeback(soa: DeviceSoa, cells: DeviceCells, view, aos, layout, stream=None):
+    _check(lib().sph_writeback(C.byref(soa.struct), C.byref(cells.struct), VIEWS.get(view, view),
+                               _ptr(aos), C.byref(layout), _stream(stream)))
+
+
+def density(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None):
+    _check(lib().sph_density(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                             C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+
+
+def force(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None):
+    _check(lib().sph_force(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                           C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+
+
+def kick_drift(soa: DeviceSoa, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):
+    _check(lib().sph_kick_drift(C.byref(soa.struct), C.byref(cells.struct), float(dt_kick),
+                                float(dt_drift), _ptr(moved), _stream(stream)))
+
+
+def reduce(soa: DeviceSoa, cells: DeviceCells, out, workspace, stream=None):
+    _check(lib().sph_reduce(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                            _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
+                            _stream(stream)))
+
+
+def density_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None):
+    _check(lib().sph_density_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
+                                 C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+
+
+def force_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None):
+    _check(lib().sph_force_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
+                               C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+
+
+def kick_drift_aos(aos, layout, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):
+    _check(lib().sph_kick_drift_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
+                                    float(dt_kick), float(dt_drift), _ptr(moved), _stream(stream)))
+
+
+def sync(stream=None):
+    _check(lib().sph_sync(_stream(stream)))

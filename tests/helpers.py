@@ -1,0 +1,64 @@
+"""Shared helpers of the GPU parity tests: run the HIP path through the C ABI,
+evaluate the oracle on the same inputs, and the error norms (relative RMSE
+normalised by the mean magnitude, as in the paper's Sec. 7)."""
+import numpy as np
+
+
+def rel_rmse(got, ref):
+    """sqrt(mean |got - ref|^2) / mean |ref| (vectors: Euclidean norms)."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    if ref.ndim == 2:
+        d = np.linalg.norm(got - ref, axis=1)
+        r = np.linalg.norm(ref, axis=1)
+    else:
+        d, r = np.abs(got - ref), np.abs(ref)
+    return float(np.sqrt((d ** 2).mean()) / r.mean())
+
+
+def rel_max(got, ref):
+    """max |got - ref| / mean |ref|."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    if ref.ndim == 2:
+        d = np.linalg.norm(got - ref, axis=1)
+        r = np.linalg.norm(ref, axis=1)
+    else:
+        d, r = np.abs(got - ref), np.abs(ref)
+    return float(d.max() / r.mean())
+
+
+def max_rel(got, ref):
+    """max_i |got_i / ref_i - 1|."""
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(got / ref - 1.0)))
+
+
+def oracle_step(orc, ps, n_c, prm=None, sel=None):
+    d = orc.density(ps, prm, n_c=n_c)
+    f = orc.force(ps, d, prm, n_c=n_c, sel=sel)
+    return d, f
+
+
+def run_gpu(ps, n_c, kind="f32", prec=None, til=None, prm=None, kick=None):
+    """Pack ps into AoS records of `kind`, run bin, convert(full), density,
+    force (and optionally kick/drift + writeback) through the C ABI."""
+    from paper_2512_05516_amd import inputs, sphmi
+    from paper_2512_05516_amd.pipeline import Pipeline
+    rec = inputs.pack_aos(ps, kind)
+    pipe = Pipeline(rec, n_c, prec=prec, til=til, prm=prm)
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    pipe.reduce()
+    if kick is not None:
+        pipe.kick_drift(*kick)
+    pipe.writeback("full")
+    return pipe
+
+
+def gpu_fields(pipe):
+    """Outputs in input (generator) order from the written-back records."""
+    r = pipe.records()
+    return {k: np.asarray(r[k], np.float64) if r[k].dtype.kind == "f" else r[k].copy()
+            for k in ("rho", "wcount", "rho_dh", "f", "P", "c", "nngb", "a", "du", "vsig",
+                      "nforce", "x", "v", "u", "cell")}

@@ -1,0 +1,138 @@
+"""CPU-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments on the host before any device
+work (these calls never reach the GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2512_05516_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def sph():
+    from paper_2512_05516_amd import sphmi
+    if not os.path.exists(sphmi.LIB_PATH):
+        from paper_2512_05516_amd import build
+        build.build(verbose=False)
+    sphmi.lib()
+    return sphmi
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "sphmi.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:sph_status|int32_t|const char \*)\s*(sph_\w+)\(",
+                                 txt, re.M)))
+
+
+def test_exports_every_header_symbol(sph):
+    syms = header_symbols()
+    assert len(syms) >= 18
+    L = sph.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(sph.EXPORTS)
+
+
+def test_abi_version_and_tiles(sph):
+    assert sph.abi_version() == 1
+    assert sph.tile_supported(64, 4)
+    assert not sph.tile_supported(48, 3)
+
+
+def test_workspace_size_validation(sph):
+    assert sph.bin_workspace_size(4096, 4) > 4 * 4 * 4096
+    assert sph.bin_workspace_size(0, 4) > 0
+    with pytest.raises(sph.SphError) as e:
+        sph.bin_workspace_size(-1, 4)
+    assert e.value.code == sph.SPH_E_INVALID
+    with pytest.raises(sph.SphError) as e:
+        sph.bin_workspace_size(10, 2)
+    assert e.value.code == sph.SPH_E_RANGE
+    assert sph.reduce_workspace_size(100) >= 8 * 8
+    p = sph.precision("f16", "bf16", "f16")
+    assert sph.host_staging_size(1000, 4, "full", p) > 1000 * (6 + 6 + 6 + 24 + 12 + 4)
+
+
+def _fake_cells(sph, n=16, n_c=4, lists=True):
+    dummy = C.c_void_p(0x1000) if lists else None
+    return sph.Cells(n, n_c, dummy, dummy, dummy, None)
+
+
+def test_host_side_validation(sph):
+    L = sph.lib()
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    cells = _fake_cells(sph)
+    ws = C.c_void_p(0x2000)
+    # NULL layout, bad stride, X not FP64, misaligned field
+    assert L.sph_bin(C.c_void_p(0x3000), None, C.byref(cells), ws, 1 << 30, None) == sph.SPH_E_INVALID
+    bad = sph.layout_from_dtype(inputs.AOS_F32)
+    bad.stride = 12
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(bad), C.byref(cells), ws, 1 << 30, None) == sph.SPH_E_INVALID
+    bad = sph.layout_from_dtype(inputs.AOS_F32)
+    bad.dtype[sph.A["X"]] = sph.F32
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(bad), C.byref(cells), ws, 1 << 30, None) == sph.SPH_E_INVALID
+    assert "X" in sph.last_error()
+    bad = sph.layout_from_dtype(inputs.AOS_F32)
+    bad.offset[sph.A["M"]] = 126
+    assert L.sph_convert(C.c_void_p(0x3000), C.byref(bad), C.byref(cells), 0,
+                         C.byref(sph.precision()), C.byref(sph.Soa()), None) == sph.SPH_E_INVALID
+    # n_c too small, negative n, workspace too small
+    small = _fake_cells(sph, 16, 2)
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(small), ws, 1 << 30, None) == sph.SPH_E_RANGE
+    neg = _fake_cells(sph, -5, 4)
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(neg), ws, 1 << 30, None) == sph.SPH_E_INVALID
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), ws, 16, None) == sph.SPH_E_NOMEM
+    # missing cell-list pointers
+    nolists = _fake_cells(sph, 16, 4, lists=False)
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(nolists), ws, 1 << 30, None) == sph.SPH_E_INVALID
+    # SoA views with NULL fields, bad precision, bad tile, bad view
+    soa = sph.Soa()
+    assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                         C.byref(sph.params()), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+    for i in range(len(sph.S_FIELDS)):
+        soa.f[i] = 0x4000 + 256 * i
+    assert L.sph_density(C.byref(soa), C.byref(sph.Precision(7, 1, 1, 0, 0, 0)), C.byref(cells),
+                         C.byref(sph.params()), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+    assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                         C.byref(sph.params()), sph.Tile(48, 3), None) == sph.SPH_E_UNSUPPORTED
+    bad_prm = sph.params(gamma_k=float("nan"))
+    assert L.sph_force(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                       C.byref(bad_prm), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+    assert L.sph_convert(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), 9,
+                         C.byref(sph.precision()), C.byref(soa), None) == sph.SPH_E_INVALID
+    assert L.sph_kick_drift(C.byref(soa), C.byref(cells), float("inf"), 1e-4, None, None) == sph.SPH_E_INVALID
+    big_scale = sph.precision("f16", "f16", "f16", scale_m=100)
+    assert L.sph_reduce(C.byref(soa), C.byref(big_scale), C.byref(cells), C.c_void_p(0x5000),
+                        C.c_void_p(0x6000), 1 << 20, None) == sph.SPH_E_INVALID
+
+
+def test_layout_from_numpy(sph):
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    assert lay.stride == 128
+    assert lay.offset[sph.A["X"]] == 8 and lay.dtype[sph.A["X"]] == sph.F64
+    assert lay.offset[sph.A["V"]] == 32 and lay.dtype[sph.A["V"]] == sph.F32
+    lay = sph.layout_from_dtype(inputs.AOS_F64)
+    assert lay.stride == 200 and lay.dtype[sph.A["RHO"]] == sph.F64
+    assert lay.dtype[sph.A["NNGB"]] == sph.I32
+
+
+def test_inputs_recipe():
+    ps = inputs.small_set(1)
+    assert ps.n == 4096
+    assert np.all((ps.x >= 0) & (ps.x < 1))
+    assert np.all(ps.m == 2.0 ** -12)
+    assert np.allclose(ps.h, inputs.ETA / 16)
+    # the jitter keeps every particle inside its lattice block of 4^3 sites
+    b = np.floor(ps.x * 4).astype(int)
+    site = np.floor(ps.x * 16).astype(int)
+    assert np.array_equal(site // 4, b)
+    # 'blocked' order: consecutive runs of 64 share one block
+    pb = inputs.lattice_set(16, 1, order="blocked")
+    blk = np.floor(pb.x * 4).astype(int)
+    key = blk[:, 0] + 4 * (blk[:, 1] + 4 * blk[:, 2])
+    assert np.all(key.reshape(-1, 64) == key.reshape(-1, 64)[:, :1])

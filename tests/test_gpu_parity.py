@@ -1,0 +1,397 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: bit-exact for binning, permutation, cell starts, quantised storage
+values and neighbour counts (the support test is taken in FP32 on both
+sides); FP32 storage within 1e-5 relative of the FP64 oracle (rho, wcount,
+f, P, c: max per-particle relative error; a, du/dt: relative RMSE normalised
+by the mean magnitude as in the paper's Sec. 7, with the maximum normalised
+error also bounded); reduced storage: kernel arithmetic checked against the
+oracle on the same dequantised inputs (FP32 bar), and the storage error
+against FP64 reported with the 2e-3 (FP16) / 8e-3 (BF16) gates where the
+format alone allows them.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_05516_amd import inputs
+
+from helpers import gpu_fields, max_rel, oracle_step, rel_max, rel_rmse, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sph():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_05516_amd import sphmi
+    sphmi.lib()          # raises if the HIP library is missing: no fallback
+    return sphmi
+
+
+def check_fp32(got, d, f, tol=FP32_TOL, tag=""):
+    errs = {
+        "rho": max_rel(got["rho"], d["rho"]),
+        "wcount": max_rel(got["wcount"], d["wcount"]),
+        "f": max_rel(got["f"], d["f"]),
+        "P": max_rel(got["P"], d["P"]),
+        "c": max_rel(got["c"], d["c"]),
+        # rho_dh enters only through h/(3 rho) rho_dh (the grad-h term)
+        "omega": float(np.max(np.abs((got["rho_dh"] - d["rho_dh"]) * got["h"] / (3 * d["rho"])))),
+        "a_rmse": rel_rmse(got["a"], f["a"]),
+        "du_rmse": rel_rmse(got["du"], f["du"]),
+        "vsig": max_rel(got["vsig"], f["vsig"]),
+    }
+    print(tag, {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, (tag, k, v)
+    assert rel_max(got["a"], f["a"]) <= 20 * tol, tag
+    assert rel_max(got["du"], f["du"]) <= 20 * tol, tag
+    return errs
+
+
+# ---------------------------------------------------------------------------
+# binning
+# ---------------------------------------------------------------------------
+
+def _bin_gpu(sph, x, n_c):
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.ParticleSet(x, np.zeros_like(x), np.ones(len(x)), np.ones(len(x)),
+                            np.ones(len(x)))
+    pipe = Pipeline(inputs.pack_aos(ps, "f32"), n_c)
+    pipe.bin()
+    torch.cuda.synchronize()
+    n = len(x)
+    return (pipe.cells.cell_start.cpu().numpy(), pipe.cells.perm[:n].cpu().numpy(),
+            pipe.cells.cell[:n].cpu().numpy(), pipe.status())
+
+
+@pytest.mark.parametrize("n,n_c", [(0, 3), (1, 3), (4096, 4), (20000, 7), (100003, 23),
+                                    (300000, 70)])
+def test_bin_bit_exact(sph, orc, n, n_c):
+    rng = np.random.default_rng(n + n_c)
+    x = rng.uniform(-0.5, 1.5, size=(n, 3))
+    if n >= 8:
+        x[:8] = [[0, 0, 0], [1 - 1e-17, 0.5, 0.5], [-1e-18, 1 / 3, 2 / 3], [1.0, 1.0, 1.0],
+                 [0.5, 0.25, 0.75], [1 / n_c, 2 / n_c, 3 / n_c], [-1.0, 2.0, 0.999999999],
+                 [0.1, 0.2, 0.3]]
+    start, perm, cell, status = _bin_gpu(sph, x, n_c)
+    ocell, ostart, operm, _ = orc.bin_cells(x, n_c)
+    assert status == 0
+    assert np.array_equal(start, ostart)
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(cell, ocell[operm])
+
+
+def test_bin_flags_non_finite(sph):
+    x = np.random.default_rng(0).uniform(0, 1, size=(100, 3))
+    x[5, 1] = np.nan
+    x[7, 2] = np.inf
+    start, perm, cell, status = _bin_gpu(sph, x, 3)
+    assert status & sph.FLAG_BAD_POSITION
+    assert start[-1] == 100 and sorted(perm.tolist()) == list(range(100))
+
+
+# ---------------------------------------------------------------------------
+# conversion (U o N o C) and storage formats
+# ---------------------------------------------------------------------------
+
+PRECS = [("f32", "f32", "f32", (0, 0, 0)), ("f16", "bf16", "f16", (12, 3, 0)),
+         ("bf16", "f16", "bf16", (0, 0, 0)), ("f16", "f16", "f16", (21, 6, -1))]
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+@pytest.mark.parametrize("pos,vel,mhu,scales", PRECS)
+def test_convert_bit_exact(sph, orc, kind, pos, vel, mhu, scales):
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.small_set(3)
+    ps.v = ps.v * 37.0            # spread of exponents in the velocity format
+    n_c = 4
+    rec = inputs.pack_aos(ps, kind)
+    src = inputs.unpack_aos(rec)  # the values the record holds, FP64
+    prec = sph.precision(pos, vel, mhu, *scales)
+    pipe = Pipeline(rec, n_c, prec=prec)
+    pipe.bin()
+    pipe.convert("full")
+    torch.cuda.synchronize()
+    ocell, ostart, operm, off = orc.bin_cells(src.x, n_c)
+
+    def bits(t):
+        t = t.cpu()
+        return t.view(torch.int16).numpy().view(np.uint16) if t.element_size() == 2 else \
+            t.view(torch.int32).numpy().view(np.uint32)
+
+    def want_bits(vals64, fmt, scale=0):
+        v32 = np.array([orc.roundtrip(float(v), "f32") for v in vals64], np.float32) * \
+            np.float32(2.0 ** scale)
+        return v32.view(np.uint32) if fmt == "f32" else orc.quant(v32, fmt)
+
+    for a, name in enumerate(("OFF_X", "OFF_Y", "OFF_Z")):
+        assert np.array_equal(bits(pipe.soa[name]), want_bits(off[operm, a], pos)), name
+    for a, name in enumerate(("VQ_X", "VQ_Y", "VQ_Z")):
+        assert np.array_equal(bits(pipe.soa[name]), want_bits(src.v[operm, a], vel)), name
+    for name, vals, s in (("M", src.m, scales[0]), ("H", src.h, scales[1]), ("U", src.u, scales[2])):
+        assert np.array_equal(bits(pipe.soa[name]), want_bits(vals[operm], mhu, s)), name
+    xw = src.x - np.floor(src.x)
+    for a, name in enumerate(("X_X", "X_Y", "X_Z")):
+        assert np.array_equal(pipe.soa[name].cpu().numpy(), xw[operm, a])
+    for a, name in enumerate(("V_X", "V_Y", "V_Z")):
+        assert np.array_equal(pipe.soa[name].cpu().numpy(), src.v[operm, a].astype(np.float32))
+
+
+def test_host_convert_matches_device(sph):
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.small_set(5)
+    rec = inputs.pack_aos(ps, "f32")
+    for prec in (sph.precision(), sph.precision("f16", "bf16", "f16", 12, 3, 0)):
+        dev = Pipeline(rec, 4, prec=prec)
+        dev.bin()
+        dev.convert("full")
+        host = Pipeline(rec, 4, prec=prec)
+        nbytes = sph.host_staging_size(ps.n, 4, "full", prec)
+        staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        sph.convert_host(rec, host.layout, host.cells, "full", host.soa, staging, nthreads=4)
+        torch.cuda.synchronize()
+        for name in ("cell_start", "perm", "cell"):
+            assert torch.equal(getattr(dev.cells, name), getattr(host.cells, name)), name
+        for name in ("OFF_X", "OFF_Y", "OFF_Z", "VQ_X", "VQ_Y", "VQ_Z", "M", "H", "U",
+                     "X_X", "X_Y", "X_Z", "V_X", "V_Y", "V_Z", "UK"):
+            a, b = dev.soa[name], host.soa[name]
+            assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
+
+
+# ---------------------------------------------------------------------------
+# density / force against the FP64 oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+def test_small_lattice_parity(sph, orc, kind):
+    ps = inputs.small_set(1)                        # 4,096 particles, shuffled order
+    n_c = 4
+    pipe = run_gpu(ps, n_c, kind)
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, kind))
+    got["h"] = ref.h
+    nd, nf = orc.count32(ref, n_c)
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    d, f = oracle_step(orc, ps, n_c)                # FP64, unrounded inputs
+    check_fp32(got, d, f, tag=f"S/{kind}")
+
+
+@pytest.fixture(scope="module")
+def ragged(orc):
+    # clustered set with a slab cut out: empty cells, nearly empty cells, cells
+    # spanning several chunks (ragged tails), uneven h
+    ps = inputs.clustered_set(30000, 5, f_blob=0.5, sigma=0.05)
+    keep = ~((ps.x[:, 0] > 0.30) & (ps.x[:, 0] < 0.52))
+    ps = ps.subset(np.nonzero(keep)[0])
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    nd, nf = orc.count32(ref, n_c)
+    d, f = oracle_step(orc, ref, n_c)
+    return ps, ref, n_c, nd, nf, d, f
+
+
+@pytest.mark.parametrize("ti,k", [(64, 4), (32, 8), (128, 2), (64, 2), (64, 1)])
+def test_ragged_clustered_parity(sph, ragged, ti, k):
+    ps, ref, n_c, nd, nf, d, f = ragged
+    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k))
+    assert pipe.status() == 0
+    counts = np.diff(pipe.cells.cell_start.cpu().numpy())
+    assert counts.min() == 0 and counts.max() > 2 * ti
+    got = gpu_fields(pipe)
+    got["h"] = ref.h
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    check_fp32(got, d, f, tag=f"clustered/{ti}x{k}")
+
+
+def test_perfect_lattice_closed_form_gpu(sph, orc):
+    ps = inputs.lattice_set(16, 0, perfect=True, order="shuffled")
+    pipe = run_gpu(ps, 4)
+    got = gpu_fields(pipe)
+    assert np.all(got["nngb"] == 57) and np.all(got["nforce"] == 56)
+    rho_cf = 1.0039808                     # a^-3 sum_k w(|k|/a), pinned on the oracle side
+    assert np.max(np.abs(got["rho"] - rho_cf)) < 2e-6
+    assert np.max(np.abs(got["wcount"] - 48.186135)) < 1e-3
+    # forces vanish by symmetry; the FP32 residue is bounded relative to the
+    # size of one pair's pressure term m 2 P/rho^2 / H^4
+    H = 1.825742 * ps.h[0]
+    pair = ps.m[0] * 2 * got["P"][0] / got["rho"][0] ** 2 / H ** 4
+    assert np.max(np.abs(got["a"])) < 1e-5 * pair
+
+
+@pytest.mark.parametrize("pos,vel,mhu,scales", PRECS[1:])
+def test_reduced_precision(sph, orc, pos, vel, mhu, scales):
+    ps = inputs.small_set(2)
+    n_c = 4
+    prec = sph.precision(pos, vel, mhu, *scales)
+    pipe = run_gpu(ps, n_c, "f32", prec=prec)
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    q = orc.dequantise_set(ref, n_c, pos, vel, mhu, scales)
+    got["h"] = q.h
+    # counts: FP32 decisions on the stored (dequantised) offsets and h
+    nd, nf = orc.count32(ref, n_c, pos=pos, hdt=mhu, h_scale=scales[1])
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    # kernel arithmetic: the oracle on the same stored values, FP32 bar
+    dq, fq = oracle_step(orc, q, n_c)
+    check_fp32(got, dq, fq, tol=2e-5, tag=f"{pos}/{vel}/{mhu} vs dequantised")
+    # storage error against FP64 on the unquantised inputs (reported)
+    d, f = oracle_step(orc, ps, n_c)
+    e = {"rho": max_rel(got["rho"], d["rho"]), "a": rel_rmse(got["a"], f["a"]),
+         "du": rel_rmse(got["du"], f["du"])}
+    print(f"storage error vs FP64 {pos}/{vel}/{mhu}:", {k: f"{v:.2e}" for k, v in e.items()})
+    if pos == "f16" and mhu == "f16":
+        assert e["rho"] <= 2e-3
+    if vel == "bf16" and pos == "f16":
+        assert e["du"] <= 8e-3
+
+
+# ---------------------------------------------------------------------------
+# AoS == SoA, determinism, kick/drift, reductions, edge cases
+# ---------------------------------------------------------------------------
+
+def test_aos_equals_soa_bitwise(sph):
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(20000, 9, f_blob=0.4, sigma=0.05)
+    rec = inputs.pack_aos(ps, "f32")
+    n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
+    a = Pipeline(rec, n_c)
+    b = Pipeline(rec, n_c)
+    for _ in range(2):
+        a.soa_step(1e-3, 1e-3)
+        b.aos_step(1e-3, 1e-3)
+    ra, rb = a.records(), b.records()
+    for k in ("x", "v", "u", "a", "du", "rho", "wcount", "rho_dh", "f", "P", "c", "vsig",
+              "nngb", "nforce"):
+        assert np.ascontiguousarray(ra[k]).tobytes() == np.ascontiguousarray(rb[k]).tobytes(), k
+
+
+def test_deterministic(sph):
+    ps = inputs.small_set(4)
+    r1 = run_gpu(ps, 4).records()
+    r2 = run_gpu(ps, 4).records()
+    assert r1.tobytes() == r2.tobytes()
+
+
+def test_kick_drift_parity(sph, orc):
+    ps = inputs.small_set(6)
+    n_c = 4
+    dt = 2e-3
+    pipe = run_gpu(ps, n_c, kick=(dt, dt))
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    d, f = oracle_step(orc, ref, n_c)
+    x1, v1, u1 = orc.kick_drift(ref.x, ref.v, ref.u, f["a"], f["du"], dt, dt)
+    dv = np.abs(got["v"] - v1).max()
+    assert dv <= 1e-5 * np.abs(f["a"]).max() * dt + 1e-8
+    dx = np.abs(got["x"] - x1)
+    dx = np.minimum(dx, 1 - dx).max()
+    assert dx <= 1e-7 * dt
+    assert np.abs(got["u"] - u1).max() <= 1e-6
+
+
+def test_kick_drift_wraps_and_counts_moves(sph, orc):
+    import torch
+    ps = inputs.small_set(7)
+    n_c = 4
+    ps.v = ps.v * 0 + np.array([0.3, -0.2, 0.05])     # large uniform drift
+    dt = 0.3
+    pipe = run_gpu(ps, n_c)
+    pipe.moved.zero_()
+    pipe.kick_drift(0.0, dt)
+    pipe.writeback("kick")
+    got = pipe.records()
+    x1 = ps.x + ps.v.astype(np.float32).astype(np.float64) * dt
+    x1 -= np.floor(x1)
+    assert np.all((got["x"] >= 0) & (got["x"] < 1))
+    assert np.max(np.abs(got["x"] - x1)) < 1e-15
+    c0 = orc.bin_cells(ps.x, n_c)[0]
+    c1 = orc.bin_cells(x1, n_c)[0]
+    torch.cuda.synchronize()
+    assert pipe.moved.item() == int((c0 != c1).sum())
+
+
+def test_reduce_fp64(sph):
+    import math
+    ps = inputs.small_set(8)
+    pipe = run_gpu(ps, 4)
+    out = pipe.red_out.cpu().numpy()
+    got = gpu_fields(pipe)
+    m = ps.m.astype(np.float32).astype(np.float64)
+    # exactly rounded FP64 sums of the same FP32 values (math.fsum)
+    va = (got["v"] * got["a"]).sum(1)
+    ref = [math.fsum(m * got["a"][:, 0]), math.fsum(m * got["a"][:, 1]),
+           math.fsum(m * got["a"][:, 2]), math.fsum(m * (va + got["du"])),
+           math.fsum(m * np.linalg.norm(got["a"], axis=1)),
+           math.fsum(m * (np.abs(va) + np.abs(got["du"])))]
+    assert np.allclose(out[:6], ref, rtol=1e-12, atol=1e-12 * ref[4])
+    assert out[6] == got["nngb"].sum() and out[7] == got["nforce"].sum()
+    # FP32 pair terms are evaluated twice, so momentum is conserved to ~FP32
+    assert np.linalg.norm(out[:3]) / out[4] < 1e-5
+    assert abs(out[3]) / out[5] < 1e-5
+
+
+def test_edge_cases(sph, orc):
+    import torch
+    # empty set: every stage is a no-op
+    empty = inputs.ParticleSet(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0),
+                               np.zeros(0))
+    pipe = run_gpu(empty, 3, kick=(1e-4, 1e-4))
+    assert pipe.cells.cell_start.cpu().numpy().sum() == 0
+    # one particle: only the self pair
+    one = inputs.ParticleSet(np.array([[0.3, 0.6, 0.9]]), np.zeros((1, 3)), np.array([0.5]),
+                             np.array([0.1]), np.array([1.0]))
+    got = gpu_fields(run_gpu(one, 3))
+    assert got["nngb"][0] == 1 and got["nforce"][0] == 0
+    H = 1.825742 * 0.1
+    assert abs(got["rho"][0] / (0.5 * (8 / np.pi) / H ** 3) - 1) < 1e-6
+    assert np.all(got["a"] == 0)
+    # smoothing length beyond the cell side raises the status flag
+    ps = inputs.small_set(1)
+    ps.h = ps.h * 2.0
+    pipe = run_gpu(ps, 4)
+    assert pipe.status() & sph.FLAG_H_TOO_LARGE
+
+
+# ---------------------------------------------------------------------------
+# full size, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+def test_full_size_medium(sph, orc):
+    """2,097,152 particles (128^3 lattice, FP32 records, default 64x4 tiling):
+    binning bit-exact, every neighbour count exact, values on a seeded
+    sample of 4,096 particles within the FP32 bar."""
+    import torch
+    ps = inputs.medium_set(2)
+    n_c = 32
+    pipe = run_gpu(ps, n_c, "f32")
+    assert pipe.status() == 0
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    ocell, ostart, operm, _ = orc.bin_cells(ref.x, n_c)
+    assert np.array_equal(pipe.cells.cell_start.cpu().numpy(), ostart)
+    assert np.array_equal(pipe.cells.perm.cpu().numpy(), operm)
+    got = gpu_fields(pipe)
+    nd, nf = orc.count32(ref, n_c)
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    sel = np.sort(np.random.default_rng(11).choice(ps.n, 4096, replace=False)).astype(np.int32)
+    d = orc.density(ps, n_c=n_c)
+    f = orc.force(ps, d, n_c=n_c, sel=sel)
+    sub = {k: v[sel] for k, v in got.items()}
+    sub["h"] = ref.h[sel]
+    dsub = {k: v[sel] for k, v in d.items()}
+    check_fp32(sub, dsub, f, tag="M/sample")
+    # FP64 reductions over all slots equal the sums of the counts
+    out = pipe.red_out.cpu().numpy()
+    assert out[6] == nd.sum() and out[7] == nf.sum()
