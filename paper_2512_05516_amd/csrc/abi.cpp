@@ -86,6 +86,13 @@ sph_status check_layout(const sph_aos_layout* l, uint32_t need, AosLayout& out) 
 
 constexpr uint32_t bit(int f) { return 1u << f; }
 
+// AoS base pointers must be 8-byte aligned (records are moved as 8-byte words)
+sph_status check_aos_ptr(const void* aos, int n) {
+  if (n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  if (reinterpret_cast<uintptr_t>(aos) % 8 != 0) return fail(SPH_E_INVALID, "aos is not 8-byte aligned");
+  return SPH_OK;
+}
+
 sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   if (!c) return fail(SPH_E_INVALID, "cells is NULL");
   if (c->n < 0) return fail(SPH_E_INVALID, "cells->n = %d is negative", c->n);
@@ -229,7 +236,7 @@ sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cell
   CellsDev c;
   SPH_TRY(check_layout(layout, bit(SPH_A_X), L));
   SPH_TRY(check_cells(cells, true, c));
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   size_t need = bin_workspace_bytes(c.n, c.n_c);
   if (!workspace) return fail(SPH_E_INVALID, "workspace is NULL");
   if (workspace_bytes < need)
@@ -249,7 +256,7 @@ sph_status sph_convert(const void* aos, const sph_aos_layout* layout, const sph_
   SPH_TRY(check_layout(layout, view_aos_fields(view), L));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   return hip_status(launch_convert(aos, L, c, view, p, *out, stream), "sph_convert");
 }
 
@@ -277,7 +284,7 @@ sph_status sph_writeback(const sph_soa* soa, const sph_cells* cells, int32_t vie
   }
   SPH_TRY(check_layout(layout, need, L));
   SPH_TRY(check_cells(cells, true, c));
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   return hip_status(launch_writeback(*soa, c, view, aos, L, stream), "sph_writeback");
 }
 
@@ -355,7 +362,7 @@ sph_status sph_density_aos(void* aos, const sph_aos_layout* layout, const sph_ce
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   return hip_status(launch_density_aos(aos, L, c, ph, ti, k, stream), "sph_density_aos");
 }
 
@@ -373,7 +380,7 @@ sph_status sph_force_aos(void* aos, const sph_aos_layout* layout, const sph_cell
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   return hip_status(launch_force_aos(aos, L, c, ph, ti, k, stream), "sph_force_aos");
 }
 
@@ -387,7 +394,7 @@ sph_status sph_kick_drift_aos(void* aos, const sph_aos_layout* layout, const sph
   SPH_TRY(check_cells(cells, false, c));
   if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
     return fail(SPH_E_INVALID, "time steps must be finite");
-  if (c.n > 0 && !aos) return fail(SPH_E_INVALID, "aos is NULL");
+  SPH_TRY(check_aos_ptr(aos, c.n));
   return hip_status(launch_kick_drift_aos(aos, L, c.n, c.n_c, dt_kick, dt_drift, moved, stream),
                     "sph_kick_drift_aos");
 }

@@ -148,12 +148,23 @@ __global__ __launch_bounds__(kThreads) void k_reduce_partial(RedSoa s, int n,
   }
 }
 
-__global__ __launch_bounds__(64) void k_reduce_final(const double* __restrict__ part, int nb,
-                                                      double* __restrict__ out) {
-  if (threadIdx.x < kReduceVals) {
+// Sum the per-block partials of each value in a fixed order: thread t adds
+// partials t, t + 256, ..., then a fixed shuffle/LDS tree combines threads.
+__global__ __launch_bounds__(kThreads) void k_reduce_final(const double* __restrict__ part, int nb,
+                                                            double* __restrict__ out) {
+  __shared__ double lds[kThreads / 64];
+  for (int q = 0; q < kReduceVals; ++q) {
     double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part[b * kReduceVals + threadIdx.x];
-    out[threadIdx.x] = t;
+    for (int b = threadIdx.x; b < nb; b += kThreads) t += part[b * kReduceVals + q];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) r += lds[w];
+      out[q] = r;
+    }
+    __syncthreads();
   }
 }
 
@@ -204,7 +215,7 @@ hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, 
   r.nforce = static_cast<const int32_t*>(soa.f[SPH_S_NFORCE]);
   double* part = static_cast<double*>(ws);
   k_reduce_partial<<<kReduceBlocks, kThreads, 0, s>>>(r, n, part);
-  k_reduce_final<<<1, 64, 0, s>>>(part, kReduceBlocks, out);
+  k_reduce_final<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
   return hipGetLastError();
 }
 

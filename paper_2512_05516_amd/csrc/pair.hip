@@ -2,14 +2,17 @@
 // (Alg. 1 CallQuadratic; Eq. density, Eq. momentum, Eq. energy).
 //
 // One workgroup per (cell, chunk of TI particles): the chunk's particles i
-// are held in registers, K lanes per particle. The workgroup gathers the
-// candidates j of the 27 surrounding cells into LDS, keeping only those whose
-// distance to the chunk's bounding box is below the largest support radius
-// (a conservative prune: every operation of the box distance is monotone in
-// the same inputs as the pair test, so no accepted pair is ever dropped).
-// Each lane then walks its share of the LDS list, applies the FP32 support
-// test and accumulates in FP32; the K partial sums of a particle are combined
-// with a fixed shuffle tree, so results are bit-identical run to run.
+// are held in registers, K lanes per particle. The workgroup walks the
+// candidates j of the 27 surrounding cells as one flattened index space and
+// stages into LDS those whose distance to the chunk's bounding box is below
+// the largest support radius (a conservative prune: every operation of the
+// box distance is monotone in the same inputs as the pair test, so no
+// accepted pair is ever dropped). Each lane then runs two phases over its
+// share of the staged candidates: (A) the FP32 support test, appending the
+// accepted candidates to a per-lane list in LDS, and (B) the kernel sums over
+// that list only, so the expensive pair arithmetic runs on accepted pairs
+// instead of on every candidate. The K partial sums of a particle are
+// combined with a fixed shuffle tree: results are bit-identical run to run.
 //
 // The loaders (SoA views or AoS records) are the only difference between
 // the SoA kernels and the plain-AoS kernels.
@@ -18,8 +21,6 @@
 namespace sph {
 namespace {
 
-constexpr int kDensCap = 2048;   // LDS candidates per round, density
-constexpr int kForceCap = 1024;  // LDS candidates per round, force
 
 // --------------------------------------------------------------------------
 // Data sources
@@ -177,28 +178,6 @@ __device__ __forceinline__ float block_min(float v, float* lds) {
   return -block_max<NT>(-v, lds);
 }
 
-// Deterministic block-wide compaction: returns the LDS slot of this thread's
-// candidate (valid only if ok) and adds the block's count to nj.
-template <int NT>
-__device__ __forceinline__ int compact_slot(bool ok, int& nj, int* wtot) {
-  constexpr int NW = NT / 64;
-  const int wave = threadIdx.x >> 6;
-  uint64_t bal = __ballot(ok);
-  int wrank = __popcll(bal & lanemask_lt());
-  if ((threadIdx.x & 63) == 0) wtot[wave] = __popcll(bal);
-  __syncthreads();
-  int pre = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    int t = wtot[w];
-    pre += (w < wave) ? t : 0;
-    tot += t;
-  }
-  int slot = nj + pre + wrank;
-  nj += tot;
-  return slot;
-}
-
 template <int K>
 __device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
@@ -242,21 +221,122 @@ __device__ __forceinline__ float box_dist2(float x, float y, float z, float lox,
 }
 
 // --------------------------------------------------------------------------
+// Neighbour-cell table of a block: the 27 cells around the block's cell,
+// their slot ranges, the prefix of their counts (a flattened candidate index
+// space) and the position shift of each cell relative to the block's cell.
+// --------------------------------------------------------------------------
+struct NbrTab {
+  int start[27];
+  int cell[27];
+  int pre[28];
+  float sh[27][3];
+};
+
+__device__ __forceinline__ void build_nbr(NbrTab& T, const CellsDev& cd, int cx, int cy, int cz,
+                                          float s32) {
+  const int tid = threadIdx.x;
+  if (tid < 27) {
+    int cn;
+    float shx, shy, shz;
+    neighbour_cell(tid, cx, cy, cz, cd.n_c, s32, cn, shx, shy, shz);
+    const int st = clamp_slot(cd.start[cn], cd.n);
+    const int en = max(clamp_slot(cd.start[cn + 1], cd.n), st);
+    T.start[tid] = st;
+    T.cell[tid] = cn;
+    T.pre[tid + 1] = en - st;
+    T.sh[tid][0] = shx;
+    T.sh[tid][1] = shy;
+    T.sh[tid][2] = shz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    T.pre[0] = 0;
+    for (int q = 0; q < 27; ++q) T.pre[q + 1] += T.pre[q];
+  }
+  __syncthreads();
+}
+
+// Deterministic block-wide compaction with one barrier: wave totals are
+// double-buffered by round parity, so a buffer is rewritten only after every
+// thread has passed the next round's barrier.
+template <int NT>
+__device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int rnd) {
+  constexpr int NW = NT / 64;
+  int* wtot = wtot2 + (rnd & 1) * NW;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(ok);
+  const int wrank = __popcll(bal & lanemask_lt());
+  if ((threadIdx.x & 63) == 0) wtot[wave] = __popcll(bal);
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int t = wtot[w];
+    pre += (w < wave) ? t : 0;
+    tot += t;
+  }
+  const int slot = nj + pre + wrank;
+  nj += tot;
+  return slot;
+}
+
+// Per-lane neighbour lists: entry e of thread tid lives at lst[e * NT + tid]
+// (phase B reads are conflict-free). A lane never holds more than kListCap
+// entries: the test phase stops for the whole wave once any lane could
+// overflow within the next 8 candidates.
+constexpr int kListCap = 48;
+constexpr int kUnroll = 8;
+
+// Chunk bounding box of the valid particles and the largest H^2
+struct ChunkBox {
+  float lox, loy, loz, hix, hiy, hiz, h2max;
+};
+
+template <int NT>
+__device__ __forceinline__ ChunkBox chunk_box(bool vi, float xi, float yi, float zi, float H2,
+                                              float* red) {
+  const float inf = __builtin_inff();
+  ChunkBox b;
+  b.lox = block_min<NT>(vi ? xi : inf, red);
+  b.loy = block_min<NT>(vi ? yi : inf, red);
+  b.loz = block_min<NT>(vi ? zi : inf, red);
+  b.hix = block_max<NT>(vi ? xi : -inf, red);
+  b.hiy = block_max<NT>(vi ? yi : -inf, red);
+  b.hiz = block_max<NT>(vi ? zi : -inf, red);
+  b.h2max = block_max<NT>(H2, red);
+  return b;
+}
+
+// --------------------------------------------------------------------------
 // Density
 // --------------------------------------------------------------------------
 template <int TI, int K, class Src>
 __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph, float s32) {
   constexpr int NT = TI * K;
-  __shared__ float4 jl[kDensCap];
-  __shared__ int wtot[NT / 64];
+  constexpr int CAP = 4 * NT;
+  constexpr int kPad = K * kUnroll;
+  __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, m_j
+  // pad [nj, roundup(nj, kPad)) with entries no particle accepts
+  auto pad_dens = [&](float4* c, int nj) {
+    const int njp = (nj + kPad - 1) / kPad * kPad;
+    if ((int)threadIdx.x < njp - nj) c[nj + threadIdx.x] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+    return njp;
+  };
+  __shared__ uint16_t lst[kListCap * NT];
+  __shared__ NbrTab T;
+  __shared__ int wtot[2 * (NT / 64)];
   __shared__ float red[NT / 64];
 
   const int n_c = cd.n_c;
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
-  const int cs = clamp_slot(cd.start[cell], cd.n), ce = clamp_slot(cd.start[cell + 1], cd.n);
+  const int cs = clamp_slot(cd.start[cell], cd.n), ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
+  if (cs == ce) return;                        // uniform: empty cell
   int cx, cy, cz;
   cell_coords(cell, n_c, cx, cy, cz);
-  const int gi = threadIdx.x / K, kk = threadIdx.x % K;
+  build_nbr(T, cd, cx, cy, cz, s32);
+  const int total = T.pre[27];
+  const int tid = threadIdx.x;
+  const int gi = tid / K, kk = tid % K;
   const float gk = ph.gamma_k;
 
   for (int base = cs; base < ce; base += TI) {
@@ -270,65 +350,82 @@ __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph
     }
     const float H2 = vi ? support2(gk, hi) : 0.0f;
     const float Hinv = vi ? 1.0f / (gk * hi) : 0.0f;
-    const float inf = __builtin_inff();
-    const float lox = block_min<NT>(vi ? xi : inf, red);
-    const float loy = block_min<NT>(vi ? yi : inf, red);
-    const float loz = block_min<NT>(vi ? zi : inf, red);
-    const float hix = block_max<NT>(vi ? xi : -inf, red);
-    const float hiy = block_max<NT>(vi ? yi : -inf, red);
-    const float hiz = block_max<NT>(vi ? zi : -inf, red);
-    const float Hmax2 = block_max<NT>(H2, red);
+    const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2, red);
     if (vi && cd.status && H2 > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
 
     float rho = 0.f, wsum = 0.f, dh = 0.f;
     int nn = 0;
-    int nj = 0;
-    auto pair_loop = [&](int cnt) {
-      for (int t = kk; t < cnt; t += K) {
-        const float4 q = jl[t];
-        float dx, dy, dz;
-        const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
-        if (r2 < H2) {
+
+    // nj candidates staged, padded with never-accepted entries up to a
+    // multiple of K * kUnroll
+    auto pair_phase = [&](int nj) {
+      const int nit = nj / K;
+      int it = 0;
+      while (it < nit) {
+        // phase A: FP32 support test, accepted candidates go to the lane's list
+        int lo = tid;                                   // next list entry
+        const int lim = tid + (kListCap - kUnroll) * NT;
+        while (it < nit) {
+          const float4* cq = cand + kk + K * it;
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const float4 q = cq[K * u];
+            float dx, dy, dz;
+            const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
+            if (r2 < H2) {
+              lst[lo] = (uint16_t)(kk + K * (it + u));
+              lo += NT;
+            }
+          }
+          it += kUnroll;
+          if (__any(lo > lim)) break;
+        }
+        // phase B: kernel sums over the accepted pairs only
+        for (int e = tid; e < lo; e += NT) {
+          const float4 q = cand[lst[e]];
+          float dx, dy, dz;
+          const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
           const float u = fast_sqrt(r2) * Hinv;
           float w, dw;
           kernel_w_dw(u, w, dw);
           rho = fmaf(q.w, w, rho);
           wsum += w;
           dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
-          ++nn;
         }
+        nn += (lo - tid) / NT;
       }
     };
 
-    for (int nb = 0; nb < 27; ++nb) {
-      int cn;
-      float shx, shy, shz;
-      neighbour_cell(nb, cx, cy, cz, n_c, s32, cn, shx, shy, shz);
-      const int js = clamp_slot(cd.start[cn], cd.n), je = clamp_slot(cd.start[cn + 1], cd.n);
-      for (int jb = js; jb < je; jb += NT) {
-        const int j = jb + threadIdx.x;
-        bool ok = j < je;
-        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ok) {
-          float ox, oy, oz;
-          src.pos(j, cn, n_c, ox, oy, oz);
-          q.x = shifted(ox, shx);
-          q.y = shifted(oy, shy);
-          q.z = shifted(oz, shz);
-          q.w = src.mass(j);
-          ok = box_dist2(q.x, q.y, q.z, lox, loy, loz, hix, hiy, hiz) < Hmax2;
-        }
-        const int slot = compact_slot<NT>(ok, nj, wtot);
-        if (ok) jl[slot] = q;
+    // gather: candidates of the 27 cells in one flattened index space
+    int nj = 0, q = 0, rnd = 0;
+    for (int b0 = 0; b0 < total; b0 += NT, ++rnd) {
+      const int idx = b0 + tid;
+      bool ok = idx < total;
+      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) {
+        while (idx >= T.pre[q + 1]) ++q;
+        const int j = T.start[q] + (idx - T.pre[q]);
+        float ox, oy, oz;
+        src.pos(j, T.cell[q], n_c, ox, oy, oz);
+        c.x = shifted(ox, T.sh[q][0]);
+        c.y = shifted(oy, T.sh[q][1]);
+        c.z = shifted(oz, T.sh[q][2]);
+        c.w = src.mass(j);
+        ok = box_dist2(c.x, c.y, c.z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz) < bx.h2max;
+      }
+      const int slot = compact_round<NT>(ok, nj, wtot, rnd);
+      if (ok) cand[slot] = c;
+      if (nj > CAP - NT - kPad) {
+        const int njp = pad_dens(cand, nj);
         __syncthreads();
-        if (nj > kDensCap - NT) {
-          pair_loop(nj);
-          nj = 0;
-          __syncthreads();
-        }
+        pair_phase(njp);
+        nj = 0;
+        __syncthreads();
       }
     }
-    pair_loop(nj);
+    const int njp = pad_dens(cand, nj);
+    __syncthreads();
+    pair_phase(njp);
     __syncthreads();
 
     rho = group_sum<K>(rho);
@@ -336,8 +433,6 @@ __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph
     dh = group_sum<K>(dh);
     nn = group_sum_i<K>(nn);
     if (vi && kk == 0) {
-      const float H = gk * hi;
-      const float Hinv = 1.0f / H;
       const float Hinv3 = Hinv * Hinv * Hinv;
       const float rho_i = rho * Hinv3;
       const float rho_dh = -gk * dh * Hinv3 * Hinv;
@@ -356,20 +451,38 @@ __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph
 template <int TI, int K, class Src>
 __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, float s32) {
   constexpr int NT = TI * K;
-  __shared__ float4 jp[kForceCap];   // x, y, z (relative to this cell), H_j^2
-  __shared__ float4 jv[kForceCap];   // v_j, m_j
-  __shared__ float4 js[kForceCap];   // 1/H_j, A_j, c_j, rho_j
-  __shared__ int jid[kForceCap];     // sorted slot of j
-  __shared__ int wtot[NT / 64];
+  constexpr int CAP = 2 * NT;
+  constexpr int kPad = K * kUnroll;
+  __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), H_j^2
+  __shared__ float4 cv[CAP];      // v_j, m_j
+  __shared__ float4 cs4[CAP];     // 1/H_j, A_j, c_j, rho_j
+  __shared__ int cid[CAP];        // sorted slot of j
+  __shared__ uint16_t lst[kListCap * NT];
+  __shared__ NbrTab T;
+  __shared__ int wtot[2 * (NT / 64)];
   __shared__ float red[NT / 64];
 
   const int n_c = cd.n_c;
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
-  const int cs = clamp_slot(cd.start[cell], cd.n), ce = clamp_slot(cd.start[cell + 1], cd.n);
+  const int cs = clamp_slot(cd.start[cell], cd.n), ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
+  if (cs == ce) return;
   int cx, cy, cz;
   cell_coords(cell, n_c, cx, cy, cz);
-  const int gi = threadIdx.x / K, kk = threadIdx.x % K;
+  build_nbr(T, cd, cx, cy, cz, s32);
+  const int total = T.pre[27];
+  const int tid = threadIdx.x;
+  const int gi = tid / K, kk = tid % K;
   const float gk = ph.gamma_k;
+  const float alpha = ph.alpha, beta = ph.beta;
+  // pad [nj, roundup(nj, kPad)) with entries no particle accepts (H_j = 0)
+  auto pad_force = [&](int nj) {
+    const int njp = (nj + kPad - 1) / kPad * kPad;
+    if ((int)threadIdx.x < njp - nj) {
+      cp[nj + threadIdx.x] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      cid[nj + threadIdx.x] = -1;
+    }
+    return njp;
+  };
 
   for (int base = cs; base < ce; base += TI) {
     const int i = base + gi;
@@ -388,30 +501,44 @@ __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, 
     const float Hinv2i = Hinvi * Hinvi;
     const float Hinv4i = Hinv2i * Hinv2i;
     const float Ai = (ph.gradh ? fi : 1.0f) * Pi_ / (rhoi * rhoi);
-    const float inf = __builtin_inff();
-    const float lox = block_min<NT>(vi ? xi : inf, red);
-    const float loy = block_min<NT>(vi ? yi : inf, red);
-    const float loz = block_min<NT>(vi ? zi : inf, red);
-    const float hix = block_max<NT>(vi ? xi : -inf, red);
-    const float hiy = block_max<NT>(vi ? yi : -inf, red);
-    const float hiz = block_max<NT>(vi ? zi : -inf, red);
-    const float Hmax2 = block_max<NT>(H2i, red);
+    const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2i, red);
     if (vi && cd.status && H2i > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
     int nf = 0;
-    int nj = 0;
-    const float alpha = ph.alpha, beta = ph.beta;
-    auto pair_loop = [&](int cnt) {
-      for (int t = kk; t < cnt; t += K) {
-        const float4 q0 = jp[t];
-        float dx, dy, dz;
-        const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
-        if (r2 < fmaxf(H2i, q0.w) && jid[t] != i) {
-          const float4 q1 = jv[t];
-          const float4 q2 = js[t];
+
+    auto pair_phase = [&](int nj) {
+      const int nit = nj / K;
+      int it = 0;
+      while (it < nit) {
+        int lo = tid;
+        const int lim = tid + (kListCap - kUnroll) * NT;
+        while (it < nit) {
+          const float4* cq = cp + kk + K * it;
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const float4 q0 = cq[K * u];
+            float dx, dy, dz;
+            const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
+            if (r2 < fmaxf(H2i, q0.w)) {
+              lst[lo] = (uint16_t)(kk + K * (it + u));
+              lo += NT;
+            }
+          }
+          it += kUnroll;
+          if (__any(lo > lim)) break;
+        }
+        for (int e = tid; e < lo; e += NT) {
+          const int t = lst[e];
+          if (cid[t] == i) continue;           // the self pair
+          const float4 q0 = cp[t];
+          const float4 q1 = cv[t];
+          const float4 q2 = cs4[t];
+          float dx, dy, dz;
+          const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
           const float r = fast_sqrt(r2);
-          const float rinv = fast_rcp(r);
+          // coincident stored positions: w'(0) = 0 makes the pair's terms vanish
+          const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
           const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
           const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
           const float hj2 = q2.x * q2.x;
@@ -432,51 +559,53 @@ __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, 
       }
     };
 
-    for (int nb = 0; nb < 27; ++nb) {
-      int cn;
-      float shx, shy, shz;
-      neighbour_cell(nb, cx, cy, cz, n_c, s32, cn, shx, shy, shz);
-      const int jstart = clamp_slot(cd.start[cn], cd.n), jend = clamp_slot(cd.start[cn + 1], cd.n);
-      for (int jb = jstart; jb < jend; jb += NT) {
-        const int j = jb + threadIdx.x;
-        bool ok = j < jend;
-        float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+    int nj = 0, q = 0, rnd = 0;
+    for (int b0 = 0; b0 < total; b0 += NT, ++rnd) {
+      const int idx = b0 + tid;
+      bool ok = idx < total;
+      int j = 0;
+      float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
+      if (ok) {
+        while (idx >= T.pre[q + 1]) ++q;
+        j = T.start[q] + (idx - T.pre[q]);
+        float ox, oy, oz;
+        src.pos(j, T.cell[q], n_c, ox, oy, oz);
+        p0.x = shifted(ox, T.sh[q][0]);
+        p0.y = shifted(oy, T.sh[q][1]);
+        p0.z = shifted(oz, T.sh[q][2]);
+        const float hj = src.hsml(j);
+        p0.w = support2(gk, hj);
+        ok = box_dist2(p0.x, p0.y, p0.z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz) <
+             fmaxf(bx.h2max, p0.w);
         if (ok) {
-          float ox, oy, oz;
-          src.pos(j, cn, n_c, ox, oy, oz);
-          p0.x = shifted(ox, shx);
-          p0.y = shifted(oy, shy);
-          p0.z = shifted(oz, shz);
-          const float hj = src.hsml(j);
-          p0.w = support2(gk, hj);
-          ok = box_dist2(p0.x, p0.y, p0.z, lox, loy, loz, hix, hiy, hiz) < fmaxf(Hmax2, p0.w);
-          if (ok) {
-            src.vel(j, p1.x, p1.y, p1.z);
-            p1.w = src.mass(j);
-            float rj, fj, Pj, cj;
-            src.dens_in(j, rj, fj, Pj, cj);
-            p2.x = 1.0f / (gk * hj);
-            p2.y = (ph.gradh ? fj : 1.0f) * Pj / (rj * rj);
-            p2.z = cj;
-            p2.w = rj;
-          }
-        }
-        const int slot = compact_slot<NT>(ok, nj, wtot);
-        if (ok) {
-          jp[slot] = p0;
-          jv[slot] = p1;
-          js[slot] = p2;
-          jid[slot] = j;
-        }
-        __syncthreads();
-        if (nj > kForceCap - NT) {
-          pair_loop(nj);
-          nj = 0;
-          __syncthreads();
+          src.vel(j, p1.x, p1.y, p1.z);
+          p1.w = src.mass(j);
+          float rj, fj, Pj, cj;
+          src.dens_in(j, rj, fj, Pj, cj);
+          p2.x = 1.0f / (gk * hj);
+          p2.y = (ph.gradh ? fj : 1.0f) * Pj / (rj * rj);
+          p2.z = cj;
+          p2.w = rj;
         }
       }
+      const int slot = compact_round<NT>(ok, nj, wtot, rnd);
+      if (ok) {
+        cp[slot] = p0;
+        cv[slot] = p1;
+        cs4[slot] = p2;
+        cid[slot] = j;
+      }
+      if (nj > CAP - NT - kPad) {
+        const int njp = pad_force(nj);
+        __syncthreads();
+        pair_phase(njp);
+        nj = 0;
+        __syncthreads();
+      }
     }
-    pair_loop(nj);
+    const int njp = pad_force(nj);
+    __syncthreads();
+    pair_phase(njp);
     __syncthreads();
 
     ax = group_sum<K>(ax);
