@@ -7,24 +7,45 @@
 // stages into LDS those whose distance to the chunk's bounding box is below
 // the largest support radius (a conservative prune: every operation of the
 // box distance is monotone in the same inputs as the pair test, so no
-// accepted pair is ever dropped). Each lane then runs two phases over its
-// share of the staged candidates: (A) the FP32 support test, appending the
-// accepted candidates to a per-lane list in LDS, and (B) the kernel sums over
-// that list only, so the expensive pair arithmetic runs on accepted pairs
-// instead of on every candidate. The K partial sums of a particle are
-// combined with a fixed shuffle tree: results are bit-identical run to run.
+// accepted pair is ever dropped). The global loads of up to kRounds rounds
+// are issued before the first one is used, so a chunk pays about one memory
+// latency for its gather; the force-only fields of the staged candidates
+// are then loaded cooperatively in one more batch.
 //
-// The loaders (SoA views or AoS records) are the only difference between
-// the SoA kernels and the plain-AoS kernels.
+// Each lane then runs two phases over its share of the staged candidates:
+// (A) the FP32 support test (kUnroll LDS reads in flight, branch-free append
+// of the candidate index to a per-lane list in LDS) and (B) the kernel sums
+// over that list only, so the pair arithmetic runs on accepted pairs instead
+// of on every candidate. The K partial sums of a particle are combined with
+// a fixed shuffle tree: results are bit-identical run to run.
+//
+// The loaders (SoA views in compile-time or run-time storage formats, or
+// AoS records) are the only difference between the SoA kernels and the
+// plain-AoS kernels.
 #include "sph_device.h"
 
 namespace sph {
 namespace {
 
-
 // --------------------------------------------------------------------------
 // Data sources
 // --------------------------------------------------------------------------
+// Element k of a stored array: format DT fixed at compile time, or taken
+// from rt when DT < 0.
+template <int DT>
+__device__ __forceinline__ float load_fmt(const void* p, int rt, int64_t k, float scale) {
+  if constexpr (DT == DT_F32) {
+    return static_cast<const float*>(p)[k] * scale;
+  } else if constexpr (DT == DT_F16) {
+    return f16_bits_to_f32(static_cast<const uint16_t*>(p)[k]) * scale;
+  } else if constexpr (DT == DT_BF16) {
+    return bf16_bits_to_f32(static_cast<const uint16_t*>(p)[k]) * scale;
+  } else {
+    return load_q(p, rt, k, scale);
+  }
+}
+
+template <int PT, int VT, int MT>
 struct SoaSrc {
   const void* off[3];
   const void* vq[3];
@@ -43,18 +64,18 @@ struct SoaSrc {
                                       float& z) const {
     (void)cell;
     (void)n_c;
-    x = load_q(off[0], pos_dt, k, 1.0f);
-    y = load_q(off[1], pos_dt, k, 1.0f);
-    z = load_q(off[2], pos_dt, k, 1.0f);
+    x = load_fmt<PT>(off[0], pos_dt, k, 1.0f);
+    y = load_fmt<PT>(off[1], pos_dt, k, 1.0f);
+    z = load_fmt<PT>(off[2], pos_dt, k, 1.0f);
   }
   __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
-    x = load_q(vq[0], vel_dt, k, 1.0f);
-    y = load_q(vq[1], vel_dt, k, 1.0f);
-    z = load_q(vq[2], vel_dt, k, 1.0f);
+    x = load_fmt<VT>(vq[0], vel_dt, k, 1.0f);
+    y = load_fmt<VT>(vq[1], vel_dt, k, 1.0f);
+    z = load_fmt<VT>(vq[2], vel_dt, k, 1.0f);
   }
-  __device__ __forceinline__ float mass(int k) const { return load_q(m, mhu_dt, k, lm); }
-  __device__ __forceinline__ float hsml(int k) const { return load_q(h, mhu_dt, k, lh); }
-  __device__ __forceinline__ float uint(int k) const { return load_q(u, mhu_dt, k, lu); }
+  __device__ __forceinline__ float mass(int k) const { return load_fmt<MT>(m, mhu_dt, k, lm); }
+  __device__ __forceinline__ float hsml(int k) const { return load_fmt<MT>(h, mhu_dt, k, lh); }
+  __device__ __forceinline__ float uint(int k) const { return load_fmt<MT>(u, mhu_dt, k, lu); }
   __device__ __forceinline__ void dens_in(int k, float& r, float& ff, float& p,
                                           float& cs) const {
     r = rho[k];
@@ -259,6 +280,7 @@ __device__ __forceinline__ void build_nbr(NbrTab& T, const CellsDev& cd, int cx,
 // Deterministic block-wide compaction with one barrier: wave totals are
 // double-buffered by round parity, so a buffer is rewritten only after every
 // thread has passed the next round's barrier.
+// Returns this thread's slot within the round and adds the round's total to nj.
 template <int NT>
 __device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int rnd) {
   constexpr int NW = NT / 64;
@@ -275,17 +297,17 @@ __device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int r
     pre += (w < wave) ? t : 0;
     tot += t;
   }
-  const int slot = nj + pre + wrank;
   nj += tot;
-  return slot;
+  return pre + wrank;
 }
 
 // Per-lane neighbour lists: entry e of thread tid lives at lst[e * NT + tid]
-// (phase B reads are conflict-free). A lane never holds more than kListCap
+// (phase B reads are conflict-free). A lane never holds more than LCAP
 // entries: the test phase stops for the whole wave once any lane could
-// overflow within the next 8 candidates.
-constexpr int kListCap = 48;
+// overflow within the next kUnroll candidates.
 constexpr int kUnroll = 8;
+constexpr int kRounds = 8;      // gather rounds whose loads are issued together
+constexpr int kFillRounds = 4;  // force-only fields: rounds issued together
 
 // Chunk bounding box of the valid particles and the largest H^2
 struct ChunkBox {
@@ -307,6 +329,38 @@ __device__ __forceinline__ ChunkBox chunk_box(bool vi, float xi, float yi, float
   return b;
 }
 
+// Phase A over the staged candidates [0, nj) (nj a multiple of K * kUnroll,
+// padded with entries nobody accepts): lane kk of its particle tests
+// candidates kk, kk + K, ... and appends the accepted ones to its list;
+// `consume(lo)` runs phase B over list entries [tid, lo) whenever the lists
+// may fill up and at the end.
+template <int NT, int K, int LCAP, class Accept, class Consume>
+__device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst, int nj, int kk,
+                                                 Accept accept, Consume consume) {
+  const int tid = threadIdx.x;
+  const int nit = nj / K;
+  int it = 0;
+  while (it < nit) {
+    int lo = tid;
+    const int lim = tid + (LCAP - kUnroll) * NT;
+    while (it < nit) {
+      const float4* cq = cp + kk + K * it;
+      float4 qv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) qv[u] = cq[K * u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const bool acc = accept(qv[u]);
+        lst[lo] = (uint16_t)(kk + K * (it + u));
+        lo += acc ? NT : 0;
+      }
+      it += kUnroll;
+      if (__any(lo > lim)) break;
+    }
+    consume(lo);
+  }
+}
+
 // --------------------------------------------------------------------------
 // Density
 // --------------------------------------------------------------------------
@@ -314,15 +368,10 @@ template <int TI, int K, class Src>
 __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph, float s32) {
   constexpr int NT = TI * K;
   constexpr int CAP = 4 * NT;
+  constexpr int LCAP = 40;
   constexpr int kPad = K * kUnroll;
   __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, m_j
-  // pad [nj, roundup(nj, kPad)) with entries no particle accepts
-  auto pad_dens = [&](float4* c, int nj) {
-    const int njp = (nj + kPad - 1) / kPad * kPad;
-    if ((int)threadIdx.x < njp - nj) c[nj + threadIdx.x] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-    return njp;
-  };
-  __shared__ uint16_t lst[kListCap * NT];
+  __shared__ uint16_t lst[LCAP * NT];
   __shared__ NbrTab T;
   __shared__ int wtot[2 * (NT / 64)];
   __shared__ float red[NT / 64];
@@ -356,77 +405,77 @@ __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph
     float rho = 0.f, wsum = 0.f, dh = 0.f;
     int nn = 0;
 
-    // nj candidates staged, padded with never-accepted entries up to a
-    // multiple of K * kUnroll
     auto pair_phase = [&](int nj) {
-      const int nit = nj / K;
-      int it = 0;
-      while (it < nit) {
-        // phase A: FP32 support test, accepted candidates go to the lane's list
-        int lo = tid;                                   // next list entry
-        const int lim = tid + (kListCap - kUnroll) * NT;
-        while (it < nit) {
-          const float4* cq = cand + kk + K * it;
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const float4 q = cq[K * u];
+      // pad [nj, roundup(nj, kPad)) with entries no particle accepts
+      const int njp = (nj + kPad - 1) / kPad * kPad;
+      if (tid < njp - nj) cand[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      __syncthreads();
+      test_and_consume<NT, K, LCAP>(
+          cand, lst, njp, kk,
+          [&](const float4& q) {
             float dx, dy, dz;
-            const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
-            if (r2 < H2) {
-              lst[lo] = (uint16_t)(kk + K * (it + u));
-              lo += NT;
+            return dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz) < H2;
+          },
+          [&](int lo) {
+            for (int e = tid; e < lo; e += NT) {
+              const float4 q = cand[lst[e]];
+              float dx, dy, dz;
+              const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
+              const float u = fast_sqrt(r2) * Hinv;
+              float w, dw;
+              kernel_w_dw(u, w, dw);
+              rho = fmaf(q.w, w, rho);
+              wsum += w;
+              dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
             }
-          }
-          it += kUnroll;
-          if (__any(lo > lim)) break;
-        }
-        // phase B: kernel sums over the accepted pairs only
-        for (int e = tid; e < lo; e += NT) {
-          const float4 q = cand[lst[e]];
-          float dx, dy, dz;
-          const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
-          const float u = fast_sqrt(r2) * Hinv;
-          float w, dw;
-          kernel_w_dw(u, w, dw);
-          rho = fmaf(q.w, w, rho);
-          wsum += w;
-          dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
-        }
-        nn += (lo - tid) / NT;
-      }
+            nn += (lo - tid) / NT;
+          });
+      __syncthreads();
     };
 
-    // gather: candidates of the 27 cells in one flattened index space
+    // gather: the 27 cells' candidates as one flattened index space; the
+    // loads of kRounds rounds are in flight before the first prune
     int nj = 0, q = 0, rnd = 0;
-    for (int b0 = 0; b0 < total; b0 += NT, ++rnd) {
-      const int idx = b0 + tid;
-      bool ok = idx < total;
-      float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok) {
-        while (idx >= T.pre[q + 1]) ++q;
-        const int j = T.start[q] + (idx - T.pre[q]);
-        float ox, oy, oz;
-        src.pos(j, T.cell[q], n_c, ox, oy, oz);
-        c.x = shifted(ox, T.sh[q][0]);
-        c.y = shifted(oy, T.sh[q][1]);
-        c.z = shifted(oz, T.sh[q][2]);
-        c.w = src.mass(j);
-        ok = box_dist2(c.x, c.y, c.z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz) < bx.h2max;
+    for (int sb = 0; sb < total; sb += kRounds * NT) {
+      float4 c[kRounds];
+      int qq[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int idx = sb + r * NT + tid;
+        c[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        qq[r] = q;
+        if (idx < total) {
+          while (idx >= T.pre[q + 1]) ++q;
+          qq[r] = q;
+          const int j = T.start[q] + (idx - T.pre[q]);
+          src.pos(j, T.cell[q], n_c, c[r].x, c[r].y, c[r].z);
+          c[r].w = src.mass(j);
+        }
       }
-      const int slot = compact_round<NT>(ok, nj, wtot, rnd);
-      if (ok) cand[slot] = c;
-      if (nj > CAP - NT - kPad) {
-        const int njp = pad_dens(cand, nj);
-        __syncthreads();
-        pair_phase(njp);
-        nj = 0;
-        __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (sb + r * NT >= total) break;       // uniform
+        const int idx = sb + r * NT + tid;
+        bool ok = idx < total;
+        if (ok) {
+          c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
+          c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
+          c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+          ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
+                         bx.hiz) < bx.h2max;
+        }
+        int njn = nj;
+        int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+        if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
+          pair_phase(nj);
+          njn -= nj;
+          nj = 0;
+        }
+        if (ok) cand[nj + slot] = c[r];
+        nj = njn;
       }
     }
-    const int njp = pad_dens(cand, nj);
-    __syncthreads();
-    pair_phase(njp);
-    __syncthreads();
+    pair_phase(nj);
 
     rho = group_sum<K>(rho);
     wsum = group_sum<K>(wsum);
@@ -451,13 +500,14 @@ __global__ __launch_bounds__(TI* K) void k_density(Src src, CellsDev cd, Phys ph
 template <int TI, int K, class Src>
 __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, float s32) {
   constexpr int NT = TI * K;
-  constexpr int CAP = 2 * NT;
+  constexpr int CAP = 5 * NT / 2;
+  constexpr int LCAP = 32;
   constexpr int kPad = K * kUnroll;
   __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), H_j^2
   __shared__ float4 cv[CAP];      // v_j, m_j
   __shared__ float4 cs4[CAP];     // 1/H_j, A_j, c_j, rho_j
   __shared__ int cid[CAP];        // sorted slot of j
-  __shared__ uint16_t lst[kListCap * NT];
+  __shared__ uint16_t lst[LCAP * NT];
   __shared__ NbrTab T;
   __shared__ int wtot[2 * (NT / 64)];
   __shared__ float red[NT / 64];
@@ -474,15 +524,6 @@ __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, 
   const int gi = tid / K, kk = tid % K;
   const float gk = ph.gamma_k;
   const float alpha = ph.alpha, beta = ph.beta;
-  // pad [nj, roundup(nj, kPad)) with entries no particle accepts (H_j = 0)
-  auto pad_force = [&](int nj) {
-    const int njp = (nj + kPad - 1) / kPad * kPad;
-    if ((int)threadIdx.x < njp - nj) {
-      cp[nj + threadIdx.x] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-      cid[nj + threadIdx.x] = -1;
-    }
-    return njp;
-  };
 
   for (int base = cs; base < ce; base += TI) {
     const int i = base + gi;
@@ -507,106 +548,138 @@ __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
     int nf = 0;
 
-    auto pair_phase = [&](int nj) {
-      const int nit = nj / K;
-      int it = 0;
-      while (it < nit) {
-        int lo = tid;
-        const int lim = tid + (kListCap - kUnroll) * NT;
-        while (it < nit) {
-          const float4* cq = cp + kk + K * it;
+    // force-only fields of staged candidates [from, to), loaded cooperatively
+    auto fill = [&](int from, int to) {
+      __syncthreads();
+      for (int s0 = from; s0 < to; s0 += kFillRounds * NT) {
+        float4 v4[kFillRounds], d4[kFillRounds];
+        float hj[kFillRounds];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) {
-            const float4 q0 = cq[K * u];
-            float dx, dy, dz;
-            const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
-            if (r2 < fmaxf(H2i, q0.w)) {
-              lst[lo] = (uint16_t)(kk + K * (it + u));
-              lo += NT;
-            }
+        for (int r = 0; r < kFillRounds; ++r) {
+          const int sl = s0 + r * NT + tid;
+          v4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+          d4[r] = make_float4(1.f, 1.f, 0.f, 0.f);
+          hj[r] = 1.f;
+          if (sl < to) {
+            const int j = cid[sl];
+            src.vel(j, v4[r].x, v4[r].y, v4[r].z);
+            v4[r].w = src.mass(j);
+            hj[r] = src.hsml(j);
+            src.dens_in(j, d4[r].x, d4[r].y, d4[r].z, d4[r].w);
           }
-          it += kUnroll;
-          if (__any(lo > lim)) break;
         }
-        for (int e = tid; e < lo; e += NT) {
-          const int t = lst[e];
-          if (cid[t] == i) continue;           // the self pair
-          const float4 q0 = cp[t];
-          const float4 q1 = cv[t];
-          const float4 q2 = cs4[t];
-          float dx, dy, dz;
-          const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
-          const float r = fast_sqrt(r2);
-          // coincident stored positions: w'(0) = 0 makes the pair's terms vanish
-          const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
-          const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-          const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
-          const float hj2 = q2.x * q2.x;
-          const float gj_ = kernel_dw(r * q2.x) * (hj2 * hj2);
-          const float w = (vxi - q1.x) * ex + (vyi - q1.y) * ey + (vzi - q1.z) * ez;
-          const float mu = fminf(w, 0.0f);
-          const float vs = ci + q2.z - beta * mu;
-          const float visc = -alpha * vs * mu * fast_rcp(rhoi + q2.w);
-          const float gbar = 0.5f * (gi_ + gj_);
-          const float kc = q1.w * (Ai * gi_ + q2.y * gj_ + visc * gbar);
-          ax = fmaf(-kc, ex, ax);
-          ay = fmaf(-kc, ey, ay);
-          az = fmaf(-kc, ez, az);
-          du = fmaf(q1.w * (Ai * gi_ + 0.5f * visc * gbar), w, du);
-          vsig = fmaxf(vsig, vs);
-          ++nf;
+#pragma unroll
+        for (int r = 0; r < kFillRounds; ++r) {
+          const int sl = s0 + r * NT + tid;
+          if (sl < to) {
+            cv[sl] = v4[r];
+            // d4 = (rho, f, P, c) -> (1/H, A, c, rho)
+            cs4[sl] = make_float4(1.0f / (gk * hj[r]),
+                                  (ph.gradh ? d4[r].y : 1.0f) * d4[r].z / (d4[r].x * d4[r].x),
+                                  d4[r].w, d4[r].x);
+          }
         }
       }
     };
 
-    int nj = 0, q = 0, rnd = 0;
-    for (int b0 = 0; b0 < total; b0 += NT, ++rnd) {
-      const int idx = b0 + tid;
-      bool ok = idx < total;
-      int j = 0;
-      float4 p0 = make_float4(0.f, 0.f, 0.f, 0.f), p1 = p0, p2 = p0;
-      if (ok) {
-        while (idx >= T.pre[q + 1]) ++q;
-        j = T.start[q] + (idx - T.pre[q]);
-        float ox, oy, oz;
-        src.pos(j, T.cell[q], n_c, ox, oy, oz);
-        p0.x = shifted(ox, T.sh[q][0]);
-        p0.y = shifted(oy, T.sh[q][1]);
-        p0.z = shifted(oz, T.sh[q][2]);
-        const float hj = src.hsml(j);
-        p0.w = support2(gk, hj);
-        ok = box_dist2(p0.x, p0.y, p0.z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz) <
-             fmaxf(bx.h2max, p0.w);
-        if (ok) {
-          src.vel(j, p1.x, p1.y, p1.z);
-          p1.w = src.mass(j);
-          float rj, fj, Pj, cj;
-          src.dens_in(j, rj, fj, Pj, cj);
-          p2.x = 1.0f / (gk * hj);
-          p2.y = (ph.gradh ? fj : 1.0f) * Pj / (rj * rj);
-          p2.z = cj;
-          p2.w = rj;
+    auto pair_phase = [&](int nj) {
+      const int njp = (nj + kPad - 1) / kPad * kPad;
+      if (tid < njp - nj) {
+        cp[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+        cid[nj + tid] = -1;
+      }
+      __syncthreads();
+      test_and_consume<NT, K, LCAP>(
+          cp, lst, njp, kk,
+          [&](const float4& q0) {
+            float dx, dy, dz;
+            return dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz) < fmaxf(H2i, q0.w);
+          },
+          [&](int lo) {
+            for (int e = tid; e < lo; e += NT) {
+              const int t = lst[e];
+              const float4 q0 = cp[t];
+              float dx, dy, dz;
+              const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
+              // the self pair has r2 = 0 exactly; so may coincident stored
+              // positions, for which w'(0) = 0 makes the pair's terms vanish
+              if (r2 == 0.0f && cid[t] == i) continue;
+              const float4 q1 = cv[t];
+              const float4 q2 = cs4[t];
+              const float r = fast_sqrt(r2);
+              const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
+              const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+              const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
+              const float hj2 = q2.x * q2.x;
+              const float gj_ = kernel_dw(r * q2.x) * (hj2 * hj2);
+              const float w = (vxi - q1.x) * ex + (vyi - q1.y) * ey + (vzi - q1.z) * ez;
+              const float mu = fminf(w, 0.0f);
+              const float vs = ci + q2.z - beta * mu;
+              const float visc = -alpha * vs * mu * fast_rcp(rhoi + q2.w);
+              const float gbar = 0.5f * (gi_ + gj_);
+              const float kc = q1.w * (Ai * gi_ + q2.y * gj_ + visc * gbar);
+              ax = fmaf(-kc, ex, ax);
+              ay = fmaf(-kc, ey, ay);
+              az = fmaf(-kc, ez, az);
+              du = fmaf(q1.w * (Ai * gi_ + 0.5f * visc * gbar), w, du);
+              vsig = fmaxf(vsig, vs);
+              ++nf;
+            }
+          });
+      __syncthreads();
+    };
+
+    int nj = 0, filled = 0, q = 0, rnd = 0;
+    for (int sb = 0; sb < total; sb += kRounds * NT) {
+      float4 c[kRounds];
+      int qq[kRounds], jj[kRounds];
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        const int idx = sb + r * NT + tid;
+        c[r] = make_float4(0.f, 0.f, 0.f, 1.f);
+        qq[r] = q;
+        jj[r] = 0;
+        if (idx < total) {
+          while (idx >= T.pre[q + 1]) ++q;
+          qq[r] = q;
+          jj[r] = T.start[q] + (idx - T.pre[q]);
+          src.pos(jj[r], T.cell[q], n_c, c[r].x, c[r].y, c[r].z);
+          c[r].w = src.hsml(jj[r]);
         }
       }
-      const int slot = compact_round<NT>(ok, nj, wtot, rnd);
-      if (ok) {
-        cp[slot] = p0;
-        cv[slot] = p1;
-        cs4[slot] = p2;
-        cid[slot] = j;
+#pragma unroll
+      for (int r = 0; r < kRounds; ++r) {
+        if (sb + r * NT >= total) break;       // uniform
+        const int idx = sb + r * NT + tid;
+        bool ok = idx < total;
+        if (ok) {
+          c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
+          c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
+          c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+          c[r].w = support2(gk, c[r].w);
+          ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
+                         bx.hiz) < fmaxf(bx.h2max, c[r].w);
+        }
+        int njn = nj;
+        int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+        if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
+          fill(filled, nj);
+          pair_phase(nj);
+          njn -= nj;
+          nj = 0;
+          filled = 0;
+        }
+        if (ok) {
+          cp[nj + slot] = c[r];
+          cid[nj + slot] = jj[r];
+        }
+        nj = njn;
       }
-      if (nj > CAP - NT - kPad) {
-        const int njp = pad_force(nj);
-        __syncthreads();
-        pair_phase(njp);
-        nj = 0;
-        __syncthreads();
-      }
+      // force-only fields of this super-round's candidates, one batch
+      fill(filled, nj);
+      filled = nj;
     }
-    const int njp = pad_force(nj);
-    __syncthreads();
-    pair_phase(njp);
-    __syncthreads();
+    pair_phase(nj);
 
     ax = group_sum<K>(ax);
     ay = group_sum<K>(ay);
@@ -618,8 +691,9 @@ __global__ __launch_bounds__(TI* K) void k_force(Src src, CellsDev cd, Phys ph, 
   }
 }
 
-SoaSrc make_soa(const sph_soa& s, const Prec& p) {
-  SoaSrc r;
+template <int PT, int VT, int MT>
+SoaSrc<PT, VT, MT> make_soa(const sph_soa& s, const Prec& p) {
+  SoaSrc<PT, VT, MT> r;
   for (int k = 0; k < 3; ++k) {
     r.off[k] = s.f[SPH_S_OFF_X + k];
     r.vq[k] = s.f[SPH_S_VQ_X + k];
@@ -691,6 +765,35 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   return hipErrorInvalidValue;
 }
 
+template <class S>
+struct RunDensity {
+  static hipError_t go(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                       hipStream_t s) {
+    return run_density(src, c, ph, ti, k, s);
+  }
+};
+template <class S>
+struct RunForce {
+  static hipError_t go(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                       hipStream_t s) {
+    return run_force(src, c, ph, ti, k, s);
+  }
+};
+
+// Storage formats with compiled-in loaders; every other combination uses the
+// run-time loader.
+template <template <class> class Run>
+hipError_t dispatch_soa(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
+                        int ti, int k, hipStream_t s) {
+  if (p.pos == DT_F32 && p.vel == DT_F32 && p.mhu == DT_F32)
+    return Run<SoaSrc<DT_F32, DT_F32, DT_F32>>::go(make_soa<DT_F32, DT_F32, DT_F32>(soa, p), c,
+                                                    ph, ti, k, s);
+  if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
+    return Run<SoaSrc<DT_F16, DT_BF16, DT_F16>>::go(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p), c,
+                                                     ph, ti, k, s);
+  return Run<SoaSrc<-1, -1, -1>>::go(make_soa<-1, -1, -1>(soa, p), c, ph, ti, k, s);
+}
+
 }  // namespace
 
 bool tile_supported(int ti, int k) {
@@ -701,13 +804,13 @@ bool tile_supported(int ti, int k) {
 hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
                           int ti, int k, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
-  return run_density(make_soa(soa, p), c, ph, ti, k, s);
+  return dispatch_soa<RunDensity>(soa, p, c, ph, ti, k, s);
 }
 
 hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
                         int ti, int k, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
-  return run_force(make_soa(soa, p), c, ph, ti, k, s);
+  return dispatch_soa<RunForce>(soa, p, c, ph, ti, k, s);
 }
 
 hipError_t launch_density_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
