@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 1
+#define SPH_ABI_VERSION 2
 
 typedef int32_t sph_status;
 enum {
@@ -92,18 +92,42 @@ typedef struct {
 } sph_aos_layout;
 
 /* ------------------------------------------------------------------ */
-/* Cell list (uniform grid over the periodic unit box)                  */
+/* Cell list (uniform grid over the periodic unit box) with an optional */
+/* finer sub-cell order inside each cell (R = 2^sub_bits sub-cells per  */
+/* axis; the sub-cell of x along an axis is floor(x * n_c * R) - c * R, */
+/* clamped to [0, R-1]; a cell's particles are ordered by the Morton    */
+/* code of their sub-cell (bit b of sx at 3b, sy at 3b+1, sz at 3b+2),  */
+/* then by input index).                                                */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int32_t n;              /* particles                                   */
   int32_t n_c;            /* cells per axis, >= 3; cell side 1/n_c must   */
                           /* be >= every support radius H = gamma_k h     */
+  int32_t sub_bits;       /* 0..3; n_c^3 * 8^sub_bits < 2^31             */
+  int32_t reserved;       /* must be 0                                    */
   int32_t *cell_start;    /* [n_c^3 + 1] slots of cell c: [start[c],     */
                           /* start[c+1])                                  */
   int32_t *perm;          /* [n] input index of sorted slot k             */
   int32_t *cell;          /* [n] cell id cx + n_c (cy + n_c cz) of slot k */
+  int32_t *sub_start;     /* [n_c^3 R^3 + 1] slots of sub-cell key        */
+                          /* cell * R^3 + morton; required when           */
+                          /* sub_bits > 0, else may be NULL               */
+  float *hmax;            /* [n_c^3] largest h of each cell (written by   */
+                          /* sph_bin when the layout has H; may be NULL)  */
   int32_t *status;        /* [1] optional (may be NULL) SPH_FLAG_* word   */
 } sph_cells;
+
+/* Work list of the persistent pair kernels: (cell, first slot) items of
+ * at most `ti` particles each, built by sph_worklist from a cell list. The
+ * caller allocates `buf` with at least sph_worklist_size(n, n_c, ti) bytes.
+ * A work list describes the cell list it was built from: rebuild it after
+ * every sph_bin. */
+typedef struct {
+  int32_t ti;             /* particles per item (the tile's ti)           */
+  int32_t reserved;       /* must be 0                                    */
+  void *buf;              /* device buffer: queues, item count, items     */
+  size_t bytes;           /* size of buf                                  */
+} sph_work;
 
 /* ------------------------------------------------------------------ */
 /* SoA buffers (sorted-slot order). One struct names every array a       */
@@ -180,9 +204,11 @@ sph_status sph_bin_workspace_size(int32_t n, int32_t n_c, size_t *bytes);
  * apart, X read as FP64): wrap x into [0,1) as x - floor(x); per axis
  * c = min(floor(x * n_c), n_c - 1) in FP64; id = cx + n_c (cy + n_c cz).
  * Writes cells->cell_start, cells->perm and cells->cell (stable order by
- * (cell id, input index): bit-identical on every run). cells->n and
- * cells->n_c are inputs. Raises SPH_FLAG_BAD_POSITION for non-finite x
- * (such particles are put in cell 0). */
+ * (cell id, sub-cell Morton code, input index): bit-identical on every
+ * run), cells->sub_start when sub_bits > 0, and cells->hmax (max h of each
+ * cell, h read as stored in the record) when it is non-NULL and the layout
+ * has H. cells->n, n_c and sub_bits are inputs. Raises
+ * SPH_FLAG_BAD_POSITION for non-finite x (such particles go to cell 0). */
 sph_status sph_bin(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
                    void *workspace, size_t workspace_bytes, hipStream_t stream);
 
@@ -217,6 +243,14 @@ sph_status sph_convert_host(const void *aos_host, const sph_aos_layout *layout,
 sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t view,
                          void *aos, const sph_aos_layout *layout, hipStream_t stream);
 
+/* Work list for the persistent pair kernels (Alg. 1 CallQuadratic over
+ * all cells of uneven occupancy in one launch): one item per chunk of at
+ * most ti consecutive slots of a cell. Items are ordered by cell; the
+ * kernels hand them out through 8 queues (one per XCD, contiguous ranges
+ * of cells) with work stealing, so results never depend on the schedule. */
+sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t *bytes);
+sph_status sph_worklist(const sph_cells *cells, sph_work *work, hipStream_t stream);
+
 /* Density loop (Eq. density; Alg. 1 CallQuadratic over the 27 cells
  * around each particle's cell). For every slot i, over every j with
  * r_ij < H_i, the self pair included (support test in FP32:
@@ -226,9 +260,14 @@ sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t vie
  *   rho_dh_i = sum m_j dW/dh          nngb_i = #j
  *   f_i = 1 / (1 + h_i rho_dh_i / (3 rho_i))   (1 if gradh = 0)
  *   P_i = (gamma-1) rho_i u_i         c_i = sqrt(gamma (gamma-1) u_i)
- * Reads OFF, M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB. */
+ * Reads OFF, M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB.
+ * work == NULL: one workgroup per cell; otherwise a persistent launch over
+ * the work list (work->ti must equal the tile's ti). Candidates come from
+ * the sub-cells (or cells, sub_bits = 0) within the chunk's bounding box
+ * widened by its largest support radius. */
 sph_status sph_density(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
-                       const sph_params *params, sph_tile tile, hipStream_t stream);
+                       const sph_params *params, sph_tile tile, const sph_work *work,
+                       hipStream_t stream);
 
 /* Force loop (Eq. momentum and Eq. energy, discrete grad-h form with
  * signal-velocity artificial viscosity). For every slot i, over j != i with
@@ -239,9 +278,11 @@ sph_status sph_density(const sph_soa *soa, const sph_precision *prec, const sph_
  *   a_i   -= m_j (A_i g_i + A_j g_j + Pi gbar) e
  *   du_i  += m_j (A_i g_i + Pi gbar / 2) w
  *   vsig_i = max_j vsig_ij,  nforce_i = #j
- * Reads OFF, VQ, M, H and RHO, F, P, C; writes A_*, DU, VSIG, NFORCE. */
+ * Reads OFF, VQ, M, H and RHO, F, P, C; writes A_*, DU, VSIG, NFORCE.
+ * Needs cells->hmax (the neighbour bound of each cell); work as above. */
 sph_status sph_force(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
-                     const sph_params *params, sph_tile tile, hipStream_t stream);
+                     const sph_params *params, sph_tile tile, const sph_work *work,
+                     hipStream_t stream);
 
 /* Kick and drift (Alg. 1 CallLinear): v += a dt_kick, u += du dt_kick
  * (FP32), then x += v dt_drift in FP64 with the kicked v and wrap into
@@ -265,9 +306,11 @@ sph_status sph_reduce(const sph_soa *soa, const sph_precision *prec, const sph_c
  * with the identical loop order and arithmetic, so FP32 records give
  * bit-identical results to the FP32 SoA path. */
 sph_status sph_density_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
-                           const sph_params *params, sph_tile tile, hipStream_t stream);
+                           const sph_params *params, sph_tile tile, const sph_work *work,
+                           hipStream_t stream);
 sph_status sph_force_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
-                         const sph_params *params, sph_tile tile, hipStream_t stream);
+                         const sph_params *params, sph_tile tile, const sph_work *work,
+                         hipStream_t stream);
 /* kick/drift over records 0..n-1 (no cell list needed; cells->n_c is used
  * for the moved count when moved != NULL) */
 sph_status sph_kick_drift_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,

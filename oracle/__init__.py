@@ -96,6 +96,7 @@ def lib():
         L.orc_dequantise_set.argtypes = [C.c_int, d, d, d, d, d, C.c_int, C.c_int, C.c_int,
                                          C.c_int, i32, d, d, d, d, d]
         L.orc_num_threads.restype = C.c_int
+        L.orc_bin_sub.argtypes = [C.c_int, d, C.c_int, C.c_int, i32, i32, i32]
         _lib = L
     return _lib
 
@@ -140,6 +141,20 @@ def bin_cells(x, n_c):
                        _p(perm, C.c_int32), _p(off, C.c_double))
     assert rc == 0
     return cell, start, perm, off
+
+
+def bin_sub(x, n_c, sub_bits):
+    """-> (key[N], sub_start[n_c^3 R^3 + 1], perm[N]) with R = 2**sub_bits"""
+    x = _f64(x)
+    n = x.shape[0]
+    R = 1 << sub_bits
+    key = np.empty(n, np.int32)
+    start = np.empty(n_c ** 3 * R ** 3 + 1, np.int32)
+    perm = np.empty(n, np.int32)
+    rc = lib().orc_bin_sub(n, _p(x, C.c_double), n_c, sub_bits, _p(key, C.c_int32),
+                           _p(start, C.c_int32), _p(perm, C.c_int32))
+    assert rc == 0
+    return key, start, perm
 
 
 def density(ps, prm=None, mode="cells", n_c=None, sel=None):

@@ -128,6 +128,59 @@ int orc_bin(int n, const double *x, int n_c, int32_t *cell, int32_t *cell_start,
   return 0;
 }
 
+/* Sub-cell order inside each cell: with R = 2^sub_bits sub-cells per axis,
+ * the sub-cell index along an axis is floor(x_w * n_c * R) - c * R (FP64,
+ * clamped to [0, R-1]), and particles of a cell are ordered by the Morton
+ * code of (sx, sy, sz) (bit b of sx at 3b, of sy at 3b+1, of sz at 3b+2),
+ * then by input index. key = cell * R^3 + morton; sub_start[C R^3 + 1] is the
+ * CSR index of the keys. sub_bits = 0 gives the plain (cell, index) order. */
+static uint32_t morton3(int sx, int sy, int sz, int bits) {
+  uint32_t m = 0;
+  for (int b = 0; b < bits; ++b) {
+    m |= (uint32_t)((sx >> b) & 1) << (3 * b);
+    m |= (uint32_t)((sy >> b) & 1) << (3 * b + 1);
+    m |= (uint32_t)((sz >> b) & 1) << (3 * b + 2);
+  }
+  return m;
+}
+
+int orc_bin_sub(int n, const double *x, int n_c, int sub_bits, int32_t *key,
+                int32_t *sub_start, int32_t *perm) {
+  if (n < 0 || n_c < 1 || sub_bits < 0 || sub_bits > 4) return -1;
+  int R = 1 << sub_bits;
+  int64_t S = (int64_t)n_c * n_c * n_c * R * R * R;
+  if (S >= (1LL << 31)) return -1;
+  int32_t *k = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *start = (int32_t *)calloc((size_t)S + 1, sizeof(int32_t));
+  for (int i = 0; i < n; ++i) {
+    int cc[3], ss[3];
+    for (int a = 0; a < 3; ++a) {
+      double xw = wrap01(x[3 * i + a]);
+      cc[a] = cell_axis(xw, n_c);
+      double t = floor(xw * (double)(n_c * R));
+      int sa = (t != t) ? 0 : (int)(t - (double)cc[a] * R);
+      if (sa < 0) sa = 0;
+      if (sa > R - 1) sa = R - 1;
+      ss[a] = sa;
+    }
+    int c = cc[0] + n_c * (cc[1] + n_c * cc[2]);
+    k[i] = (int32_t)((int64_t)c * R * R * R + morton3(ss[0], ss[1], ss[2], sub_bits));
+    start[k[i] + 1] += 1;
+  }
+  for (int64_t c = 0; c < S; ++c) start[c + 1] += start[c];
+  if (perm) {
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)S);
+    memcpy(fill, start, sizeof(int32_t) * (size_t)S);
+    for (int i = 0; i < n; ++i) perm[fill[k[i]]++] = i;   /* stable */
+    free(fill);
+  }
+  if (key) memcpy(key, k, sizeof(int32_t) * (size_t)n);
+  if (sub_start) memcpy(sub_start, start, sizeof(int32_t) * ((size_t)S + 1));
+  free(k);
+  free(start);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Neighbour lists                                                           */
 /* ------------------------------------------------------------------------ */

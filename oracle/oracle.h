@@ -46,6 +46,11 @@ double orc_dWdh(double r, double h, double gamma_k);
 int orc_bin(int n, const double *x, int n_c, int32_t *cell, int32_t *cell_start,
             int32_t *perm, double *off);
 
+/* binning with sub-cell order: key = cell * R^3 + Morton(sub-cell), R = 2^sub_bits;
+ * perm stable by (key, input index); sub_start[n_c^3 R^3 + 1] */
+int orc_bin_sub(int n, const double *x, int n_c, int sub_bits, int32_t *key,
+                int32_t *sub_start, int32_t *perm);
+
 /* density; mode 0 = brute force over all pairs, 1 = own cell list.
  * sel (nsel entries) selects which i to evaluate; sel == NULL means all. */
 int orc_density(int n, const double *x, const double *m, const double *h,

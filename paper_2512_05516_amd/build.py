@@ -16,7 +16,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphmi.so")
-SOURCES = ["abi.cpp", "host_convert.cpp", "bin.hip", "convert.hip", "pair.hip", "kick.hip"]
+SOURCES = ["abi.cpp", "host_convert.cpp", "bin.hip", "convert.hip", "pair.hip", "kick.hip",
+           "worklist.hip", "pair_dens_f32.hip", "pair_dens_r.hip", "pair_dens_gen.hip",
+           "pair_dens_aos.hip", "pair_force_f32.hip", "pair_force_r.hip", "pair_force_gen.hip",
+           "pair_force_aos.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")
 
@@ -46,8 +49,11 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(os.cpu_count() or 8, 16)) as ex:
+        # longest first: the kernel instantiation units
+        order = sorted(SOURCES, key=lambda f: (not f.startswith("pair_"), f))
+        done = dict(zip(order, ex.map(_compile, order)))
+        objs = [done[f] for f in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     p = subprocess.run(cmd, capture_output=True, text=True)

@@ -98,14 +98,38 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   if (c->n < 0) return fail(SPH_E_INVALID, "cells->n = %d is negative", c->n);
   if (c->n_c < 3) return fail(SPH_E_RANGE, "cells->n_c = %d must be >= 3", c->n_c);
   if (c->n_c > 1290) return fail(SPH_E_RANGE, "cells->n_c = %d: n_c^3 overflows int32", c->n_c);
+  if (c->sub_bits < 0 || c->sub_bits > 3)
+    return fail(SPH_E_RANGE, "cells->sub_bits = %d must be in [0, 3]", c->sub_bits);
+  if (c->reserved != 0) return fail(SPH_E_INVALID, "cells->reserved must be 0");
+  const int64_t C = (int64_t)c->n_c * c->n_c * c->n_c;
+  if ((C << (3 * c->sub_bits)) >= (1LL << 31))
+    return fail(SPH_E_RANGE, "n_c^3 * 8^sub_bits must be < 2^31");
   if (need_lists && (!c->cell_start || !c->perm || !c->cell))
     return fail(SPH_E_INVALID, "cells->cell_start, perm and cell must be device pointers");
+  if (need_lists && c->sub_bits > 0 && !c->sub_start)
+    return fail(SPH_E_INVALID, "cells->sub_start is required when sub_bits > 0");
   out.n = c->n;
   out.n_c = c->n_c;
+  out.sub_bits = c->sub_bits;
   out.start = c->cell_start;
   out.perm = c->perm;
   out.cell = c->cell;
+  out.sub_start = c->sub_bits > 0 ? c->sub_start : c->cell_start;
+  out.hmax = c->hmax;
   out.status = c->status;
+  return SPH_OK;
+}
+
+// Work list for a persistent launch with tile ti (NULL: one workgroup per cell)
+sph_status check_work(const sph_work* w, const CellsDev& c, int ti, WorkDev& out, bool& use) {
+  use = w != nullptr;
+  if (!w) return SPH_OK;
+  if (!w->buf) return fail(SPH_E_INVALID, "work->buf is NULL");
+  if (w->ti != ti) return fail(SPH_E_INVALID, "work->ti = %d differs from the tile's ti = %d", w->ti, ti);
+  if (w->reserved != 0) return fail(SPH_E_INVALID, "work->reserved must be 0");
+  if (w->bytes < worklist_bytes(c.n, c.n_c, w->ti))
+    return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", w->bytes, worklist_bytes(c.n, c.n_c, w->ti));
+  out = work_view(*w, c.n, c.n_c);
   return SPH_OK;
 }
 
@@ -226,8 +250,30 @@ sph_status sph_bin_workspace_size(int32_t n, int32_t n_c, size_t* bytes) {
   if (!bytes) return fail(SPH_E_INVALID, "bytes is NULL");
   if (n < 0) return fail(SPH_E_INVALID, "n = %d is negative", n);
   if (n_c < 3 || n_c > 1290) return fail(SPH_E_RANGE, "n_c = %d out of range [3, 1290]", n_c);
-  *bytes = bin_workspace_bytes(n, n_c);
+  *bytes = bin_workspace_bytes(n, n_c, 0);
   return SPH_OK;
+}
+
+sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t* bytes) {
+  if (!bytes) return fail(SPH_E_INVALID, "bytes is NULL");
+  if (n < 0) return fail(SPH_E_INVALID, "n = %d is negative", n);
+  if (n_c < 3 || n_c > 1290) return fail(SPH_E_RANGE, "n_c = %d out of range [3, 1290]", n_c);
+  if (ti < 1 || ti > 4096) return fail(SPH_E_INVALID, "ti = %d out of range [1, 4096]", ti);
+  *bytes = worklist_bytes(n, n_c, ti);
+  return SPH_OK;
+}
+
+sph_status sph_worklist(const sph_cells* cells, sph_work* work, hipStream_t stream) {
+  CellsDev c;
+  SPH_TRY(check_cells(cells, true, c));
+  if (!work || !work->buf) return fail(SPH_E_INVALID, "work or work->buf is NULL");
+  if (work->ti < 1 || work->ti > 4096) return fail(SPH_E_INVALID, "work->ti = %d out of range", work->ti);
+  if (work->reserved != 0) return fail(SPH_E_INVALID, "work->reserved must be 0");
+  if (work->bytes < worklist_bytes(c.n, c.n_c, work->ti))
+    return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", work->bytes,
+                worklist_bytes(c.n, c.n_c, work->ti));
+  WorkDev w = work_view(*work, c.n, c.n_c);
+  return hip_status(launch_worklist(c, w, stream), "sph_worklist");
 }
 
 sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,
@@ -237,12 +283,13 @@ sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cell
   SPH_TRY(check_layout(layout, bit(SPH_A_X), L));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_aos_ptr(aos, c.n));
-  size_t need = bin_workspace_bytes(c.n, c.n_c);
+  size_t need = bin_workspace_bytes(c.n, c.n_c, c.sub_bits);
   if (!workspace) return fail(SPH_E_INVALID, "workspace is NULL");
   if (workspace_bytes < need)
     return fail(SPH_E_NOMEM, "workspace has %zu bytes, sph_bin needs %zu", workspace_bytes, need);
-  return hip_status(launch_bin(aos, L, c, cells->cell_start, cells->perm, cells->cell, workspace,
-                               stream),
+  return hip_status(launch_bin(aos, L, c, cells->cell_start, cells->perm, cells->cell,
+                               cells->sub_bits > 0 ? cells->sub_start : nullptr, cells->hmax,
+                               workspace, stream),
                     "sph_bin");
 }
 
@@ -289,31 +336,41 @@ sph_status sph_writeback(const sph_soa* soa, const sph_cells* cells, int32_t vie
 }
 
 sph_status sph_density(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
-                       const sph_params* params, sph_tile tile, hipStream_t stream) {
+                       const sph_params* params, sph_tile tile, const sph_work* work,
+                       hipStream_t stream) {
   CellsDev c;
   Prec p;
   Phys ph;
+  WorkDev w;
+  bool use_w;
   int ti, k;
   SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_density"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
-  return hip_status(launch_density(*soa, p, c, ph, ti, k, stream), "sph_density");
+  SPH_TRY(check_work(work, c, ti, w, use_w));
+  return hip_status(launch_density(*soa, p, c, ph, ti, k, use_w ? &w : nullptr, stream),
+                    "sph_density");
 }
 
 sph_status sph_force(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
-                     const sph_params* params, sph_tile tile, hipStream_t stream) {
+                     const sph_params* params, sph_tile tile, const sph_work* work,
+                     hipStream_t stream) {
   CellsDev c;
   Prec p;
   Phys ph;
+  WorkDev w;
+  bool use_w;
   int ti, k;
   SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_force"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
-  return hip_status(launch_force(*soa, p, c, ph, ti, k, stream), "sph_force");
+  SPH_TRY(check_work(work, c, ti, w, use_w));
+  return hip_status(launch_force(*soa, p, c, ph, ti, k, use_w ? &w : nullptr, stream),
+                    "sph_force");
 }
 
 sph_status sph_kick_drift(const sph_soa* soa, const sph_cells* cells, double dt_kick,
@@ -349,10 +406,13 @@ sph_status sph_reduce(const sph_soa* soa, const sph_precision* prec, const sph_c
 }
 
 sph_status sph_density_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
-                           const sph_params* params, sph_tile tile, hipStream_t stream) {
+                           const sph_params* params, sph_tile tile, const sph_work* work,
+                           hipStream_t stream) {
   AosLayout L;
   CellsDev c;
   Phys ph;
+  WorkDev w;
+  bool use_w;
   int ti, k;
   SPH_TRY(check_layout(layout,
                        bit(SPH_A_X) | bit(SPH_A_M) | bit(SPH_A_H) | bit(SPH_A_U) | bit(SPH_A_RHO) |
@@ -363,14 +423,19 @@ sph_status sph_density_aos(void* aos, const sph_aos_layout* layout, const sph_ce
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
   SPH_TRY(check_aos_ptr(aos, c.n));
-  return hip_status(launch_density_aos(aos, L, c, ph, ti, k, stream), "sph_density_aos");
+  SPH_TRY(check_work(work, c, ti, w, use_w));
+  return hip_status(launch_density_aos(aos, L, c, ph, ti, k, use_w ? &w : nullptr, stream),
+                    "sph_density_aos");
 }
 
 sph_status sph_force_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
-                         const sph_params* params, sph_tile tile, hipStream_t stream) {
+                         const sph_params* params, sph_tile tile, const sph_work* work,
+                         hipStream_t stream) {
   AosLayout L;
   CellsDev c;
   Phys ph;
+  WorkDev w;
+  bool use_w;
   int ti, k;
   SPH_TRY(check_layout(layout,
                        bit(SPH_A_X) | bit(SPH_A_V) | bit(SPH_A_A) | bit(SPH_A_M) | bit(SPH_A_H) |
@@ -381,7 +446,9 @@ sph_status sph_force_aos(void* aos, const sph_aos_layout* layout, const sph_cell
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
   SPH_TRY(check_aos_ptr(aos, c.n));
-  return hip_status(launch_force_aos(aos, L, c, ph, ti, k, stream), "sph_force_aos");
+  SPH_TRY(check_work(work, c, ti, w, use_w));
+  return hip_status(launch_force_aos(aos, L, c, ph, ti, k, use_w ? &w : nullptr, stream),
+                    "sph_force_aos");
 }
 
 sph_status sph_kick_drift_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,

@@ -12,25 +12,60 @@ constexpr int kTile = kThreads * kRounds;     // keys per radix block
 constexpr int kScanPer = 16;                  // elements per thread in scans
 constexpr int kScanTile = kThreads * kScanPer;
 
+// Morton code of a sub-cell (bit b of sx at 3b, sy at 3b+1, sz at 3b+2)
+__device__ __forceinline__ int morton3(int sx, int sy, int sz, int bits) {
+  int m = 0;
+  for (int b = 0; b < bits; ++b)
+    m |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) |
+         (((sz >> b) & 1) << (3 * b + 2));
+  return m;
+}
+
+// key = cell * R^3 + Morton(sub-cell); also the per-cell max of h
 __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ aos,
-                                                        uint32_t stride, uint32_t offx, int n,
-                                                        int n_c, int32_t* __restrict__ keys,
+                                                        uint32_t stride, uint32_t offx,
+                                                        uint32_t offh, int dth, int n, int n_c,
+                                                        int sub_bits, int32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
+                                                        float* __restrict__ hmax,
                                                         int32_t* status) {
   int i = blockIdx.x * kThreads + threadIdx.x;
   if (i >= n) return;
-  const double* x = reinterpret_cast<const double*>(aos + (size_t)i * stride + offx);
+  const char* rec = aos + (size_t)i * stride;
+  const double* x = reinterpret_cast<const double*>(rec + offx);
+  const int R = 1 << sub_bits;
   bool bad = false;
-  int c[3];
+  int c[3], sc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double xv = x[k];
     bad |= !isfinite(xv);
-    c[k] = cell_axis(wrap01(xv), n_c);
+    const double xw = wrap01(xv);
+    c[k] = cell_axis(xw, n_c);
+    const double t = floor(xw * (double)(n_c * R));
+    int sa = (t == t) ? (int)fmin(fmax(t - (double)c[k] * R, 0.0), (double)(R - 1)) : 0;
+    sc[k] = sa;
   }
-  keys[i] = c[0] + n_c * (c[1] + n_c * c[2]);
+  const int cell = c[0] + n_c * (c[1] + n_c * c[2]);
+  keys[i] = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
   vals[i] = i;
+  if (hmax && offh != kAbsent) {
+    const float h = rec_load32(rec, offh, dth);
+    if (h > 0.0f) atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
+  }
   if (bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, int n, float v) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_key_to_cell(const int32_t* __restrict__ keys, int n,
+                                                           int sub_bits,
+                                                           int32_t* __restrict__ cell) {
+  int i = blockIdx.x * kThreads + threadIdx.x;
+  if (i < n) cell[i] = keys[i] >> (3 * sub_bits);
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restrict__ kin,
@@ -192,7 +227,7 @@ BinWs carve(void* ws, int n, int nblk) {
   return w;
 }
 
-hipError_t scan(int32_t* data, int len, int32_t* partials, hipStream_t s) {
+hipError_t scan_local(int32_t* data, int len, int32_t* partials, hipStream_t s) {
   int nt = cdiv(len, kScanTile);
   if (nt == 0) return hipSuccess;
   k_scan_tiles<<<nt, kThreads, 0, s>>>(data, len, partials);
@@ -203,8 +238,15 @@ hipError_t scan(int32_t* data, int len, int32_t* partials, hipStream_t s) {
 
 }  // namespace
 
-size_t bin_workspace_bytes(int n, int n_c) {
+size_t scan_partials_count(int len) { return (size_t)cdiv(len, kScanTile) + 1; }
+
+hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s) {
+  return scan_local(data, len, partials, s);
+}
+
+size_t bin_workspace_bytes(int n, int n_c, int sub_bits) {
   (void)n_c;
+  (void)sub_bits;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   int nblk = cdiv(n, kTile);
   size_t hl = (size_t)256 * (size_t)(nblk > 0 ? nblk : 1);
@@ -213,37 +255,44 @@ size_t bin_workspace_bytes(int n, int n_c) {
 }
 
 hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
-                      int32_t* perm, int32_t* cell, void* ws, hipStream_t s) {
-  const int n = c.n, n_c = c.n_c;
+                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax, void* ws,
+                      hipStream_t s) {
+  const int n = c.n, n_c = c.n_c, sb = c.sub_bits;
   const int C = n_c * n_c * n_c;
+  const int S = C << (3 * sb);
   const int nblk = cdiv(n, kTile);
   BinWs w = carve(ws, n, nblk);
+  if (hmax) k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
+  int32_t* skeys = cell;                 // sorted keys (cell ids when sb == 0)
   if (n > 0) {
-    k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(static_cast<const char*>(aos), L.stride,
-                                                       L.off[SPH_A_X], n, n_c, w.ka, w.va,
-                                                       c.status);
+    k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(
+        static_cast<const char*>(aos), L.stride, L.off[SPH_A_X], L.off[SPH_A_H], L.dt[SPH_A_H],
+        n, n_c, sb, w.ka, w.va, hmax, c.status);
     int bits = 1;
-    while ((1 << bits) < C) ++bits;
+    while ((1 << bits) < S) ++bits;
     int passes = (bits + 7) / 8;
     int32_t *ks = w.ka, *vs = w.va;
     for (int p = 0; p < passes; ++p) {
       int32_t *kd, *vd;
       if (p == passes - 1) {
-        kd = cell;
+        kd = sb ? ((ks == w.ka) ? w.kb : w.ka) : cell;
         vd = perm;
       } else {
         kd = (ks == w.ka) ? w.kb : w.ka;
         vd = (vs == w.va) ? w.vb : w.va;
       }
       k_radix_hist<<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p);
-      hipError_t e = scan(w.hist, 256 * nblk, w.partials, s);
+      hipError_t e = scan_local(w.hist, 256 * nblk, w.partials, s);
       if (e != hipSuccess) return e;
       k_radix_scatter<<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p);
       ks = kd;
       vs = vd;
     }
+    skeys = ks;
+    if (sb) k_key_to_cell<<<cdiv(n, kThreads), kThreads, 0, s>>>(skeys, n, sb, cell);
   }
   k_cell_start<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(cell, n, C, cell_start);
+  if (sb) k_cell_start<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(skeys, n, S, sub_start);
   return hipGetLastError();
 }
 

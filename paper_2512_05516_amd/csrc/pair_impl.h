@@ -1,0 +1,994 @@
+// Quadratic kernels (implementation header, included by the pair_*.hip
+// translation units): the density loop and the force loop over the cell list
+// (Alg. 1 CallQuadratic; Eq. density, Eq. momentum, Eq. energy).
+//
+// One workgroup per (cell, chunk of TI particles): the chunk's particles i
+// are held in registers, K lanes per particle. The workgroup walks the
+// candidates j of the 27 surrounding cells as one flattened index space and
+// stages into LDS those whose distance to the chunk's bounding box is below
+// the largest support radius (a conservative prune: every operation of the
+// box distance is monotone in the same inputs as the pair test, so no
+// accepted pair is ever dropped). The global loads of up to kRounds rounds
+// are issued before the first one is used, so a chunk pays about one memory
+// latency for its gather; the force-only fields of the staged candidates
+// are then loaded cooperatively in one more batch.
+//
+// Each lane then runs two phases over its share of the staged candidates:
+// (A) the FP32 support test (kUnroll LDS reads in flight, branch-free append
+// of the candidate index to a per-lane list in LDS) and (B) the kernel sums
+// over that list only, so the pair arithmetic runs on accepted pairs instead
+// of on every candidate. The K partial sums of a particle are combined with
+// a fixed shuffle tree: results are bit-identical run to run.
+//
+// The loaders (SoA views in compile-time or run-time storage formats, or
+// AoS records) are the only difference between the SoA kernels and the
+// plain-AoS kernels.
+#pragma once
+#include "sph_device.h"
+
+namespace sph {
+namespace pairk {
+
+// --------------------------------------------------------------------------
+// Data sources
+// --------------------------------------------------------------------------
+// Element k of a stored array: format DT fixed at compile time, or taken
+// from rt when DT < 0.
+template <int DT>
+__device__ __forceinline__ float load_fmt(const void* p, int rt, int64_t k, float scale) {
+  if constexpr (DT == DT_F32) {
+    return static_cast<const float*>(p)[k] * scale;
+  } else if constexpr (DT == DT_F16) {
+    return f16_bits_to_f32(static_cast<const uint16_t*>(p)[k]) * scale;
+  } else if constexpr (DT == DT_BF16) {
+    return bf16_bits_to_f32(static_cast<const uint16_t*>(p)[k]) * scale;
+  } else {
+    return load_q(p, rt, k, scale);
+  }
+}
+
+template <int PT, int VT, int MT>
+struct SoaSrc {
+  const void* off[3];
+  const void* vq[3];
+  const void* m;
+  const void* h;
+  const void* u;
+  int pos_dt, vel_dt, mhu_dt;
+  float lm, lh, lu;
+  const float *rho, *f, *P, *c;
+  float *o_rho, *o_wcount, *o_rho_dh, *o_f, *o_P, *o_c;
+  int32_t* o_nngb;
+  float *o_ax, *o_ay, *o_az, *o_du, *o_vsig;
+  int32_t* o_nforce;
+
+  __device__ __forceinline__ void pos(int k, int cell, int n_c, float& x, float& y,
+                                      float& z) const {
+    (void)cell;
+    (void)n_c;
+    x = load_fmt<PT>(off[0], pos_dt, k, 1.0f);
+    y = load_fmt<PT>(off[1], pos_dt, k, 1.0f);
+    z = load_fmt<PT>(off[2], pos_dt, k, 1.0f);
+  }
+  __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
+    x = load_fmt<VT>(vq[0], vel_dt, k, 1.0f);
+    y = load_fmt<VT>(vq[1], vel_dt, k, 1.0f);
+    z = load_fmt<VT>(vq[2], vel_dt, k, 1.0f);
+  }
+  __device__ __forceinline__ float mass(int k) const { return load_fmt<MT>(m, mhu_dt, k, lm); }
+  __device__ __forceinline__ float hsml(int k) const { return load_fmt<MT>(h, mhu_dt, k, lh); }
+  __device__ __forceinline__ float uint(int k) const { return load_fmt<MT>(u, mhu_dt, k, lu); }
+  __device__ __forceinline__ void dens_in(int k, float& r, float& ff, float& p,
+                                          float& cs) const {
+    r = rho[k];
+    ff = f[k];
+    p = P[k];
+    cs = c[k];
+  }
+  __device__ __forceinline__ void dens_out(int k, float r, float wc, float dh, float ff, float p,
+                                           float cs, int nn) const {
+    o_rho[k] = r;
+    o_wcount[k] = wc;
+    o_rho_dh[k] = dh;
+    o_f[k] = ff;
+    o_P[k] = p;
+    o_c[k] = cs;
+    o_nngb[k] = nn;
+  }
+  __device__ __forceinline__ void force_out(int k, float ax, float ay, float az, float du,
+                                            float vs, int nf) const {
+    o_ax[k] = ax;
+    o_ay[k] = ay;
+    o_az[k] = az;
+    o_du[k] = du;
+    o_vsig[k] = vs;
+    if (o_nforce) o_nforce[k] = nf;
+  }
+};
+
+struct AosSrc {
+  char* base;
+  AosLayout L;
+  const int32_t* perm;
+
+  __device__ __forceinline__ char* rec(int k) const {
+    return base + (size_t)perm[k] * L.stride;
+  }
+  __device__ __forceinline__ void pos(int k, int cell, int n_c, float& x, float& y,
+                                      float& z) const {
+    const char* r = rec(k);
+    int cx, cy, cz;
+    cell_coords(cell, n_c, cx, cy, cz);
+    const double* xp = reinterpret_cast<const double*>(r + L.off[SPH_A_X]);
+    x = cell_offset(wrap01(xp[0]), cx, n_c);
+    y = cell_offset(wrap01(xp[1]), cy, n_c);
+    z = cell_offset(wrap01(xp[2]), cz, n_c);
+  }
+  __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
+    const char* r = rec(k);
+    x = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 0);
+    y = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 1);
+    z = rec_load32(r, L.off[SPH_A_V], L.dt[SPH_A_V], 2);
+  }
+  __device__ __forceinline__ float mass(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_M], L.dt[SPH_A_M]);
+  }
+  __device__ __forceinline__ float hsml(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_H], L.dt[SPH_A_H]);
+  }
+  __device__ __forceinline__ float uint(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_U], L.dt[SPH_A_U]);
+  }
+  __device__ __forceinline__ void dens_in(int k, float& rr, float& ff, float& p,
+                                          float& cs) const {
+    const char* r = rec(k);
+    rr = rec_load32(r, L.off[SPH_A_RHO], L.dt[SPH_A_RHO]);
+    ff = rec_load32(r, L.off[SPH_A_F], L.dt[SPH_A_F]);
+    p = rec_load32(r, L.off[SPH_A_P], L.dt[SPH_A_P]);
+    cs = rec_load32(r, L.off[SPH_A_C], L.dt[SPH_A_C]);
+  }
+  __device__ __forceinline__ void dens_out(int k, float rr, float wc, float dh, float ff,
+                                           float p, float cs, int nn) const {
+    char* r = rec(k);
+    rec_store32(r, L.off[SPH_A_RHO], L.dt[SPH_A_RHO], rr);
+    rec_store32(r, L.off[SPH_A_WCOUNT], L.dt[SPH_A_WCOUNT], wc);
+    rec_store32(r, L.off[SPH_A_RHO_DH], L.dt[SPH_A_RHO_DH], dh);
+    rec_store32(r, L.off[SPH_A_F], L.dt[SPH_A_F], ff);
+    rec_store32(r, L.off[SPH_A_P], L.dt[SPH_A_P], p);
+    rec_store32(r, L.off[SPH_A_C], L.dt[SPH_A_C], cs);
+    rec_store_i32(r, L.off[SPH_A_NNGB], nn);
+  }
+  __device__ __forceinline__ void force_out(int k, float ax, float ay, float az, float du,
+                                            float vs, int nf) const {
+    char* r = rec(k);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], ax, 0);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], ay, 1);
+    rec_store32(r, L.off[SPH_A_A], L.dt[SPH_A_A], az, 2);
+    rec_store32(r, L.off[SPH_A_DU], L.dt[SPH_A_DU], du);
+    rec_store32(r, L.off[SPH_A_VSIG], L.dt[SPH_A_VSIG], vs);
+    rec_store_i32(r, L.off[SPH_A_NFORCE], nf);
+  }
+};
+
+// Slot indices read from the cell table are clamped to [0, n], so a
+// corrupted table can never send a load outside the particle arrays.
+__device__ __forceinline__ int clamp_slot(int v, int n) { return min(max(v, 0), n); }
+
+// Spread consecutive workgroups over the 8 XCDs in contiguous ranges: block b
+// runs on XCD b % 8, so logical work item (b % 8) * per + b / 8 gives each
+// XCD a contiguous slab of cells (shared neighbour cells stay in one L2).
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  int per = G >> 3;
+  if (b >= (per << 3)) return b;
+  return (b & 7) * per + (b >> 3);
+}
+
+template <int NT>
+__device__ __forceinline__ float block_max(float v, float* lds) {
+  constexpr int NW = NT / 64;
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = fmaxf(r, lds[w]);
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ float block_min(float v, float* lds) {
+  return -block_max<NT>(-v, lds);
+}
+
+template <int K>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int K>
+__device__ __forceinline__ int group_sum_i(int v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+template <int K>
+__device__ __forceinline__ float group_max(float v) {
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ __forceinline__ void neighbour_cell(int nb, int cx, int cy, int cz, int n_c, float s,
+                                               int& cn, float& shx, float& shy, float& shz) {
+  int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+  int nx = cx + dx, ny = cy + dy, nz = cz + dz;
+  nx += (nx < 0) ? n_c : ((nx >= n_c) ? -n_c : 0);
+  ny += (ny < 0) ? n_c : ((ny >= n_c) ? -n_c : 0);
+  nz += (nz < 0) ? n_c : ((nz >= n_c) ? -n_c : 0);
+  cn = nx + n_c * (ny + n_c * nz);
+  shx = dx < 0 ? -s : (dx > 0 ? s : 0.0f);
+  shy = dy < 0 ? -s : (dy > 0 ? s : 0.0f);
+  shz = dz < 0 ? -s : (dz > 0 ? s : 0.0f);
+}
+
+__device__ __forceinline__ float box_dist2(float x, float y, float z, float lox, float loy,
+                                           float loz, float hix, float hiy, float hiz) {
+#pragma clang fp contract(off)
+  float bx = fmaxf(fmaxf(lox - x, x - hix), 0.0f);
+  float by = fmaxf(fmaxf(loy - y, y - hiy), 0.0f);
+  float bz = fmaxf(fmaxf(loz - z, z - hiz), 0.0f);
+  float xx = bx * bx;
+  return __builtin_fmaf(bz, bz, __builtin_fmaf(by, by, xx));
+}
+
+// --------------------------------------------------------------------------
+// Neighbour cells of a chunk's cell: ids, the position shift of each relative
+// to the chunk's cell (delta * s, delta in {-1, 0, 1}), and the support-radius
+// bound of each (gamma_k * max h * (1 + 2^-8), covering storage rounding of h;
+// the cell side when no bound table is given).
+// --------------------------------------------------------------------------
+struct NbrCells {
+  int cell[27];
+  float sh[27][3];
+  float hb[27];
+  float hb_max;
+};
+
+__device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int cx, int cy,
+                                          int cz, float s32, float gk) {
+  const int tid = threadIdx.x;
+  if (tid < 27) {
+    int cn;
+    float shx, shy, shz;
+    neighbour_cell(tid, cx, cy, cz, cd.n_c, s32, cn, shx, shy, shz);
+    T.cell[tid] = cn;
+    T.sh[tid][0] = shx;
+    T.sh[tid][1] = shy;
+    T.sh[tid][2] = shz;
+    T.hb[tid] = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float m = 0.0f;
+    for (int q = 0; q < 27; ++q) m = fmaxf(m, T.hb[q]);
+    T.hb_max = m;
+  }
+  __syncthreads();
+}
+
+// Block-wide exclusive scan of two ints in thread order; returns the block
+// totals. Two barriers.
+template <int NT>
+__device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int& ta, int& tb,
+                                            int* lds) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ia = a, ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xa = __shfl_up(ia, o), xb = __shfl_up(ib, o);
+    if (lane >= o) {
+      ia += xa;
+      ib += xb;
+    }
+  }
+  if (lane == 63) {
+    lds[wave] = ia;
+    lds[NW + wave] = ib;
+  }
+  __syncthreads();
+  int pa = 0, pb = 0;
+  ta = 0;
+  tb = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int wa = lds[w], wb = lds[NW + w];
+    pa += (w < wave) ? wa : 0;
+    pb += (w < wave) ? wb : 0;
+    ta += wa;
+    tb += wb;
+  }
+  ea = pa + ia - a;
+  eb = pb + ib - b;
+  __syncthreads();
+}
+
+// Range table of one batch of sub-cells: slot ranges, prefix of counts and
+// the neighbour index q of each.
+template <int NT>
+struct RangeTab {
+  int start[NT];
+  int pre[NT + 1];
+  unsigned char q[NT];
+  int scan[2 * (NT / 64)];
+  int ntab, total;
+};
+
+// The sub-cells (R = 2^sub_bits per axis; R = 1: cells) whose boxes lie
+// within `bound(q)` of the chunk box [lo, hi], in batches of at most NT:
+// for each batch, `batch(tab)` gathers the particles of the batch's ranges.
+template <int NT, class Bound, class Batch>
+__device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells& T,
+                                              RangeTab<NT>& tab, float s32, float lox, float loy,
+                                              float loz, float hix, float hiy, float hiz,
+                                              float bext, Bound bound, Batch batch) {
+  const int sb = cd.sub_bits, R = 1 << sb;
+  const float ss = s32 / (float)R;
+  const float mg = ss * 0x1p-8f;                    // rounding margin of stored offsets
+  const float inv = (float)R / s32;
+  auto lo_idx = [&](float v) { return max((int)floorf((v - bext) * inv) - 1, -R); };
+  auto hi_idx = [&](float v) { return min((int)floorf((v + bext) * inv) + 1, 2 * R - 1); };
+  const int ax0 = lo_idx(lox), ay0 = lo_idx(loy), az0 = lo_idx(loz);
+  const int nqx = max(hi_idx(hix) - ax0 + 1, 0), nqy = max(hi_idx(hiy) - ay0 + 1, 0),
+            nqz = max(hi_idx(hiz) - az0 + 1, 0);
+  const int NQ = nqx * nqy * nqz;
+  const int* sstart = sb ? cd.sub_start : cd.start;
+  const int tid = threadIdx.x;
+  for (int b0 = 0; b0 < NQ; b0 += NT) {
+    const int t = b0 + tid;
+    bool ok = t < NQ;
+    int st = 0, cnt = 0, q = 0;
+    if (ok) {
+      const int rx = t % nqx, ry = (t / nqx) % nqy, rz = t / (nqx * nqy);
+      const int gx = ax0 + rx, gy = ay0 + ry, gz = az0 + rz;
+      const int dx = (gx + R) / R - 1, dy = (gy + R) / R - 1, dz = (gz + R) / R - 1;
+      const int sx = gx - dx * R, sy = gy - dy * R, sz = gz - dz * R;
+      q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+      const float bx0 = gx * ss - mg, bx1 = (gx + 1) * ss + mg;
+      const float by0 = gy * ss - mg, by1 = (gy + 1) * ss + mg;
+      const float bz0 = gz * ss - mg, bz1 = (gz + 1) * ss + mg;
+      const float ex = fmaxf(fmaxf(bx0 - hix, lox - bx1), 0.0f);
+      const float ey = fmaxf(fmaxf(by0 - hiy, loy - by1), 0.0f);
+      const float ez = fmaxf(fmaxf(bz0 - hiz, loz - bz1), 0.0f);
+      const float bq = bound(q);
+      ok = ex * ex + ey * ey + ez * ez < bq * bq * (1.0f + 0x1p-10f);
+      if (ok) {
+        int m = 0;
+        for (int b = 0; b < sb; ++b)
+          m |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) |
+               (((sz >> b) & 1) << (3 * b + 2));
+        const int key = (T.cell[q] << (3 * sb)) + m;
+        st = clamp_slot(sstart[key], cd.n);
+        cnt = max(clamp_slot(sstart[key + 1], cd.n) - st, 0);
+        ok = cnt > 0;
+      }
+    }
+    int e_idx, e_pre, ntab, total;
+    block_scan2<NT>(ok ? 1 : 0, ok ? cnt : 0, e_idx, e_pre, ntab, total, tab.scan);
+    if (ok) {
+      tab.start[e_idx] = st;
+      tab.pre[e_idx] = e_pre;
+      tab.q[e_idx] = (unsigned char)q;
+    }
+    if (tid == 0) {
+      tab.pre[ntab] = total;
+      tab.ntab = ntab;
+      tab.total = total;
+    }
+    __syncthreads();
+    batch(tab);
+    __syncthreads();
+  }
+}
+
+// Entry e of the range table holding flattened candidate idx < total
+template <int NT>
+__device__ __forceinline__ int find_range(const RangeTab<NT>& tab, int idx) {
+  int lo = 0, hi = tab.ntab - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab.pre[mid] <= idx) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Deterministic block-wide compaction with one barrier: wave totals are
+// double-buffered by round parity, so a buffer is rewritten only after every
+// thread has passed the next round's barrier.
+// Returns this thread's slot within the round and adds the round's total to nj.
+template <int NT>
+__device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int rnd) {
+  constexpr int NW = NT / 64;
+  int* wtot = wtot2 + (rnd & 1) * NW;
+  const int wave = threadIdx.x >> 6;
+  const uint64_t bal = __ballot(ok);
+  const int wrank = __popcll(bal & lanemask_lt());
+  if ((threadIdx.x & 63) == 0) wtot[wave] = __popcll(bal);
+  __syncthreads();
+  int pre = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int t = wtot[w];
+    pre += (w < wave) ? t : 0;
+    tot += t;
+  }
+  nj += tot;
+  return pre + wrank;
+}
+
+// Per-lane neighbour lists: entry e of thread tid lives at lst[e * NT + tid]
+// (phase B reads are conflict-free). A lane never holds more than LCAP
+// entries: the test phase stops for the whole wave once any lane could
+// overflow within the next kUnroll candidates.
+constexpr int kUnroll = 8;
+constexpr int kRounds = 4;      // gather rounds whose loads are issued together
+constexpr int kFillRounds = 4;  // force-only fields: rounds issued together
+
+// Chunk bounding box of the valid particles and the largest H^2
+struct ChunkBox {
+  float lox, loy, loz, hix, hiy, hiz, h2max;
+};
+
+template <int NT>
+__device__ __forceinline__ ChunkBox chunk_box(bool vi, float xi, float yi, float zi, float H2,
+                                              float* red) {
+  const float inf = __builtin_inff();
+  ChunkBox b;
+  b.lox = block_min<NT>(vi ? xi : inf, red);
+  b.loy = block_min<NT>(vi ? yi : inf, red);
+  b.loz = block_min<NT>(vi ? zi : inf, red);
+  b.hix = block_max<NT>(vi ? xi : -inf, red);
+  b.hiy = block_max<NT>(vi ? yi : -inf, red);
+  b.hiz = block_max<NT>(vi ? zi : -inf, red);
+  b.h2max = block_max<NT>(H2, red);
+  return b;
+}
+
+// Phase A over the staged candidates [0, nj) (nj a multiple of K * kUnroll,
+// padded with entries nobody accepts): lane kk of its particle tests
+// candidates kk, kk + K, ... and appends the accepted ones to its list;
+// `consume(lo)` runs phase B over list entries [tid, lo) whenever the lists
+// may fill up and at the end.
+template <int NT, int K, int LCAP, class Accept, class Consume>
+__device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst, int nj, int kk,
+                                                 Accept accept, Consume consume) {
+  const int tid = threadIdx.x;
+  const int nit = nj / K;
+  int it = 0;
+  while (it < nit) {
+    int lo = tid;
+    const int lim = tid + (LCAP - kUnroll) * NT;
+    while (it < nit) {
+      const float4* cq = cp + kk + K * it;
+      float4 qv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) qv[u] = cq[K * u];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const bool acc = accept(qv[u]);
+        lst[lo] = (uint16_t)(kk + K * (it + u));
+        lo += acc ? NT : 0;
+      }
+      it += kUnroll;
+      if (__any(lo > lim)) break;
+    }
+    consume(lo);
+  }
+}
+
+// Work distribution: one workgroup per cell (chunks of TI in turn), or a
+// persistent grid taking (cell, first slot) items from 8 queues.
+template <class Chunk>
+__device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk, int TI,
+                                          Chunk chunk) {
+  if (!wk.items) {
+    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+    const int cs = clamp_slot(cd.start[cell], cd.n);
+    const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
+    for (int base = cs; base < ce; base += TI) chunk(cell, base, min(base + TI, ce));
+    return;
+  }
+  __shared__ int s_item;
+  const int q0 = blockIdx.x & (kQueues - 1);
+  int qi = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int got = -1;
+      while (qi < kQueues) {
+        const int q = (q0 + qi) & (kQueues - 1);
+        const int idx = atomicAdd(&wk.counters[q], 1);
+        if (idx < wk.meta[2 + q]) {
+          got = idx;
+          break;
+        }
+        ++qi;
+      }
+      s_item = got;
+    }
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it < 0) break;
+    const int2 item = wk.items[it];
+    const int cell = min(max(item.x, 0), cd.n_c * cd.n_c * cd.n_c - 1);
+    const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), 0);
+    const int base = clamp_slot(item.y, ce);
+    chunk(cell, base, min(base + TI, ce));
+  }
+}
+
+// --------------------------------------------------------------------------
+// Density
+// --------------------------------------------------------------------------
+template <int TI, int K, class Src>
+__global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, CellsDev cd, Phys ph,
+                                                                    float s32, WorkDev wk) {
+  constexpr int NT = TI * K;
+  constexpr int CAP = 4 * NT;
+  constexpr int LCAP = 32;
+  constexpr int kPad = K * kUnroll;
+  __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, m_j
+  __shared__ uint16_t lst[LCAP * NT];
+  __shared__ NbrCells T;
+  __shared__ RangeTab<NT> tab;
+  __shared__ int wtot[2 * (NT / 64)];
+  __shared__ float red[NT / 64];
+
+  const int n_c = cd.n_c;
+  const int tid = threadIdx.x;
+  const int gi = tid / K, kk = tid % K;
+  const float gk = ph.gamma_k;
+
+  run_items(cd, wk, TI, [&](int cell, int c0, int c1) {
+    int cx, cy, cz;
+    cell_coords(cell, n_c, cx, cy, cz);
+    build_nbr(T, cd, cx, cy, cz, s32, gk);
+    const int i = c0 + gi;
+    const bool vi = i < c1;
+    float xi = 0.f, yi = 0.f, zi = 0.f, hi = 0.f, ui = 0.f;
+    if (vi) {
+      src.pos(i, cell, n_c, xi, yi, zi);
+      hi = src.hsml(i);
+      ui = src.uint(i);
+    }
+    const float H2 = vi ? support2(gk, hi) : 0.0f;
+    const float Hinv = vi ? 1.0f / (gk * hi) : 0.0f;
+    const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2, red);
+    if (vi && cd.status && H2 > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
+    const float bext = sqrtf(bx.h2max);
+
+    float rho = 0.f, wsum = 0.f, dh = 0.f;
+    int nn = 0;
+
+    auto pair_phase = [&](int nj) {
+      // pad [nj, roundup(nj, kPad)) with entries no particle accepts
+      const int njp = (nj + kPad - 1) / kPad * kPad;
+      if (tid < njp - nj) cand[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      __syncthreads();
+      test_and_consume<NT, K, LCAP>(
+          cand, lst, njp, kk,
+          [&](const float4& q) {
+            float dx, dy, dz;
+            return dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz) < H2;
+          },
+          [&](int lo) {
+            for (int e = tid; e < lo; e += NT) {
+              const float4 q = cand[lst[e]];
+              float dx, dy, dz;
+              const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
+              const float u = fast_sqrt(r2) * Hinv;
+              float w, dw;
+              kernel_w_dw(u, w, dw);
+              rho = fmaf(q.w, w, rho);
+              wsum += w;
+              dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
+            }
+            nn += (lo - tid) / NT;
+          });
+      __syncthreads();
+    };
+
+    int nj = 0, rnd = 0;
+    for_sub_cells<NT>(
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, bext,
+        [&](int) { return bext; },
+        [&](const RangeTab<NT>& tb) {
+          const int total = tb.total;
+          for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
+            float4 c[kRounds];
+            int qq[kRounds];
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+              const int idx = sbase + r * NT + tid;
+              c[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+              qq[r] = 0;
+              if (idx < total) {
+                const int e = find_range<NT>(tb, idx);
+                qq[r] = tb.q[e];
+                const int j = tb.start[e] + (idx - tb.pre[e]);
+                src.pos(j, T.cell[qq[r]], n_c, c[r].x, c[r].y, c[r].z);
+                c[r].w = src.mass(j);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+              if (sbase + r * NT >= total) break;       // uniform
+              const int idx = sbase + r * NT + tid;
+              bool ok = idx < total;
+              if (ok) {
+                c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
+                c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
+                c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+                ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
+                               bx.hiz) < bx.h2max;
+              }
+              int njn = nj;
+              const int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+              if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
+                pair_phase(nj);
+                njn -= nj;
+                nj = 0;
+              }
+              if (ok) cand[nj + slot] = c[r];
+              nj = njn;
+            }
+          }
+        });
+    pair_phase(nj);
+
+    rho = group_sum<K>(rho);
+    wsum = group_sum<K>(wsum);
+    dh = group_sum<K>(dh);
+    nn = group_sum_i<K>(nn);
+    if (vi && kk == 0) {
+      const float Hinv3 = Hinv * Hinv * Hinv;
+      const float rho_i = rho * Hinv3;
+      const float rho_dh = -gk * dh * Hinv3 * Hinv;
+      const float omega = 1.0f + hi * rho_dh / (3.0f * rho_i);
+      const float f = ph.gradh ? 1.0f / omega : 1.0f;
+      const float P = (ph.gamma - 1.0f) * rho_i * ui;
+      const float c = sqrtf(ph.gamma * (ph.gamma - 1.0f) * ui);
+      src.dens_out(i, rho_i, kFourPiThird * wsum, rho_dh, f, P, c, nn);
+    }
+    __syncthreads();
+  });
+}
+
+// --------------------------------------------------------------------------
+// Force
+// --------------------------------------------------------------------------
+template <int TI, int K, class Src>
+__global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsDev cd, Phys ph,
+                                                                 float s32, WorkDev wk) {
+  constexpr int NT = TI * K;
+  constexpr int CAP = 2 * NT;
+  constexpr int LCAP = 32;
+  constexpr int kPad = K * kUnroll;
+  __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), H_j^2
+  __shared__ float4 cv[CAP];      // v_j, m_j
+  __shared__ float4 cs4[CAP];     // 1/H_j, A_j, c_j, rho_j
+  __shared__ int cid[CAP];        // sorted slot of j
+  __shared__ uint16_t lst[LCAP * NT];
+  __shared__ NbrCells T;
+  __shared__ RangeTab<NT> tab;
+  __shared__ int wtot[2 * (NT / 64)];
+  __shared__ float red[NT / 64];
+
+  const int n_c = cd.n_c;
+  const int tid = threadIdx.x;
+  const int gi = tid / K, kk = tid % K;
+  const float gk = ph.gamma_k;
+  const float alpha = ph.alpha, beta = ph.beta;
+
+  run_items(cd, wk, TI, [&](int cell, int c0, int c1) {
+    int cx, cy, cz;
+    cell_coords(cell, n_c, cx, cy, cz);
+    build_nbr(T, cd, cx, cy, cz, s32, gk);
+    const int i = c0 + gi;
+    const bool vi = i < c1;
+    // lanes without a particle sit far outside the box and accept nothing
+    float xi = 1e30f, yi = 1e30f, zi = 1e30f, hi = 1.f, vxi = 0.f, vyi = 0.f, vzi = 0.f;
+    float rhoi = 1.f, fi = 1.f, Pi_ = 0.f, ci = 0.f;
+    if (vi) {
+      src.pos(i, cell, n_c, xi, yi, zi);
+      src.vel(i, vxi, vyi, vzi);
+      hi = src.hsml(i);
+      src.dens_in(i, rhoi, fi, Pi_, ci);
+    }
+    const float H2i = vi ? support2(gk, hi) : 0.0f;
+    const float Hinvi = 1.0f / (gk * hi);
+    const float Hinv2i = Hinvi * Hinvi;
+    const float Hinv4i = Hinv2i * Hinv2i;
+    const float Ai = (ph.gradh ? fi : 1.0f) * Pi_ / (rhoi * rhoi);
+    const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2i, red);
+    if (vi && cd.status && H2i > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
+    const float bi = sqrtf(bx.h2max);
+
+    float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
+    int nf = 0;
+
+    // force-only fields of staged candidates [from, to), loaded cooperatively
+    auto fill = [&](int from, int to) {
+      __syncthreads();
+      for (int s0 = from; s0 < to; s0 += kFillRounds * NT) {
+        float4 v4[kFillRounds], d4[kFillRounds];
+        float hj[kFillRounds];
+#pragma unroll
+        for (int r = 0; r < kFillRounds; ++r) {
+          const int sl = s0 + r * NT + tid;
+          v4[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+          d4[r] = make_float4(1.f, 1.f, 0.f, 0.f);
+          hj[r] = 1.f;
+          if (sl < to) {
+            const int j = cid[sl];
+            src.vel(j, v4[r].x, v4[r].y, v4[r].z);
+            v4[r].w = src.mass(j);
+            hj[r] = src.hsml(j);
+            src.dens_in(j, d4[r].x, d4[r].y, d4[r].z, d4[r].w);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kFillRounds; ++r) {
+          const int sl = s0 + r * NT + tid;
+          if (sl < to) {
+            cv[sl] = v4[r];
+            // d4 = (rho, f, P, c) -> (1/H, A, c, rho)
+            cs4[sl] = make_float4(1.0f / (gk * hj[r]),
+                                  (ph.gradh ? d4[r].y : 1.0f) * d4[r].z / (d4[r].x * d4[r].x),
+                                  d4[r].w, d4[r].x);
+          }
+        }
+      }
+    };
+
+    auto pair_phase = [&](int nj) {
+      const int njp = (nj + kPad - 1) / kPad * kPad;
+      if (tid < njp - nj) {
+        cp[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+        cid[nj + tid] = -1;
+      }
+      __syncthreads();
+      test_and_consume<NT, K, LCAP>(
+          cp, lst, njp, kk,
+          [&](const float4& q0) {
+            float dx, dy, dz;
+            return dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz) < fmaxf(H2i, q0.w);
+          },
+          [&](int lo) {
+            for (int e = tid; e < lo; e += NT) {
+              const int t = lst[e];
+              const float4 q0 = cp[t];
+              float dx, dy, dz;
+              const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
+              // the self pair has r2 = 0 exactly; so may coincident stored
+              // positions, for which w'(0) = 0 makes the pair's terms vanish
+              if (r2 == 0.0f && cid[t] == i) continue;
+              const float4 q1 = cv[t];
+              const float4 q2 = cs4[t];
+              const float r = fast_sqrt(r2);
+              const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
+              const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
+              const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
+              const float hj2 = q2.x * q2.x;
+              const float gj_ = kernel_dw(r * q2.x) * (hj2 * hj2);
+              const float w = (vxi - q1.x) * ex + (vyi - q1.y) * ey + (vzi - q1.z) * ez;
+              const float mu = fminf(w, 0.0f);
+              const float vs = ci + q2.z - beta * mu;
+              const float visc = -alpha * vs * mu * fast_rcp(rhoi + q2.w);
+              const float gbar = 0.5f * (gi_ + gj_);
+              const float kc = q1.w * (Ai * gi_ + q2.y * gj_ + visc * gbar);
+              ax = fmaf(-kc, ex, ax);
+              ay = fmaf(-kc, ey, ay);
+              az = fmaf(-kc, ez, az);
+              du = fmaf(q1.w * (Ai * gi_ + 0.5f * visc * gbar), w, du);
+              vsig = fmaxf(vsig, vs);
+              ++nf;
+            }
+          });
+      __syncthreads();
+    };
+
+    int nj = 0, filled = 0, rnd = 0;
+    for_sub_cells<NT>(
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, fmaxf(bi, T.hb_max),
+        [&](int q) { return fmaxf(bi, T.hb[q]); },
+        [&](const RangeTab<NT>& tb) {
+          const int total = tb.total;
+          for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
+            float4 c[kRounds];
+            int qq[kRounds], jj[kRounds];
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+              const int idx = sbase + r * NT + tid;
+              c[r] = make_float4(0.f, 0.f, 0.f, 1.f);
+              qq[r] = 0;
+              jj[r] = 0;
+              if (idx < total) {
+                const int e = find_range<NT>(tb, idx);
+                qq[r] = tb.q[e];
+                jj[r] = tb.start[e] + (idx - tb.pre[e]);
+                src.pos(jj[r], T.cell[qq[r]], n_c, c[r].x, c[r].y, c[r].z);
+                c[r].w = src.hsml(jj[r]);
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < kRounds; ++r) {
+              if (sbase + r * NT >= total) break;       // uniform
+              const int idx = sbase + r * NT + tid;
+              bool ok = idx < total;
+              if (ok) {
+                c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
+                c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
+                c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+                c[r].w = support2(gk, c[r].w);
+                ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
+                               bx.hiz) < fmaxf(bx.h2max, c[r].w);
+              }
+              int njn = nj;
+              const int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+              if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
+                fill(filled, nj);
+                pair_phase(nj);
+                njn -= nj;
+                nj = 0;
+                filled = 0;
+              }
+              if (ok) {
+                cp[nj + slot] = c[r];
+                cid[nj + slot] = jj[r];
+              }
+              nj = njn;
+            }
+            // force-only fields of this super-round's candidates, one batch
+            fill(filled, nj);
+            filled = nj;
+          }
+        });
+    pair_phase(nj);
+
+    ax = group_sum<K>(ax);
+    ay = group_sum<K>(ay);
+    az = group_sum<K>(az);
+    du = group_sum<K>(du);
+    vsig = group_max<K>(vsig);
+    nf = group_sum_i<K>(nf);
+    if (vi && kk == 0) src.force_out(i, ax, ay, az, du, vsig, nf);
+    __syncthreads();
+  });
+}
+
+template <int PT, int VT, int MT>
+SoaSrc<PT, VT, MT> make_soa(const sph_soa& s, const Prec& p) {
+  SoaSrc<PT, VT, MT> r;
+  for (int k = 0; k < 3; ++k) {
+    r.off[k] = s.f[SPH_S_OFF_X + k];
+    r.vq[k] = s.f[SPH_S_VQ_X + k];
+  }
+  r.m = s.f[SPH_S_M];
+  r.h = s.f[SPH_S_H];
+  r.u = s.f[SPH_S_U];
+  r.pos_dt = p.pos;
+  r.vel_dt = p.vel;
+  r.mhu_dt = p.mhu;
+  r.lm = p.load_m;
+  r.lh = p.load_h;
+  r.lu = p.load_u;
+  r.rho = static_cast<const float*>(s.f[SPH_S_RHO]);
+  r.f = static_cast<const float*>(s.f[SPH_S_F]);
+  r.P = static_cast<const float*>(s.f[SPH_S_P]);
+  r.c = static_cast<const float*>(s.f[SPH_S_C]);
+  r.o_rho = static_cast<float*>(s.f[SPH_S_RHO]);
+  r.o_wcount = static_cast<float*>(s.f[SPH_S_WCOUNT]);
+  r.o_rho_dh = static_cast<float*>(s.f[SPH_S_RHO_DH]);
+  r.o_f = static_cast<float*>(s.f[SPH_S_F]);
+  r.o_P = static_cast<float*>(s.f[SPH_S_P]);
+  r.o_c = static_cast<float*>(s.f[SPH_S_C]);
+  r.o_nngb = static_cast<int32_t*>(s.f[SPH_S_NNGB]);
+  r.o_ax = static_cast<float*>(s.f[SPH_S_A_X]);
+  r.o_ay = static_cast<float*>(s.f[SPH_S_A_Y]);
+  r.o_az = static_cast<float*>(s.f[SPH_S_A_Z]);
+  r.o_du = static_cast<float*>(s.f[SPH_S_DU]);
+  r.o_vsig = static_cast<float*>(s.f[SPH_S_VSIG]);
+  r.o_nforce = static_cast<int32_t*>(s.f[SPH_S_NFORCE]);
+  return r;
+}
+
+// Persistent grid size: resident workgroups per CU times CUs
+static int persistent_grid(const void* kernel, int block) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1024;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess ||
+      per < 1)
+    per = 1;
+  return cus * per;
+}
+
+static __global__ void k_reset_queues(WorkDev w) {
+  if (threadIdx.x < kQueues) w.counters[threadIdx.x] = w.meta[1 + threadIdx.x];
+}
+
+template <class S>
+hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                       const WorkDev* w, hipStream_t s) {
+  WorkDev wv{};
+  if (w) wv = *w;
+  const int C = c.n_c * c.n_c * c.n_c;
+  const float s32 = (float)(1.0 / (double)c.n_c);
+  if (w) k_reset_queues<<<1, 64, 0, s>>>(*w);
+#define SPH_DENS_CASE(TI_, K_)                                                        \
+  if (ti == TI_ && k == K_) {                                                         \
+    auto kern = k_density<TI_, K_, S>;                                                \
+    const int G = w ? persistent_grid((const void*)kern, TI_ * K_) : C;              \
+    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
+    return hipGetLastError();                                                         \
+  }
+  SPH_DENS_CASE(64, 4)
+  SPH_DENS_CASE(32, 8)
+  SPH_DENS_CASE(128, 2)
+  SPH_DENS_CASE(64, 2)
+  SPH_DENS_CASE(64, 1)
+  SPH_DENS_CASE(16, 16)
+#undef SPH_DENS_CASE
+  return hipErrorInvalidValue;
+}
+
+template <class S>
+hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                       const WorkDev* w, hipStream_t s) {
+  WorkDev wv{};
+  if (w) wv = *w;
+  const int C = c.n_c * c.n_c * c.n_c;
+  const float s32 = (float)(1.0 / (double)c.n_c);
+  if (w) k_reset_queues<<<1, 64, 0, s>>>(*w);
+#define SPH_FORCE_CASE(TI_, K_)                                                       \
+  if (ti == TI_ && k == K_) {                                                         \
+    auto kern = k_force<TI_, K_, S>;                                                  \
+    const int G = w ? persistent_grid((const void*)kern, TI_ * K_) : C;              \
+    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
+    return hipGetLastError();                                                         \
+  }
+  SPH_FORCE_CASE(64, 4)
+  SPH_FORCE_CASE(32, 8)
+  SPH_FORCE_CASE(128, 2)
+  SPH_FORCE_CASE(64, 2)
+  SPH_FORCE_CASE(64, 1)
+  SPH_FORCE_CASE(16, 16)
+#undef SPH_FORCE_CASE
+  return hipErrorInvalidValue;
+}
+
+// instantiated in pair_*.hip
+hipError_t run_density_dens_f32(const SoaSrc<DT_F32, DT_F32, DT_F32>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_density_dens_r(const SoaSrc<DT_F16, DT_BF16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_density_dens_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_density_dens_aos(const AosSrc& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_f32(const SoaSrc<DT_F32, DT_F32, DT_F32>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_r(const SoaSrc<DT_F16, DT_BF16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_aos(const AosSrc& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+
+}  // namespace pairk
+}  // namespace sph

@@ -35,16 +35,41 @@ struct Phys {
 
 struct CellsDev {
   int n, n_c;
+  int sub_bits;
   const int32_t* start;
   const int32_t* perm;
   const int32_t* cell;
+  const int32_t* sub_start;
+  const float* hmax;
   int32_t* status;
 };
 
+// Persistent-kernel work list (device buffer layout): 8 queue counters, the
+// item count and the 8 queue boundaries, then items (cell, first slot).
+struct WorkDev {
+  int ti;
+  int capacity;
+  int32_t* counters;   // [8] next item index of each queue
+  int32_t* meta;       // [0] item count, [1..9] queue boundaries
+  int2* items;         // [capacity]
+};
+constexpr int kQueues = 8;
+constexpr size_t kWorkHeader = 256;   // bytes before the items
+
 // --- launchers (return hipError_t of the launch) ---
-size_t bin_workspace_bytes(int n, int n_c);
+size_t bin_workspace_bytes(int n, int n_c, int sub_bits);
 hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
-                      int32_t* perm, int32_t* cell, void* ws, hipStream_t s);
+                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax, void* ws,
+                      hipStream_t s);
+
+// exclusive scan of int32 in place; partials: scan_partials_count(len) ints
+size_t scan_partials_count(int len);
+hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s);
+
+size_t worklist_bytes(int n, int n_c, int ti);
+int worklist_capacity(int n, int n_c, int ti);
+hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s);
+WorkDev work_view(const sph_work& w, int n, int n_c);
 
 hipError_t launch_convert(const void* aos, const AosLayout& L, const CellsDev& c, int view,
                           const Prec& p, const sph_soa& out, hipStream_t s);
@@ -53,13 +78,13 @@ hipError_t launch_writeback(const sph_soa& in, const CellsDev& c, int view, void
 
 bool tile_supported(int ti, int k);
 hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
-                          int ti, int k, hipStream_t s);
+                          int ti, int k, const WorkDev* w, hipStream_t s);
 hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
-                        int ti, int k, hipStream_t s);
+                        int ti, int k, const WorkDev* w, hipStream_t s);
 hipError_t launch_density_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
-                              int ti, int k, hipStream_t s);
+                              int ti, int k, const WorkDev* w, hipStream_t s);
 hipError_t launch_force_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
-                            int ti, int k, hipStream_t s);
+                            int ti, int k, const WorkDev* w, hipStream_t s);
 
 hipError_t launch_kick_drift(const sph_soa& soa, const CellsDev& c, double dtk, double dtd,
                              int32_t* moved, hipStream_t s);

@@ -14,7 +14,8 @@ from . import sphmi
 
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
-                 prm=None, stream=None):
+                 prm=None, stream=None, sub_bits: int = 0, persistent: bool = False,
+                 til_force=None):
         import torch
         self.torch = torch
         self.n = int(aos_np.shape[0])
@@ -26,8 +27,17 @@ class Pipeline:
         self.prec = prec or sphmi.precision()
         self.prm = prm or sphmi.params()
         self.til = til or sphmi.tile()
+        self.til_force = til_force or self.til
         self.stream = stream
-        self.cells = sphmi.DeviceCells(self.n, self.n_c, device)
+        self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits)
+        self.persistent = persistent
+        self.work = self.work_force = None
+        if persistent:
+            ti_d = self.til.ti or 64
+            ti_f = self.til_force.ti or 64
+            self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device)
+            self.work_force = (self.work if ti_f == ti_d else
+                               sphmi.DeviceWork(self.n, self.n_c, ti_f, device))
         self.bin_ws = torch.empty(sphmi.bin_workspace_size(self.n, self.n_c), dtype=torch.uint8,
                                   device=device)
         self.soa = sphmi.DeviceSoa(self.n, self.prec, device)
@@ -39,15 +49,19 @@ class Pipeline:
     # --- individual stages -------------------------------------------------
     def bin(self):
         sphmi.bin(self.aos, self.layout, self.cells, self.bin_ws, self.stream)
+        if self.persistent:
+            sphmi.worklist(self.cells, self.work, self.stream)
+            if self.work_force is not self.work:
+                sphmi.worklist(self.cells, self.work_force, self.stream)
 
     def convert(self, view="full"):
         sphmi.convert(self.aos, self.layout, self.cells, view, self.soa, self.stream)
 
     def density(self):
-        sphmi.density(self.soa, self.cells, self.prm, self.til, self.stream)
+        sphmi.density(self.soa, self.cells, self.prm, self.til, self.stream, self.work)
 
     def force(self):
-        sphmi.force(self.soa, self.cells, self.prm, self.til, self.stream)
+        sphmi.force(self.soa, self.cells, self.prm, self.til_force, self.stream, self.work_force)
 
     def reduce(self):
         sphmi.reduce(self.soa, self.cells, self.red_out, self.red_ws, self.stream)
@@ -59,10 +73,12 @@ class Pipeline:
         sphmi.writeback(self.soa, self.cells, view, self.aos, self.layout, self.stream)
 
     def density_aos(self):
-        sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream)
+        sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream,
+                          self.work)
 
     def force_aos(self):
-        sphmi.force_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream)
+        sphmi.force_aos(self.aos, self.layout, self.cells, self.prm, self.til_force, self.stream,
+                        self.work_force)
 
     def kick_drift_aos(self, dt_kick, dt_drift):
         sphmi.kick_drift_aos(self.aos, self.layout, self.cells, dt_kick, dt_drift, self.moved,

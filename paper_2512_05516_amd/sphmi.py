@@ -49,8 +49,15 @@ class AosLayout(C.Structure):
 
 
 class Cells(C.Structure):
-    _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("cell_start", C.c_void_p),
-                ("perm", C.c_void_p), ("cell", C.c_void_p), ("status", C.c_void_p)]
+    _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("sub_bits", C.c_int32),
+                ("reserved", C.c_int32), ("cell_start", C.c_void_p), ("perm", C.c_void_p),
+                ("cell", C.c_void_p), ("sub_start", C.c_void_p), ("hmax", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+class Work(C.Structure):
+    _fields_ = [("ti", C.c_int32), ("reserved", C.c_int32), ("buf", C.c_void_p),
+                ("bytes", C.c_size_t)]
 
 
 class Soa(C.Structure):
@@ -75,7 +82,8 @@ EXPORTS = [
     "sph_abi_version", "sph_last_error", "sph_tile_supported", "sph_bin_workspace_size",
     "sph_bin", "sph_convert", "sph_host_staging_size", "sph_convert_host", "sph_writeback",
     "sph_density", "sph_force", "sph_kick_drift", "sph_reduce_workspace_size", "sph_reduce",
-    "sph_density_aos", "sph_force_aos", "sph_kick_drift_aos", "sph_sync",
+    "sph_density_aos", "sph_force_aos", "sph_kick_drift_aos", "sph_sync", "sph_worklist_size",
+    "sph_worklist",
 ]
 
 _lib = None
@@ -103,13 +111,15 @@ def lib():
     L.sph_convert_host.argtypes = [vp, P(AosLayout), P(Cells), i32, P(Precision), P(Soa), vp, sz,
                                    i32, vp]
     L.sph_writeback.argtypes = [P(Soa), P(Cells), i32, vp, P(AosLayout), vp]
-    L.sph_density.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp]
-    L.sph_force.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp]
+    L.sph_worklist_size.argtypes = [i32, i32, i32, P(sz)]
+    L.sph_worklist.argtypes = [P(Cells), P(Work), vp]
+    L.sph_density.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, P(Work), vp]
+    L.sph_force.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift.argtypes = [P(Soa), P(Cells), C.c_double, C.c_double, vp, vp]
     L.sph_reduce_workspace_size.argtypes = [i32, P(sz)]
     L.sph_reduce.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp, sz, vp]
-    L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, vp]
-    L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, vp]
+    L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
+    L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
     L.sph_sync.argtypes = [vp]
     for name in EXPORTS[3:]:
@@ -178,21 +188,41 @@ _TORCH_DT = {F32: "float32", F16: "float16", BF16: "bfloat16"}
 
 
 class DeviceCells:
-    """Cell list arrays on the device: cell_start[C+1], perm[n], cell[n], status[1]."""
+    """Cell list arrays on the device: cell_start[C+1], perm[n], cell[n],
+    sub_start[C 8^sub_bits + 1] (sub_bits > 0), hmax[C], status[1]."""
 
-    def __init__(self, n: int, n_c: int, device="cuda"):
+    def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0):
         import torch
-        self.n, self.n_c = int(n), int(n_c)
+        self.n, self.n_c, self.sub_bits = int(n), int(n_c), int(sub_bits)
         C_ = self.n_c ** 3
         self.cell_start = torch.zeros(C_ + 1, dtype=torch.int32, device=device)
         self.perm = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
         self.cell = torch.zeros(max(self.n, 1), dtype=torch.int32, device=device)
+        self.sub_start = (torch.zeros(C_ * 8 ** self.sub_bits + 1, dtype=torch.int32, device=device)
+                          if self.sub_bits else None)
+        self.hmax = torch.zeros(C_, dtype=torch.float32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
-        self._s = Cells(self.n, self.n_c, self.cell_start.data_ptr(), self.perm.data_ptr(),
-                        self.cell.data_ptr(), self.status.data_ptr())
+        self._s = Cells(self.n, self.n_c, self.sub_bits, 0, self.cell_start.data_ptr(),
+                        self.perm.data_ptr(), self.cell.data_ptr(),
+                        self.sub_start.data_ptr() if self.sub_start is not None else None,
+                        self.hmax.data_ptr(), self.status.data_ptr())
 
     @property
     def struct(self) -> Cells:
+        return self._s
+
+
+class DeviceWork:
+    """Work-list buffer of the persistent pair kernels for tile size ti."""
+
+    def __init__(self, n: int, n_c: int, ti: int, device="cuda"):
+        import torch
+        nbytes = worklist_size(n, n_c, ti)
+        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self._s = Work(int(ti), 0, self.buf.data_ptr(), nbytes)
+
+    @property
+    def struct(self) -> Work:
         return self._s
 
 
@@ -253,6 +283,20 @@ def reduce_workspace_size(n) -> int:
     return out.value
 
 
+def worklist_size(n, n_c, ti) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_worklist_size(n, n_c, ti, C.byref(out)))
+    return out.value
+
+
+def worklist(cells: DeviceCells, work: DeviceWork, stream=None):
+    _check(lib().sph_worklist(C.byref(cells.struct), C.byref(work.struct), _stream(stream)))
+
+
+def _wk(work):
+    return C.byref(work.struct) if work is not None else None
+
+
 def host_staging_size(n, n_c, view, prec) -> int:
     out = C.c_size_t()
     _check(lib().sph_host_staging_size(n, n_c, VIEWS.get(view, view), C.byref(prec), C.byref(out)))
@@ -284,14 +328,16 @@ def writeback(soa: DeviceSoa, cells: DeviceCells, view, aos, layout, stream=None
                                _ptr(aos), C.byref(layout), _stream(stream)))
 
 
-def density(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None):
+def density(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None, work=None):
     _check(lib().sph_density(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
-                             C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+                             C.byref(prm or params()), til or Tile(0, 0), _wk(work),
+                             _stream(stream)))
 
 
-def force(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None):
+def force(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None, work=None):
     _check(lib().sph_force(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
-                           C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+                           C.byref(prm or params()), til or Tile(0, 0), _wk(work),
+                           _stream(stream)))
 
 
 def kick_drift(soa: DeviceSoa, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):
@@ -305,14 +351,16 @@ def reduce(soa: DeviceSoa, cells: DeviceCells, out, workspace, stream=None):
                             _stream(stream)))
 
 
-def density_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None):
+def density_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None, work=None):
     _check(lib().sph_density_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
-                                 C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+                                 C.byref(prm or params()), til or Tile(0, 0), _wk(work),
+                                 _stream(stream)))
 
 
-def force_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None):
+def force_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None, work=None):
     _check(lib().sph_force_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
-                               C.byref(prm or params()), til or Tile(0, 0), _stream(stream)))
+                               C.byref(prm or params()), til or Tile(0, 0), _wk(work),
+                               _stream(stream)))
 
 
 def kick_drift_aos(aos, layout, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):

@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 1
+    assert sph.abi_version() == 2
     assert sph.tile_supported(64, 4)
     assert not sph.tile_supported(48, 3)
 
@@ -54,13 +54,16 @@ def test_workspace_size_validation(sph):
         sph.bin_workspace_size(10, 2)
     assert e.value.code == sph.SPH_E_RANGE
     assert sph.reduce_workspace_size(100) >= 8 * 8
+    assert sph.worklist_size(4096, 4, 64) >= 256 + 8 * (64 + 64)
+    with pytest.raises(sph.SphError):
+        sph.worklist_size(4096, 4, 0)
     p = sph.precision("f16", "bf16", "f16")
     assert sph.host_staging_size(1000, 4, "full", p) > 1000 * (6 + 6 + 6 + 24 + 12 + 4)
 
 
-def _fake_cells(sph, n=16, n_c=4, lists=True):
+def _fake_cells(sph, n=16, n_c=4, lists=True, sub_bits=0, sub=True):
     dummy = C.c_void_p(0x1000) if lists else None
-    return sph.Cells(n, n_c, dummy, dummy, dummy, None)
+    return sph.Cells(n, n_c, sub_bits, 0, dummy, dummy, dummy, dummy if sub else None, None, None)
 
 
 def test_host_side_validation(sph):
@@ -93,16 +96,33 @@ def test_host_side_validation(sph):
     # SoA views with NULL fields, bad precision, bad tile, bad view
     soa = sph.Soa()
     assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
-                         C.byref(sph.params()), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+                         C.byref(sph.params()), sph.Tile(0, 0), None, None) == sph.SPH_E_INVALID
     for i in range(len(sph.S_FIELDS)):
         soa.f[i] = 0x4000 + 256 * i
     assert L.sph_density(C.byref(soa), C.byref(sph.Precision(7, 1, 1, 0, 0, 0)), C.byref(cells),
-                         C.byref(sph.params()), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+                         C.byref(sph.params()), sph.Tile(0, 0), None, None) == sph.SPH_E_INVALID
     assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
-                         C.byref(sph.params()), sph.Tile(48, 3), None) == sph.SPH_E_UNSUPPORTED
+                         C.byref(sph.params()), sph.Tile(48, 3), None, None) == sph.SPH_E_UNSUPPORTED
     bad_prm = sph.params(gamma_k=float("nan"))
     assert L.sph_force(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
-                       C.byref(bad_prm), sph.Tile(0, 0), None) == sph.SPH_E_INVALID
+                       C.byref(bad_prm), sph.Tile(0, 0), None, None) == sph.SPH_E_INVALID
+    # work list: tile mismatch, missing buffer, too small
+    wk = sph.Work(32, 0, C.c_void_p(0x7000), 1 << 30)
+    assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                         C.byref(sph.params()), sph.Tile(64, 4), C.byref(wk), None) == sph.SPH_E_INVALID
+    wk = sph.Work(64, 0, C.c_void_p(0x7000), 64)
+    assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                         C.byref(sph.params()), sph.Tile(64, 4), C.byref(wk), None) == sph.SPH_E_NOMEM
+    assert L.sph_worklist(C.byref(cells), C.byref(sph.Work(64, 0, None, 1 << 30)), None) == sph.SPH_E_INVALID
+    assert L.sph_worklist(C.byref(cells), C.byref(sph.Work(64, 0, C.c_void_p(0x7000), 64)),
+                          None) == sph.SPH_E_NOMEM
+    # sub-cells: range and the required sub_start table
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, sub_bits=4)), ws,
+                     1 << 30, None) == sph.SPH_E_RANGE
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, sub_bits=2, sub=False)),
+                     ws, 1 << 30, None) == sph.SPH_E_INVALID
+    assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, n_c=1000, sub_bits=1)),
+                     ws, 1 << 36, None) == sph.SPH_E_RANGE
     assert L.sph_convert(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), 9,
                          C.byref(sph.precision()), C.byref(soa), None) == sph.SPH_E_INVALID
     assert L.sph_kick_drift(C.byref(soa), C.byref(cells), float("inf"), 1e-4, None, None) == sph.SPH_E_INVALID

@@ -57,17 +57,21 @@ def check_fp32(got, d, f, tol=FP32_TOL, tag=""):
 # binning
 # ---------------------------------------------------------------------------
 
-def _bin_gpu(sph, x, n_c):
+def _bin_gpu(sph, x, n_c, sub_bits=0, h=None):
     import torch
     from paper_2512_05516_amd.pipeline import Pipeline
-    ps = inputs.ParticleSet(x, np.zeros_like(x), np.ones(len(x)), np.ones(len(x)),
-                            np.ones(len(x)))
-    pipe = Pipeline(inputs.pack_aos(ps, "f32"), n_c)
+    hh = np.ones(len(x)) if h is None else h
+    ps = inputs.ParticleSet(x, np.zeros_like(x), np.ones(len(x)), hh, np.ones(len(x)))
+    pipe = Pipeline(inputs.pack_aos(ps, "f32"), n_c, sub_bits=sub_bits)
     pipe.bin()
     torch.cuda.synchronize()
     n = len(x)
-    return (pipe.cells.cell_start.cpu().numpy(), pipe.cells.perm[:n].cpu().numpy(),
-            pipe.cells.cell[:n].cpu().numpy(), pipe.status())
+    out = (pipe.cells.cell_start.cpu().numpy(), pipe.cells.perm[:n].cpu().numpy(),
+           pipe.cells.cell[:n].cpu().numpy(), pipe.status())
+    if sub_bits or h is not None:
+        sub = pipe.cells.sub_start.cpu().numpy() if sub_bits else None
+        return out + (sub, pipe.cells.hmax.cpu().numpy())
+    return out
 
 
 @pytest.mark.parametrize("n,n_c", [(0, 3), (1, 3), (4096, 4), (20000, 7), (100003, 23),
@@ -85,6 +89,27 @@ def test_bin_bit_exact(sph, orc, n, n_c):
     assert np.array_equal(start, ostart)
     assert np.array_equal(perm, operm)
     assert np.array_equal(cell, ocell[operm])
+
+
+@pytest.mark.parametrize("n,n_c,bits", [(4096, 4, 1), (30011, 7, 2), (200000, 23, 3),
+                                         (1, 3, 2), (0, 3, 1)])
+def test_bin_sub_cells_bit_exact(sph, orc, n, n_c, bits):
+    rng = np.random.default_rng(n + 7 * bits)
+    x = rng.uniform(-0.5, 1.5, size=(n, 3))
+    h = rng.uniform(0.01, 0.02, size=n)
+    start, perm, cell, status, sub, hmax = _bin_gpu(sph, x, n_c, bits, h)
+    key, osub, operm = orc.bin_sub(x, n_c, bits)
+    ocell, ostart, _, _ = orc.bin_cells(x, n_c)
+    assert status == 0
+    assert np.array_equal(perm, operm)
+    assert np.array_equal(sub, osub)
+    assert np.array_equal(start, ostart)
+    assert np.array_equal(cell, ocell[operm])
+    # hmax: the largest stored (FP32) h of each cell, 0 for empty cells
+    h32 = h.astype(np.float32)
+    want = np.zeros(n_c ** 3, np.float32)
+    np.maximum.at(want, ocell, h32)
+    assert np.array_equal(hmax, want)
 
 
 def test_bin_flags_non_finite(sph):
@@ -170,11 +195,14 @@ def test_host_convert_matches_device(sph):
 # density / force against the FP64 oracle
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kind", ["f32", "f64"])
-def test_small_lattice_parity(sph, orc, kind):
+@pytest.mark.parametrize("kind,mode", [("f32", {}), ("f64", {}),
+                                       ("f32", {"sub_bits": 1, "persistent": True}),
+                                       ("f64", {"sub_bits": 2, "persistent": True}),
+                                       ("f32", {"sub_bits": 1})])
+def test_small_lattice_parity(sph, orc, kind, mode):
     ps = inputs.small_set(1)                        # 4,096 particles, shuffled order
     n_c = 4
-    pipe = run_gpu(ps, n_c, kind)
+    pipe = run_gpu(ps, n_c, kind, **mode)
     assert pipe.status() == 0
     got = gpu_fields(pipe)
     ref = inputs.unpack_aos(inputs.pack_aos(ps, kind))
@@ -183,7 +211,7 @@ def test_small_lattice_parity(sph, orc, kind):
     assert np.array_equal(got["nngb"], nd)
     assert np.array_equal(got["nforce"], nf)
     d, f = oracle_step(orc, ps, n_c)                # FP64, unrounded inputs
-    check_fp32(got, d, f, tag=f"S/{kind}")
+    check_fp32(got, d, f, tag=f"S/{kind}/{mode}")
 
 
 @pytest.fixture(scope="module")
@@ -200,10 +228,14 @@ def ragged(orc):
     return ps, ref, n_c, nd, nf, d, f
 
 
-@pytest.mark.parametrize("ti,k", [(64, 4), (32, 8), (128, 2), (64, 2), (64, 1)])
-def test_ragged_clustered_parity(sph, ragged, ti, k):
+@pytest.mark.parametrize("ti,k,bits,pers", [(64, 4, 0, False), (32, 8, 0, False),
+                                            (128, 2, 0, False), (64, 2, 0, False),
+                                            (64, 1, 0, False), (64, 4, 2, True),
+                                            (32, 8, 3, True), (16, 16, 2, True),
+                                            (128, 2, 1, True), (64, 1, 3, True)])
+def test_ragged_clustered_parity(sph, ragged, ti, k, bits, pers):
     ps, ref, n_c, nd, nf, d, f = ragged
-    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k))
+    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k), sub_bits=bits, persistent=pers)
     assert pipe.status() == 0
     counts = np.diff(pipe.cells.cell_start.cpu().numpy())
     assert counts.min() == 0 and counts.max() > 2 * ti
@@ -211,7 +243,7 @@ def test_ragged_clustered_parity(sph, ragged, ti, k):
     got["h"] = ref.h
     assert np.array_equal(got["nngb"], nd)
     assert np.array_equal(got["nforce"], nf)
-    check_fp32(got, d, f, tag=f"clustered/{ti}x{k}")
+    check_fp32(got, d, f, tag=f"clustered/{ti}x{k}/sub{bits}/{'persistent' if pers else 'cells'}")
 
 
 def test_perfect_lattice_closed_form_gpu(sph, orc):
@@ -261,13 +293,14 @@ def test_reduced_precision(sph, orc, pos, vel, mhu, scales):
 # AoS == SoA, determinism, kick/drift, reductions, edge cases
 # ---------------------------------------------------------------------------
 
-def test_aos_equals_soa_bitwise(sph):
+@pytest.mark.parametrize("mode", [{}, {"sub_bits": 2, "persistent": True}])
+def test_aos_equals_soa_bitwise(sph, mode):
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.clustered_set(20000, 9, f_blob=0.4, sigma=0.05)
     rec = inputs.pack_aos(ps, "f32")
     n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
-    a = Pipeline(rec, n_c)
-    b = Pipeline(rec, n_c)
+    a = Pipeline(rec, n_c, **mode)
+    b = Pipeline(rec, n_c, **mode)
     for _ in range(2):
         a.soa_step(1e-3, 1e-3)
         b.aos_step(1e-3, 1e-3)
@@ -277,10 +310,12 @@ def test_aos_equals_soa_bitwise(sph):
         assert np.ascontiguousarray(ra[k]).tobytes() == np.ascontiguousarray(rb[k]).tobytes(), k
 
 
-def test_deterministic(sph):
-    ps = inputs.small_set(4)
-    r1 = run_gpu(ps, 4).records()
-    r2 = run_gpu(ps, 4).records()
+@pytest.mark.parametrize("mode", [{}, {"sub_bits": 1, "persistent": True}])
+def test_deterministic(sph, mode):
+    ps = inputs.clustered_set(30000, 4, f_blob=0.5, sigma=0.05)
+    n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
+    r1 = run_gpu(ps, n_c, **mode).records()
+    r2 = run_gpu(ps, n_c, **mode).records()
     assert r1.tobytes() == r2.tobytes()
 
 

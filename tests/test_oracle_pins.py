@@ -426,3 +426,31 @@ def test_dequantise_set_roundtrips(orc, small):
     h16 = (small.h * 2 ** 3).astype(np.float32).astype(np.float16).astype(np.float64)
     assert np.array_equal(q.h, h16 / 2 ** 3)
     assert np.array_equal(q.u, small.u.astype(np.float32).astype(np.float16).astype(np.float64))
+
+
+@pytest.mark.parametrize("n_c,bits", [(4, 0), (4, 1), (5, 2), (3, 3)])
+def test_sub_cell_order(orc, n_c, bits):
+    # key = cell * R^3 + Morton(sub-cell); perm is numpy's stable lexsort by
+    # (key, index); sub_start is the CSR of the keys; bits = 0 is the plain
+    # cell order
+    rng = np.random.default_rng(n_c * 10 + bits)
+    x = rng.uniform(-0.2, 1.2, size=(3000, 3))
+    x[:3] = [[0.0, 0.0, 0.0], [1 - 1e-17, 0.5, 0.5], [0.25, 0.5, 0.75]]
+    key, start, perm = orc.bin_sub(x, n_c, bits)
+    R = 1 << bits
+    xw = x - np.floor(x)
+    c3 = np.minimum(np.floor(xw * n_c).astype(int), n_c - 1)
+    s3 = np.clip(np.floor(xw * (n_c * R)).astype(int) - c3 * R, 0, R - 1)
+    mort = np.zeros(len(x), np.int64)
+    for b in range(bits):
+        for a in range(3):
+            mort |= ((s3[:, a] >> b) & 1) << (3 * b + a)
+    cell = c3[:, 0] + n_c * (c3[:, 1] + n_c * c3[:, 2])
+    assert np.array_equal(key, cell * R ** 3 + mort)
+    assert np.array_equal(perm, np.lexsort((np.arange(len(x)), key)))
+    assert np.array_equal(start, np.searchsorted(np.sort(key), np.arange(n_c ** 3 * R ** 3 + 1)))
+    if bits == 0:
+        assert np.array_equal(perm, orc.bin_cells(x, n_c)[2])
+    # particles of one sub-cell lie inside its box
+    side = 1.0 / (n_c * R)
+    assert np.all(xw >= (c3 * R + s3) * side - 1e-15)
