@@ -117,14 +117,21 @@ typedef struct {
   int32_t *status;        /* [1] optional (may be NULL) SPH_FLAG_* word   */
 } sph_cells;
 
-/* Work list of the persistent pair kernels: (cell, first slot) items of
- * at most `ti` particles each, built by sph_worklist from a cell list. The
- * caller allocates `buf` with at least sph_worklist_size(n, n_c, ti) bytes.
- * A work list describes the cell list it was built from: rebuild it after
- * every sph_bin. */
+/* Work list of the pair kernels for a launch over all cells of uneven
+ * occupancy: (cell, first slot) items of at most `ti` particles each, built
+ * by sph_worklist from a cell list, split into 8 contiguous ranges (one per
+ * XCD) of about equal estimated cost. The caller allocates `buf` with at
+ * least sph_worklist_size(n, n_c, ti) bytes. A work list describes the cell
+ * list it was built from: rebuild it after every sph_bin. `sched` picks how
+ * workgroups take items; it changes only the timing, never a result. */
+enum {
+  SPH_SCHED_GRID = 0,     /* one workgroup per item, dispatched by the hardware */
+  SPH_SCHED_STATIC = 1,   /* persistent grid, items of an XCD's range in turn  */
+  SPH_SCHED_DYNAMIC = 2   /* persistent grid, per-XCD queues with stealing      */
+};
 typedef struct {
   int32_t ti;             /* particles per item (the tile's ti)           */
-  int32_t reserved;       /* must be 0                                    */
+  int32_t sched;          /* SPH_SCHED_*                                  */
   void *buf;              /* device buffer: queues, item count, items     */
   size_t bytes;           /* size of buf                                  */
 } sph_work;
@@ -243,11 +250,13 @@ sph_status sph_convert_host(const void *aos_host, const sph_aos_layout *layout,
 sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t view,
                          void *aos, const sph_aos_layout *layout, hipStream_t stream);
 
-/* Work list for the persistent pair kernels (Alg. 1 CallQuadratic over
- * all cells of uneven occupancy in one launch): one item per chunk of at
- * most ti consecutive slots of a cell. Items are ordered by cell; the
- * kernels hand them out through 8 queues (one per XCD, contiguous ranges
- * of cells) with work stealing, so results never depend on the schedule. */
+/* Work list for the pair kernels (Alg. 1 CallQuadratic over all cells of
+ * uneven occupancy in one launch): one item per chunk of at most ti
+ * consecutive slots of a cell, in cell order. The cost of an item is
+ * estimated as its particle count times the particle count of the 27 cells
+ * around its cell; the 8 XCD ranges split the total cost evenly. Items are
+ * independent (each writes only its own particles), so no result depends on
+ * the schedule. work->sched is not used here. */
 sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t *bytes);
 sph_status sph_worklist(const sph_cells *cells, sph_work *work, hipStream_t stream);
 
@@ -261,8 +270,8 @@ sph_status sph_worklist(const sph_cells *cells, sph_work *work, hipStream_t stre
  *   f_i = 1 / (1 + h_i rho_dh_i / (3 rho_i))   (1 if gradh = 0)
  *   P_i = (gamma-1) rho_i u_i         c_i = sqrt(gamma (gamma-1) u_i)
  * Reads OFF, M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB.
- * work == NULL: one workgroup per cell; otherwise a persistent launch over
- * the work list (work->ti must equal the tile's ti). Candidates come from
+ * work == NULL: one workgroup per cell; otherwise one launch over the work
+ * list with schedule work->sched (work->ti must equal the tile's ti). Candidates come from
  * the sub-cells (or cells, sub_bits = 0) within the chunk's bounding box
  * widened by its largest support radius. */
 sph_status sph_density(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,

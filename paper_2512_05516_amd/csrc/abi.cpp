@@ -120,13 +120,14 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   return SPH_OK;
 }
 
-// Work list for a persistent launch with tile ti (NULL: one workgroup per cell)
+// Work list of a launch over items with tile ti (NULL: one workgroup per cell)
 sph_status check_work(const sph_work* w, const CellsDev& c, int ti, WorkDev& out, bool& use) {
   use = w != nullptr;
   if (!w) return SPH_OK;
   if (!w->buf) return fail(SPH_E_INVALID, "work->buf is NULL");
   if (w->ti != ti) return fail(SPH_E_INVALID, "work->ti = %d differs from the tile's ti = %d", w->ti, ti);
-  if (w->reserved != 0) return fail(SPH_E_INVALID, "work->reserved must be 0");
+  if (w->sched < SPH_SCHED_GRID || w->sched > SPH_SCHED_DYNAMIC)
+    return fail(SPH_E_INVALID, "work->sched = %d is not an SPH_SCHED_* value", w->sched);
   if (w->bytes < worklist_bytes(c.n, c.n_c, w->ti))
     return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", w->bytes, worklist_bytes(c.n, c.n_c, w->ti));
   out = work_view(*w, c.n, c.n_c);
@@ -268,7 +269,8 @@ sph_status sph_worklist(const sph_cells* cells, sph_work* work, hipStream_t stre
   SPH_TRY(check_cells(cells, true, c));
   if (!work || !work->buf) return fail(SPH_E_INVALID, "work or work->buf is NULL");
   if (work->ti < 1 || work->ti > 4096) return fail(SPH_E_INVALID, "work->ti = %d out of range", work->ti);
-  if (work->reserved != 0) return fail(SPH_E_INVALID, "work->reserved must be 0");
+  if (work->sched < SPH_SCHED_GRID || work->sched > SPH_SCHED_DYNAMIC)
+    return fail(SPH_E_INVALID, "work->sched = %d is not an SPH_SCHED_* value", work->sched);
   if (work->bytes < worklist_bytes(c.n, c.n_c, work->ti))
     return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", work->bytes,
                 worklist_bytes(c.n, c.n_c, work->ti));

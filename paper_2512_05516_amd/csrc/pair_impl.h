@@ -489,8 +489,17 @@ __device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst
   }
 }
 
-// Work distribution: one workgroup per cell (chunks of TI in turn), or a
-// persistent grid taking (cell, first slot) items from 8 queues.
+// Work distribution. No work list: one workgroup per cell, taking the
+// cell's chunks of TI in turn. With a work list, items (cell, first slot)
+// of XCD range x = blockIdx % 8 (workgroups are dispatched to the 8 XCDs in
+// turn):
+//   GRID / STATIC: workgroup l of its XCD takes items lo_x + l, + G/8, ...
+//     (GRID launches about one workgroup per item, STATIC only as many as
+//     stay resident);
+//   DYNAMIC: resident workgroups take items from their XCD's queue with an
+//     atomic counter and then steal from the other queues; the counter of
+//     the next item is bumped while the current one is processed, so the
+//     atomic's latency overlaps the work.
 template <class Chunk>
 __device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk, int TI,
                                           Chunk chunk) {
@@ -501,32 +510,55 @@ __device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk,
     for (int base = cs; base < ce; base += TI) chunk(cell, base, min(base + TI, ce));
     return;
   }
+  const int C = cd.n_c * cd.n_c * cd.n_c;
+  auto item = [&](int it) {
+    const int2 v = wk.items[it];
+    const int cell = min(max(v.x, 0), C - 1);
+    const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), 0);
+    const int base = clamp_slot(v.y, ce);
+    chunk(cell, base, min(base + TI, ce));
+  };
+  const int x = blockIdx.x & (kQueues - 1);
+  const int total = min(wk.meta[0], wk.capacity);
+  if (wk.sched != SPH_SCHED_DYNAMIC) {
+    const int nl = gridDim.x / kQueues;
+    const int lo = max(wk.meta[1 + x], 0), hi = min(wk.meta[2 + x], total);
+    for (int it = lo + (int)(blockIdx.x / kQueues); it < hi; it += nl) item(it);
+    return;
+  }
   __shared__ int s_item;
-  const int q0 = blockIdx.x & (kQueues - 1);
-  int qi = 0;
-  for (;;) {
+  int qi = 0;   // thread 0: queues tried so far (own queue first)
+  auto grab = [&]() {
+    while (qi < kQueues) {
+      const int q = (x + qi) & (kQueues - 1);
+      const int idx = atomicAdd(&wk.counters[q], 1);
+      if (idx < min(wk.meta[2 + q], total)) return idx;
+      ++qi;
+    }
+    return -1;
+  };
+  if (threadIdx.x == 0) s_item = grab();
+  __syncthreads();
+  int it = __builtin_amdgcn_readfirstlane(s_item);
+  while (it >= 0) {
+    int nxt = -1, nq = 0;
+    if (threadIdx.x == 0 && qi < kQueues) {
+      nq = (x + qi) & (kQueues - 1);
+      nxt = atomicAdd(&wk.counters[nq], 1);
+    }
+    __syncthreads();   // every thread has read s_item
+    item(it);
     if (threadIdx.x == 0) {
-      int got = -1;
-      while (qi < kQueues) {
-        const int q = (q0 + qi) & (kQueues - 1);
-        const int idx = atomicAdd(&wk.counters[q], 1);
-        if (idx < wk.meta[2 + q]) {
-          got = idx;
-          break;
-        }
+      if (qi >= kQueues) {
+        nxt = -1;
+      } else if (nxt >= min(wk.meta[2 + nq], total)) {
         ++qi;
+        nxt = grab();
       }
-      s_item = got;
+      s_item = nxt;
     }
     __syncthreads();
-    const int it = s_item;
-    __syncthreads();
-    if (it < 0) break;
-    const int2 item = wk.items[it];
-    const int cell = min(max(item.x, 0), cd.n_c * cd.n_c * cd.n_c - 1);
-    const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), 0);
-    const int base = clamp_slot(item.y, ce);
-    chunk(cell, base, min(base + TI, ce));
+    it = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
 
@@ -906,7 +938,7 @@ SoaSrc<PT, VT, MT> make_soa(const sph_soa& s, const Prec& p) {
   return r;
 }
 
-// Persistent grid size: resident workgroups per CU times CUs
+// Resident workgroups (per CU times CUs), a multiple of the 8 XCDs
 static int persistent_grid(const void* kernel, int block) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
@@ -915,7 +947,15 @@ static int persistent_grid(const void* kernel, int block) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess ||
       per < 1)
     per = 1;
-  return cus * per;
+  return max(cus * per / kQueues, 1) * kQueues;
+}
+
+// Grid of a pair launch: cells, about one workgroup per item (rounded up to
+// the 8 XCDs), or the resident workgroups.
+static int pair_grid(const void* kernel, int block, int C, const WorkDev* w) {
+  if (!w) return C;
+  if (w->sched == SPH_SCHED_GRID) return (w->capacity + kQueues - 1) / kQueues * kQueues;
+  return persistent_grid(kernel, block);
 }
 
 static __global__ void k_reset_queues(WorkDev w) {
@@ -929,11 +969,11 @@ hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, 
   if (w) wv = *w;
   const int C = c.n_c * c.n_c * c.n_c;
   const float s32 = (float)(1.0 / (double)c.n_c);
-  if (w) k_reset_queues<<<1, 64, 0, s>>>(*w);
+  if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_DENS_CASE(TI_, K_)                                                        \
   if (ti == TI_ && k == K_) {                                                         \
     auto kern = k_density<TI_, K_, S>;                                                \
-    const int G = w ? persistent_grid((const void*)kern, TI_ * K_) : C;              \
+    const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
     kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
     return hipGetLastError();                                                         \
   }
@@ -954,11 +994,11 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   if (w) wv = *w;
   const int C = c.n_c * c.n_c * c.n_c;
   const float s32 = (float)(1.0 / (double)c.n_c);
-  if (w) k_reset_queues<<<1, 64, 0, s>>>(*w);
+  if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_FORCE_CASE(TI_, K_)                                                       \
   if (ti == TI_ && k == K_) {                                                         \
     auto kern = k_force<TI_, K_, S>;                                                  \
-    const int G = w ? persistent_grid((const void*)kern, TI_ * K_) : C;              \
+    const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
     kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
     return hipGetLastError();                                                         \
   }

@@ -44,13 +44,15 @@ struct CellsDev {
   int32_t* status;
 };
 
-// Persistent-kernel work list (device buffer layout): 8 queue counters, the
-// item count and the 8 queue boundaries, then items (cell, first slot).
+// Work list of the pair kernels (device buffer layout): 8 queue counters,
+// the item count and the 8 XCD range boundaries, then items (cell, first
+// slot). sched: SPH_SCHED_GRID / _STATIC / _DYNAMIC.
 struct WorkDev {
   int ti;
+  int sched;
   int capacity;
   int32_t* counters;   // [8] next item index of each queue
-  int32_t* meta;       // [0] item count, [1..9] queue boundaries
+  int32_t* meta;       // [0] item count, [1..9] range boundaries
   int2* items;         // [capacity]
 };
 constexpr int kQueues = 8;

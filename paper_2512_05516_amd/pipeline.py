@@ -14,7 +14,7 @@ from . import sphmi
 
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
-                 prm=None, stream=None, sub_bits: int = 0, persistent: bool = False,
+                 prm=None, stream=None, sub_bits: int = 0, sched=None,
                  til_force=None):
         import torch
         self.torch = torch
@@ -30,14 +30,23 @@ class Pipeline:
         self.til_force = til_force or self.til
         self.stream = stream
         self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits)
-        self.persistent = persistent
+        # sched: None (one workgroup per cell) or a work-list schedule, one
+        # for both loops or a (density, force) pair
+        sd, sf = sched if isinstance(sched, (tuple, list)) else (sched, sched)
+        self.sched = (sd, sf)
         self.work = self.work_force = None
-        if persistent:
-            ti_d = self.til.ti or 64
-            ti_f = self.til_force.ti or 64
-            self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device)
-            self.work_force = (self.work if ti_f == ti_d else
-                               sphmi.DeviceWork(self.n, self.n_c, ti_f, device))
+        self._lists = []
+        ti_d = self.til.ti or 64
+        ti_f = self.til_force.ti or 64
+        if sd:
+            self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device, sd)
+            self._lists.append(self.work)
+        if sf:
+            if self.work is not None and ti_f == ti_d:
+                self.work_force = self.work.with_sched(sf)
+            else:
+                self.work_force = sphmi.DeviceWork(self.n, self.n_c, ti_f, device, sf)
+                self._lists.append(self.work_force)
         self.bin_ws = torch.empty(sphmi.bin_workspace_size(self.n, self.n_c), dtype=torch.uint8,
                                   device=device)
         self.soa = sphmi.DeviceSoa(self.n, self.prec, device)
@@ -49,10 +58,8 @@ class Pipeline:
     # --- individual stages -------------------------------------------------
     def bin(self):
         sphmi.bin(self.aos, self.layout, self.cells, self.bin_ws, self.stream)
-        if self.persistent:
-            sphmi.worklist(self.cells, self.work, self.stream)
-            if self.work_force is not self.work:
-                sphmi.worklist(self.cells, self.work_force, self.stream)
+        for w in self._lists:
+            sphmi.worklist(self.cells, w, self.stream)
 
     def convert(self, view="full"):
         sphmi.convert(self.aos, self.layout, self.cells, view, self.soa, self.stream)

@@ -56,7 +56,7 @@ class Cells(C.Structure):
 
 
 class Work(C.Structure):
-    _fields_ = [("ti", C.c_int32), ("reserved", C.c_int32), ("buf", C.c_void_p),
+    _fields_ = [("ti", C.c_int32), ("sched", C.c_int32), ("buf", C.c_void_p),
                 ("bytes", C.c_size_t)]
 
 
@@ -212,14 +212,24 @@ class DeviceCells:
         return self._s
 
 
-class DeviceWork:
-    """Work-list buffer of the persistent pair kernels for tile size ti."""
+SCHEDS = {"grid": 0, "static": 1, "dynamic": 2}
 
-    def __init__(self, n: int, n_c: int, ti: int, device="cuda"):
+
+class DeviceWork:
+    """Work-list buffer of the pair kernels for tile size ti, taken with
+    schedule `sched` ("grid", "static" or "dynamic"); with_sched() gives a
+    view of the same list under another schedule."""
+
+    def __init__(self, n: int, n_c: int, ti: int, device="cuda", sched="grid", _buf=None):
         import torch
         nbytes = worklist_size(n, n_c, ti)
-        self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self._s = Work(int(ti), 0, self.buf.data_ptr(), nbytes)
+        self.n, self.n_c, self.ti, self.sched = n, n_c, int(ti), sched
+        self.buf = (_buf if _buf is not None else
+                    torch.empty(nbytes, dtype=torch.uint8, device=device))
+        self._s = Work(int(ti), SCHEDS[sched], self.buf.data_ptr(), nbytes)
+
+    def with_sched(self, sched: str) -> "DeviceWork":
+        return DeviceWork(self.n, self.n_c, self.ti, sched=sched, _buf=self.buf)
 
     @property
     def struct(self) -> Work:

@@ -41,7 +41,7 @@ def oracle_step(orc, ps, n_c, prm=None, sel=None):
 def run_gpu(ps, n_c, kind="f32", prec=None, til=None, prm=None, kick=None, **kw):
     """Pack ps into AoS records of `kind`, run bin, convert(full), density,
     force (and optionally kick/drift + writeback) through the C ABI. kw go to
-    Pipeline (sub_bits, persistent, til_force)."""
+    Pipeline (sub_bits, sched, til_force)."""
     from paper_2512_05516_amd import inputs, sphmi
     from paper_2512_05516_amd.pipeline import Pipeline
     rec = inputs.pack_aos(ps, kind)

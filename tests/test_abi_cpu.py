@@ -116,6 +116,12 @@ def test_host_side_validation(sph):
     assert L.sph_worklist(C.byref(cells), C.byref(sph.Work(64, 0, None, 1 << 30)), None) == sph.SPH_E_INVALID
     assert L.sph_worklist(C.byref(cells), C.byref(sph.Work(64, 0, C.c_void_p(0x7000), 64)),
                           None) == sph.SPH_E_NOMEM
+    for bad_sched in (-1, 3):
+        wk = sph.Work(64, bad_sched, C.c_void_p(0x7000), 1 << 30)
+        assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                             C.byref(sph.params()), sph.Tile(64, 4), C.byref(wk),
+                             None) == sph.SPH_E_INVALID
+        assert "sched" in sph.last_error()
     # sub-cells: range and the required sub_start table
     assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, sub_bits=4)), ws,
                      1 << 30, None) == sph.SPH_E_RANGE

@@ -191,13 +191,64 @@ def test_host_convert_matches_device(sph):
             assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
 
 
+def _worklist_reference(start, n, n_c, ti):
+    """Items and XCD range boundaries of the work list, rebuilt on the host
+    from the cell table: items (cell, first slot) in cell order; the cost of
+    a cell is ceil(count * (count of its 27 cells) / 4096), clamped so the
+    sum fits in int32; range q starts at the first item of the first cell
+    whose cost prefix reaches ceil(q * total / 8)."""
+    C = n_c ** 3
+    counts = np.diff(start).astype(np.int64)
+    items = [(c, f) for c in range(C) for f in range(start[c], start[c + 1], ti)]
+    grid = counts.reshape(n_c, n_c, n_c)
+    nb = sum(np.roll(grid, (dz, dy, dx), axis=(0, 1, 2))
+             for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)).reshape(-1)
+    cap = (2 ** 31 - 1) // (C + 1)
+    cost = np.minimum((counts * nb + 4095) >> 12, cap)
+    prefix = np.concatenate([[0], np.cumsum(cost)])
+    pos = np.concatenate([[0], np.cumsum((counts + ti - 1) // ti)])
+    total = len(items)
+    bounds = [0]
+    for q in range(1, 8):
+        target = (int(prefix[-1]) * q + 7) // 8
+        c = int(np.searchsorted(prefix, target, side="left"))
+        bounds.append(min(int(pos[c]), total))
+    bounds.append(total)
+    return np.array(items, np.int32).reshape(-1, 2), np.array(bounds, np.int32)
+
+
+@pytest.mark.parametrize("ti", [16, 64, 128])
+def test_worklist_bit_exact(sph, ti):
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(30000, 5, f_blob=0.5, sigma=0.05)
+    n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    pipe = Pipeline(rec, n_c, til=sph.tile(ti, 256 // ti), sched="grid")
+    pipe.bin()
+    torch.cuda.synchronize()
+    start = pipe.cells.cell_start.cpu().numpy()
+    items_ref, bounds_ref = _worklist_reference(start, ps.n, n_c, ti)
+    buf = pipe.work.buf.cpu().numpy()
+    meta = buf[64:104].view(np.int32)
+    C = n_c ** 3
+    cap = (ps.n + (ti - 1) * min(C, ps.n)) // ti + 1
+    assert len(items_ref) <= cap
+    assert meta[0] == len(items_ref)
+    items = buf[len(buf) - 8 * cap:].view(np.int32).reshape(-1, 2)[:meta[0]]
+    assert np.array_equal(items, items_ref)
+    assert np.array_equal(meta[1:10], bounds_ref)
+    assert np.all(np.diff(bounds_ref) >= 0)
+
+
 # ---------------------------------------------------------------------------
 # density / force against the FP64 oracle
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("kind,mode", [("f32", {}), ("f64", {}),
-                                       ("f32", {"sub_bits": 1, "persistent": True}),
-                                       ("f64", {"sub_bits": 2, "persistent": True}),
+                                       ("f32", {"sub_bits": 1, "sched": "dynamic"}),
+                                       ("f64", {"sub_bits": 2, "sched": "static"}),
+                                       ("f32", {"sched": "grid"}),
                                        ("f32", {"sub_bits": 1})])
 def test_small_lattice_parity(sph, orc, kind, mode):
     ps = inputs.small_set(1)                        # 4,096 particles, shuffled order
@@ -228,14 +279,15 @@ def ragged(orc):
     return ps, ref, n_c, nd, nf, d, f
 
 
-@pytest.mark.parametrize("ti,k,bits,pers", [(64, 4, 0, False), (32, 8, 0, False),
-                                            (128, 2, 0, False), (64, 2, 0, False),
-                                            (64, 1, 0, False), (64, 4, 2, True),
-                                            (32, 8, 3, True), (16, 16, 2, True),
-                                            (128, 2, 1, True), (64, 1, 3, True)])
-def test_ragged_clustered_parity(sph, ragged, ti, k, bits, pers):
+@pytest.mark.parametrize("ti,k,bits,sched", [(64, 4, 0, None), (32, 8, 0, None),
+                                             (128, 2, 0, None), (64, 2, 0, None),
+                                             (64, 1, 0, None), (64, 4, 2, "dynamic"),
+                                             (32, 8, 3, "static"), (16, 16, 2, "grid"),
+                                             (128, 2, 1, "dynamic"), (64, 1, 3, "grid"),
+                                             (64, 4, 1, "static"), (32, 8, 2, "grid")])
+def test_ragged_clustered_parity(sph, ragged, ti, k, bits, sched):
     ps, ref, n_c, nd, nf, d, f = ragged
-    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k), sub_bits=bits, persistent=pers)
+    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k), sub_bits=bits, sched=sched)
     assert pipe.status() == 0
     counts = np.diff(pipe.cells.cell_start.cpu().numpy())
     assert counts.min() == 0 and counts.max() > 2 * ti
@@ -243,7 +295,7 @@ def test_ragged_clustered_parity(sph, ragged, ti, k, bits, pers):
     got["h"] = ref.h
     assert np.array_equal(got["nngb"], nd)
     assert np.array_equal(got["nforce"], nf)
-    check_fp32(got, d, f, tag=f"clustered/{ti}x{k}/sub{bits}/{'persistent' if pers else 'cells'}")
+    check_fp32(got, d, f, tag=f"clustered/{ti}x{k}/sub{bits}/{sched or 'cells'}")
 
 
 def test_perfect_lattice_closed_form_gpu(sph, orc):
@@ -293,7 +345,8 @@ def test_reduced_precision(sph, orc, pos, vel, mhu, scales):
 # AoS == SoA, determinism, kick/drift, reductions, edge cases
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("mode", [{}, {"sub_bits": 2, "persistent": True}])
+@pytest.mark.parametrize("mode", [{}, {"sub_bits": 2, "sched": "dynamic"},
+                                  {"sub_bits": 1, "sched": ("grid", "static")}])
 def test_aos_equals_soa_bitwise(sph, mode):
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.clustered_set(20000, 9, f_blob=0.4, sigma=0.05)
@@ -310,7 +363,7 @@ def test_aos_equals_soa_bitwise(sph, mode):
         assert np.ascontiguousarray(ra[k]).tobytes() == np.ascontiguousarray(rb[k]).tobytes(), k
 
 
-@pytest.mark.parametrize("mode", [{}, {"sub_bits": 1, "persistent": True}])
+@pytest.mark.parametrize("mode", [{}, {"sub_bits": 1, "sched": "dynamic"}])
 def test_deterministic(sph, mode):
     ps = inputs.clustered_set(30000, 4, f_blob=0.5, sigma=0.05)
     n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
