@@ -6,13 +6,16 @@ box (seeded), FP32 AoS records of 128 bytes (FP64 positions), resident in HBM.
 One step = bin -> AoS->SoA convert (GPU) -> density -> force -> FP64
 reductions -> kick/drift -> SoA->AoS writeback, all through the C ABI on one
 stream. The headline value is in-support pair interactions (density pairs
-incl. self + force pairs) per second over whole steps.
+incl. self + force pairs) per second over whole steps. The pair loops' tiling
+(sub-cell depth, tile, schedule) is chosen by the autotuner before timing.
 
 Beside it: per-kernel times (HIP events on the launch stream), HBM GB/s of
 convert / kick-drift / writeback at algorithmic bytes, the plain-AoS step and
 the reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) on the same
-particles, the host-side convert variant, and the FP64 CPU oracle timed on a
-bounded sample (rank 0, N = 1).
+particles, the host-side convert variant, the clustered 4,194,304-particle
+set (occupancy 1..~2,000 per cell) with its own tuned tiling in FP32 and
+FP16 storage, and the FP64 CPU oracle timed on a bounded sample (rank 0,
+N = 1).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -104,6 +107,46 @@ def cpu_baseline(ps):
                       f"({t2 - t1:.2f} s)"}
 
 
+def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
+    """Clustered 4,194,304-particle set: tuned tiling, whole FP32 SoA steps
+    and FP16-store steps (FP16 offsets, BF16 v, FP16 m/h/u)."""
+    log("generating the clustered 4M set")
+    ps = inputs.clustered_k_set(3)
+    n_c = int(np.floor(1.0 / (sphmi.params().gamma_k * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    n = ps.n
+    del ps
+    steps = max(1, min(args.steps, 10))
+    warm = max(1, min(args.warmup, 2))
+    out = {"workload": f"clustered: {n} particles, 37% in 8 Gaussian blobs (sigma 0.03) over "
+                       f"a uniform background, n_c = {n_c}", "particles": n, "n_c": n_c,
+           "steps": steps}
+    for name, prec in (("fp32", sphmi.precision()),
+                       ("fp16_store", sphmi.precision("f16", "bf16", "f16", scale_m=22,
+                                                      scale_h=7, scale_u=0))):
+        log(f"clustered {name}: autotuning")
+        sub = (0, 1, 2) if name == "fp32" else (out["fp32"]["sub_bits"],)
+        ch = tune.tune(rec, n_c, prec=prec, sub_bits=sub, reps=2, cache_path=None, log=log)
+        pipe = Pipeline(rec, n_c, prec=prec, **tune.pipeline_kwargs(ch))
+        log(f"clustered {name}: steps")
+        secs, per = timed_steps(torch, pipe, "soa", steps, warm)
+        red = pipe.red_out.cpu().numpy()
+        pd, pf = float(red[6]), float(red[7])
+        occ = np.diff(pipe.cells.cell_start.cpu().numpy())
+        out[name] = {"tiling": tune.describe(ch), "sub_bits": ch["sub_bits"],
+                     "ms_per_step": 1e3 * secs / steps,
+                     "value": (pd + pf) * steps / secs, "unit": "pair-interactions/s",
+                     "pair_loops_pairs_per_s": (pd + pf) / ((per["density"] + per["force"]) * 1e-3),
+                     "pairs_per_step": {"density": pd, "force": pf},
+                     "kernels_ms": {k: round(v, 4) for k, v in per.items()},
+                     "status_flags": pipe.status()}
+        out["occupancy"] = {"min": int(occ.min()), "max": int(occ.max()),
+                            "p50": float(np.median(occ)), "p99": float(np.percentile(occ, 99))}
+        del pipe
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +155,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="time only the FP32 SoA step (profiling runs)")
+    ap.add_argument("--no-clustered", action="store_true",
+                    help="skip the clustered 4M-particle variant")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -123,7 +168,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2512_05516_amd import inputs, sphmi
+    from paper_2512_05516_amd import inputs, sphmi, tune
     from paper_2512_05516_amd.pipeline import Pipeline
 
     if not torch.cuda.is_available():
@@ -136,9 +181,15 @@ def main():
     rec = inputs.pack_aos(ps, "f32")
     n = ps.n
 
+    # ---- tiling chosen by the autotuner (outside the timed region) ------------
+    log("autotuning the pair loops")
+    choice = tune.tune(rec, N_C, reps=3, cache_path=None, log=log)
+    kw = tune.pipeline_kwargs(choice)
+    log("chosen:", tune.describe(choice))
+
     # ---- headline: FP32 SoA step, GPU-side convert ---------------------------
     log("FP32 SoA step")
-    pipe = Pipeline(rec, N_C)
+    pipe = Pipeline(rec, N_C, **kw)
     secs, per = timed_steps(torch, pipe, "soa", args.steps, args.warmup)
     red = pipe.red_out.cpu().numpy()
     pairs_d, pairs_f = float(red[6]), float(red[7])
@@ -169,7 +220,7 @@ def main():
                                "(128 B, FP64 x) resident in HBM, GPU-side AoS->SoA convert",
                    "particles": n, "n_c": N_C, "cells": N_C ** 3, "dt": DT,
                    "step": "bin+convert+density+force+reduce+kick_drift+writeback",
-                   "tile": "64x4"},
+                   "tiling": tune.describe(choice)},
         "roofline": roofline,
         "pairs_per_step": {"density": pairs_d, "force": pairs_f},
         "kernels_ms": {k: round(v, 4) for k, v in per.items()},
@@ -177,6 +228,10 @@ def main():
         "hbm_gbs": hbm,
         "hbm_frac": {k: round(v / PEAK_HBM_GBS, 4) for k, v in hbm.items()},
         "status_flags": status,
+        "autotune": {"choice": tune.describe(choice),
+                     "density_ms": round(choice["density"]["ms"], 4),
+                     "force_ms": round(choice["force"]["ms"], 4),
+                     "candidates_timed": len(choice["table"])},
     }
     del pipe
     torch.cuda.empty_cache()
@@ -184,13 +239,13 @@ def main():
     if not args.no_variants:
         # ---- plain AoS step (Eq. gpu_native) ---------------------------------
         log("plain AoS step")
-        pa = Pipeline(rec, N_C)
+        pa = Pipeline(rec, N_C, **kw)
         s_aos, per_aos = timed_steps(torch, pa, "aos", args.steps, args.warmup)
         del pa
         # ---- reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) -----
         log("FP16-store SoA step")
         prec = sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
-        pr = Pipeline(rec, N_C, prec=prec)
+        pr = Pipeline(rec, N_C, prec=prec, **kw)
         s_r, per_r = timed_steps(torch, pr, "soa", args.steps, args.warmup)
         del pr
         torch.cuda.empty_cache()
@@ -239,6 +294,9 @@ def main():
         result["convert_placement"] = variants
         del ph, staging
         torch.cuda.empty_cache()
+
+    if not args.no_clustered:
+        result["clustered"] = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)
 
     if args.copy_probe_mib:
         log("device copy probe")

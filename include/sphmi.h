@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 2
+#define SPH_ABI_VERSION 3
 
 typedef int32_t sph_status;
 enum {
@@ -233,9 +233,11 @@ sph_status sph_convert(const void *aos, const sph_aos_layout *layout, const sph_
  * host AoS (aos_host, n records) with nthreads OpenMP threads and gathers
  * the view into pinned host staging (staging_host, at least
  * sph_host_staging_size bytes, allocated with hipHostMalloc), then copies
- * the cell list and the view to the device buffers of cells / out on
- * stream. Returns after the copies are enqueued; staging must stay alive
- * until the stream reaches them. */
+ * the cell list (cell_start, perm, cell and, when non-NULL, hmax with the
+ * definition of sph_bin) and the view to the device buffers of cells / out
+ * on stream. Returns after the copies are enqueued; staging must stay alive
+ * until the stream reaches them. Sub-cell order is built by sph_bin only:
+ * cells->sub_bits must be 0 (else SPH_E_UNSUPPORTED). */
 sph_status sph_host_staging_size(int32_t n, int32_t n_c, int32_t view,
                                  const sph_precision *prec, size_t *bytes);
 sph_status sph_convert_host(const void *aos_host, const sph_aos_layout *layout,
@@ -325,6 +327,38 @@ sph_status sph_force_aos(void *aos, const sph_aos_layout *layout, const sph_cell
 sph_status sph_kick_drift_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
                               double dt_kick, double dt_drift, int32_t *moved,
                               hipStream_t stream);
+
+/* Autotuner of the pair loops' cell-to-workgroup tiling (the batched
+ * launch over cells of uneven occupancy). One candidate is a tile and a
+ * schedule: sched = -1 launches one workgroup per cell (no work list),
+ * otherwise the work list is built for the tile's ti and taken with that
+ * SPH_SCHED_* schedule. */
+typedef struct {
+  sph_tile tile;
+  int32_t sched;          /* -1 or SPH_SCHED_*                              */
+  float ms;               /* out: mean time of one launch; -1 if skipped    */
+} sph_tune_entry;
+
+/* The default candidate set: every supported tile with each schedule.
+ * Writes min(count, max) entries to out (may be NULL when max = 0) and the
+ * full count to *count. */
+sph_status sph_tune_candidates(sph_tune_entry *out, int32_t max, int32_t *count);
+
+/* Times `reps` launches (after one untimed launch) of sph_density
+ * (loop = 0) or sph_force (loop = 1) for each of cand[0..ncand) on the
+ * caller's SoA and cell list, with HIP events on `stream`, and stores the
+ * mean launch time in cand[i].ms. Candidates whose work list needs more
+ * than work_bytes get ms = -1. *best = index of the fastest. The loop's
+ * outputs are written as by a normal call, by the last candidate timed;
+ * different tiles sum in different orders, so rerun the loop with the
+ * chosen candidate where bit-reproducible outputs matter. sph_force reads
+ * the density outputs: run the density loop first. Blocking: returns after
+ * the stream has drained. work_buf (device, work_bytes) holds each
+ * candidate's work list in turn and may be NULL when no candidate uses one. */
+sph_status sph_autotune(int32_t loop, const sph_soa *soa, const sph_precision *prec,
+                        const sph_cells *cells, const sph_params *params,
+                        sph_tune_entry *cand, int32_t ncand, int32_t reps, void *work_buf,
+                        size_t work_bytes, int32_t *best, hipStream_t stream);
 
 /* hipStreamSynchronize with the error mapped to sph_status */
 sph_status sph_sync(hipStream_t stream);

@@ -69,16 +69,17 @@ def lib():
         L.orc_dWdh.restype = C.c_double
         L.orc_dWdh.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_bin.argtypes = [C.c_int, d, C.c_int, i32, i32, i32, d]
+        u8 = C.POINTER(C.c_uint8)
         L.orc_density.argtypes = [C.c_int, d, d, d, d, C.POINTER(Params), C.c_int, C.c_int,
-                                  i32, C.c_int, d, d, d, d, d, d, i32]
+                                  i32, C.c_int, u8, d, d, d, d, d, d, i32]
         L.orc_force.argtypes = [C.c_int, d, d, d, d, d, d, d, d, C.POINTER(Params), C.c_int,
-                                C.c_int, i32, C.c_int, d, d, d, i32]
+                                C.c_int, i32, C.c_int, u8, d, d, d, i32]
         L.orc_kick_drift.argtypes = [C.c_int, d, d, d, d, d, C.c_double, C.c_double]
         L.orc_kick_drift.restype = None
         L.orc_reduce.argtypes = [C.c_int, d, d, d, d, d]
         L.orc_reduce.restype = None
         L.orc_count32.argtypes = [C.c_int, d, d, C.c_int, C.c_double, C.c_int, C.c_int,
-                                  C.c_int, C.c_int, i32, i32]
+                                  C.c_int, C.c_int, C.POINTER(C.c_uint8), i32, i32]
         L.orc_f32_to_f16.restype = C.c_uint16
         L.orc_f32_to_f16.argtypes = [C.c_float]
         L.orc_f16_to_f32.restype = C.c_float
@@ -157,8 +158,14 @@ def bin_sub(x, n_c, sub_bits):
     return key, start, perm
 
 
-def density(ps, prm=None, mode="cells", n_c=None, sel=None):
-    """FP64 density loop. Returns a dict of arrays (length N, or len(sel))."""
+def _mask(jmask):
+    return None if jmask is None else np.ascontiguousarray(jmask, dtype=np.uint8)
+
+
+def density(ps, prm=None, mode="cells", n_c=None, sel=None, jmask=None):
+    """FP64 density loop. Returns a dict of arrays (length N, or len(sel)).
+    jmask (bool per particle) restricts the neighbours j to a subset: the
+    sums over one cell pair, as a serving task computes them."""
     prm = prm or params()
     x, m, h, u = _f64(ps.x), _f64(ps.m), _f64(ps.h), _f64(ps.u)
     n = x.shape[0]
@@ -170,7 +177,7 @@ def density(ps, prm=None, mode="cells", n_c=None, sel=None):
     md = 0 if mode == "brute" else 1
     rc = lib().orc_density(n, _p(x, C.c_double), _p(m, C.c_double), _p(h, C.c_double),
                            _p(u, C.c_double), C.byref(prm), md, int(n_c or 0),
-                           _p(sel, C.c_int32), cnt,
+                           _p(sel, C.c_int32), cnt, _p(_mask(jmask), C.c_uint8),
                            *[_p(out[k], C.c_double) for k in ("rho", "wcount", "rho_dh", "f",
                                                                "P", "c")],
                            _p(out["nngb"], C.c_int32))
@@ -179,8 +186,9 @@ def density(ps, prm=None, mode="cells", n_c=None, sel=None):
     return out
 
 
-def force(ps, dens, prm=None, mode="cells", n_c=None, sel=None):
-    """FP64 force loop; ``dens`` holds rho, f, P, c over all particles."""
+def force(ps, dens, prm=None, mode="cells", n_c=None, sel=None, jmask=None):
+    """FP64 force loop; ``dens`` holds rho, f, P, c over all particles.
+    jmask as for density()."""
     prm = prm or params()
     x, v, m, h = _f64(ps.x), _f64(ps.v), _f64(ps.m), _f64(ps.h)
     n = x.shape[0]
@@ -195,7 +203,8 @@ def force(ps, dens, prm=None, mode="cells", n_c=None, sel=None):
     md = 0 if mode == "brute" else 1
     rc = lib().orc_force(n, _p(x, C.c_double), _p(v, C.c_double), _p(m, C.c_double),
                          _p(h, C.c_double), *[_p(t, C.c_double) for t in arr], C.byref(prm),
-                         md, int(n_c or 0), _p(sel, C.c_int32), cnt, _p(a, C.c_double),
+                         md, int(n_c or 0), _p(sel, C.c_int32), cnt, _p(_mask(jmask), C.c_uint8),
+                         _p(a, C.c_double),
                          _p(du, C.c_double), _p(vsig, C.c_double), _p(nf, C.c_int32))
     if rc != 0:
         raise ValueError(f"orc_force failed ({rc})")
@@ -218,15 +227,18 @@ def reduce(m, v, a, du):
     return out
 
 
-def count32(ps, n_c, pos="f32", hdt="f32", h_scale=0, mode="cells", gamma_k=GAMMA_K):
-    """Neighbour counts with the support test in FP32 -> (n_density, n_force)."""
+def count32(ps, n_c, pos="f32", hdt="f32", h_scale=0, mode="cells", gamma_k=GAMMA_K,
+            jmask=None):
+    """Neighbour counts with the support test in FP32 -> (n_density, n_force);
+    jmask restricts j as for density()."""
     x, h = _f64(ps.x), _f64(ps.h)
     n = x.shape[0]
     nd = np.empty(n, np.int32)
     nf = np.empty(n, np.int32)
     rc = lib().orc_count32(n, _p(x, C.c_double), _p(h, C.c_double), int(n_c), float(gamma_k),
                            DTYPE_CODES[pos], DTYPE_CODES[hdt], int(h_scale),
-                           0 if mode == "brute" else 1, _p(nd, C.c_int32), _p(nf, C.c_int32))
+                           0 if mode == "brute" else 1, _p(_mask(jmask), C.c_uint8),
+                           _p(nd, C.c_int32), _p(nf, C.c_int32))
     assert rc == 0
     return nd, nf
 
@@ -265,3 +277,26 @@ def dequantise_set(ps, n_c, pos="f32", vel="f32", mhu="f32", scales=(0, 0, 0)):
                              _p(xq, C.c_double), _p(vq, C.c_double), _p(mq, C.c_double),
                              _p(hq, C.c_double), _p(uq, C.c_double))
     return ParticleSet(xq, vq, mq, hq, uq, ps.name + "_dq")
+
+
+def task_partials(ps, n_c, tasks, dens, prm=None, perm=None, cell=None):
+    """Partial sums of serving tasks (one cell pair each): for task
+    (kind, ci, cj, i_begin, i_end) the density (kind 0) or force (kind 1)
+    sums over i = perm[i_begin:i_end] (sorted-slot order of the cell list)
+    and j restricted to cell cj, evaluated by density()/force() with that j
+    subset. dens: full density outputs (rho, f, P, c) over all particles.
+    Returns a list of dicts, one per task."""
+    if perm is None or cell is None:
+        cell, _, perm, _ = bin_cells(ps.x, n_c)
+    out = []
+    for (kind, ci, cj, ib, ie) in tasks:
+        sel = perm[ib:ie]
+        jm = cell == cj
+        if kind == 0:
+            d = density(ps, prm, n_c=n_c, sel=sel, jmask=jm)
+            out.append({"rho": d["rho"], "wcount": d["wcount"], "rho_dh": d["rho_dh"],
+                        "count": d["nngb"]})
+        else:
+            f = force(ps, dens, prm, n_c=n_c, sel=sel, jmask=jm)
+            out.append({"a": f["a"], "du": f["du"], "vsig": f["vsig"], "count": f["nforce"]})
+    return out

@@ -232,14 +232,18 @@ static void grid_free(cellgrid *g) {
 
 /* kind 0: density list {j : r_ij < H_i}, self included.
  * kind 1: force list {j != i : r_ij < max(H_i, H_j)}.
+ * jmask (NULL: every j) restricts j to the particles with jmask[j] != 0, so
+ * a sum over a subset of pairs (one cell pair) is the same expression.
  * The list comes back sorted by ascending j. */
 static void neighbours(int kind, int i, int n, const double *x, const double *h,
-                       double gamma_k, int mode, const cellgrid *g, nlist *out) {
+                       double gamma_k, int mode, const cellgrid *g,
+                       const uint8_t *jmask, nlist *out) {
   out->n = 0;
   double Hi = gamma_k * h[i];
   double d[3];
   if (mode == 0) {
     for (int j = 0; j < n; ++j) {
+      if (jmask && !jmask[j]) continue;
       double r2 = sep2(x, i, j, d);
       double r = sqrt(r2);
       if (kind == 0) {
@@ -261,6 +265,7 @@ static void neighbours(int kind, int i, int n, const double *x, const double *h,
           int cn = nx + n_c * (ny + n_c * nz);
           for (int t = g->start[cn]; t < g->start[cn + 1]; ++t) {
             int j = g->perm[t];
+            if (jmask && !jmask[j]) continue;
             double r2 = sep2(x, i, j, d);
             double r = sqrt(r2);
             if (kind == 0) {
@@ -291,8 +296,9 @@ static int grid_ok(int n, const double *h, double gamma_k, int n_c) {
 
 int orc_density(int n, const double *x, const double *m, const double *h,
                 const double *u, const orc_params *p, int mode, int n_c,
-                const int32_t *sel, int nsel, double *rho, double *wcount,
-                double *rho_dh, double *f, double *P, double *c, int32_t *nngb) {
+                const int32_t *sel, int nsel, const uint8_t *jmask, double *rho,
+                double *wcount, double *rho_dh, double *f, double *P, double *c,
+                int32_t *nngb) {
   cellgrid g;
   memset(&g, 0, sizeof g);
   if (mode == 1) {
@@ -306,7 +312,7 @@ int orc_density(int n, const double *x, const double *m, const double *h,
 #pragma omp for schedule(dynamic, 64)
     for (int s = 0; s < cnt; ++s) {
       int i = sel ? sel[s] : s;
-      neighbours(0, i, n, x, h, p->gamma_k, mode, &g, &l);
+      neighbours(0, i, n, x, h, p->gamma_k, mode, &g, jmask, &l);
       double rho_i = 0.0, S = 0.0, dh = 0.0, d[3];
       for (int t = 0; t < l.n; ++t) {
         int j = l.idx[t];
@@ -346,8 +352,8 @@ int orc_density(int n, const double *x, const double *m, const double *h,
 int orc_force(int n, const double *x, const double *v, const double *m,
               const double *h, const double *rho, const double *f,
               const double *P, const double *c, const orc_params *p, int mode,
-              int n_c, const int32_t *sel, int nsel, double *a, double *du,
-              double *vsig, int32_t *nforce) {
+              int n_c, const int32_t *sel, int nsel, const uint8_t *jmask, double *a,
+              double *du, double *vsig, int32_t *nforce) {
   cellgrid g;
   memset(&g, 0, sizeof g);
   if (mode == 1) {
@@ -361,7 +367,7 @@ int orc_force(int n, const double *x, const double *v, const double *m,
 #pragma omp for schedule(dynamic, 64)
     for (int s = 0; s < cnt; ++s) {
       int i = sel ? sel[s] : s;
-      neighbours(1, i, n, x, h, p->gamma_k, mode, &g, &l);
+      neighbours(1, i, n, x, h, p->gamma_k, mode, &g, jmask, &l);
       double ai[3] = {0.0, 0.0, 0.0}, dui = 0.0, vs = 0.0, d[3];
       double fi = p->gradh ? f[i] : 1.0;
       double Ai = fi * P[i] / (rho[i] * rho[i]);
@@ -569,7 +575,7 @@ int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
 
 int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
                 int pos_dtype, int h_dtype, int h_scale, int mode,
-                int32_t *nd, int32_t *nf) {
+                const uint8_t *jmask, int32_t *nd, int32_t *nf) {
   if (n_c < 3) return -1;
   cellgrid g;
   double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
@@ -603,6 +609,7 @@ int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k
           for (int t = lo; t < hi; ++t) {
             int j = (mode == 1) ? g.perm[t] : t;
             if (mode == 0 && g.cell[j] != cn) continue;
+            if (jmask && !jmask[j]) continue;
             float dd[3];
             for (int k = 0; k < 3; ++k) {
               float xr = o32[3 * j + k] + sh[k];

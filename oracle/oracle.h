@@ -55,14 +55,15 @@ int orc_bin_sub(int n, const double *x, int n_c, int sub_bits, int32_t *key,
  * sel (nsel entries) selects which i to evaluate; sel == NULL means all. */
 int orc_density(int n, const double *x, const double *m, const double *h,
                 const double *u, const orc_params *p, int mode, int n_c,
-                const int32_t *sel, int nsel, double *rho, double *wcount,
-                double *rho_dh, double *f, double *P, double *c, int32_t *nngb);
+                const int32_t *sel, int nsel, const uint8_t *jmask, double *rho,
+                double *wcount, double *rho_dh, double *f, double *P, double *c,
+                int32_t *nngb);
 
 int orc_force(int n, const double *x, const double *v, const double *m,
               const double *h, const double *rho, const double *f,
               const double *P, const double *c, const orc_params *p, int mode,
-              int n_c, const int32_t *sel, int nsel, double *a, double *du,
-              double *vsig, int32_t *nforce);
+              int n_c, const int32_t *sel, int nsel, const uint8_t *jmask, double *a,
+              double *du, double *vsig, int32_t *nforce);
 
 void orc_kick_drift(int n, double *x, double *v, double *u, const double *a,
                     const double *du, double dt_kick, double dt_drift);
@@ -75,7 +76,7 @@ void orc_reduce(int n, const double *m, const double *v, const double *a,
 /* neighbour counts with the support test taken in FP32, as the GPU takes it */
 int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
                 int pos_dtype, int h_dtype, int h_scale, int mode,
-                int32_t *nd, int32_t *nf);
+                const uint8_t *jmask, int32_t *nd, int32_t *nf);
 
 /* quantisers (RNE), FP32 -> {FP16, BF16} bits and back */
 uint16_t orc_f32_to_f16(float v);

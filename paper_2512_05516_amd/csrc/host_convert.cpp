@@ -27,7 +27,7 @@ size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 int esz(int dt) { return (dt == SPH_F32) ? 4 : 2; }
 
 struct Plan {
-  size_t off_start, off_perm, off_cell;
+  size_t off_start, off_perm, off_cell, off_hmax;
   size_t off_pos[3], off_vq[3], off_m, off_h, off_u, off_x[3], off_v[3], off_uk;
   size_t total;
   bool pair, kick, vq, u;
@@ -49,6 +49,7 @@ Plan plan(int n, int n_c, int view, const sph_precision& p) {
   pl.off_start = take(4 * (C + 1));
   pl.off_perm = take(4 * (size_t)n);
   pl.off_cell = take(4 * (size_t)n);
+  pl.off_hmax = take(4 * (size_t)C);
   for (int a = 0; a < 3; ++a) {
     pl.off_pos[a] = pl.pair ? take((size_t)n * esz(p.pos)) : 0;
     pl.off_vq[a] = pl.vq ? take((size_t)n * esz(p.vel)) : 0;
@@ -136,6 +137,9 @@ sph_status sph_convert_host(const void* aos_host, const sph_aos_layout* layout,
   if (n > 0 && !aos_host) return host_fail(SPH_E_INVALID, "sph_convert_host: aos_host is NULL");
   if (!cells->cell_start || !cells->perm || !cells->cell)
     return host_fail(SPH_E_INVALID, "sph_convert_host: cell list pointers are NULL");
+  if (cells->sub_bits != 0)
+    return host_fail(SPH_E_UNSUPPORTED,
+                     "sph_convert_host: sub-cell order (sub_bits > 0) is built by sph_bin only");
   const int fmt[3] = {prec->pos, prec->vel, prec->mhu};
   for (int f : fmt)
     if (f != SPH_F32 && f != SPH_F16 && f != SPH_BF16)
@@ -169,9 +173,13 @@ sph_status sph_convert_host(const void* aos_host, const sph_aos_layout* layout,
 
   // 1. cell ids (FP64, same definition as the device binning) and
   //    per-thread histograms over contiguous input ranges
+  //    and per-thread largest h of each cell (h as stored, read as FP32;
+  //    positive values only, 0 for a cell without any)
   const int T = (n < 4096) ? 1 : nthreads;
+  const bool want_hmax = cells->hmax != nullptr && L.offset[SPH_A_H] != SPH_ABSENT;
   std::vector<int32_t> cid((size_t)std::max(n, 1));
   std::vector<int32_t> hist((size_t)T * C, 0);
+  std::vector<float> hm(want_hmax ? (size_t)T * C : 0, 0.0f);
   parallel_for(T, n, [&](int t, int64_t lo, int64_t hi) {
     int32_t* h = hist.data() + (size_t)t * C;
     for (int64_t i = lo; i < hi; ++i) {
@@ -184,8 +192,21 @@ sph_status sph_convert_host(const void* aos_host, const sph_aos_layout* layout,
       int c = c3[0] + n_c * (c3[1] + n_c * c3[2]);
       cid[(size_t)i] = c;
       h[c]++;
+      if (want_hmax) {
+        const float hv = (float)rec_d(rec, L.offset[SPH_A_H], L.dtype[SPH_A_H]);
+        float& m = hm[(size_t)t * C + c];
+        if (hv > 0.0f && hv > m) m = hv;
+      }
     }
   });
+  float* hmax = reinterpret_cast<float*>(st + pl.off_hmax);
+  if (want_hmax) {
+    for (int c = 0; c < C; ++c) {
+      float m = 0.0f;
+      for (int t = 0; t < T; ++t) m = std::max(m, hm[(size_t)t * C + c]);
+      hmax[c] = m;
+    }
+  }
   // 2. stable positions: cell-major, then thread (input range) order
   int32_t run = 0;
   for (int c = 0; c < C; ++c) {
@@ -251,6 +272,7 @@ sph_status sph_convert_host(const void* aos_host, const sph_aos_layout* layout,
   std::vector<Cp> cps = {{cells->cell_start, pl.off_start, 4 * ((size_t)C + 1)},
                          {cells->perm, pl.off_perm, 4 * (size_t)n},
                          {cells->cell, pl.off_cell, 4 * (size_t)n}};
+  if (want_hmax) cps.push_back({cells->hmax, pl.off_hmax, 4 * (size_t)C});
   for (int a = 0; a < 3; ++a) {
     if (pl.pair) cps.push_back({out->f[SPH_S_OFF_X + a], pl.off_pos[a], (size_t)n * esz(prec->pos)});
     if (pl.vq) cps.push_back({out->f[SPH_S_VQ_X + a], pl.off_vq[a], (size_t)n * esz(prec->vel)});

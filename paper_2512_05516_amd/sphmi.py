@@ -78,12 +78,16 @@ class Tile(C.Structure):
     _fields_ = [("ti", C.c_int32), ("k", C.c_int32)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("tile", Tile), ("sched", C.c_int32), ("ms", C.c_float)]
+
+
 EXPORTS = [
     "sph_abi_version", "sph_last_error", "sph_tile_supported", "sph_bin_workspace_size",
     "sph_bin", "sph_convert", "sph_host_staging_size", "sph_convert_host", "sph_writeback",
     "sph_density", "sph_force", "sph_kick_drift", "sph_reduce_workspace_size", "sph_reduce",
     "sph_density_aos", "sph_force_aos", "sph_kick_drift_aos", "sph_sync", "sph_worklist_size",
-    "sph_worklist",
+    "sph_worklist", "sph_tune_candidates", "sph_autotune",
 ]
 
 _lib = None
@@ -122,6 +126,9 @@ def lib():
     L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
     L.sph_sync.argtypes = [vp]
+    L.sph_tune_candidates.argtypes = [P(TuneEntry), i32, P(i32)]
+    L.sph_autotune.argtypes = [i32, P(Soa), P(Precision), P(Cells), P(Params), P(TuneEntry), i32,
+                               i32, vp, sz, P(i32), vp]
     for name in EXPORTS[3:]:
         getattr(L, name).restype = st
     _lib = L
@@ -348,6 +355,40 @@ def force(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None, w
     _check(lib().sph_force(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
                            C.byref(prm or params()), til or Tile(0, 0), _wk(work),
                            _stream(stream)))
+
+
+SCHED_NAMES = {-1: None, 0: "grid", 1: "static", 2: "dynamic"}
+
+
+def tune_candidates():
+    """The library's default candidate set: [(ti, k, sched), ...] with sched
+    None (one workgroup per cell) or a schedule name."""
+    n = C.c_int32()
+    _check(lib().sph_tune_candidates(None, 0, C.byref(n)))
+    arr = (TuneEntry * n.value)()
+    _check(lib().sph_tune_candidates(arr, n.value, C.byref(n)))
+    return [(e.tile.ti, e.tile.k, SCHED_NAMES[e.sched]) for e in arr]
+
+
+def autotune(loop: str, soa: "DeviceSoa", cells: "DeviceCells", prm=None, cand=None, reps=3,
+             work_buf=None, stream=None):
+    """Time each candidate (ti, k, sched) of the density or force loop
+    ('density' / 'force') through sph_autotune; returns ([(ti, k, sched, ms)],
+    index of the fastest)."""
+    cand = cand if cand is not None else tune_candidates()
+    arr = (TuneEntry * len(cand))()
+    inv = {v: k for k, v in SCHED_NAMES.items()}
+    for e, (ti, k, sc) in zip(arr, cand):
+        e.tile = Tile(ti, k)
+        e.sched = inv[sc]
+        e.ms = -1.0
+    best = C.c_int32(-1)
+    nbytes = int(work_buf.numel()) if work_buf is not None else 0
+    _check(lib().sph_autotune({"density": 0, "force": 1}[loop], C.byref(soa.struct),
+                              C.byref(soa.prec), C.byref(cells.struct), C.byref(prm or params()),
+                              arr, len(cand), int(reps), _ptr(work_buf), nbytes, C.byref(best),
+                              _stream(stream)))
+    return [(e.tile.ti, e.tile.k, SCHED_NAMES[e.sched], float(e.ms)) for e in arr], best.value
 
 
 def kick_drift(soa: DeviceSoa, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):

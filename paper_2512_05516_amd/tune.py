@@ -1,0 +1,130 @@
+"""Autotuner of the pair loops' cell-to-workgroup tiling.
+
+The batched launch over cells of uneven occupancy has three knobs: the
+sub-cell depth of the cell list (Morton order inside each cell, sub_bits),
+the tile (ti particles per work item, k lanes per particle) and the
+schedule (one workgroup per cell, or a work list taken by the hardware
+grid, a static or a dynamic persistent grid). sph_autotune times every
+(tile, schedule) candidate of one loop on a binned and converted particle
+set; this driver repeats that for each sub-cell depth (which needs a
+re-bin), picks the depth with the smallest density + force time and the
+fastest candidate of each loop, and keeps the result in a JSON cache keyed
+by the workload's signature (particle count, cells, occupancy statistics,
+storage formats, device). The choice changes only timings: every
+candidate computes the same interactions.
+"""
+import json
+import os
+
+import numpy as np
+
+from . import sphmi
+from .pipeline import Pipeline
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "sphmi", "tune.json")
+
+
+def signature(pipe: Pipeline) -> dict:
+    """Workload signature of a binned pipeline: the tuner's cache key."""
+    import torch
+    start = pipe.cells.cell_start.cpu().numpy()
+    occ = np.diff(start)
+    p = pipe.prec
+    return {
+        "abi": sphmi.abi_version(),
+        "device": torch.cuda.get_device_name(),
+        "n": pipe.n, "n_c": pipe.n_c,
+        "occ_max": int(occ.max()) if occ.size else 0,
+        "occ_p50": float(np.median(occ)) if occ.size else 0.0,
+        "occ_p99": float(np.percentile(occ, 99)) if occ.size else 0.0,
+        "formats": [p.pos, p.vel, p.mhu, p.scale_m, p.scale_h, p.scale_u],
+    }
+
+
+def _key(sig: dict) -> str:
+    return json.dumps(sig, sort_keys=True)
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, cache):
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), cand=None,
+         reps: int = 3, cache_path=DEFAULT_CACHE, refresh: bool = False, log=None) -> dict:
+    """Choose sub_bits and each loop's (tile, schedule) for the AoS records
+    `rec` binned with n_c cells per axis. Returns {"sub_bits", "density":
+    {ti, k, sched, ms}, "force": {...}, "table": [...], "signature", "cached"}."""
+    import torch
+    first = Pipeline(rec, n_c, prec=prec, prm=prm, sub_bits=sub_bits[0])
+    first.bin()
+    sig = signature(first)
+    sig["sub_bits"] = list(sub_bits)
+    sig["reps"] = reps
+    sig["candidates"] = cand if cand is None else [list(c) for c in cand]
+    cache = _load(cache_path) if cache_path else {}
+    if not refresh and _key(sig) in cache:
+        out = dict(cache[_key(sig)])
+        out["cached"] = True
+        return out
+    cand = cand if cand is not None else sphmi.tune_candidates()
+    tis = sorted({c[0] for c in cand})
+    wbytes = max(sphmi.worklist_size(first.n, n_c, t) for t in tis)
+    wbuf = torch.empty(wbytes, dtype=torch.uint8, device=first.aos.device)
+    table, best = [], None
+    for sb in sub_bits:
+        pipe = first if sb == sub_bits[0] else Pipeline(rec, n_c, prec=prec, prm=prm, sub_bits=sb)
+        pipe.bin()
+        pipe.convert("full")
+        dres, di = sphmi.autotune("density", pipe.soa, pipe.cells, pipe.prm, cand, reps, wbuf)
+        fres, fi = sphmi.autotune("force", pipe.soa, pipe.cells, pipe.prm, cand, reps, wbuf)
+        for loop, res in (("density", dres), ("force", fres)):
+            table += [{"sub_bits": sb, "loop": loop, "ti": t, "k": k, "sched": s, "ms": ms}
+                      for (t, k, s, ms) in res]
+        d, f = dres[di], fres[fi]
+        tot = d[3] + f[3]
+        if log:
+            log(f"tune sub_bits={sb}: density {d[0]}x{d[1]} {d[2]} {d[3]:.3f} ms, "
+                f"force {f[0]}x{f[1]} {f[2]} {f[3]:.3f} ms")
+        if best is None or tot < best[0]:
+            best = (tot, sb, d, f)
+        if pipe is not first:
+            del pipe
+    del first, wbuf
+    torch.cuda.empty_cache()
+    _, sb, d, f = best
+    out = {"sub_bits": sb,
+           "density": {"ti": d[0], "k": d[1], "sched": d[2], "ms": d[3]},
+           "force": {"ti": f[0], "k": f[1], "sched": f[2], "ms": f[3]},
+           "table": table, "signature": sig}
+    if cache_path:
+        cache = _load(cache_path)
+        cache[_key(sig)] = out
+        _store(cache_path, cache)
+    out = dict(out)
+    out["cached"] = False
+    return out
+
+
+def pipeline_kwargs(choice: dict) -> dict:
+    """Pipeline keyword arguments that apply a tuner choice."""
+    d, f = choice["density"], choice["force"]
+    return {"sub_bits": choice["sub_bits"], "til": sphmi.tile(d["ti"], d["k"]),
+            "til_force": sphmi.tile(f["ti"], f["k"]), "sched": (d["sched"], f["sched"])}
+
+
+def describe(choice: dict) -> str:
+    d, f = choice["density"], choice["force"]
+    return (f"sub_bits {choice['sub_bits']}; density {d['ti']}x{d['k']} "
+            f"{d['sched'] or 'per-cell'}; force {f['ti']}x{f['k']} {f['sched'] or 'per-cell'}")

@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 2
+    assert sph.abi_version() == 3
     assert sph.tile_supported(64, 4)
     assert not sph.tile_supported(48, 3)
 
@@ -135,6 +135,50 @@ def test_host_side_validation(sph):
     big_scale = sph.precision("f16", "f16", "f16", scale_m=100)
     assert L.sph_reduce(C.byref(soa), C.byref(big_scale), C.byref(cells), C.c_void_p(0x5000),
                         C.c_void_p(0x6000), 1 << 20, None) == sph.SPH_E_INVALID
+
+
+def test_tuner_host_side(sph):
+    L = sph.lib()
+    cand = sph.tune_candidates()
+    assert len(cand) == 24
+    assert len(set(cand)) == 24
+    assert {c[2] for c in cand} == {None, "grid", "static", "dynamic"}
+    assert all(sph.tile_supported(t, k) for t, k, _ in cand)
+    n = C.c_int32()
+    assert L.sph_tune_candidates(None, 5, C.byref(n)) == sph.SPH_E_INVALID
+    assert L.sph_tune_candidates(None, 0, None) == sph.SPH_E_INVALID
+    cells = _fake_cells(sph)
+    soa = sph.Soa()
+    arr = (sph.TuneEntry * 2)()
+    arr[0].tile = sph.Tile(64, 4)
+    arr[1].tile = sph.Tile(32, 8)
+    best = C.c_int32()
+    args = lambda loop, a, nc, reps: L.sph_autotune(loop, C.byref(soa), C.byref(sph.precision()),
+                                                  C.byref(cells), C.byref(sph.params()), a, nc,
+                                                  reps, None, 0, C.byref(best), None)
+    assert args(2, arr, 2, 3) == sph.SPH_E_INVALID
+    assert args(0, arr, 0, 3) == sph.SPH_E_INVALID
+    assert args(0, arr, 2, 0) == sph.SPH_E_INVALID
+    arr[1].sched = 3
+    assert args(1, arr, 2, 3) == sph.SPH_E_INVALID
+    arr[1].sched = 0
+    arr[1].tile = sph.Tile(48, 3)
+    assert args(0, arr, 2, 3) == sph.SPH_E_UNSUPPORTED
+
+
+def test_host_convert_rejects_sub_cells(sph):
+    import numpy as np
+    L = sph.lib()
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    rec = np.zeros(16, dtype=inputs.AOS_F32)
+    cells = _fake_cells(sph, 16, 4, sub_bits=1)
+    soa = sph.Soa()
+    buf = np.zeros(1 << 16, np.uint8)
+    st = L.sph_convert_host(C.c_void_p(rec.ctypes.data), C.byref(lay), C.byref(cells), 3,
+                            C.byref(sph.precision()), C.byref(soa), C.c_void_p(buf.ctypes.data),
+                            buf.size, 1, None)
+    assert st == sph.SPH_E_UNSUPPORTED
+    assert "sub_bits" in sph.last_error()
 
 
 def test_layout_from_numpy(sph):

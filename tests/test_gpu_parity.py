@@ -169,24 +169,40 @@ def test_convert_bit_exact(sph, orc, kind, pos, vel, mhu, scales):
         assert np.array_equal(pipe.soa[name].cpu().numpy(), src.v[operm, a].astype(np.float32))
 
 
-def test_host_convert_matches_device(sph):
+@pytest.mark.parametrize("kind", ["lattice", "clustered"])
+def test_host_convert_matches_device(sph, kind):
+    """Host-side binning + gather gives the device's cell list (hmax
+    included) and SoA bit for bit, and the pair loops after it agree bit
+    for bit with the loops after the device convert."""
     import torch
     from paper_2512_05516_amd.pipeline import Pipeline
-    ps = inputs.small_set(5)
+    if kind == "lattice":
+        ps, n_c = inputs.small_set(5), 4
+    else:
+        ps = inputs.clustered_set(20000, 7, f_blob=0.4, sigma=0.05)
+        n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
     rec = inputs.pack_aos(ps, "f32")
     for prec in (sph.precision(), sph.precision("f16", "bf16", "f16", 12, 3, 0)):
-        dev = Pipeline(rec, 4, prec=prec)
+        dev = Pipeline(rec, n_c, prec=prec)
         dev.bin()
         dev.convert("full")
-        host = Pipeline(rec, 4, prec=prec)
-        nbytes = sph.host_staging_size(ps.n, 4, "full", prec)
+        host = Pipeline(rec, n_c, prec=prec)
+        nbytes = sph.host_staging_size(ps.n, n_c, "full", prec)
         staging = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
         sph.convert_host(rec, host.layout, host.cells, "full", host.soa, staging, nthreads=4)
         torch.cuda.synchronize()
-        for name in ("cell_start", "perm", "cell"):
-            assert torch.equal(getattr(dev.cells, name), getattr(host.cells, name)), name
+        for name in ("cell_start", "perm", "cell", "hmax"):
+            a, b = getattr(dev.cells, name), getattr(host.cells, name)
+            assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
         for name in ("OFF_X", "OFF_Y", "OFF_Z", "VQ_X", "VQ_Y", "VQ_Z", "M", "H", "U",
                      "X_X", "X_Y", "X_Z", "V_X", "V_Y", "V_Z", "UK"):
+            a, b = dev.soa[name], host.soa[name]
+            assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
+        for p in (dev, host):
+            p.density()
+            p.force()
+        torch.cuda.synchronize()
+        for name in ("RHO", "F", "NNGB", "A_X", "A_Y", "A_Z", "DU", "VSIG", "NFORCE"):
             a, b = dev.soa[name], host.soa[name]
             assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
 
@@ -296,6 +312,26 @@ def test_ragged_clustered_parity(sph, ragged, ti, k, bits, sched):
     assert np.array_equal(got["nngb"], nd)
     assert np.array_equal(got["nforce"], nf)
     check_fp32(got, d, f, tag=f"clustered/{ti}x{k}/sub{bits}/{sched or 'cells'}")
+
+
+def test_autotuned_config_parity(sph, ragged, tmp_path):
+    from paper_2512_05516_amd import tune
+    ps, ref, n_c, nd, nf, d, f = ragged
+    rec = inputs.pack_aos(ps, "f32")
+    cache = str(tmp_path / "tune.json")
+    choice = tune.tune(rec, n_c, sub_bits=(0, 2), reps=1, cache_path=cache)
+    assert not choice["cached"]
+    assert len(choice["table"]) == 2 * 2 * len(sph.tune_candidates())
+    assert all(r["ms"] > 0 for r in choice["table"])
+    again = tune.tune(rec, n_c, sub_bits=(0, 2), reps=1, cache_path=cache)
+    assert again["cached"] and again["density"] == choice["density"]
+    pipe = run_gpu(ps, n_c, "f32", **tune.pipeline_kwargs(choice))
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    got["h"] = ref.h
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    check_fp32(got, d, f, tag=f"clustered/tuned/{tune.describe(choice)}")
 
 
 def test_perfect_lattice_closed_form_gpu(sph, orc):

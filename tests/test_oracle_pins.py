@@ -454,3 +454,47 @@ def test_sub_cell_order(orc, n_c, bits):
     # particles of one sub-cell lie inside its box
     side = 1.0 / (n_c * R)
     assert np.all(xw >= (c3 * R + s3) * side - 1e-15)
+
+
+def test_cell_pair_partials_partition_the_full_sums(orc):
+    """Restricting j to one neighbour cell (a serving task) splits each sum:
+    over the 27 cells around i's cell the partial counts add up exactly to
+    the full counts (brute force), and the partial rho, a, du to the full
+    values within FP64 summation rounding; vsig is the max of the partial
+    maxima."""
+    ps = inputs.clustered_set(3000, 11, f_blob=0.4, sigma=0.06)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    assert n_c >= 3
+    dens = orc.density(ps, mode="brute")
+    full_f = orc.force(ps, dens, mode="brute")
+    nd32, nf32 = orc.count32(ps, n_c, mode="brute")
+    cell, start, perm, _ = orc.bin_cells(ps.x, n_c)
+    rng = np.random.default_rng(5)
+    cells = rng.choice(np.nonzero(np.diff(start) > 0)[0], size=6, replace=False)
+    for ci in cells:
+        cx, cy, cz = ci % n_c, (ci // n_c) % n_c, ci // (n_c * n_c)
+        nbr = sorted({((cx + dx) % n_c) + n_c * (((cy + dy) % n_c) + n_c * ((cz + dz) % n_c))
+                      for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)})
+        tasks = [(k, ci, cj, start[ci], start[ci + 1]) for k in (0, 1) for cj in nbr]
+        parts = orc.task_partials(ps, n_c, tasks, dens, perm=perm, cell=cell)
+        idx = perm[start[ci]:start[ci + 1]]
+        dp = [p for t, p in zip(tasks, parts) if t[0] == 0]
+        fp = [p for t, p in zip(tasks, parts) if t[0] == 1]
+        assert np.array_equal(sum(p["count"] for p in dp), dens["nngb"][idx])
+        assert np.array_equal(sum(p["count"] for p in fp), full_f["nforce"][idx])
+        np.testing.assert_allclose(sum(p["rho"] for p in dp), dens["rho"][idx], rtol=1e-13)
+        np.testing.assert_allclose(sum(p["rho_dh"] for p in dp), dens["rho_dh"][idx],
+                                   rtol=1e-12, atol=1e-12 * np.abs(dens["rho_dh"]).max())
+        asum = sum(p["a"] for p in fp)
+        scale = np.abs(full_f["a"]).max()
+        np.testing.assert_allclose(asum, full_f["a"][idx], rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(sum(p["du"] for p in fp), full_f["du"][idx], rtol=0,
+                                   atol=1e-12 * np.abs(full_f["du"]).max())
+        vmax = np.max(np.stack([p["vsig"] for p in fp]), axis=0)
+        assert np.array_equal(vmax, full_f["vsig"][idx])
+        # the FP32 replica splits the same way
+        jm_counts = np.zeros(len(idx), np.int64)
+        for cj in nbr:
+            ndj, _ = orc.count32(ps, n_c, mode="brute", jmask=(cell == cj))
+            jm_counts += ndj[idx]
+        assert np.array_equal(jm_counts, nd32[idx])
