@@ -360,6 +360,141 @@ sph_status sph_autotune(int32_t loop, const sph_soa *soa, const sph_precision *p
                         sph_tune_entry *cand, int32_t ncand, int32_t reps, void *work_buf,
                         size_t work_bytes, int32_t *best, hipStream_t stream);
 
+/* ------------------------------------------------------------------ */
+/* Cell-pair tasks (serving): the density or force sums of a range of i */
+/* particles of one cell over the j particles of one neighbouring cell. */
+/* The sum over the 27 cells around ci of a particle's task results is  */
+/* its full loop result (counts exactly; floating point up to the order */
+/* of summation).                                                       */
+/* ------------------------------------------------------------------ */
+enum { SPH_TASK_DENSITY = 0, SPH_TASK_FORCE = 1 };
+typedef struct {
+  int32_t kind;           /* SPH_TASK_DENSITY or SPH_TASK_FORCE             */
+  int32_t ci, cj;         /* cell of the i particles; cj is one of the 27   */
+                          /* cells around ci (ci itself included)           */
+  int32_t i_begin, i_end; /* sorted slots cell_start[ci] <= i_begin <=      */
+                          /* i_end <= cell_start[ci + 1]                    */
+} sph_task;
+#define SPH_TASK_MAX_I 1024   /* largest i_end - i_begin of one task      */
+
+/* One result record per i particle of a task (32 bytes):
+ *   density: v = {rho, wcount, rho_dh, 0, 0}, count = nngb  (over j in cj)
+ *   force:   v = {a_x, a_y, a_z, du_dt, vsig}, count = nforce
+ * with the definitions of sph_density / sph_force restricted to j in cj
+ * (rho and rho_dh normalised by h_i as there; vsig is the maximum over
+ * the task's pairs, 0 if none). */
+typedef struct {
+  float v[5];
+  int32_t count;
+  int32_t pad[2];
+} sph_task_result;
+
+/* Tiles of the task kernels (ti particles per workgroup, k lanes each) */
+int32_t sph_task_tile_supported(sph_tile tile);
+
+/* One launch per kind over a batch of tasks (device arrays): items are
+ * (task index, first slot) pairs, one per chunk of at most tile.ti slots
+ * of a task, density items first (n_dens of them), then force items
+ * (n_force); out_off[t] is the index in `out` of task t's first result;
+ * `out` holds n_out records. Reads the view of sph_density (density
+ * items) or sph_force (force items) from soa. Every index read from the
+ * device arrays is clamped to the cell list and to n_out, so bad entries
+ * cannot address memory outside them; the host checks tasks before they
+ * reach the device (sph_server_submit). */
+sph_status sph_tasks_run(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                         const sph_params *params, sph_tile tile, const sph_task *tasks,
+                         const int32_t *out_off, const int32_t *items, int32_t n_dens,
+                         int32_t n_force, sph_task_result *out, int32_t n_out,
+                         hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Serving loop: cell-pair tasks over particle state resident in HBM,  */
+/* continuously batched. A dispatcher thread takes the tasks whose      */
+/* arrival time has passed, in arrival order, as long as their result  */
+/* records fit in the device result pool (admission by memory           */
+/* footprint), and launches them as one batch on a free stream; up to  */
+/* `streams` batches run on the device at once, so tasks that arrive    */
+/* while others run are admitted as soon as a stream and pool memory   */
+/* free up. A completion thread copies each finished batch's records to */
+/* the requests' host buffers, frees its pool memory and time-stamps    */
+/* it. A task's records depend only on the task and the resident state, */
+/* never on the batch it ran in.                                        */
+/* ------------------------------------------------------------------ */
+typedef struct sph_server sph_server;   /* opaque */
+
+typedef struct {
+  sph_tile tile;          /* task kernel tile ({0, 0}: 64 x 4)              */
+  int32_t streams;        /* batches in flight, 1..8                        */
+  int32_t max_batch;      /* tasks per batch, 1..4096                       */
+  size_t pool_bytes;      /* device bytes for the records of in-flight      */
+                          /* tasks (>= SPH_TASK_MAX_I records)              */
+} sph_server_config;
+
+typedef struct {
+  sph_task task;
+  int32_t reserved;       /* must be 0                                      */
+  int64_t arrival_ns;     /* sph_now_ns clock; not started before this      */
+  sph_task_result *out;   /* host memory for i_end - i_begin records        */
+                          /* (pinned recommended), or NULL to drop them     */
+} sph_request;            /* 40 bytes */
+
+typedef struct {
+  int64_t id;             /* from sph_server_submit                         */
+  int64_t arrival_ns, admit_ns, launch_ns, done_ns;
+  int32_t batch;          /* batch sequence number                          */
+  int32_t batch_tasks;    /* tasks in that batch                            */
+} sph_task_done;          /* 48 bytes */
+
+typedef struct {
+  int64_t submitted, done, batches;
+  int64_t admission_waits;   /* dispatcher rounds that found arrived tasks  */
+                             /* but no pool memory for the next one         */
+  int32_t max_inflight;      /* most batches on the device at once          */
+  int32_t reserved;
+  int64_t pool_high_water;   /* most pool bytes in use at once              */
+} sph_server_stats;
+
+/* Steady clock of the server, in ns */
+int64_t sph_now_ns(void);
+
+/* Device workspace bytes of a server with this configuration (the result
+ * pool plus each stream's task descriptors). */
+sph_status sph_server_workspace_size(const sph_server_config *cfg, size_t *bytes);
+
+/* Starts a server over the resident state: soa (the views of sph_density
+ * and sph_force, density outputs included for force tasks), prec, cells
+ * (its cell_start is read once, to check tasks) and params are copied by
+ * value, the device buffers they name must stay alive and unchanged until
+ * sph_server_destroy. workspace: device, sph_server_workspace_size bytes.
+ * Creates its streams (default priority) and pinned staging. */
+sph_status sph_server_create(const sph_server_config *cfg, const sph_soa *soa,
+                             const sph_precision *prec, const sph_cells *cells,
+                             const sph_params *params, void *workspace, size_t workspace_bytes,
+                             sph_server **out);
+
+/* Queues n requests (thread-safe); ids are consecutive from *first_id.
+ * Every task is checked against the cell list first: a bad one rejects the
+ * whole call (SPH_E_INVALID / SPH_E_RANGE, nothing queued). */
+sph_status sph_server_submit(sph_server *srv, const sph_request *req, int32_t n,
+                             int64_t *first_id);
+
+/* Moves up to max completion records to done (in completion order), waiting
+ * up to wait_ms for the first one; *n = records written. A HIP error of the
+ * serving threads is reported here (SPH_E_HIP) and stops the server. */
+sph_status sph_server_poll(sph_server *srv, sph_task_done *done, int32_t max, int32_t *n,
+                           int32_t wait_ms);
+
+sph_status sph_server_get_stats(sph_server *srv, sph_server_stats *stats);
+
+/* Waits until every queued task is done (or timeout_ms passes:
+ * SPH_E_RANGE). Completion records stay for sph_server_poll. */
+sph_status sph_server_drain(sph_server *srv, int32_t timeout_ms);
+
+/* Stops the threads after the batches in flight finish, releases the
+ * streams and pinned memory. Queued tasks that have not started are
+ * dropped. */
+sph_status sph_server_destroy(sph_server *srv);
+
 /* hipStreamSynchronize with the error mapped to sph_status */
 sph_status sph_sync(hipStream_t stream);
 

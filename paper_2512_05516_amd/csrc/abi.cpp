@@ -375,6 +375,38 @@ sph_status sph_force(const sph_soa* soa, const sph_precision* prec, const sph_ce
                     "sph_force");
 }
 
+int32_t sph_task_tile_supported(sph_tile tile) {
+  return task_tile_supported(tile.ti, tile.k) ? 1 : 0;
+}
+
+sph_status sph_tasks_run(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                         const sph_params* params, sph_tile tile, const sph_task* tasks,
+                         const int32_t* out_off, const int32_t* items, int32_t n_dens,
+                         int32_t n_force, sph_task_result* out, int32_t n_out,
+                         hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  Phys ph;
+  if (n_dens < 0 || n_force < 0 || n_out < 0)
+    return fail(SPH_E_INVALID, "sph_tasks_run: negative count");
+  if (n_dens > 0) SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_tasks_run"));
+  if (n_force > 0) SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_tasks_run"));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_params(params, ph));
+  const int ti = tile.ti ? tile.ti : 64, k = tile.k ? tile.k : 4;
+  if (!task_tile_supported(ti, k))
+    return fail(SPH_E_UNSUPPORTED, "sph_tasks_run: tile %dx%d not supported", ti, k);
+  if (n_dens + n_force == 0) return SPH_OK;
+  if (!tasks || !out_off || !items || !out)
+    return fail(SPH_E_INVALID, "sph_tasks_run: NULL task array");
+  if ((reinterpret_cast<uintptr_t>(out) & 15) || (reinterpret_cast<uintptr_t>(items) & 7))
+    return fail(SPH_E_INVALID, "sph_tasks_run: out must be 16-byte and items 8-byte aligned");
+  return hip_status(launch_tasks(*soa, p, c, ph, ti, k, tasks, out_off, items, n_dens, n_force,
+                                 out, n_out, stream),
+                    "sph_tasks_run");
+}
+
 sph_status sph_kick_drift(const sph_soa* soa, const sph_cells* cells, double dt_kick,
                           double dt_drift, int32_t* moved, hipStream_t stream) {
   CellsDev c;

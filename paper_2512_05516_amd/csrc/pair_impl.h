@@ -500,14 +500,21 @@ __device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst
 //     atomic counter and then steal from the other queues; the counter of
 //     the next item is bumped while the current one is processed, so the
 //     atomic's latency overlaps the work.
-template <class Chunk>
-__device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk, int TI,
-                                          Chunk chunk) {
+// The chunk callback takes (cell, c0, c1, only_q, out, obase): slots
+// [c0, c1) of `cell`, the neighbour cell index q (0..26) the j particles are
+// restricted to (-1: all 27), and the task result records (out == nullptr:
+// the full loop's outputs) with slot i's record at out[obase + i].
+struct LoopItems {
+  WorkDev wk;
+
+  template <class Chunk>
+  __device__ __forceinline__ void run(const CellsDev& cd, int TI, Chunk chunk) const {
   if (!wk.items) {
     const int cell = xcd_remap(blockIdx.x, gridDim.x);
     const int cs = clamp_slot(cd.start[cell], cd.n);
     const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
-    for (int base = cs; base < ce; base += TI) chunk(cell, base, min(base + TI, ce));
+    for (int base = cs; base < ce; base += TI)
+      chunk(cell, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
     return;
   }
   const int C = cd.n_c * cd.n_c * cd.n_c;
@@ -516,7 +523,7 @@ __device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk,
     const int cell = min(max(v.x, 0), C - 1);
     const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), 0);
     const int base = clamp_slot(v.y, ce);
-    chunk(cell, base, min(base + TI, ce));
+    chunk(cell, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
   };
   const int x = blockIdx.x & (kQueues - 1);
   const int total = min(wk.meta[0], wk.capacity);
@@ -561,13 +568,56 @@ __device__ __forceinline__ void run_items(const CellsDev& cd, const WorkDev& wk,
     it = __builtin_amdgcn_readfirstlane(s_item);
   }
 }
+};
+
+// Neighbour index q = (dx+1) + 3 (dy+1) + 9 (dz+1) of cell cj seen from
+// cell ci (periodic), or -2 if cj is not one of the 27 cells around ci.
+__device__ __forceinline__ int nbr_index(int ci, int cj, int n_c) {
+  int ax, ay, az, bx, by, bz;
+  cell_coords(ci, n_c, ax, ay, az);
+  cell_coords(cj, n_c, bx, by, bz);
+  auto wrap = [&](int d) { return d > 1 ? d - n_c : (d < -1 ? d + n_c : d); };
+  const int dx = wrap(bx - ax), dy = wrap(by - ay), dz = wrap(bz - az);
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1) return -2;
+  return (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+}
+
+// Work items of a batch of cell-pair tasks: workgroup b takes item b =
+// (task, first slot), i.e. up to TI slots of the task's i range against
+// the task's neighbour cell only.
+struct TaskItems {
+  const sph_task* tasks;
+  const int32_t* out_off;
+  const int2* items;
+  int nitems;
+  sph_task_result* out;
+  int n_out;
+
+  template <class Chunk>
+  __device__ __forceinline__ void run(const CellsDev& cd, int TI, Chunk chunk) const {
+    const int b = blockIdx.x;
+    if (b >= nitems) return;
+    const int C = cd.n_c * cd.n_c * cd.n_c;
+    const int2 it = items[b];
+    const sph_task t = tasks[it.x];
+    const int ci = min(max(t.ci, 0), C - 1), cj = min(max(t.cj, 0), C - 1);
+    const int cs = clamp_slot(cd.start[ci], cd.n);
+    const int ce = max(clamp_slot(cd.start[ci + 1], cd.n), cs);
+    const int ib = min(max(t.i_begin, cs), ce), ie = min(max(t.i_end, ib), ce);
+    const int c0 = min(max(it.y, ib), ie), c1 = min(c0 + TI, ie);
+    const int o = min(max(out_off[it.x], 0), n_out);
+    // records past n_out are dropped: clamp the range to what fits
+    const int c1o = min(c1, c0 + max(n_out - (o + (c0 - ib)), 0));
+    chunk(ci, c0, c1o, nbr_index(ci, cj, cd.n_c), out, o - ib);
+  }
+};
 
 // --------------------------------------------------------------------------
 // Density
 // --------------------------------------------------------------------------
-template <int TI, int K, class Src>
+template <int TI, int K, class Src, class Items>
 __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, CellsDev cd, Phys ph,
-                                                                    float s32, WorkDev wk) {
+                                                                    float s32, Items items) {
   constexpr int NT = TI * K;
   constexpr int CAP = 4 * NT;
   constexpr int LCAP = 32;
@@ -584,7 +634,8 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
   const int gi = tid / K, kk = tid % K;
   const float gk = ph.gamma_k;
 
-  run_items(cd, wk, TI, [&](int cell, int c0, int c1) {
+  items.run(cd, TI, [&](int cell, int c0, int c1, int only_q, sph_task_result* tout,
+                        int tbase) {
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
     build_nbr(T, cd, cx, cy, cz, s32, gk);
@@ -636,7 +687,7 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
     int nj = 0, rnd = 0;
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, bext,
-        [&](int) { return bext; },
+        [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
@@ -685,7 +736,12 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
     wsum = group_sum<K>(wsum);
     dh = group_sum<K>(dh);
     nn = group_sum_i<K>(nn);
-    if (vi && kk == 0) {
+    if (vi && kk == 0 && tout) {
+      const float Hinv3 = Hinv * Hinv * Hinv;
+      float4* r = reinterpret_cast<float4*>(tout + (tbase + i));
+      r[0] = make_float4(rho * Hinv3, kFourPiThird * wsum, -gk * dh * Hinv3 * Hinv, 0.0f);
+      r[1] = make_float4(0.0f, __int_as_float(nn), 0.0f, 0.0f);
+    } else if (vi && kk == 0) {
       const float Hinv3 = Hinv * Hinv * Hinv;
       const float rho_i = rho * Hinv3;
       const float rho_dh = -gk * dh * Hinv3 * Hinv;
@@ -702,9 +758,9 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
 // --------------------------------------------------------------------------
 // Force
 // --------------------------------------------------------------------------
-template <int TI, int K, class Src>
+template <int TI, int K, class Src, class Items>
 __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsDev cd, Phys ph,
-                                                                 float s32, WorkDev wk) {
+                                                                 float s32, Items items) {
   constexpr int NT = TI * K;
   constexpr int CAP = 2 * NT;
   constexpr int LCAP = 32;
@@ -725,7 +781,8 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
   const float gk = ph.gamma_k;
   const float alpha = ph.alpha, beta = ph.beta;
 
-  run_items(cd, wk, TI, [&](int cell, int c0, int c1) {
+  items.run(cd, TI, [&](int cell, int c0, int c1, int only_q, sph_task_result* tout,
+                        int tbase) {
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
     build_nbr(T, cd, cx, cy, cz, s32, gk);
@@ -836,7 +893,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     int nj = 0, filled = 0, rnd = 0;
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, fmaxf(bi, T.hb_max),
-        [&](int q) { return fmaxf(bi, T.hb[q]); },
+        [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
@@ -897,7 +954,13 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     du = group_sum<K>(du);
     vsig = group_max<K>(vsig);
     nf = group_sum_i<K>(nf);
-    if (vi && kk == 0) src.force_out(i, ax, ay, az, du, vsig, nf);
+    if (vi && kk == 0 && tout) {
+      float4* r = reinterpret_cast<float4*>(tout + (tbase + i));
+      r[0] = make_float4(ax, ay, az, du);
+      r[1] = make_float4(vsig, __int_as_float(nf), 0.0f, 0.0f);
+    } else if (vi && kk == 0) {
+      src.force_out(i, ax, ay, az, du, vsig, nf);
+    }
     __syncthreads();
   });
 }
@@ -972,9 +1035,9 @@ hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, 
   if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_DENS_CASE(TI_, K_)                                                        \
   if (ti == TI_ && k == K_) {                                                         \
-    auto kern = k_density<TI_, K_, S>;                                                \
+    auto kern = k_density<TI_, K_, S, LoopItems>;                                     \
     const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
-    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
+    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, LoopItems{wv});                      \
     return hipGetLastError();                                                         \
   }
   SPH_DENS_CASE(64, 4)
@@ -997,9 +1060,9 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_FORCE_CASE(TI_, K_)                                                       \
   if (ti == TI_ && k == K_) {                                                         \
-    auto kern = k_force<TI_, K_, S>;                                                  \
+    auto kern = k_force<TI_, K_, S, LoopItems>;                                       \
     const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
-    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, wv);                                 \
+    kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, LoopItems{wv});                      \
     return hipGetLastError();                                                         \
   }
   SPH_FORCE_CASE(64, 4)
@@ -1009,6 +1072,26 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   SPH_FORCE_CASE(64, 1)
   SPH_FORCE_CASE(16, 16)
 #undef SPH_FORCE_CASE
+  return hipErrorInvalidValue;
+}
+
+// Task batches: one workgroup per item, density and force kernels
+template <class S>
+hipError_t run_tasks(const S& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                     const TaskItems& dens, const TaskItems& force, hipStream_t s) {
+  const float s32 = (float)(1.0 / (double)c.n_c);
+#define SPH_TASK_CASE(TI_, K_)                                                         \
+  if (ti == TI_ && k == K_) {                                                          \
+    if (dens.nitems > 0)                                                               \
+      k_density<TI_, K_, S, TaskItems><<<dens.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, dens); \
+    if (force.nitems > 0)                                                              \
+      k_force<TI_, K_, S, TaskItems><<<force.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, force); \
+    return hipGetLastError();                                                          \
+  }
+  SPH_TASK_CASE(64, 4)
+  SPH_TASK_CASE(32, 8)
+  SPH_TASK_CASE(16, 16)
+#undef SPH_TASK_CASE
   return hipErrorInvalidValue;
 }
 
@@ -1029,6 +1112,15 @@ hipError_t run_force_force_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c,
                   const WorkDev* w, hipStream_t s);
 hipError_t run_force_force_aos(const AosSrc& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);
+hipError_t run_tasks_f32(const SoaSrc<DT_F32, DT_F32, DT_F32>& src, const CellsDev& c,
+                         const Phys& ph, int ti, int k, const TaskItems& dens,
+                         const TaskItems& force, hipStream_t s);
+hipError_t run_tasks_r(const SoaSrc<DT_F16, DT_BF16, DT_F16>& src, const CellsDev& c,
+                       const Phys& ph, int ti, int k, const TaskItems& dens,
+                       const TaskItems& force, hipStream_t s);
+hipError_t run_tasks_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c, const Phys& ph,
+                         int ti, int k, const TaskItems& dens, const TaskItems& force,
+                         hipStream_t s);
 
 }  // namespace pairk
 }  // namespace sph

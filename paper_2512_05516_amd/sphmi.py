@@ -78,6 +78,17 @@ class Tile(C.Structure):
     _fields_ = [("ti", C.c_int32), ("k", C.c_int32)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("tile", Tile), ("streams", C.c_int32), ("max_batch", C.c_int32),
+                ("pool_bytes", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("done", C.c_int64), ("batches", C.c_int64),
+                ("admission_waits", C.c_int64), ("max_inflight", C.c_int32),
+                ("reserved", C.c_int32), ("pool_high_water", C.c_int64)]
+
+
 class TuneEntry(C.Structure):
     _fields_ = [("tile", Tile), ("sched", C.c_int32), ("ms", C.c_float)]
 
@@ -87,7 +98,10 @@ EXPORTS = [
     "sph_bin", "sph_convert", "sph_host_staging_size", "sph_convert_host", "sph_writeback",
     "sph_density", "sph_force", "sph_kick_drift", "sph_reduce_workspace_size", "sph_reduce",
     "sph_density_aos", "sph_force_aos", "sph_kick_drift_aos", "sph_sync", "sph_worklist_size",
-    "sph_worklist", "sph_tune_candidates", "sph_autotune",
+    "sph_worklist", "sph_tune_candidates", "sph_autotune", "sph_task_tile_supported",
+    "sph_tasks_run", "sph_now_ns", "sph_server_workspace_size", "sph_server_create",
+    "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
+    "sph_server_destroy",
 ]
 
 _lib = None
@@ -127,10 +141,24 @@ def lib():
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
     L.sph_sync.argtypes = [vp]
     L.sph_tune_candidates.argtypes = [P(TuneEntry), i32, P(i32)]
+    L.sph_task_tile_supported.argtypes = [Tile]
+    L.sph_tasks_run.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp, vp, vp, i32,
+                                i32, vp, i32, vp]
+    L.sph_now_ns.argtypes = []
+    L.sph_server_workspace_size.argtypes = [P(ServerConfig), P(sz)]
+    L.sph_server_create.argtypes = [P(ServerConfig), P(Soa), P(Precision), P(Cells), P(Params),
+                                    vp, sz, P(vp)]
+    L.sph_server_submit.argtypes = [vp, vp, i32, P(C.c_int64)]
+    L.sph_server_poll.argtypes = [vp, vp, i32, P(i32), i32]
+    L.sph_server_get_stats.argtypes = [vp, P(ServerStats)]
+    L.sph_server_drain.argtypes = [vp, i32]
+    L.sph_server_destroy.argtypes = [vp]
     L.sph_autotune.argtypes = [i32, P(Soa), P(Precision), P(Cells), P(Params), P(TuneEntry), i32,
                                i32, vp, sz, P(i32), vp]
     for name in EXPORTS[3:]:
         getattr(L, name).restype = st
+    L.sph_task_tile_supported.restype = i32
+    L.sph_now_ns.restype = C.c_int64
     _lib = L
     return L
 

@@ -25,7 +25,7 @@ def sph():
 
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "sphmi.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:sph_status|int32_t|const char \*)\s*(sph_\w+)\(",
+    return sorted(set(re.findall(r"^\s*(?:sph_status|int32_t|int64_t|const char \*)\s*(sph_\w+)\(",
                                  txt, re.M)))
 
 
@@ -179,6 +179,66 @@ def test_host_convert_rejects_sub_cells(sph):
                             buf.size, 1, None)
     assert st == sph.SPH_E_UNSUPPORTED
     assert "sub_bits" in sph.last_error()
+
+
+def test_server_host_side(sph):
+    L = sph.lib()
+    nb = C.c_size_t()
+    T0 = sph.Tile(0, 0)
+    good = sph.ServerConfig(T0, 4, 256, 64 << 20)
+    assert L.sph_server_workspace_size(C.byref(good), C.byref(nb)) == sph.SPH_OK
+    assert nb.value >= 64 << 20
+    bad = [(sph.ServerConfig(T0, 0, 256, 64 << 20), sph.SPH_E_INVALID),
+           (sph.ServerConfig(T0, 9, 256, 64 << 20), sph.SPH_E_INVALID),
+           (sph.ServerConfig(T0, 4, 0, 64 << 20), sph.SPH_E_INVALID),
+           (sph.ServerConfig(T0, 4, 5000, 64 << 20), sph.SPH_E_INVALID),
+           (sph.ServerConfig(T0, 4, 256, 1000), sph.SPH_E_INVALID),
+           (sph.ServerConfig(sph.Tile(48, 3), 4, 256, 64 << 20), sph.SPH_E_UNSUPPORTED),
+           (sph.ServerConfig(sph.Tile(128, 2), 4, 256, 64 << 20), sph.SPH_E_UNSUPPORTED)]
+    for cfg, code in bad:
+        assert L.sph_server_workspace_size(C.byref(cfg), C.byref(nb)) == code
+    h = C.c_void_p()
+    assert L.sph_server_create(C.byref(good), None, None, None, None, None, 0,
+                               C.byref(h)) == sph.SPH_E_INVALID
+    assert L.sph_task_tile_supported(sph.Tile(64, 4)) == 1
+    assert L.sph_task_tile_supported(sph.Tile(16, 16)) == 1
+    assert L.sph_task_tile_supported(sph.Tile(128, 2)) == 0
+    cells = _fake_cells(sph)
+    soa = sph.Soa()
+    for i in range(len(sph.S_FIELDS)):
+        soa.f[i] = 0x4000 + 256 * i
+    args = lambda nd, nf, tile=T0, out=C.c_void_p(0x9000): L.sph_tasks_run(
+        C.byref(soa), C.byref(sph.precision()), C.byref(cells), C.byref(sph.params()), tile,
+        C.c_void_p(0x7000), C.c_void_p(0x7100), C.c_void_p(0x7200), nd, nf, out, 1 << 20, None)
+    assert args(-1, 0) == sph.SPH_E_INVALID
+    assert args(1, 0, tile=sph.Tile(128, 2)) == sph.SPH_E_UNSUPPORTED
+    assert args(1, 1, out=None) == sph.SPH_E_INVALID
+    assert args(1, 1, out=C.c_void_p(0x9004)) == sph.SPH_E_INVALID
+    assert args(0, 0) == sph.SPH_OK                    # nothing to launch
+    t0 = L.sph_now_ns()
+    assert L.sph_now_ns() >= t0 > 0
+
+
+def test_task_stream_generator():
+    from paper_2512_05516_amd import serve
+    n_c = 5
+    occ = np.random.default_rng(1).integers(0, 900, n_c ** 3)
+    start = np.concatenate([[0], np.cumsum(occ)])
+    tasks = serve.make_tasks(start, n_c, 2000, seed=3)
+    assert tasks.shape == (2000, 5)
+    size = tasks[:, 4] - tasks[:, 3]
+    assert size.min() >= 16 // 2 and size.max() <= 512
+    assert np.all(tasks[:, 3] >= start[tasks[:, 1]]) and np.all(tasks[:, 4] <= start[tasks[:, 1] + 1])
+    assert np.all(occ[tasks[:, 2]] >= 16) and np.all(occ[tasks[:, 1]] >= 16)
+    c = lambda v: np.stack([v % n_c, (v // n_c) % n_c, v // n_c ** 2], 1)
+    d = (c(tasks[:, 2]) - c(tasks[:, 1])) % n_c
+    assert np.all((d == 0) | (d == 1) | (d == n_c - 1))
+    assert 0.4 < tasks[:, 0].mean() < 0.6
+    arr = serve.poisson_arrivals(20000, 1e4, 0, seed=2)
+    gaps = np.diff(arr) * 1e-9
+    assert abs(gaps.mean() - 1e-4) < 5e-6 and np.all(gaps >= 0)
+    req, offs = serve.requests(tasks, np.zeros(2000, np.int64), out_ptr=1 << 20)
+    assert req["out"][1] - req["out"][0] == 32 * size[0]
 
 
 def test_layout_from_numpy(sph):

@@ -1,0 +1,214 @@
+"""Serving loop on the GPU: cell-pair task results against the FP64 oracle
+restricted to the task's pairs, the 27-cell partition against the full
+loops, the same records alone and in a mix, admission under a small pool,
+and rejection of bad tasks on the host."""
+import numpy as np
+import pytest
+
+from paper_2512_05516_amd import inputs
+
+from helpers import rel_rmse
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5          # FP32 storage, as for the full loops
+
+
+@pytest.fixture(scope="module")
+def sph():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_05516_amd import sphmi
+    sphmi.lib()
+    return sphmi
+
+
+@pytest.fixture(scope="module")
+def state(sph, orc):
+    """Resident FP32 state of a clustered set: binned, converted, density
+    (and force, for the partition test) computed by the full loops."""
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(30000, 12, f_blob=0.5, sigma=0.05)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    pipe = Pipeline(rec, n_c)
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    torch.cuda.synchronize()
+    cell, start, perm, _ = orc.bin_cells(ref.x, n_c)
+    assert np.array_equal(start, pipe.cells.cell_start.cpu().numpy())
+    dens = orc.density(ref, n_c=n_c)
+    force = orc.force(ref, dens, n_c=n_c)
+    return dict(ps=ps, ref=ref, n_c=n_c, pipe=pipe, cell=cell, start=start, perm=perm,
+                dens=dens, force=force)
+
+
+def _run(st, tasks, rate=None, seed=0, **cfg):
+    """Run tasks through a server; returns (records per task, completion
+    records, stats)."""
+    from paper_2512_05516_amd import serve
+    sizes = tasks[:, 4] - tasks[:, 3]
+    buf = np.zeros(int(sizes.sum()), serve.RESULT)
+    t0 = serve.now_ns()
+    arr = (serve.poisson_arrivals(len(tasks), rate, t0, seed) if rate
+           else np.full(len(tasks), t0, np.int64))
+    req, offs = serve.requests(tasks, arr, buf.ctypes.data)
+    with serve.Server(st["pipe"], **cfg) as srv:
+        done = srv.run(req)
+        stats = srv.stats()
+    recs = [buf[o:o + s] for o, s in zip(offs, sizes)]
+    return recs, done, stats
+
+
+def _tasks(st, count, seed):
+    from paper_2512_05516_amd import serve
+    t = serve.make_tasks(st["start"], st["n_c"], count, seed)
+    # a few self pairs (ci == cj) for certain
+    t[:8, 2] = t[:8, 1]
+    return t
+
+
+def test_task_results_match_oracle(sph, orc, state):
+    st = state
+    tasks = _tasks(st, 240, seed=1)
+    recs, done, stats = _run(st, tasks)
+    assert stats["done"] == len(tasks) and len(done) == len(tasks)
+    parts = orc.task_partials(st["ref"], st["n_c"], [tuple(t) for t in tasks], st["dens"],
+                              perm=st["perm"], cell=st["cell"])
+    dens, force = st["dens"], st["force"]
+    e = {"rho": 0.0, "wcount": 0.0, "omega": 0.0, "a": [], "du": [], "vsig": 0.0}
+    a_ref, a_got, du_ref, du_got = [], [], [], []
+    counts = {cj: orc.count32(st["ref"], st["n_c"], jmask=(st["cell"] == cj))
+              for cj in np.unique(tasks[:, 2])}
+    for t, r, p in zip(tasks, recs, parts):
+        idx = st["perm"][t[3]:t[4]]
+        nd, nf = counts[t[2]]
+        if t[0] == 0:
+            assert np.array_equal(r["count"], nd[idx])
+            assert np.array_equal(r["count"], p["count"])
+            rho_full = dens["rho"][idx]
+            e["rho"] = max(e["rho"], np.max(np.abs(r["v"][:, 0] - p["rho"]) / rho_full))
+            e["wcount"] = max(e["wcount"], np.max(np.abs(r["v"][:, 1] - p["wcount"]) /
+                                                  dens["wcount"][idx]))
+            h = st["ref"].h[idx]
+            e["omega"] = max(e["omega"], np.max(np.abs(r["v"][:, 2] - p["rho_dh"]) * h /
+                                                (3 * rho_full)))
+        else:
+            assert np.array_equal(r["count"], nf[idx])
+            a_ref.append(p["a"])
+            a_got.append(r["v"][:, :3])
+            du_ref.append(p["du"])
+            du_got.append(r["v"][:, 3])
+            e["vsig"] = max(e["vsig"], np.max(np.abs(r["v"][:, 4] - p["vsig"]) /
+                                              force["vsig"][idx]))
+    a_ref, a_got = np.concatenate(a_ref), np.concatenate(a_got)
+    du_ref, du_got = np.concatenate(du_ref), np.concatenate(du_got)
+    a_scale = np.linalg.norm(force["a"], axis=1).mean()
+    du_scale = np.abs(force["du"]).mean()
+    e["a"] = float(np.sqrt((np.linalg.norm(a_got - a_ref, axis=1) ** 2).mean()) / a_scale)
+    e["du"] = float(np.sqrt(((du_got - du_ref) ** 2).mean()) / du_scale)
+    print({k: f"{v:.2e}" for k, v in e.items()})
+    for k, v in e.items():
+        assert v <= TOL, (k, v)
+
+
+def test_partition_of_full_loops(sph, state):
+    """All 27 (ci, cj) tasks of a cell add up to the full loops' results:
+    counts exactly, sums within FP32 reordering."""
+    st = state
+    n_c, start = st["n_c"], st["start"]
+    occ = np.diff(start)
+    cells = np.nonzero((occ >= 16) & (occ <= 1024))[0][:5]
+    tasks = []
+    for ci in cells:
+        cx, cy, cz = ci % n_c, (ci // n_c) % n_c, ci // (n_c * n_c)
+        for k in (0, 1):
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        cj = ((cx + dx) % n_c) + n_c * (((cy + dy) % n_c) + n_c * ((cz + dz) % n_c))
+                        tasks.append((k, ci, cj, start[ci], start[ci + 1]))
+    tasks = np.array(tasks, np.int32)
+    recs, _, _ = _run(st, tasks)
+    soa = st["pipe"].soa
+    for ci in cells:
+        sl = slice(start[ci], start[ci + 1])
+        for k, cnt_name in ((0, "NNGB"), (1, "NFORCE")):
+            rr = [r for t, r in zip(tasks, recs) if t[0] == k and t[1] == ci]
+            assert len(rr) == 27
+            total = sum(r["count"].astype(np.int64) for r in rr)
+            assert np.array_equal(total, soa[cnt_name][sl].cpu().numpy())
+            v = sum(r["v"].astype(np.float64) for r in rr)
+            if k == 0:
+                ref = soa["RHO"][sl].cpu().numpy()
+                assert np.max(np.abs(v[:, 0] / ref - 1)) < 2e-6
+            else:
+                ax = np.stack([soa[n][sl].cpu().numpy() for n in ("A_X", "A_Y", "A_Z")], 1)
+                assert rel_rmse(v[:, :3], ax) < 2e-6
+                vs = np.max(np.stack([r["v"][:, 4] for r in rr]), axis=0)
+                assert np.array_equal(vs, soa["VSIG"][sl].cpu().numpy())
+
+
+@pytest.mark.parametrize("tile", [(64, 4), (16, 16)])
+def test_alone_equals_mix(sph, state, tile):
+    """Each task's records are bit-identical whether it runs alone or
+    batched with others arriving around it."""
+    st = state
+    til = sph.tile(*tile)
+    tasks = _tasks(st, 600, seed=7)
+    mix, done, stats = _run(st, tasks, rate=2e5, seed=3, tile=til, streams=4, max_batch=64)
+    assert stats["batches"] < len(tasks)            # tasks were batched together
+    assert done["batch_tasks"].max() > 1
+    for t in range(0, len(tasks), 37):
+        alone, d1, _ = _run(st, tasks[t:t + 1], tile=til, streams=1, max_batch=1)
+        assert d1["batch_tasks"][0] == 1
+        assert alone[0].tobytes() == mix[t].tobytes(), t
+
+
+def test_admission_by_pool_footprint(sph, state):
+    """A pool of SPH_TASK_MAX_I records admits only a few tasks at a time:
+    the dispatcher waits for memory, every task still completes with the
+    records of an unconstrained run."""
+    from paper_2512_05516_amd import serve
+    st = state
+    tasks = _tasks(st, 300, seed=9)
+    big, _, _ = _run(st, tasks, streams=4, max_batch=256)
+    small, done, stats = _run(st, tasks, streams=4, max_batch=256,
+                              pool_bytes=serve.TASK_MAX_I * serve.RESULT.itemsize)
+    assert stats["done"] == len(tasks)
+    assert stats["pool_high_water"] <= serve.TASK_MAX_I * serve.RESULT.itemsize
+    assert stats["admission_waits"] > 0
+    assert all(a.tobytes() == b.tobytes() for a, b in zip(big, small))
+    lat = done["done_ns"] - done["arrival_ns"]
+    assert np.all(lat > 0) and np.all(done["launch_ns"] >= done["admit_ns"])
+
+
+def test_bad_tasks_rejected(sph, state):
+    from paper_2512_05516_amd import serve
+    st = state
+    n_c, start = st["n_c"], st["start"]
+    good = _tasks(st, 4, seed=2)
+    ci = int(good[0, 1])
+    cx, cy, cz = ci % n_c, (ci // n_c) % n_c, ci // (n_c * n_c)
+    far = ((cx + 2) % n_c) + n_c * (cy + n_c * cz)
+    bad = [(0, ci, far, start[ci], start[ci] + 1),              # not a neighbour
+           (1, ci, ci, start[ci] - 1, start[ci] + 1),            # i range outside ci
+           (0, ci, ci, start[ci], start[ci]),                    # empty range
+           (2, ci, ci, start[ci], start[ci] + 1),                # bad kind
+           (0, n_c ** 3, ci, 0, 1)]                              # cell out of range
+    with serve.Server(st["pipe"]) as srv:
+        for b in bad:
+            t = np.concatenate([good, np.array([b], np.int32)])
+            req, _ = serve.requests(t, np.zeros(len(t), np.int64))
+            with pytest.raises(sph.SphError):
+                srv.submit(req)
+        assert srv.stats()["submitted"] == 0
+        req, _ = serve.requests(good, np.zeros(len(good), np.int64))
+        srv.submit(req)
+        srv.drain()
+        assert srv.stats()["done"] == len(good)
