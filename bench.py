@@ -14,8 +14,9 @@ convert / kick-drift / writeback at algorithmic bytes, the plain-AoS step and
 the reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) on the same
 particles, the host-side convert variant, the clustered 4,194,304-particle
 set (occupancy 1..~2,000 per cell) with its own tuned tiling in FP32 and
-FP16 storage, and the FP64 CPU oracle timed on a bounded sample (rank 0,
-N = 1).
+FP16 storage, the serving loop on that resident state (Poisson streams of
+cell-pair tasks, p50/p99 latency), and the FP64 CPU oracle timed on a
+bounded sample (rank 0, N = 1).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -107,6 +108,58 @@ def cpu_baseline(ps):
                       f"({t2 - t1:.2f} s)"}
 
 
+SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
+SERVE_SECONDS = 1.0                    # arrivals per rate
+
+
+def serving_variant(pipe, n_c, seed=4):
+    """Continuous-batching server over the resident state of `pipe`: for
+    each offered rate, a Poisson stream of cell-pair tasks (half density,
+    half force; both sides 16..512 particles) for SERVE_SECONDS; latency =
+    completion - arrival per task."""
+    from paper_2512_05516_amd import serve
+    start = pipe.cells.cell_start.cpu().numpy()
+    nmax = int(max(SERVE_RATES) * SERVE_SECONDS)
+    tasks_all = serve.make_tasks(start, n_c, nmax, seed)
+    sizes = (tasks_all[:, 4] - tasks_all[:, 3]).astype(np.int64)
+    buf = np.zeros(int(sizes.sum()), serve.RESULT)
+    cfg = {"streams": 4, "max_batch": 256, "pool_bytes": 64 << 20}
+    out = {"config": dict(cfg, tile="64x4", task_sides="16..512 particles",
+                          mix="50% density / 50% force", seconds_per_rate=SERVE_SECONDS)}
+    with serve.Server(pipe, **cfg) as srv:
+        warm, _ = serve.requests(tasks_all[:256], np.zeros(256, np.int64))
+        srv.run(warm)
+        for rate in SERVE_RATES:
+            n = int(rate * SERVE_SECONDS)
+            tasks = tasks_all[:n]
+            t0 = serve.now_ns() + 2_000_000
+            arr = serve.poisson_arrivals(n, rate, t0, seed + int(rate))
+            req, _ = serve.requests(tasks, arr, buf.ctypes.data)
+            s0 = srv.stats()
+            done = srv.run(req)
+            s1 = srv.stats()
+            lat = (done["done_ns"] - done["arrival_ns"]) * 1e-6
+            qwait = (done["admit_ns"] - done["arrival_ns"]) * 1e-6
+            wall = (int(done["done_ns"].max()) - int(arr.min())) * 1e-9
+            pairs = float(buf["count"][: int(sizes[:n].sum())].sum())
+            nb = s1["batches"] - s0["batches"]
+            out[str(int(rate))] = {
+                "tasks": n, "offered_per_s": rate, "achieved_tasks_per_s": n / wall,
+                "pair_interactions_per_s": pairs / wall,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                               "p99": float(np.percentile(lat, 99)),
+                               "max": float(lat.max())},
+                "queue_wait_ms_p99": float(np.percentile(qwait, 99)),
+                "batches": int(nb), "mean_batch": n / max(nb, 1),
+                "max_inflight": s1["max_inflight"],
+                "admission_waits": s1["admission_waits"] - s0["admission_waits"],
+            }
+            log(f"serving {int(rate)}/s: p50 {out[str(int(rate))]['latency_ms']['p50']:.3f} ms, "
+                f"p99 {out[str(int(rate))]['latency_ms']['p99']:.3f} ms, "
+                f"{nb} batches")
+    return out
+
+
 def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
     """Clustered 4,194,304-particle set: tuned tiling, whole FP32 SoA steps
     and FP16-store steps (FP16 offsets, BF16 v, FP16 m/h/u)."""
@@ -142,6 +195,9 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
                      "status_flags": pipe.status()}
         out["occupancy"] = {"min": int(occ.min()), "max": int(occ.max()),
                             "p50": float(np.median(occ)), "p99": float(np.percentile(occ, 99))}
+        if not args.no_serving:
+            log(f"clustered {name}: serving loop")
+            out[name]["serving"] = serving_variant(pipe, n_c)
         del pipe
         torch.cuda.empty_cache()
     return out
@@ -157,6 +213,8 @@ def main():
                     help="time only the FP32 SoA step (profiling runs)")
     ap.add_argument("--no-clustered", action="store_true",
                     help="skip the clustered 4M-particle variant")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving loop on the clustered state")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()

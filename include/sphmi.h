@@ -392,7 +392,7 @@ typedef struct {
 /* Tiles of the task kernels (ti particles per workgroup, k lanes each) */
 int32_t sph_task_tile_supported(sph_tile tile);
 
-/* One launch per kind over a batch of tasks (device arrays): items are
+/* One launch per kind over a batch of n_tasks tasks (device arrays): items are
  * (task index, first slot) pairs, one per chunk of at most tile.ti slots
  * of a task, density items first (n_dens of them), then force items
  * (n_force); out_off[t] is the index in `out` of task t's first result;
@@ -403,8 +403,8 @@ int32_t sph_task_tile_supported(sph_tile tile);
  * reach the device (sph_server_submit). */
 sph_status sph_tasks_run(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
                          const sph_params *params, sph_tile tile, const sph_task *tasks,
-                         const int32_t *out_off, const int32_t *items, int32_t n_dens,
-                         int32_t n_force, sph_task_result *out, int32_t n_out,
+                         int32_t n_tasks, const int32_t *out_off, const int32_t *items,
+                         int32_t n_dens, int32_t n_force, sph_task_result *out, int32_t n_out,
                          hipStream_t stream);
 
 /* ------------------------------------------------------------------ */

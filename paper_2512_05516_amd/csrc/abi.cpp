@@ -381,13 +381,13 @@ int32_t sph_task_tile_supported(sph_tile tile) {
 
 sph_status sph_tasks_run(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
                          const sph_params* params, sph_tile tile, const sph_task* tasks,
-                         const int32_t* out_off, const int32_t* items, int32_t n_dens,
-                         int32_t n_force, sph_task_result* out, int32_t n_out,
+                         int32_t n_tasks, const int32_t* out_off, const int32_t* items,
+                         int32_t n_dens, int32_t n_force, sph_task_result* out, int32_t n_out,
                          hipStream_t stream) {
   CellsDev c;
   Prec p;
   Phys ph;
-  if (n_dens < 0 || n_force < 0 || n_out < 0)
+  if (n_dens < 0 || n_force < 0 || n_out < 0 || n_tasks < 0)
     return fail(SPH_E_INVALID, "sph_tasks_run: negative count");
   if (n_dens > 0) SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_tasks_run"));
   if (n_force > 0) SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_tasks_run"));
@@ -398,12 +398,13 @@ sph_status sph_tasks_run(const sph_soa* soa, const sph_precision* prec, const sp
   if (!task_tile_supported(ti, k))
     return fail(SPH_E_UNSUPPORTED, "sph_tasks_run: tile %dx%d not supported", ti, k);
   if (n_dens + n_force == 0) return SPH_OK;
+  if (n_tasks == 0) return fail(SPH_E_INVALID, "sph_tasks_run: items but no tasks");
   if (!tasks || !out_off || !items || !out)
     return fail(SPH_E_INVALID, "sph_tasks_run: NULL task array");
   if ((reinterpret_cast<uintptr_t>(out) & 15) || (reinterpret_cast<uintptr_t>(items) & 7))
     return fail(SPH_E_INVALID, "sph_tasks_run: out must be 16-byte and items 8-byte aligned");
-  return hip_status(launch_tasks(*soa, p, c, ph, ti, k, tasks, out_off, items, n_dens, n_force,
-                                 out, n_out, stream),
+  return hip_status(launch_tasks(*soa, p, c, ph, ti, k, tasks, n_tasks, out_off, items, n_dens,
+                                 n_force, out, n_out, stream),
                     "sph_tasks_run");
 }
 

@@ -51,13 +51,13 @@ bool task_tile_supported(int ti, int k) {
 }
 
 hipError_t launch_tasks(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
-                        int ti, int k, const sph_task* tasks, const int32_t* out_off,
-                        const int32_t* items, int n_dens, int n_force, sph_task_result* out,
-                        int n_out, hipStream_t s) {
+                        int ti, int k, const sph_task* tasks, int n_tasks,
+                        const int32_t* out_off, const int32_t* items, int n_dens, int n_force,
+                        sph_task_result* out, int n_out, hipStream_t s) {
   if (c.n == 0 || n_dens + n_force == 0) return hipSuccess;
   const int2* it = reinterpret_cast<const int2*>(items);
-  const TaskItems d{tasks, out_off, it, n_dens, out, n_out};
-  const TaskItems f{tasks, out_off, it + n_dens, n_force, out, n_out};
+  const TaskItems d{tasks, n_tasks, out_off, it, n_dens, out, n_out};
+  const TaskItems f{tasks, n_tasks, out_off, it + n_dens, n_force, out, n_out};
   if (p.pos == DT_F32 && p.vel == DT_F32 && p.mhu == DT_F32)
     return run_tasks_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p), c, ph, ti, k, d, f, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)

@@ -587,6 +587,7 @@ __device__ __forceinline__ int nbr_index(int ci, int cj, int n_c) {
 // the task's neighbour cell only.
 struct TaskItems {
   const sph_task* tasks;
+  int ntasks;
   const int32_t* out_off;
   const int2* items;
   int nitems;
@@ -599,13 +600,14 @@ struct TaskItems {
     if (b >= nitems) return;
     const int C = cd.n_c * cd.n_c * cd.n_c;
     const int2 it = items[b];
-    const sph_task t = tasks[it.x];
+    const int ti_ = min(max(it.x, 0), ntasks - 1);
+    const sph_task t = tasks[ti_];
     const int ci = min(max(t.ci, 0), C - 1), cj = min(max(t.cj, 0), C - 1);
     const int cs = clamp_slot(cd.start[ci], cd.n);
     const int ce = max(clamp_slot(cd.start[ci + 1], cd.n), cs);
     const int ib = min(max(t.i_begin, cs), ce), ie = min(max(t.i_end, ib), ce);
     const int c0 = min(max(it.y, ib), ie), c1 = min(c0 + TI, ie);
-    const int o = min(max(out_off[it.x], 0), n_out);
+    const int o = min(max(out_off[ti_], 0), n_out);
     // records past n_out are dropped: clamp the range to what fits
     const int c1o = min(c1, c0 + max(n_out - (o + (c0 - ib)), 0));
     chunk(ci, c0, c1o, nbr_index(ci, cj, cd.n_c), out, o - ib);

@@ -222,7 +222,7 @@ struct sph_server {
                          hipMemcpyHostToDevice, S.stream);
     if (e != hipSuccess) return e;
     st = sph_tasks_run(&soa, &prec, &cells, &prm, sph_tile{d.ti, d.k},
-                       reinterpret_cast<const sph_task*>(S.desc_dev),
+                       reinterpret_cast<const sph_task*>(S.desc_dev), nb,
                        reinterpret_cast<const int32_t*>(S.desc_dev + d.tasks_b),
                        reinterpret_cast<const int32_t*>(S.desc_dev + d.tasks_b + d.off_b), nd,
                        ni - nd, pool_dev, (int32_t)d.pool_recs, S.stream);

@@ -90,9 +90,9 @@ hipError_t launch_force_aos(void* aos, const AosLayout& L, const CellsDev& c, co
 
 bool task_tile_supported(int ti, int k);
 hipError_t launch_tasks(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
-                        int ti, int k, const sph_task* tasks, const int32_t* out_off,
-                        const int32_t* items, int n_dens, int n_force, sph_task_result* out,
-                        int n_out, hipStream_t s);
+                        int ti, int k, const sph_task* tasks, int n_tasks,
+                        const int32_t* out_off, const int32_t* items, int n_dens, int n_force,
+                        sph_task_result* out, int n_out, hipStream_t s);
 
 hipError_t launch_kick_drift(const sph_soa& soa, const CellsDev& c, double dtk, double dtd,
                              int32_t* moved, hipStream_t s);

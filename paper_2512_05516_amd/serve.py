@@ -80,7 +80,7 @@ class Server:
     def __exit__(self, *exc):
         self.close()
 
-    def run(self, req: np.ndarray, timeout_ms=120000) -> np.ndarray:
+    def run(self, req: np.ndarray, timeout_ms=30000) -> np.ndarray:
         """Submit all requests, wait until they are done, return their
         completion records ordered by request."""
         first = self.submit(req)

@@ -142,8 +142,8 @@ def lib():
     L.sph_sync.argtypes = [vp]
     L.sph_tune_candidates.argtypes = [P(TuneEntry), i32, P(i32)]
     L.sph_task_tile_supported.argtypes = [Tile]
-    L.sph_tasks_run.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp, vp, vp, i32,
-                                i32, vp, i32, vp]
+    L.sph_tasks_run.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp, i32, vp, vp,
+                                i32, i32, vp, i32, vp]
     L.sph_now_ns.argtypes = []
     L.sph_server_workspace_size.argtypes = [P(ServerConfig), P(sz)]
     L.sph_server_create.argtypes = [P(ServerConfig), P(Soa), P(Precision), P(Cells), P(Params),

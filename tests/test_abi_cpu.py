@@ -209,7 +209,7 @@ def test_server_host_side(sph):
         soa.f[i] = 0x4000 + 256 * i
     args = lambda nd, nf, tile=T0, out=C.c_void_p(0x9000): L.sph_tasks_run(
         C.byref(soa), C.byref(sph.precision()), C.byref(cells), C.byref(sph.params()), tile,
-        C.c_void_p(0x7000), C.c_void_p(0x7100), C.c_void_p(0x7200), nd, nf, out, 1 << 20, None)
+        C.c_void_p(0x7000), 4, C.c_void_p(0x7100), C.c_void_p(0x7200), nd, nf, out, 1 << 20, None)
     assert args(-1, 0) == sph.SPH_E_INVALID
     assert args(1, 0, tile=sph.Tile(128, 2)) == sph.SPH_E_UNSUPPORTED
     assert args(1, 1, out=None) == sph.SPH_E_INVALID
