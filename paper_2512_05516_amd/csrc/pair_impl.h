@@ -253,7 +253,6 @@ struct NbrCells {
   int cell[27];
   float sh[27][3];
   float hb[27];
-  float hb_max;
 };
 
 __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int cx, int cy,
@@ -268,12 +267,6 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
     T.sh[tid][1] = shy;
     T.sh[tid][2] = shz;
     T.hb[tid] = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    float m = 0.0f;
-    for (int q = 0; q < 27; ++q) m = fmaxf(m, T.hb[q]);
-    T.hb_max = m;
   }
   __syncthreads();
 }
@@ -315,8 +308,9 @@ __device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int&
   __syncthreads();
 }
 
-// Range table of one batch of sub-cells: slot ranges, prefix of counts and
-// the neighbour index q of each.
+// Range table of one batch of candidate ranges: slot ranges, prefix of
+// counts and the neighbour index q of each; and, per neighbour cell q, its
+// entries: the whole cell, or its sub-cells inside the query box.
 template <int NT>
 struct RangeTab {
   int start[NT];
@@ -324,56 +318,123 @@ struct RangeTab {
   unsigned char q[NT];
   int scan[2 * (NT / 64)];
   int ntab, total;
+  int qn[27];                   // entries of cell q (0: skipped)
+  int qpre[28];                 // prefix of qn
+  unsigned char qw[27];         // 1: whole cell, 0: sub-cells qr
+  unsigned char qr[27][6];      // local sub-cell ranges x0, x1, y0, y1, z0, z1
 };
 
-// The sub-cells (R = 2^sub_bits per axis; R = 1: cells) whose boxes lie
-// within `bound(q)` of the chunk box [lo, hi], in batches of at most NT:
-// for each batch, `batch(tab)` gathers the particles of the batch's ranges.
+// A neighbour cell is split into its R^3 sub-cells only when it holds more
+// than kSplitFactor * R^3 particles and the query box does not cover it:
+// below that, one range for the whole cell costs less than the table work
+// of its sub-cells.
+constexpr int kSplitFactor = 2;
+
+// The candidate ranges of a chunk: for each of the 27 neighbour cells q
+// with bound(q) > 0, the sub-cells (R = 2^sub_bits per axis) of q whose
+// boxes lie within bound(q) of the chunk box [lo, hi], or the whole of q
+// (a superset) when q is sparse or covered. Entries are processed in
+// batches of at most NT: for each batch, `batch(tab)` gathers the
+// particles of the batch's ranges.
 template <int NT, class Bound, class Batch>
 __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells& T,
                                               RangeTab<NT>& tab, float s32, float lox, float loy,
                                               float loz, float hix, float hiy, float hiz,
-                                              float bext, Bound bound, Batch batch) {
+                                              Bound bound, Batch batch) {
   const int sb = cd.sub_bits, R = 1 << sb;
   const float ss = s32 / (float)R;
-  const float mg = ss * 0x1p-8f;                    // rounding margin of stored offsets
   const float inv = (float)R / s32;
-  auto lo_idx = [&](float v) { return max((int)floorf((v - bext) * inv) - 1, -R); };
-  auto hi_idx = [&](float v) { return min((int)floorf((v + bext) * inv) + 1, 2 * R - 1); };
-  const int ax0 = lo_idx(lox), ay0 = lo_idx(loy), az0 = lo_idx(loz);
-  const int nqx = max(hi_idx(hix) - ax0 + 1, 0), nqy = max(hi_idx(hiy) - ay0 + 1, 0),
-            nqz = max(hi_idx(hiz) - az0 + 1, 0);
-  const int NQ = nqx * nqy * nqz;
   const int* sstart = sb ? cd.sub_start : cd.start;
   const int tid = threadIdx.x;
+  if (tid < 27) {
+    const int q = tid;
+    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+    const float bq = bound(q);
+    int n = 0;
+    if (bq > 0.0f) {
+      auto lo_i = [&](float v, int d) { return max((int)floorf((v - bq) * inv) - 1 - d * R, 0); };
+      auto hi_i = [&](float v, int d) {
+        return min((int)floorf((v + bq) * inv) + 1 - d * R, R - 1);
+      };
+      const int x0 = lo_i(lox, dx), x1 = hi_i(hix, dx);
+      const int y0 = lo_i(loy, dy), y1 = hi_i(hiy, dy);
+      const int z0 = lo_i(loz, dz), z1 = hi_i(hiz, dz);
+      if (x0 <= x1 && y0 <= y1 && z0 <= z1) {
+        const int c = T.cell[q];
+        const int a0 = clamp_slot(cd.start[c], cd.n);
+        const int cnt = max(clamp_slot(cd.start[c + 1], cd.n) - a0, 0);
+        const bool covered = x0 == 0 && y0 == 0 && z0 == 0 && x1 == R - 1 && y1 == R - 1 &&
+                             z1 == R - 1;
+        const bool whole = sb == 0 || covered || cnt <= kSplitFactor * R * R * R;
+        if (cnt > 0) n = whole ? 1 : (x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
+        tab.qw[q] = whole ? 1 : 0;
+        unsigned char* r = tab.qr[q];
+        r[0] = (unsigned char)x0;
+        r[1] = (unsigned char)x1;
+        r[2] = (unsigned char)y0;
+        r[3] = (unsigned char)y1;
+        r[4] = (unsigned char)z0;
+        r[5] = (unsigned char)z1;
+      }
+    }
+    tab.qn[q] = n;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int q = 0; q < 27; ++q) {
+      tab.qpre[q] = acc;
+      acc += tab.qn[q];
+    }
+    tab.qpre[27] = acc;
+  }
+  __syncthreads();
+  const int NQ = tab.qpre[27];
   for (int b0 = 0; b0 < NQ; b0 += NT) {
     const int t = b0 + tid;
     bool ok = t < NQ;
     int st = 0, cnt = 0, q = 0;
     if (ok) {
-      const int rx = t % nqx, ry = (t / nqx) % nqy, rz = t / (nqx * nqy);
-      const int gx = ax0 + rx, gy = ay0 + ry, gz = az0 + rz;
-      const int dx = (gx + R) / R - 1, dy = (gy + R) / R - 1, dz = (gz + R) / R - 1;
-      const int sx = gx - dx * R, sy = gy - dy * R, sz = gz - dz * R;
-      q = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
-      const float bx0 = gx * ss - mg, bx1 = (gx + 1) * ss + mg;
-      const float by0 = gy * ss - mg, by1 = (gy + 1) * ss + mg;
-      const float bz0 = gz * ss - mg, bz1 = (gz + 1) * ss + mg;
-      const float ex = fmaxf(fmaxf(bx0 - hix, lox - bx1), 0.0f);
-      const float ey = fmaxf(fmaxf(by0 - hiy, loy - by1), 0.0f);
-      const float ez = fmaxf(fmaxf(bz0 - hiz, loz - bz1), 0.0f);
-      const float bq = bound(q);
-      ok = ex * ex + ey * ey + ez * ez < bq * bq * (1.0f + 0x1p-10f);
-      if (ok) {
+      int lo = 0, hi = 26;   // last q with qpre[q] <= t
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab.qpre[mid] <= t) lo = mid;
+        else hi = mid - 1;
+      }
+      q = lo;
+      const int e = t - tab.qpre[q];
+      const int c = T.cell[q];
+      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      float bx0, bx1, by0, by1, bz0, bz1;
+      if (tab.qw[q]) {
+        const float mg = s32 * 0x1p-8f;       // rounding margin of stored offsets
+        bx0 = dx * s32 - mg, bx1 = (dx + 1) * s32 + mg;
+        by0 = dy * s32 - mg, by1 = (dy + 1) * s32 + mg;
+        bz0 = dz * s32 - mg, bz1 = (dz + 1) * s32 + mg;
+        st = clamp_slot(cd.start[c], cd.n);
+        cnt = max(clamp_slot(cd.start[c + 1], cd.n) - st, 0);
+      } else {
+        const unsigned char* r = tab.qr[q];
+        const int nx = r[1] - r[0] + 1, ny = r[3] - r[2] + 1;
+        const int sx = r[0] + e % nx, sy = r[2] + (e / nx) % ny, sz = r[4] + e / (nx * ny);
+        const float mg = ss * 0x1p-8f;
+        const int gx = dx * R + sx, gy = dy * R + sy, gz = dz * R + sz;
+        bx0 = gx * ss - mg, bx1 = (gx + 1) * ss + mg;
+        by0 = gy * ss - mg, by1 = (gy + 1) * ss + mg;
+        bz0 = gz * ss - mg, bz1 = (gz + 1) * ss + mg;
         int m = 0;
         for (int b = 0; b < sb; ++b)
           m |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) |
                (((sz >> b) & 1) << (3 * b + 2));
-        const int key = (T.cell[q] << (3 * sb)) + m;
+        const int key = (c << (3 * sb)) + m;
         st = clamp_slot(sstart[key], cd.n);
         cnt = max(clamp_slot(sstart[key + 1], cd.n) - st, 0);
-        ok = cnt > 0;
       }
+      const float ex = fmaxf(fmaxf(bx0 - hix, lox - bx1), 0.0f);
+      const float ey = fmaxf(fmaxf(by0 - hiy, loy - by1), 0.0f);
+      const float ez = fmaxf(fmaxf(bz0 - hiz, loz - bz1), 0.0f);
+      const float bq = bound(q);
+      ok = cnt > 0 && ex * ex + ey * ey + ez * ez < bq * bq * (1.0f + 0x1p-10f);
     }
     int e_idx, e_pre, ntab, total;
     block_scan2<NT>(ok ? 1 : 0, ok ? cnt : 0, e_idx, e_pre, ntab, total, tab.scan);
@@ -688,7 +749,7 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
 
     int nj = 0, rnd = 0;
     for_sub_cells<NT>(
-        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, bext,
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
@@ -894,7 +955,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
 
     int nj = 0, filled = 0, rnd = 0;
     for_sub_cells<NT>(
-        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, fmaxf(bi, T.hb_max),
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
