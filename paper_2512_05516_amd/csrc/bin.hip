@@ -29,9 +29,9 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
                                                         int32_t* __restrict__ vals,
                                                         float* __restrict__ hmax,
                                                         int32_t* status) {
-  int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i >= n) return;
-  const char* rec = aos + (size_t)i * stride;
+  const int i = blockIdx.x * kThreads + threadIdx.x;
+  const bool valid = i < n;   // no early exit: the whole wave takes part in the h reduction
+  const char* rec = aos + (size_t)(valid ? i : 0) * stride;
   const double* x = reinterpret_cast<const double*>(rec + offx);
   const int R = 1 << sub_bits;
   bool bad = false;
@@ -47,13 +47,26 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
     sc[k] = sa;
   }
   const int cell = c[0] + n_c * (c[1] + n_c * c[2]);
-  keys[i] = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
-  vals[i] = i;
-  if (hmax && offh != kAbsent) {
-    const float h = rec_load32(rec, offh, dth);
-    if (h > 0.0f) atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
+  if (valid) {
+    keys[i] = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
+    vals[i] = i;
   }
-  if (bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
+  if (hmax && offh != kAbsent) {
+    const float h = valid ? rec_load32(rec, offh, dth) : 0.0f;
+    const bool contrib = valid && h > 0.0f;
+    // input in cell order (buffers of co-located particles): when every
+    // contributing lane of the wave has the same cell, one atomic per wave
+    const int lead = __shfl(cell, __ffsll((long long)__ballot(contrib)) - 1);
+    if (__all(!contrib || cell == lead)) {
+      float m = contrib ? h : 0.0f;
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+      if ((threadIdx.x & 63) == 0 && m > 0.0f)
+        atomicMax(reinterpret_cast<int*>(hmax) + lead, __float_as_int(m));
+    } else if (contrib) {
+      atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
+    }
+  }
+  if (valid && bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, int n, float v) {

@@ -325,15 +325,14 @@ struct RangeTab {
 };
 
 // A neighbour cell is split into its R^3 sub-cells only when it holds more
-// than kSplitFactor * R^3 particles and the query box does not cover it:
-// below that, one range for the whole cell costs less than the table work
-// of its sub-cells.
+// than kSplitFactor * R^3 particles: below that, one range for the whole
+// cell costs less than the table work of its sub-cells.
 constexpr int kSplitFactor = 2;
 
 // The candidate ranges of a chunk: for each of the 27 neighbour cells q
 // with bound(q) > 0, the sub-cells (R = 2^sub_bits per axis) of q whose
 // boxes lie within bound(q) of the chunk box [lo, hi], or the whole of q
-// (a superset) when q is sparse or covered. Entries are processed in
+// (a superset) when q is sparse. Entries are processed in
 // batches of at most NT: for each batch, `batch(tab)` gathers the
 // particles of the batch's ranges.
 template <int NT, class Bound, class Batch>
@@ -363,9 +362,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         const int c = T.cell[q];
         const int a0 = clamp_slot(cd.start[c], cd.n);
         const int cnt = max(clamp_slot(cd.start[c + 1], cd.n) - a0, 0);
-        const bool covered = x0 == 0 && y0 == 0 && z0 == 0 && x1 == R - 1 && y1 == R - 1 &&
-                             z1 == R - 1;
-        const bool whole = sb == 0 || covered || cnt <= kSplitFactor * R * R * R;
+        const bool whole = sb == 0 || cnt <= kSplitFactor * R * R * R;
         if (cnt > 0) n = whole ? 1 : (x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
         tab.qw[q] = whole ? 1 : 0;
         unsigned char* r = tab.qr[q];

@@ -24,17 +24,21 @@ def sph():
     return sphmi
 
 
-@pytest.fixture(scope="module")
-def state(sph, orc):
-    """Resident FP32 state of a clustered set: binned, converted, density
-    (and force, for the partition test) computed by the full loops."""
+REDUCED = ("f16", "bf16", "f16", (15, 3, 0))    # offsets, v, m/h/u formats; m, h, u scales
+
+
+def _state(sph, orc, formats=None):
+    """Resident state of a clustered set: binned, converted, density (and
+    force, for the partition test) computed by the full loops; the oracle's
+    full sums on the values the storage formats hold."""
     import torch
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.clustered_set(30000, 12, f_blob=0.5, sigma=0.05)
     n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
     rec = inputs.pack_aos(ps, "f32")
     ref = inputs.unpack_aos(rec)
-    pipe = Pipeline(rec, n_c)
+    prec = sph.precision(*formats[:3], *formats[3]) if formats else None
+    pipe = Pipeline(rec, n_c, prec=prec)
     pipe.bin()
     pipe.convert("full")
     pipe.density()
@@ -42,10 +46,22 @@ def state(sph, orc):
     torch.cuda.synchronize()
     cell, start, perm, _ = orc.bin_cells(ref.x, n_c)
     assert np.array_equal(start, pipe.cells.cell_start.cpu().numpy())
-    dens = orc.density(ref, n_c=n_c)
-    force = orc.force(ref, dens, n_c=n_c)
-    return dict(ps=ps, ref=ref, n_c=n_c, pipe=pipe, cell=cell, start=start, perm=perm,
-                dens=dens, force=force)
+    q = orc.dequantise_set(ref, n_c, *formats[:3], formats[3]) if formats else ref
+    dens = orc.density(q, n_c=n_c)
+    force = orc.force(q, dens, n_c=n_c)
+    cnt_kw = dict(pos=formats[0], hdt=formats[2], h_scale=formats[3][1]) if formats else {}
+    return dict(ps=ps, ref=ref, q=q, n_c=n_c, pipe=pipe, cell=cell, start=start, perm=perm,
+                dens=dens, force=force, cnt_kw=cnt_kw)
+
+
+@pytest.fixture(scope="module")
+def state(sph, orc):
+    return _state(sph, orc)
+
+
+@pytest.fixture(scope="module")
+def state_r(sph, orc):
+    return _state(sph, orc, REDUCED)
 
 
 def _run(st, tasks, rate=None, seed=0, **cfg):
@@ -73,17 +89,22 @@ def _tasks(st, count, seed):
     return t
 
 
-def test_task_results_match_oracle(sph, orc, state):
-    st = state
+@pytest.mark.parametrize("storage", ["f32", "reduced"])
+def test_task_results_match_oracle(sph, orc, request, storage):
+    """Task records against the oracle's cell-pair sums on the values the
+    storage holds (FP32 bar; reduced storage: the 2e-5 bar of the full-loop
+    test); counts against the FP32 replica, bit for bit."""
+    st = request.getfixturevalue("state" if storage == "f32" else "state_r")
+    tol = TOL if storage == "f32" else 2e-5
     tasks = _tasks(st, 240, seed=1)
     recs, done, stats = _run(st, tasks)
     assert stats["done"] == len(tasks) and len(done) == len(tasks)
-    parts = orc.task_partials(st["ref"], st["n_c"], [tuple(t) for t in tasks], st["dens"],
+    parts = orc.task_partials(st["q"], st["n_c"], [tuple(t) for t in tasks], st["dens"],
                               perm=st["perm"], cell=st["cell"])
     dens, force = st["dens"], st["force"]
     e = {"rho": 0.0, "wcount": 0.0, "omega": 0.0, "a": [], "du": [], "vsig": 0.0}
     a_ref, a_got, du_ref, du_got = [], [], [], []
-    counts = {cj: orc.count32(st["ref"], st["n_c"], jmask=(st["cell"] == cj))
+    counts = {cj: orc.count32(st["ref"], st["n_c"], jmask=(st["cell"] == cj), **st["cnt_kw"])
               for cj in np.unique(tasks[:, 2])}
     for t, r, p in zip(tasks, recs, parts):
         idx = st["perm"][t[3]:t[4]]
@@ -95,7 +116,7 @@ def test_task_results_match_oracle(sph, orc, state):
             e["rho"] = max(e["rho"], np.max(np.abs(r["v"][:, 0] - p["rho"]) / rho_full))
             e["wcount"] = max(e["wcount"], np.max(np.abs(r["v"][:, 1] - p["wcount"]) /
                                                   dens["wcount"][idx]))
-            h = st["ref"].h[idx]
+            h = st["q"].h[idx]
             e["omega"] = max(e["omega"], np.max(np.abs(r["v"][:, 2] - p["rho_dh"]) * h /
                                                 (3 * rho_full)))
         else:
@@ -112,9 +133,9 @@ def test_task_results_match_oracle(sph, orc, state):
     du_scale = np.abs(force["du"]).mean()
     e["a"] = float(np.sqrt((np.linalg.norm(a_got - a_ref, axis=1) ** 2).mean()) / a_scale)
     e["du"] = float(np.sqrt(((du_got - du_ref) ** 2).mean()) / du_scale)
-    print({k: f"{v:.2e}" for k, v in e.items()})
+    print(storage, {k: f"{v:.2e}" for k, v in e.items()})
     for k, v in e.items():
-        assert v <= TOL, (k, v)
+        assert v <= tol, (k, v)
 
 
 def test_partition_of_full_loops(sph, state):
