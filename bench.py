@@ -179,7 +179,8 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
                                                       scale_h=7, scale_u=0))):
         log(f"clustered {name}: autotuning")
         sub = (0, 1, 2) if name == "fp32" else (out["fp32"]["sub_bits"],)
-        ch = tune.tune(rec, n_c, prec=prec, sub_bits=sub, reps=2, cache_path=None, log=log)
+        ch = tune.tune(rec, n_c, prec=prec, sub_bits=sub, reps=2, cache_path=args.tune_cache,
+                       log=log)
         pipe = Pipeline(rec, n_c, prec=prec, **tune.pipeline_kwargs(ch))
         log(f"clustered {name}: steps")
         secs, per = timed_steps(torch, pipe, "soa", steps, warm)
@@ -215,6 +216,10 @@ def main():
                     help="skip the clustered 4M-particle variant")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop on the clustered state")
+    ap.add_argument("--clustered-only", action="store_true",
+                    help="time only the clustered variant (profiling runs)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: tune afresh every run)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -234,6 +239,10 @@ def main():
         sys.exit(1)
     sphmi.lib()
     torch.cuda.set_device(0)
+    if args.clustered_only:
+        out = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)
+        print(json.dumps({"metric": METRIC, "clustered": out}), flush=True)
+        return
     log("generating 128^3 jittered lattice")
     ps = inputs.medium_set(SEED)
     rec = inputs.pack_aos(ps, "f32")
@@ -241,7 +250,7 @@ def main():
 
     # ---- tiling chosen by the autotuner (outside the timed region) ------------
     log("autotuning the pair loops")
-    choice = tune.tune(rec, N_C, reps=3, cache_path=None, log=log)
+    choice = tune.tune(rec, N_C, reps=3, cache_path=args.tune_cache, log=log)
     kw = tune.pipeline_kwargs(choice)
     log("chosen:", tune.describe(choice))
 
