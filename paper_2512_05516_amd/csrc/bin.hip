@@ -21,18 +21,42 @@ __device__ __forceinline__ int morton3(int sx, int sy, int sz, int bits) {
   return m;
 }
 
-// key = cell * R^3 + Morton(sub-cell); also the per-cell max of h
+// Largest record span staged through LDS by k_bin_keys (8-byte words)
+constexpr int kSpanWords = 16;
+
+// key = cell * R^3 + Morton(sub-cell); also the per-cell max of h.
+// nw > 0: the block first copies bytes [lo, lo + 8 nw) of each of its
+// records into LDS with consecutive threads on consecutive words (x and h
+// read from there), so every record line is fetched once and the loads
+// coalesce; nw = 0: each thread reads its record's fields directly.
 __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ aos,
                                                         uint32_t stride, uint32_t offx,
-                                                        uint32_t offh, int dth, int n, int n_c,
-                                                        int sub_bits, int32_t* __restrict__ keys,
+                                                        uint32_t offh, int dth, uint32_t lo,
+                                                        int nw, int n, int n_c, int sub_bits,
+                                                        int32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
                                                         float* __restrict__ hmax,
                                                         int32_t* status) {
-  const int i = blockIdx.x * kThreads + threadIdx.x;
+  __shared__ uint2 span[kThreads * kSpanWords];
+  const int i0 = blockIdx.x * kThreads;
+  const int i = i0 + threadIdx.x;
   const bool valid = i < n;   // no early exit: the whole wave takes part in the h reduction
-  const char* rec = aos + (size_t)(valid ? i : 0) * stride;
-  const double* x = reinterpret_cast<const double*>(rec + offx);
+  const char* rec;            // record bytes as seen at offsets offx, offh
+  uint32_t rx = offx, rh = offh;
+  if (nw > 0) {
+    const int nrec = min(kThreads, n - i0);
+    for (int w = threadIdx.x; w < nrec * nw; w += kThreads) {
+      const int r = w / nw, j = w - r * nw;
+      span[w] = *reinterpret_cast<const uint2*>(aos + (size_t)(i0 + r) * stride + lo + 8 * j);
+    }
+    __syncthreads();
+    rec = reinterpret_cast<const char*>(span + (valid ? threadIdx.x : 0) * nw);
+    rx = offx - lo;
+    rh = offh - lo;
+  } else {
+    rec = aos + (size_t)(valid ? i : 0) * stride;
+  }
+  const double* x = reinterpret_cast<const double*>(rec + rx);
   const int R = 1 << sub_bits;
   bool bad = false;
   int c[3], sc[3];
@@ -52,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
     vals[i] = i;
   }
   if (hmax && offh != kAbsent) {
-    const float h = valid ? rec_load32(rec, offh, dth) : 0.0f;
+    const float h = valid ? rec_load32(rec, rh, dth) : 0.0f;
     const bool contrib = valid && h > 0.0f;
     // input in cell order (buffers of co-located particles): when every
     // contributing lane of the wave has the same cell, one atomic per wave
@@ -278,9 +302,16 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
   if (hmax) k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
   int32_t* skeys = cell;                 // sorted keys (cell ids when sb == 0)
   if (n > 0) {
+    // span of the record bytes the keys need: x, and h when hmax is wanted
+    const uint32_t ox = L.off[SPH_A_X], oh = L.off[SPH_A_H];
+    const bool want_h = hmax && oh != kAbsent;
+    const uint32_t hsz = L.dt[SPH_A_H] == DT_F64 ? 8u : 4u;
+    const uint32_t lo = (want_h ? min(ox, oh) : ox) & ~7u;
+    const uint32_t hi = (max(ox + 24u, want_h ? oh + hsz : 0u) + 7u) & ~7u;
+    const int nw = (hi - lo) / 8 <= (uint32_t)kSpanWords ? (int)((hi - lo) / 8) : 0;
     k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(
-        static_cast<const char*>(aos), L.stride, L.off[SPH_A_X], L.off[SPH_A_H], L.dt[SPH_A_H],
-        n, n_c, sb, w.ka, w.va, hmax, c.status);
+        static_cast<const char*>(aos), L.stride, ox, oh, L.dt[SPH_A_H], lo, nw, n, n_c, sb, w.ka,
+        w.va, want_h ? hmax : nullptr, c.status);
     int bits = 1;
     while ((1 << bits) < S) ++bits;
     int passes = (bits + 7) / 8;

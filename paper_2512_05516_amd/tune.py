@@ -30,9 +30,10 @@ def signature(pipe: Pipeline) -> dict:
     start = pipe.cells.cell_start.cpu().numpy()
     occ = np.diff(start)
     p = pipe.prec
+    props = torch.cuda.get_device_properties(pipe.aos.device)
     return {
         "abi": sphmi.abi_version(),
-        "device": torch.cuda.get_device_name(),
+        "device": f"{props.gcnArchName.split(':')[0]}/{props.multi_processor_count}cu",
         "n": pipe.n, "n_c": pipe.n_c,
         "occ_max": int(occ.max()) if occ.size else 0,
         "occ_p50": float(np.median(occ)) if occ.size else 0.0,
