@@ -88,6 +88,19 @@ def timed_steps(torch, pipe, kind, steps, warmup):
     return t1 - t0, per
 
 
+def force_traffic(choice):
+    """HBM bytes per k_force launch (FETCH_SIZE + WRITE_SIZE, calibrated) from
+    the committed counter profile, if it was taken with the tiling chosen
+    now and the kernel's sources have not changed since; else None."""
+    from paper_2512_05516_amd import prof_summary
+    t = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "step_lattice128_f32.txt"))
+    f = choice["force"]
+    tiling = f"sub_bits{choice['sub_bits']}/force{f['ti']}x{f['k']}{f['sched'] or 'percell'}"
+    if not t or t.get("tiling") != tiling or t.get("source_sha256") != prof_summary.source_hash():
+        return None
+    return int(t["fetch_bytes"]) + int(t["write_bytes"])
+
+
 def cpu_baseline(ps):
     """FP64 oracle (cells mode, OpenMP) on a bounded sample of the workload:
     density over all particles and force over every 8th particle."""
@@ -122,7 +135,8 @@ def serving_variant(pipe, n_c, seed=4):
     nmax = int(max(SERVE_RATES) * SERVE_SECONDS)
     tasks_all = serve.make_tasks(start, n_c, nmax, seed)
     sizes = (tasks_all[:, 4] - tasks_all[:, 3]).astype(np.int64)
-    buf = np.zeros(int(sizes.sum()), serve.RESULT)
+    buf = np.empty(int(sizes.sum()), serve.RESULT)
+    buf.view(np.uint8).fill(0)        # fault the pages in before any task completes
     cfg = {"streams": 4, "max_batch": 256, "pool_bytes": 64 << 20}
     out = {"config": dict(cfg, tile="64x4", task_sides="16..512 particles",
                           mix="50% density / 50% force", seconds_per_rate=SERVE_SECONDS)}
@@ -271,7 +285,7 @@ def main():
     achieved = FLOP_FORCE_PAIR * pairs_f / force_s / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "kernel": "k_force (FP32 SoA)",
+                "traffic": force_traffic(choice), "kernel": "k_force (FP32 SoA)",
                 "flop_per_unit": FLOP_FORCE_PAIR, "units_per_launch": pairs_f}
     dens_tf = FLOP_DENSITY_PAIR * pairs_d / (per["density"] * 1e-3) / 1e12
     gbs = lambda b, ms: b * n / (ms * 1e-3) / 1e9

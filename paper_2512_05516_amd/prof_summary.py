@@ -2,19 +2,50 @@
 
     python -m paper_2512_05516_amd.prof_summary KTRACE.db [--fetch FETCH.db]
         [--write WRITE.db] [--copy-bytes N] [--title T]
+        [--traffic-kernel SUBSTR --tiling T]
 
 Kernel trace: calls and average / min / max duration per kernel. Counter
 runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch): the per-kernel average,
 and, when --copy-bytes is given, the factor that makes the counters of the
 largest device copy (__amd_rocclr_copyBuffer) read its known size, applied
-to every kernel.
+to every kernel. --traffic-kernel adds one machine-readable line with the
+scaled FETCH + WRITE bytes per launch of that kernel, the tiling the run
+used and the SHA-256 of the kernel's sources (source_hash()), so a reader
+can tell whether the counters still describe the current code.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
+import os
 import sqlite3
 import sys
 from collections import defaultdict
+
+# sources of the FP32 SoA pair kernels (the dominant kernel of the step)
+KERNEL_SOURCES = ("csrc/pair_impl.h", "csrc/pair_force_f32.hip", "csrc/pair_dens_f32.hip",
+                  "csrc/sph_device.h")
+
+
+def source_hash() -> str:
+    here = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(path: str):
+    """The traffic line of a summary file as a dict, or None."""
+    try:
+        with open(path) as fh:
+            for line in fh:
+                if line.startswith("traffic "):
+                    return dict(kv.split("=", 1) for kv in line.split()[1:])
+    except OSError:
+        return None
+    return None
 
 
 def short(name: str) -> str:
@@ -55,6 +86,8 @@ def main(argv=None):
     ap.add_argument("--write")
     ap.add_argument("--copy-bytes", type=int, default=0)
     ap.add_argument("--title", default="")
+    ap.add_argument("--traffic-kernel", default="")
+    ap.add_argument("--tiling", default="")
     a = ap.parse_args(argv)
     out = []
     if a.title:
@@ -65,6 +98,7 @@ def main(argv=None):
     for name, v in sorted(k.items(), key=lambda kv: -sum(kv[1])):
         out.append(f"{name:90s} {len(v):5d} {sum(v)/len(v):9.1f} {min(v):9.1f} {max(v):9.1f} "
                    f"{100*sum(v)/tot:6.2f}")
+    per_launch = {}
     for counter, path in (("FETCH_SIZE", a.fetch), ("WRITE_SIZE", a.write)):
         if not path:
             continue
@@ -80,6 +114,13 @@ def main(argv=None):
         for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]) / len(kv[1])):
             avg = sum(v) / len(v)
             out.append(f"{name:90s} {len(v):5d} {avg * scale:14.1f}")
+            if a.traffic_kernel and a.traffic_kernel in name:
+                per_launch[counter] = avg * scale * 1024.0
+    if a.traffic_kernel and len(per_launch) == 2:
+        out.append("")
+        out.append(f"traffic kernel={a.traffic_kernel.replace(' ', '')} tiling={a.tiling} "
+                   f"fetch_bytes={per_launch['FETCH_SIZE']:.0f} "
+                   f"write_bytes={per_launch['WRITE_SIZE']:.0f} source_sha256={source_hash()}")
     print("\n".join(out))
 
 
