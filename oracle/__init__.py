@@ -79,7 +79,8 @@ def lib():
         L.orc_reduce.argtypes = [C.c_int, d, d, d, d, d]
         L.orc_reduce.restype = None
         L.orc_count32.argtypes = [C.c_int, d, d, C.c_int, C.c_double, C.c_int, C.c_int,
-                                  C.c_int, C.c_int, C.POINTER(C.c_uint8), i32, i32]
+                                  C.c_int, C.c_int, C.POINTER(C.c_uint8), i32, C.c_int,
+                                  i32, i32]
         L.orc_f32_to_f16.restype = C.c_uint16
         L.orc_f32_to_f16.argtypes = [C.c_float]
         L.orc_f16_to_f32.restype = C.c_float
@@ -228,17 +229,20 @@ def reduce(m, v, a, du):
 
 
 def count32(ps, n_c, pos="f32", hdt="f32", h_scale=0, mode="cells", gamma_k=GAMMA_K,
-            jmask=None):
+            jmask=None, sel=None):
     """Neighbour counts with the support test in FP32 -> (n_density, n_force);
-    jmask restricts j as for density()."""
+    jmask restricts j as for density(); sel selects the i (outputs per entry)."""
     x, h = _f64(ps.x), _f64(ps.h)
     n = x.shape[0]
-    nd = np.empty(n, np.int32)
-    nf = np.empty(n, np.int32)
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+    cnt = n if sel is None else sel.shape[0]
+    nd = np.empty(cnt, np.int32)
+    nf = np.empty(cnt, np.int32)
     rc = lib().orc_count32(n, _p(x, C.c_double), _p(h, C.c_double), int(n_c), float(gamma_k),
                            DTYPE_CODES[pos], DTYPE_CODES[hdt], int(h_scale),
                            0 if mode == "brute" else 1, _p(_mask(jmask), C.c_uint8),
-                           _p(nd, C.c_int32), _p(nf, C.c_int32))
+                           _p(sel, C.c_int32), cnt, _p(nd, C.c_int32), _p(nf, C.c_int32))
     assert rc == 0
     return nd, nf
 

@@ -571,11 +571,13 @@ int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
 /*   H_i    = FP32(gamma_k) * h_i, H2_i = H_i * H_i (FP32)                   */
 /* density: r2 < H2_i (self included); force: j != i and r2 < max(H2_i,H2_j) */
 /* off and h are the stored values (pos_dtype, h_dtype) read back as FP32.   */
+/* sel (nsel entries, NULL: all) selects the i; outputs are per entry of sel. */
 /* ------------------------------------------------------------------------ */
 
 int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
                 int pos_dtype, int h_dtype, int h_scale, int mode,
-                const uint8_t *jmask, int32_t *nd, int32_t *nf) {
+                const uint8_t *jmask, const int32_t *sel, int nsel, int32_t *nd,
+                int32_t *nf) {
   if (n_c < 3) return -1;
   cellgrid g;
   double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
@@ -591,8 +593,10 @@ int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k
     H2[i] = Hi * Hi;
   }
   float s = (float)(1.0 / (double)n_c);
+  int cnt = sel ? nsel : n;
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int i = 0; i < n; ++i) {
+  for (int s_ = 0; s_ < cnt; ++s_) {
+    int i = sel ? sel[s_] : s_;
     int ci = g.cell[i];
     int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
     int cnt_d = 0, cnt_f = 0;
@@ -620,8 +624,8 @@ int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k
             if (j != i && (r2 < H2[i] || r2 < H2[j])) cnt_f++;
           }
         }
-    if (nd) nd[i] = cnt_d;
-    if (nf) nf[i] = cnt_f;
+    if (nd) nd[s_] = cnt_d;
+    if (nf) nf[s_] = cnt_f;
   }
   grid_free(&g);
   free(off);

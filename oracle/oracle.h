@@ -76,7 +76,8 @@ void orc_reduce(int n, const double *m, const double *v, const double *a,
 /* neighbour counts with the support test taken in FP32, as the GPU takes it */
 int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
                 int pos_dtype, int h_dtype, int h_scale, int mode,
-                const uint8_t *jmask, int32_t *nd, int32_t *nf);
+                const uint8_t *jmask, const int32_t *sel, int nsel, int32_t *nd,
+                int32_t *nf);
 
 /* quantisers (RNE), FP32 -> {FP16, BF16} bits and back */
 uint16_t orc_f32_to_f16(float v);

@@ -493,17 +493,22 @@ def test_edge_cases(sph, orc):
 # ---------------------------------------------------------------------------
 
 def test_full_size_medium(sph, orc):
-    """2,097,152 particles (128^3 lattice, FP32 records, default 64x4 tiling):
-    binning bit-exact, every neighbour count exact, values on a seeded
-    sample of 4,096 particles within the FP32 bar."""
-    import torch
+    """2,097,152 particles (128^3 lattice, FP32 records) in the tiling the
+    benchmark's autotuner chooses: binning bit-exact, every neighbour count
+    exact, values on a seeded sample of 4,096 particles within the FP32 bar."""
+    from paper_2512_05516_amd import tune
     ps = inputs.medium_set(2)
     n_c = 32
-    pipe = run_gpu(ps, n_c, "f32")
+    rec = inputs.pack_aos(ps, "f32")
+    choice = tune.tune(rec, n_c, reps=3, cache_path=None)
+    kw = tune.pipeline_kwargs(choice)
+    pipe = run_gpu(ps, n_c, "f32", **kw)
     assert pipe.status() == 0
-    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
-    ocell, ostart, operm, _ = orc.bin_cells(ref.x, n_c)
+    ref = inputs.unpack_aos(rec)
+    _, ostart, operm, _ = orc.bin_cells(ref.x, n_c)
     assert np.array_equal(pipe.cells.cell_start.cpu().numpy(), ostart)
+    if kw["sub_bits"]:
+        _, _, operm = orc.bin_sub(ref.x, n_c, kw["sub_bits"])
     assert np.array_equal(pipe.cells.perm.cpu().numpy(), operm)
     got = gpu_fields(pipe)
     nd, nf = orc.count32(ref, n_c)
@@ -515,7 +520,82 @@ def test_full_size_medium(sph, orc):
     sub = {k: v[sel] for k, v in got.items()}
     sub["h"] = ref.h[sel]
     dsub = {k: v[sel] for k, v in d.items()}
-    check_fp32(sub, dsub, f, tag="M/sample")
+    check_fp32(sub, dsub, f, tag=f"M/sample/{tune.describe(choice)}")
     # FP64 reductions over all slots equal the sums of the counts
     out = pipe.red_out.cpu().numpy()
     assert out[6] == nd.sum() and out[7] == nf.sum()
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16_store"])
+def test_full_size_clustered(sph, orc, storage):
+    """4,194,304 clustered particles (occupancy 1..~2,000) in the tiling the
+    benchmark's autotuner chooses for each storage: binning bit-exact, counts
+    exact and values within the bar on a seeded sample of 2,048 particles
+    (blob and background), against the oracle on the stored values."""
+    from paper_2512_05516_amd import tune
+    ps = inputs.clustered_k_set(3)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    if storage == "fp32":
+        prec, fm, tol = None, None, FP32_TOL
+        sub_bits = (0, 1, 2)
+    else:
+        fm = ("f16", "bf16", "f16", (22, 7, 0))
+        prec, tol = sph.precision(*fm[:3], *fm[3]), 2e-5
+        sub_bits = (2,)
+    choice = tune.tune(rec, n_c, prec=prec, sub_bits=sub_bits, reps=2, cache_path=None)
+    pipe = run_gpu(ps, n_c, "f32", prec=prec, **tune.pipeline_kwargs(choice))
+    assert pipe.status() == 0
+    _, ostart, _, _ = orc.bin_cells(ref.x, n_c)
+    assert np.array_equal(pipe.cells.cell_start.cpu().numpy(), ostart)
+    occ = np.diff(ostart)
+    assert occ.max() > 1500 and occ.min() <= 2
+    got = gpu_fields(pipe)
+    rng = np.random.default_rng(12)
+    cell_of = np.minimum((ref.x * n_c).astype(int), n_c - 1) @ np.array([1, n_c, n_c * n_c])
+    blob = np.nonzero(occ[cell_of] > 500)[0]
+    sel = np.unique(np.concatenate([rng.choice(ps.n, 512, replace=False),
+                                    rng.choice(blob, 256, replace=False)])).astype(np.int32)
+    cnt_kw = dict(pos=fm[0], hdt=fm[2], h_scale=fm[3][1]) if fm else {}
+    nd, nf = orc.count32(ref, n_c, sel=sel, **cnt_kw)
+    assert np.array_equal(got["nngb"][sel], nd)
+    assert np.array_equal(got["nforce"][sel], nf)
+    q = orc.dequantise_set(ref, n_c, *fm[:3], fm[3]) if fm else ref
+    # the oracle's density is needed at the sample and at its force neighbours
+    # (r < max(H_i, H_j)); find those by a plain distance search
+    need = _force_neighbours(q, n_c, sel, orc.GAMMA_K)
+    dn = orc.density(q, n_c=n_c, sel=need)
+    d = {k: np.full(ps.n, np.nan) for k in ("rho", "wcount", "rho_dh", "f", "P", "c")}
+    d["nngb"] = np.full(ps.n, -1, np.int32)
+    for k in d:
+        d[k][need] = dn[k]
+    f = orc.force(q, d, n_c=n_c, sel=sel)
+    assert np.all(np.isfinite(f["a"])) and np.all(np.isfinite(f["du"]))
+    sub = {k: v[sel] for k, v in got.items()}
+    sub["h"] = q.h[sel]
+    dsub = {k: v[sel] for k, v in d.items()}
+    check_fp32(sub, dsub, f, tol=tol, tag=f"K/{storage}/sample/{tune.describe(choice)}")
+
+
+def _force_neighbours(ps, n_c, sel, gamma_k):
+    """Indices of sel and of every j with r_ij < max(H_i, H_j) for some i in
+    sel (periodic minimum image; candidates from the 27 cells around i)."""
+    x, H = np.asarray(ps.x), gamma_k * np.asarray(ps.h)
+    cell = np.minimum((x * n_c).astype(int), n_c - 1)
+    cid = cell @ np.array([1, n_c, n_c * n_c])
+    order = np.argsort(cid, kind="stable")
+    start = np.searchsorted(cid[order], np.arange(n_c ** 3 + 1))
+    out = [np.asarray(sel)]
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    for i in sel:
+        c = cell[i]
+        cand = np.concatenate([order[start[k]:start[k + 1]] for k in
+                               {((c[0] + dx) % n_c) + n_c * (((c[1] + dy) % n_c) +
+                                                           n_c * ((c[2] + dz) % n_c))
+                                for dx, dy, dz in offs}])
+        d = x[cand] - x[i]
+        d -= np.rint(d)
+        r = np.sqrt((d * d).sum(1))
+        out.append(cand[r < np.maximum(H[i], H[cand])])
+    return np.unique(np.concatenate(out)).astype(np.int32)

@@ -498,3 +498,13 @@ def test_cell_pair_partials_partition_the_full_sums(orc):
             ndj, _ = orc.count32(ps, n_c, mode="brute", jmask=(cell == cj))
             jm_counts += ndj[idx]
         assert np.array_equal(jm_counts, nd32[idx])
+
+
+def test_count32_selection_is_a_subset(orc):
+    """count32 over selected i returns exactly the full counts at those i."""
+    ps = inputs.clustered_set(5000, 3, f_blob=0.4, sigma=0.06)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    nd, nf = orc.count32(ps, n_c)
+    sel = np.random.default_rng(2).choice(ps.n, 300, replace=False).astype(np.int32)
+    a, b = orc.count32(ps, n_c, sel=sel)
+    assert np.array_equal(a, nd[sel]) and np.array_equal(b, nf[sel])
