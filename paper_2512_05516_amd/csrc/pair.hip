@@ -6,8 +6,8 @@ namespace sph {
 using namespace pairk;
 
 bool tile_supported(int ti, int k) {
-  return (ti == 64 && (k == 4 || k == 2 || k == 1)) || (ti == 32 && k == 8) ||
-         (ti == 128 && k == 2) || (ti == 16 && k == 16);
+  return (ti == 64 && (k == 4 || k == 2 || k == 1)) || (ti == 32 && (k == 8 || k == 2)) ||
+         (ti == 128 && k == 2) || (ti == 16 && (k == 16 || k == 4));
 }
 
 // Storage formats with compiled-in loaders; every other combination uses the

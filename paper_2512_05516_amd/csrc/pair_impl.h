@@ -1106,6 +1106,8 @@ hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, 
   SPH_DENS_CASE(64, 2)
   SPH_DENS_CASE(64, 1)
   SPH_DENS_CASE(16, 16)
+  SPH_DENS_CASE(16, 4)
+  SPH_DENS_CASE(32, 2)
 #undef SPH_DENS_CASE
   return hipErrorInvalidValue;
 }
@@ -1131,6 +1133,8 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   SPH_FORCE_CASE(64, 2)
   SPH_FORCE_CASE(64, 1)
   SPH_FORCE_CASE(16, 16)
+  SPH_FORCE_CASE(16, 4)
+  SPH_FORCE_CASE(32, 2)
 #undef SPH_FORCE_CASE
   return hipErrorInvalidValue;
 }

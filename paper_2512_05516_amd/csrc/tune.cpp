@@ -14,7 +14,7 @@ sph_status host_fail(sph_status code, const char* msg);
 namespace {
 
 // Tiles in the order they are tried (ti, k)
-const int kTiles[][2] = {{64, 4}, {32, 8}, {128, 2}, {64, 2}, {64, 1}, {16, 16}};
+const int kTiles[][2] = {{64, 4}, {32, 8}, {128, 2}, {64, 2}, {64, 1}, {16, 16}, {16, 4}, {32, 2}};
 const int kScheds[] = {-1, SPH_SCHED_GRID, SPH_SCHED_STATIC, SPH_SCHED_DYNAMIC};
 
 struct Events {

@@ -41,6 +41,7 @@ def test_exports_every_header_symbol(sph):
 def test_abi_version_and_tiles(sph):
     assert sph.abi_version() == 3
     assert sph.tile_supported(64, 4)
+    assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
 
 
@@ -140,8 +141,8 @@ def test_host_side_validation(sph):
 def test_tuner_host_side(sph):
     L = sph.lib()
     cand = sph.tune_candidates()
-    assert len(cand) == 24
-    assert len(set(cand)) == 24
+    assert len(cand) == 32
+    assert len(set(cand)) == 32
     assert {c[2] for c in cand} == {None, "grid", "static", "dynamic"}
     assert all(sph.tile_supported(t, k) for t, k, _ in cand)
     n = C.c_int32()

@@ -300,7 +300,9 @@ def ragged(orc):
                                              (64, 1, 0, None), (64, 4, 2, "dynamic"),
                                              (32, 8, 3, "static"), (16, 16, 2, "grid"),
                                              (128, 2, 1, "dynamic"), (64, 1, 3, "grid"),
-                                             (64, 4, 1, "static"), (32, 8, 2, "grid")])
+                                             (64, 4, 1, "static"), (32, 8, 2, "grid"),
+                                             (16, 4, 0, None), (32, 2, 2, "grid"),
+                                             (16, 4, 3, "static")])
 def test_ragged_clustered_parity(sph, ragged, ti, k, bits, sched):
     ps, ref, n_c, nd, nf, d, f = ragged
     pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k), sub_bits=bits, sched=sched)
