@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 4
+#define SPH_ABI_VERSION 3
 
 typedef int32_t sph_status;
 enum {
@@ -114,10 +114,6 @@ typedef struct {
                           /* sub_bits > 0, else may be NULL               */
   float *hmax;            /* [n_c^3] largest h of each cell (written by   */
                           /* sph_bin when the layout has H; may be NULL)  */
-  float *sub_hmax;        /* [n_c^3 R^3] largest h of each sub-cell key    */
-                          /* (written by sph_bin when sub_bits > 0 and the */
-                          /* layout has H; may be NULL). The force loop   */
-                          /* bounds its search per sub-cell with it.      */
   int32_t *status;        /* [1] optional (may be NULL) SPH_FLAG_* word   */
 } sph_cells;
 
@@ -217,8 +213,8 @@ sph_status sph_bin_workspace_size(int32_t n, int32_t n_c, size_t *bytes);
  * Writes cells->cell_start, cells->perm and cells->cell (stable order by
  * (cell id, sub-cell Morton code, input index): bit-identical on every
  * run), cells->sub_start when sub_bits > 0, and cells->hmax (max h of each
- * cell, h read as stored in the record) and cells->sub_hmax (the same per
- * sub-cell key, sub_bits > 0) when they are non-NULL and the layout has H. cells->n, n_c and sub_bits are inputs. Raises
+ * cell, h read as stored in the record) when it is non-NULL and the layout
+ * has H. cells->n, n_c and sub_bits are inputs. Raises
  * SPH_FLAG_BAD_POSITION for non-finite x (such particles go to cell 0). */
 sph_status sph_bin(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
                    void *workspace, size_t workspace_bytes, hipStream_t stream);

@@ -116,7 +116,6 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   out.cell = c->cell;
   out.sub_start = c->sub_bits > 0 ? c->sub_start : c->cell_start;
   out.hmax = c->hmax;
-  out.sub_hmax = c->sub_bits > 0 ? c->sub_hmax : nullptr;
   out.status = c->status;
   return SPH_OK;
 }
@@ -292,8 +291,7 @@ sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cell
     return fail(SPH_E_NOMEM, "workspace has %zu bytes, sph_bin needs %zu", workspace_bytes, need);
   return hip_status(launch_bin(aos, L, c, cells->cell_start, cells->perm, cells->cell,
                                cells->sub_bits > 0 ? cells->sub_start : nullptr, cells->hmax,
-                               cells->sub_bits > 0 ? cells->sub_hmax : nullptr, workspace,
-                               stream),
+                               workspace, stream),
                     "sph_bin");
 }
 

@@ -36,7 +36,6 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
                                                         int32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
                                                         float* __restrict__ hmax,
-                                                        float* __restrict__ sub_hmax,
                                                         int32_t* status) {
   __shared__ uint2 span[kThreads * kSpanWords];
   const int i0 = blockIdx.x * kThreads;
@@ -72,28 +71,23 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
     sc[k] = sa;
   }
   const int cell = c[0] + n_c * (c[1] + n_c * c[2]);
-  const int key = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
   if (valid) {
-    keys[i] = key;
+    keys[i] = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
     vals[i] = i;
   }
-  if ((hmax || sub_hmax) && offh != kAbsent) {
+  if (hmax && offh != kAbsent) {
     const float h = valid ? rec_load32(rec, rh, dth) : 0.0f;
     const bool contrib = valid && h > 0.0f;
-    if (sub_hmax && contrib) atomicMax(reinterpret_cast<int*>(sub_hmax) + key, __float_as_int(h));
     // input in cell order (buffers of co-located particles): when every
     // contributing lane of the wave has the same cell, one atomic per wave
-    // (hmax is a kernel argument, so the branch is uniform)
-    if (hmax) {
-      const int lead = __shfl(cell, __ffsll((long long)__ballot(contrib)) - 1);
-      if (__all(!contrib || cell == lead)) {
-        float m = contrib ? h : 0.0f;
-        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-        if ((threadIdx.x & 63) == 0 && m > 0.0f)
-          atomicMax(reinterpret_cast<int*>(hmax) + lead, __float_as_int(m));
-      } else if (contrib) {
-        atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
-      }
+    const int lead = __shfl(cell, __ffsll((long long)__ballot(contrib)) - 1);
+    if (__all(!contrib || cell == lead)) {
+      float m = contrib ? h : 0.0f;
+      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+      if ((threadIdx.x & 63) == 0 && m > 0.0f)
+        atomicMax(reinterpret_cast<int*>(hmax) + lead, __float_as_int(m));
+    } else if (contrib) {
+      atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
     }
   }
   if (valid && bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
@@ -298,28 +292,26 @@ size_t bin_workspace_bytes(int n, int n_c, int sub_bits) {
 }
 
 hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
-                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax,
-                      float* sub_hmax, void* ws, hipStream_t s) {
+                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax, void* ws,
+                      hipStream_t s) {
   const int n = c.n, n_c = c.n_c, sb = c.sub_bits;
   const int C = n_c * n_c * n_c;
   const int S = C << (3 * sb);
   const int nblk = cdiv(n, kTile);
   BinWs w = carve(ws, n, nblk);
   if (hmax) k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
-  if (!sb) sub_hmax = nullptr;
-  if (sub_hmax) k_fill_f32<<<cdiv(S, kThreads), kThreads, 0, s>>>(sub_hmax, S, 0.0f);
   int32_t* skeys = cell;                 // sorted keys (cell ids when sb == 0)
   if (n > 0) {
     // span of the record bytes the keys need: x, and h when hmax is wanted
     const uint32_t ox = L.off[SPH_A_X], oh = L.off[SPH_A_H];
-    const bool want_h = (hmax || sub_hmax) && oh != kAbsent;
+    const bool want_h = hmax && oh != kAbsent;
     const uint32_t hsz = L.dt[SPH_A_H] == DT_F64 ? 8u : 4u;
     const uint32_t lo = (want_h ? min(ox, oh) : ox) & ~7u;
     const uint32_t hi = (max(ox + 24u, want_h ? oh + hsz : 0u) + 7u) & ~7u;
     const int nw = (hi - lo) / 8 <= (uint32_t)kSpanWords ? (int)((hi - lo) / 8) : 0;
     k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(
         static_cast<const char*>(aos), L.stride, ox, oh, L.dt[SPH_A_H], lo, nw, n, n_c, sb, w.ka,
-        w.va, want_h ? hmax : nullptr, want_h ? sub_hmax : nullptr, c.status);
+        w.va, want_h ? hmax : nullptr, c.status);
     int bits = 1;
     while ((1 << bits) < S) ++bits;
     int passes = (bits + 7) / 8;

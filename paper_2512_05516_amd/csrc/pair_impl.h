@@ -331,15 +331,15 @@ constexpr int kSplitFactor = 2;
 
 // The candidate ranges of a chunk: for each of the 27 neighbour cells q
 // with bound(q) > 0, the sub-cells (R = 2^sub_bits per axis) of q whose
-// boxes lie within sub_bound(q, key) (<= bound(q)) of the chunk box
-// [lo, hi], or the whole of q (a superset) when q is sparse. Entries are processed in
+// boxes lie within bound(q) of the chunk box [lo, hi], or the whole of q
+// (a superset) when q is sparse. Entries are processed in
 // batches of at most NT: for each batch, `batch(tab)` gathers the
 // particles of the batch's ranges.
-template <int NT, class Bound, class SubBound, class Batch>
+template <int NT, class Bound, class Batch>
 __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells& T,
                                               RangeTab<NT>& tab, float s32, float lox, float loy,
                                               float loz, float hix, float hiy, float hiz,
-                                              Bound bound, SubBound sub_bound, Batch batch) {
+                                              Bound bound, Batch batch) {
   const int sb = cd.sub_bits, R = 1 << sb;
   const float ss = s32 / (float)R;
   const float inv = (float)R / s32;
@@ -391,7 +391,6 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
     const int t = b0 + tid;
     bool ok = t < NQ;
     int st = 0, cnt = 0, q = 0;
-    float bq = 0.0f;
     if (ok) {
       int lo = 0, hi = 26;   // last q with qpre[q] <= t
       while (lo < hi) {
@@ -411,7 +410,6 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         bz0 = dz * s32 - mg, bz1 = (dz + 1) * s32 + mg;
         st = clamp_slot(cd.start[c], cd.n);
         cnt = max(clamp_slot(cd.start[c + 1], cd.n) - st, 0);
-        bq = bound(q);
       } else {
         const unsigned char* r = tab.qr[q];
         const int nx = r[1] - r[0] + 1, ny = r[3] - r[2] + 1;
@@ -428,11 +426,11 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         const int key = (c << (3 * sb)) + m;
         st = clamp_slot(sstart[key], cd.n);
         cnt = max(clamp_slot(sstart[key + 1], cd.n) - st, 0);
-        bq = sub_bound(q, key);
       }
       const float ex = fmaxf(fmaxf(bx0 - hix, lox - bx1), 0.0f);
       const float ey = fmaxf(fmaxf(by0 - hiy, loy - by1), 0.0f);
       const float ez = fmaxf(fmaxf(bz0 - hiz, loz - bz1), 0.0f);
+      const float bq = bound(q);
       ok = cnt > 0 && ex * ex + ey * ey + ez * ez < bq * bq * (1.0f + 0x1p-10f);
     }
     int e_idx, e_pre, ntab, total;
@@ -750,7 +748,6 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
-        [&](int q, int) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
@@ -957,13 +954,6 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
-        [&](int q, int key) {
-          // the sub-cell's own largest H (storage rounding of h covered as
-          // for the cell bound); the cell's when no sub-cell table is given
-          if (!(only_q == -1 || q == only_q)) return 0.0f;
-          return cd.sub_hmax ? fmaxf(bi, gk * cd.sub_hmax[key] * (1.0f + 0x1p-8f))
-                             : fmaxf(bi, T.hb[q]);
-        },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {

@@ -41,7 +41,6 @@ struct CellsDev {
   const int32_t* cell;
   const int32_t* sub_start;
   const float* hmax;
-  const float* sub_hmax;   // per sub-cell key (sub_bits > 0), or nullptr
   int32_t* status;
 };
 
@@ -62,8 +61,8 @@ constexpr size_t kWorkHeader = 256;   // bytes before the items
 // --- launchers (return hipError_t of the launch) ---
 size_t bin_workspace_bytes(int n, int n_c, int sub_bits);
 hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, int32_t* cell_start,
-                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax,
-                      float* sub_hmax, void* ws, hipStream_t s);
+                      int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax, void* ws,
+                      hipStream_t s);
 
 // exclusive scan of int32 in place; partials: scan_partials_count(len) ints
 size_t scan_partials_count(int len);

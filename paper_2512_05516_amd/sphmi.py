@@ -52,7 +52,7 @@ class Cells(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("sub_bits", C.c_int32),
                 ("reserved", C.c_int32), ("cell_start", C.c_void_p), ("perm", C.c_void_p),
                 ("cell", C.c_void_p), ("sub_start", C.c_void_p), ("hmax", C.c_void_p),
-                ("sub_hmax", C.c_void_p), ("status", C.c_void_p)]
+                ("status", C.c_void_p)]
 
 
 class Work(C.Structure):
@@ -224,8 +224,7 @@ _TORCH_DT = {F32: "float32", F16: "float16", BF16: "bfloat16"}
 
 class DeviceCells:
     """Cell list arrays on the device: cell_start[C+1], perm[n], cell[n],
-    sub_start[C 8^sub_bits + 1] and sub_hmax[C 8^sub_bits] (sub_bits > 0),
-    hmax[C], status[1]."""
+    sub_start[C 8^sub_bits + 1] (sub_bits > 0), hmax[C], status[1]."""
 
     def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0):
         import torch
@@ -237,15 +236,11 @@ class DeviceCells:
         self.sub_start = (torch.zeros(C_ * 8 ** self.sub_bits + 1, dtype=torch.int32, device=device)
                           if self.sub_bits else None)
         self.hmax = torch.zeros(C_, dtype=torch.float32, device=device)
-        self.sub_hmax = (torch.zeros(C_ * 8 ** self.sub_bits, dtype=torch.float32, device=device)
-                         if self.sub_bits else None)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self._s = Cells(self.n, self.n_c, self.sub_bits, 0, self.cell_start.data_ptr(),
                         self.perm.data_ptr(), self.cell.data_ptr(),
                         self.sub_start.data_ptr() if self.sub_start is not None else None,
-                        self.hmax.data_ptr(),
-                        self.sub_hmax.data_ptr() if self.sub_hmax is not None else None,
-                        self.status.data_ptr())
+                        self.hmax.data_ptr(), self.status.data_ptr())
 
     @property
     def struct(self) -> Cells:

@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 4
+    assert sph.abi_version() == 3
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
@@ -64,8 +64,7 @@ def test_workspace_size_validation(sph):
 
 def _fake_cells(sph, n=16, n_c=4, lists=True, sub_bits=0, sub=True):
     dummy = C.c_void_p(0x1000) if lists else None
-    return sph.Cells(n, n_c, sub_bits, 0, dummy, dummy, dummy, dummy if sub else None, None, None,
-                     None)
+    return sph.Cells(n, n_c, sub_bits, 0, dummy, dummy, dummy, dummy if sub else None, None, None)
 
 
 def test_host_side_validation(sph):

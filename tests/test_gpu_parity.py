@@ -70,8 +70,7 @@ def _bin_gpu(sph, x, n_c, sub_bits=0, h=None):
            pipe.cells.cell[:n].cpu().numpy(), pipe.status())
     if sub_bits or h is not None:
         sub = pipe.cells.sub_start.cpu().numpy() if sub_bits else None
-        sub_h = pipe.cells.sub_hmax.cpu().numpy() if sub_bits else None
-        return out + (sub, pipe.cells.hmax.cpu().numpy(), sub_h)
+        return out + (sub, pipe.cells.hmax.cpu().numpy())
     return out
 
 
@@ -98,7 +97,7 @@ def test_bin_sub_cells_bit_exact(sph, orc, n, n_c, bits):
     rng = np.random.default_rng(n + 7 * bits)
     x = rng.uniform(-0.5, 1.5, size=(n, 3))
     h = rng.uniform(0.01, 0.02, size=n)
-    start, perm, cell, status, sub, hmax, sub_h = _bin_gpu(sph, x, n_c, bits, h)
+    start, perm, cell, status, sub, hmax = _bin_gpu(sph, x, n_c, bits, h)
     key, osub, operm = orc.bin_sub(x, n_c, bits)
     ocell, ostart, _, _ = orc.bin_cells(x, n_c)
     assert status == 0
@@ -111,10 +110,6 @@ def test_bin_sub_cells_bit_exact(sph, orc, n, n_c, bits):
     want = np.zeros(n_c ** 3, np.float32)
     np.maximum.at(want, ocell, h32)
     assert np.array_equal(hmax, want)
-    # sub_hmax: the same per sub-cell key
-    want = np.zeros(n_c ** 3 * 8 ** bits, np.float32)
-    np.maximum.at(want, key, h32)
-    assert np.array_equal(sub_h, want)
 
 
 def test_bin_flags_non_finite(sph):
