@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 F32, F16, BF16, F64 = 0, 1, 2, 3
 DTYPE_CODES = {"f32": F32, "f16": F16, "bf16": BF16, "f64": F64}
+TRUNC = 0x100
+# truncate_mantissa storage of T bits in total: "t9" ... "t64"
+DTYPE_CODES.update({f"t{T}": TRUNC + T for T in range(9, 65)})
 
 # Constants of the method (paper Sec. 2.1 names the cubic spline; the values
 # are the readings listed in the design notes).

@@ -520,9 +520,39 @@ void orc_dequant_array(int64_t n, const uint16_t *in, float *out, int dtype) {
     out[i] = dtype == ORC_BF16 ? orc_bf16_to_f32(in[i]) : orc_f16_to_f32(in[i]);
 }
 
+/* truncate_mantissa(T) storage (Sec. 3.2, Table 2), T bits in total: where T
+ * is an IEEE size (64, 32, 16) that format is used; otherwise the smallest
+ * IEEE layout wider than T keeps its sign and exponent fields and the top
+ * T - 1 - e bits of its mantissa (e = 11, 8, 5 for 33..63, 17..31, 9..15),
+ * the lower bits being cut off (rounding toward zero). A value reaches its
+ * base layout by the IEEE conversion (round to nearest even): FP64 -> FP32
+ * for T <= 32, then FP32 -> half for T <= 16. Written on the bit patterns:
+ * the stored code is the top T bits of the base pattern. */
+static double trunc_roundtrip(double v, int T, int scale) {
+  if (T >= 64) return v;
+  if (T >= 33) {
+    uint64_t b;
+    double s = ldexp(v, scale);
+    memcpy(&b, &s, 8);
+    b = (b >> (64 - T)) << (64 - T);
+    memcpy(&s, &b, 8);
+    return ldexp(s, -scale);
+  }
+  float s = ldexpf((float)v, scale);
+  if (T >= 17) {
+    uint32_t b = f32_bits(s);
+    b = (b >> (32 - T)) << (32 - T);
+    return (double)ldexpf(bits_f32(b), -scale);
+  }
+  uint16_t h = orc_f32_to_f16(s);
+  h = (uint16_t)((h >> (16 - T)) << (16 - T));
+  return (double)ldexpf(orc_f16_to_f32(h), -scale);
+}
+
 /* stored value of v: RNE to FP32, times 2^scale (exact), RNE to the storage
  * format; read back: widen to FP32, times 2^-scale. FP64 storage is exact. */
 static float roundtrip32(double v, int dtype, int scale) {
+  if (dtype >= ORC_TRUNC) return (float)trunc_roundtrip(v, dtype - ORC_TRUNC, scale);
   float q32 = (float)v;
   if (dtype == ORC_F32) return q32;
   float s = ldexpf(q32, scale);
@@ -533,6 +563,7 @@ static float roundtrip32(double v, int dtype, int scale) {
 
 double orc_roundtrip(double v, int dtype, int scale) {
   if (dtype == ORC_F64) return v;
+  if (dtype >= ORC_TRUNC) return trunc_roundtrip(v, dtype - ORC_TRUNC, scale);
   return (double)roundtrip32(v, dtype, scale);
 }
 

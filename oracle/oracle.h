@@ -35,6 +35,9 @@ typedef struct {
 
 /* dtype codes shared with the quantiser entry points */
 enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_F64 = 3 };
+/* truncate_mantissa storage of total size T bits (Sec. 3.2, Table 2):
+ * dtype ORC_TRUNC + T, 9 <= T <= 64 */
+enum { ORC_TRUNC = 0x100 };
 
 /* kernel */
 double orc_w_hat(double u);

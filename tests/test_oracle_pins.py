@@ -508,3 +508,59 @@ def test_count32_selection_is_a_subset(orc):
     sel = np.random.default_rng(2).choice(ps.n, 300, replace=False).astype(np.int32)
     a, b = orc.count32(ps, n_c, sel=sel)
     assert np.array_equal(a, nd[sel]) and np.array_equal(b, nf[sel])
+
+
+def test_truncated_storage_formats(orc):
+    """truncate_mantissa storage of T bits (Table 2): the IEEE sizes are the
+    IEEE formats, other sizes keep the next wider layout's sign and exponent
+    and cut its mantissa to T - 1 - e bits (toward zero)."""
+    rng = np.random.default_rng(4)
+    vals = np.concatenate([rng.normal(0, 1, 500), rng.uniform(-1e-3, 1e-3, 200),
+                           [0.0, -0.0, 1.0, -2.5, 1e-30]])
+    for v in vals:
+        assert orc.roundtrip(v, "t64") == v
+        assert orc.roundtrip(v, "t32") == orc.roundtrip(v, "f32")
+        assert orc.roundtrip(v, "t16", 6) == orc.roundtrip(v, "f16", 6)
+    # cut, not rounded: T = 40 (double layout, 28 mantissa bits), T = 20
+    # (single layout, 11 bits), T = 12 (half layout, 6 bits)
+    for T, m in (("t40", 28), ("t20", 11), ("t12", 6)):
+        assert orc.roundtrip(1 + 2.0 ** -m, T) == 1 + 2.0 ** -m
+        assert orc.roundtrip(1 + 2.0 ** -(m + 1), T) == 1.0
+        assert orc.roundtrip(1 + 2.0 ** -m + 2.0 ** -(m + 1), T) == 1 + 2.0 ** -m
+        assert orc.roundtrip(-(1 + 2.0 ** -(m + 1)), T) == -1.0
+        assert orc.roundtrip(2 - 2.0 ** -(m + 1), T) == 2 - 2.0 ** -m
+    # relative error of the cut: below 2^-m (plus the IEEE rounding to the base)
+    for T in range(9, 64):
+        e = 11 if T > 32 else (8 if T > 16 else 5)
+        m = T - 1 - e
+        base = 0.0 if T > 32 else (2.0 ** -24 if T > 16 else 2.0 ** -11 + 2.0 ** -24)
+        for v in rng.uniform(0.5, 2.0, 50):
+            q = orc.roundtrip(v, f"t{T}")
+            assert abs(q) <= abs(v) * (1 + base)
+            assert abs(q - v) <= (2.0 ** -m + base) * abs(v)
+
+
+def test_truncation_error_curve_shape(orc):
+    """Acceleration error of one force evaluation on truncated storage (all
+    fields, T bits) against FP64, with FP64 arithmetic: zero at 64 bits,
+    growing as bits are cut within each layout, and lower at exactly 32 and
+    16 bits than one bit above, where the base layout switches to IEEE
+    single and half (the shape the paper reports for its figure on the
+    force kernel's error)."""
+    ps = inputs.small_set(1)
+    n_c = 4
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f64"))
+    d0 = orc.density(ref, n_c=n_c)
+    f0 = orc.force(ref, d0, n_c=n_c)
+    e = {}
+    for T in range(9, 65):
+        q = orc.dequantise_set(ref, n_c, f"t{T}", f"t{T}", f"t{T}", (12, 3, 0))
+        d = orc.density(q, n_c=n_c)
+        f = orc.force(q, d, n_c=n_c)
+        e[T] = np.sqrt((np.linalg.norm(f["a"] - f0["a"], axis=1) ** 2).mean()) / \
+            np.linalg.norm(f0["a"], axis=1).mean()
+    assert e[64] == 0.0
+    for lo, hi in ((33, 63), (17, 31), (9, 15)):
+        for T in range(lo, hi):
+            assert e[T] > e[T + 1], T
+    assert e[32] < e[33] and e[16] < e[17]
