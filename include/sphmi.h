@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 3
+#define SPH_ABI_VERSION 4
 
 typedef int32_t sph_status;
 enum {
@@ -67,8 +67,16 @@ enum {
 
 /* storage formats (Table 2: 64, 32 and 16 total bits; plus bfloat16) */
 typedef enum {
-  SPH_F64 = 0, SPH_F32 = 1, SPH_F16 = 2, SPH_BF16 = 3, SPH_I32 = 4
+  SPH_F64 = 0, SPH_F32 = 1, SPH_F16 = 2, SPH_BF16 = 3, SPH_I32 = 4,
+  SPH_TRUNC = 0x100
 } sph_dtype;
+/* truncate_mantissa storage of T bits in total (Sec. 3.2, Table 2), for
+ * the narrowed SoA views, 9 <= T <= 32: the top T bits of the value's IEEE
+ * single (T > 16) or half (T <= 16) pattern, the rest of the mantissa cut
+ * off (toward zero); T = 32 and 16 are single and half. The codes form one
+ * bitstream per field: value k at bits [kT, kT + T) of little-endian 32-bit
+ * words. A field buffer holds sph_storage_bytes(n, dtype) bytes. */
+#define SPH_TRUNC_BITS(T) (SPH_TRUNC + (T))
 
 /* ------------------------------------------------------------------ */
 /* AoS record description (Table 1 fields; "all variants derive from   */
@@ -160,11 +168,14 @@ typedef struct {
   void *f[SPH_S_NFIELDS];
 } sph_soa;
 
-/* storage precision of the narrowed views. pos: SPH_F32 | SPH_F16 |
- * SPH_BF16; vel and mhu: SPH_F32 | SPH_F16 | SPH_BF16. A field with scale
- * s is stored as RNE(RNE32(v) * 2^s) and read back as stored * 2^-s
- * (|s| <= 64; exact power-of-two scaling keeps small masses and
- * smoothing lengths in the normal range of FP16). */
+/* storage precision of the narrowed views. pos, vel and mhu: SPH_F32 |
+ * SPH_F16 | SPH_BF16 | SPH_TRUNC_BITS(T). A field with scale s is stored as
+ * Q(RNE32(v) * 2^s) and read back as stored * 2^-s (|s| <= 64; exact
+ * power-of-two scaling keeps small masses and smoothing lengths in the
+ * normal range of FP16); Q rounds to nearest even for the IEEE formats and
+ * cuts the mantissa for SPH_TRUNC_BITS. Truncated formats are written by
+ * sph_convert only (records of at most 208 bytes), and read by the kernels'
+ * run-time format path. */
 typedef struct {
   int32_t pos, vel, mhu;
   int32_t scale_m, scale_h, scale_u;
@@ -198,6 +209,10 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 
 int32_t sph_abi_version(void);
+
+/* Bytes of an SoA field of n values stored in dtype (SPH_F32, SPH_F16,
+ * SPH_BF16 or SPH_TRUNC_BITS(T)). */
+sph_status sph_storage_bytes(int32_t n, int32_t dtype, size_t *bytes);
 const char *sph_last_error(void);
 
 /* 1 if the tiling is compiled in, else 0. */

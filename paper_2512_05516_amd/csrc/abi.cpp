@@ -34,7 +34,9 @@ sph_status hip_status(hipError_t e, const char* what) {
 }
 
 bool is_float_dt(int dt) { return dt == SPH_F32 || dt == SPH_F64; }
-bool is_store_dt(int dt) { return dt == SPH_F32 || dt == SPH_F16 || dt == SPH_BF16; }
+bool is_store_dt(int dt) {
+  return dt == SPH_F32 || dt == SPH_F16 || dt == SPH_BF16 || is_trunc(dt);
+}
 
 int elem_size(int dt) {
   switch (dt) {
@@ -137,7 +139,8 @@ sph_status check_work(const sph_work* w, const CellsDev& c, int ti, WorkDev& out
 sph_status check_prec(const sph_precision* p, Prec& out) {
   if (!p) return fail(SPH_E_INVALID, "precision is NULL");
   if (!is_store_dt(p->pos) || !is_store_dt(p->vel) || !is_store_dt(p->mhu))
-    return fail(SPH_E_INVALID, "precision formats must be SPH_F32, SPH_F16 or SPH_BF16");
+    return fail(SPH_E_INVALID,
+                "precision formats must be SPH_F32, SPH_F16, SPH_BF16 or SPH_TRUNC_BITS(9..32)");
   const int32_t sc[3] = {p->scale_m, p->scale_h, p->scale_u};
   for (int q = 0; q < 3; ++q)
     if (sc[q] < -64 || sc[q] > 64) return fail(SPH_E_INVALID, "precision scale %d out of range", sc[q]);
@@ -243,6 +246,14 @@ extern "C" {
 
 int32_t sph_abi_version(void) { return SPH_ABI_VERSION; }
 
+sph_status sph_storage_bytes(int32_t n, int32_t dtype, size_t* bytes) {
+  if (!bytes || n < 0) return fail(SPH_E_INVALID, "sph_storage_bytes: bad arguments");
+  if (!is_store_dt(dtype))
+    return fail(SPH_E_INVALID, "sph_storage_bytes: dtype %d is not a storage format", dtype);
+  *bytes = storage_bytes(n, dtype);
+  return SPH_OK;
+}
+
 const char* sph_last_error(void) { return g_err.c_str(); }
 
 int32_t sph_tile_supported(sph_tile tile) { return tile_supported(tile.ti, tile.k) ? 1 : 0; }
@@ -306,6 +317,10 @@ sph_status sph_convert(const void* aos, const sph_aos_layout* layout, const sph_
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
   SPH_TRY(check_aos_ptr(aos, c.n));
+  if ((is_trunc(p.pos) || is_trunc(p.vel) || is_trunc(p.mhu)) && L.stride > kMaxPackedStride)
+    return fail(SPH_E_UNSUPPORTED,
+                "sph_convert: truncated storage needs records of at most %u bytes",
+                kMaxPackedStride);
   return hip_status(launch_convert(aos, L, c, view, p, *out, stream), "sph_convert");
 }
 

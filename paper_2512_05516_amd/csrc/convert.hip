@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_writeback_direct(SoaIn s, CellsDev
 
 // --- whole-record staging ----------------------------------------------------
 constexpr int kTileSlots = 256;                 // slots per workgroup
-constexpr int kMaxStagedStride = 248;           // (stride/8 + 1) * 8 * 256 <= 64 KiB
+// kMaxStagedStride (248): (stride/8 + 1) * 8 * 256 <= 64 KiB
 
 // Copy the records of slots [k0, k0 + nk) between global memory and LDS rows
 // of W + 1 words. Word e of the tile is (record e / W, word e % W); the
@@ -156,12 +156,17 @@ __device__ __forceinline__ void stage_records(uint64_t* rows, const int* prm, ch
   }
 }
 
-template <int W_>
+// Narrowed fields of the pair views, in the order of SoaOut's arrays
+enum : int { kF_OFF = 0, kF_VQ = 3, kF_M = 6, kF_H = 7, kF_U = 8, kNarrowed = 9 };
+
+template <int W_, bool PACK>
 __global__ __launch_bounds__(kThreads) void k_convert_staged(const char* __restrict__ aos,
                                                               AosLayout L, CellsDev cd, int view,
                                                               Prec p, SoaOut o) {
   extern __shared__ uint64_t rows[];
   __shared__ int prm[kTileSlots];
+  // codes of the truncated fields, assembled into whole words at the end
+  __shared__ uint32_t codes[PACK ? kNarrowed : 1][PACK ? kTileSlots : 1];
   const int W = W_ > 0 ? W_ : (int)(L.stride >> 3), pitch = W + 1;
   const int k0 = blockIdx.x * kTileSlots;
   const int nk = min(kTileSlots, cd.n - k0);
@@ -170,42 +175,80 @@ __global__ __launch_bounds__(kThreads) void k_convert_staged(const char* __restr
   stage_records<W_, true>(rows, prm, const_cast<char*>(aos), nk, W, L.stride);
   __syncthreads();
   const int t = threadIdx.x;
-  if (t >= nk) return;
-  const int k = k0 + t;
-  const char* rec = reinterpret_cast<const char*>(rows + t * pitch);
   const bool pair_view = view != SPH_VIEW_KICK;
   const bool need_v = view != SPH_VIEW_DENSITY;
   const bool need_u = view != SPH_VIEW_FORCE;
-  const double* xp = reinterpret_cast<const double*>(rec + L.off[SPH_A_X]);
-  double xw[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) xw[a] = wrap01(xp[a]);
-  double v[3] = {0.0, 0.0, 0.0};
-  if (need_v) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = rec_load(rec, L.off[SPH_A_V], L.dt[SPH_A_V], a);
+  // narrowed field f of slot k: an IEEE store, or this slot's code
+  auto put = [&](int f, void* dst, int dt, int k, float q) {
+    if constexpr (PACK) {
+      if (dt >= DT_TRUNC) {
+        codes[f][t] = trunc_code(q, dt - DT_TRUNC);
+        return;
+      }
+    }
+    store_q32(dst, dt, k, q, 1.0f);
+  };
+  if constexpr (PACK) {
+    for (int f = 0; f < kNarrowed; ++f) codes[f][t] = 0u;   // slots past n
   }
-  const double u = need_u ? rec_load(rec, L.off[SPH_A_U], L.dt[SPH_A_U]) : 0.0;
-  if (pair_view) {
-    int c3[3];
-    cell_coords(cd.cell[k], cd.n_c, c3[0], c3[1], c3[2]);
+  if (t < nk) {
+    const int k = k0 + t;
+    const char* rec = reinterpret_cast<const char*>(rows + t * pitch);
+    const double* xp = reinterpret_cast<const double*>(rec + L.off[SPH_A_X]);
+    double xw[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) store_q32(o.off[a], p.pos, k, cell_offset(xw[a], c3[a], cd.n_c), 1.0f);
-    store_q(o.m, p.mhu, k, rec_load(rec, L.off[SPH_A_M], L.dt[SPH_A_M]), p.store_m);
-    store_q(o.h, p.mhu, k, rec_load(rec, L.off[SPH_A_H], L.dt[SPH_A_H]), p.store_h);
-    if (view != SPH_VIEW_FORCE) store_q(o.u, p.mhu, k, u, p.store_u);
-    if (view != SPH_VIEW_DENSITY) {
+    for (int a = 0; a < 3; ++a) xw[a] = wrap01(xp[a]);
+    double v[3] = {0.0, 0.0, 0.0};
+    if (need_v) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) store_q(o.vq[a], p.vel, k, v[a], 1.0f);
+      for (int a = 0; a < 3; ++a) v[a] = rec_load(rec, L.off[SPH_A_V], L.dt[SPH_A_V], a);
+    }
+    const double u = need_u ? rec_load(rec, L.off[SPH_A_U], L.dt[SPH_A_U]) : 0.0;
+    if (pair_view) {
+      int c3[3];
+      cell_coords(cd.cell[k], cd.n_c, c3[0], c3[1], c3[2]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        put(kF_OFF + a, o.off[a], p.pos, k, cell_offset(xw[a], c3[a], cd.n_c));
+      put(kF_M, o.m, p.mhu, k, (float)rec_load(rec, L.off[SPH_A_M], L.dt[SPH_A_M]) * p.store_m);
+      put(kF_H, o.h, p.mhu, k, (float)rec_load(rec, L.off[SPH_A_H], L.dt[SPH_A_H]) * p.store_h);
+      if (view != SPH_VIEW_FORCE) put(kF_U, o.u, p.mhu, k, (float)u * p.store_u);
+      if (view != SPH_VIEW_DENSITY) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) put(kF_VQ + a, o.vq[a], p.vel, k, (float)v[a]);
+      }
+    }
+    if (view == SPH_VIEW_KICK || view == SPH_VIEW_FULL) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        o.x[a][k] = xw[a];
+        o.v[a][k] = (float)v[a];
+      }
+      o.uk[k] = (float)u;
     }
   }
-  if (view == SPH_VIEW_KICK || view == SPH_VIEW_FULL) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      o.x[a][k] = xw[a];
-      o.v[a][k] = (float)v[a];
+  if constexpr (!PACK) return;
+  if (!pair_view) return;
+  __syncthreads();
+  // the tile's 256 codes of T bits fill words [8 T b, 8 T (b + 1)) exactly
+  for (int f = 0; f < kNarrowed; ++f) {
+    const int dt = f < kF_VQ ? p.pos : (f < kF_M ? p.vel : p.mhu);
+    void* dst = f < kF_VQ ? o.off[f] : (f < kF_M ? o.vq[f - kF_VQ] : (f == kF_M ? o.m : (f == kF_H ? o.h : o.u)));
+    const bool present = (f < kF_VQ || f == kF_M || f == kF_H) ||
+                         (f < kF_M ? view != SPH_VIEW_DENSITY : view != SPH_VIEW_FORCE);
+    if (dt < DT_TRUNC || !present) continue;     // uniform
+    const int T = dt - DT_TRUNC;
+    const int nw = 8 * T;
+    for (int w = t; w < nw; w += kThreads) {
+      const int b0 = 32 * w;
+      uint32_t word = 0u;
+      for (int j = b0 / T; j <= (b0 + 31) / T && j < kTileSlots; ++j) {
+        const int sh = j * T - b0;
+        const uint64_t c = codes[f][j];
+        word |= sh >= 0 ? (uint32_t)(c << sh) : (uint32_t)(c >> -sh);
+      }
+      static_cast<uint32_t*>(dst)[(size_t)blockIdx.x * nw + w] = word;
     }
-    o.uk[k] = (float)u;
   }
 }
 
@@ -276,10 +319,16 @@ hipError_t launch_convert(const void* aos, const AosLayout& L, const CellsDev& c
   if (L.stride <= kMaxStagedStride) {
     const size_t lds = (size_t)kTileSlots * ((L.stride >> 3) + 1) * 8;
     const int G = (c.n + kTileSlots - 1) / kTileSlots;
-    if (L.stride == 128)
-      k_convert_staged<16><<<G, kThreads, lds, s>>>(static_cast<const char*>(aos), L, c, view, p, o);
+    const char* a = static_cast<const char*>(aos);
+    const bool pack = p.pos >= DT_TRUNC || p.vel >= DT_TRUNC || p.mhu >= DT_TRUNC;
+    if (L.stride == 128 && pack)
+      k_convert_staged<16, true><<<G, kThreads, lds, s>>>(a, L, c, view, p, o);
+    else if (L.stride == 128)
+      k_convert_staged<16, false><<<G, kThreads, lds, s>>>(a, L, c, view, p, o);
+    else if (pack)
+      k_convert_staged<0, true><<<G, kThreads, lds, s>>>(a, L, c, view, p, o);
     else
-      k_convert_staged<0><<<G, kThreads, lds, s>>>(static_cast<const char*>(aos), L, c, view, p, o);
+      k_convert_staged<0, false><<<G, kThreads, lds, s>>>(a, L, c, view, p, o);
   } else {
     k_convert_direct<<<(c.n + kThreads - 1) / kThreads, kThreads, 0, s>>>(
         static_cast<const char*>(aos), L, c, view, p, o);

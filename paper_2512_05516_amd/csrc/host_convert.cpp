@@ -141,9 +141,13 @@ sph_status sph_convert_host(const void* aos_host, const sph_aos_layout* layout,
     return host_fail(SPH_E_UNSUPPORTED,
                      "sph_convert_host: sub-cell order (sub_bits > 0) is built by sph_bin only");
   const int fmt[3] = {prec->pos, prec->vel, prec->mhu};
-  for (int f : fmt)
+  for (int f : fmt) {
+    if (f >= SPH_TRUNC + 9 && f <= SPH_TRUNC + 32)
+      return host_fail(SPH_E_UNSUPPORTED,
+                       "sph_convert_host: truncated storage is written by sph_convert only");
     if (f != SPH_F32 && f != SPH_F16 && f != SPH_BF16)
       return host_fail(SPH_E_INVALID, "sph_convert_host: bad precision format");
+  }
   const sph_aos_layout& L = *layout;
   if (L.stride == 0 || L.offset[SPH_A_X] == SPH_ABSENT || L.dtype[SPH_A_X] != SPH_F64)
     return host_fail(SPH_E_INVALID, "sph_convert_host: layout needs an FP64 X field");

@@ -28,11 +28,30 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) {
   return __uint_as_float((uint32_t)b << 16);
 }
 
+// truncate_mantissa storage of T bits (9 <= T <= 32; Table 2): the code of a
+// value is the top T bits of its IEEE single (T > 16) or half (T <= 16)
+// pattern, i.e. the mantissa cut toward zero; codes are packed into a
+// little-endian bitstream of 32-bit words, value k at bits [kT, kT + T).
+__device__ __forceinline__ uint32_t trunc_code(float q, int T) {
+  if (T > 16) return __float_as_uint(q) >> (32 - T);
+  return (uint32_t)f32_to_f16_bits(q) >> (16 - T);
+}
+__device__ __forceinline__ float trunc_load(const void* p, int T, int64_t k) {
+  const uint32_t* w = static_cast<const uint32_t*>(p);
+  const uint64_t b = (uint64_t)k * (uint64_t)T;
+  const uint64_t i = b >> 5;
+  const uint64_t v = (uint64_t)w[i] | ((uint64_t)w[i + 1] << 32);
+  const uint32_t code = (uint32_t)(v >> (b & 31)) & (T == 32 ? 0xffffffffu : (1u << T) - 1u);
+  if (T > 16) return __uint_as_float(code << (32 - T));
+  return f16_bits_to_f32((uint16_t)(code << (16 - T)));
+}
+
 // Read element k of an array stored in `dt`, widened to FP32, times `scale`
 // (an exact power of two, 1 when unscaled).
 __device__ __forceinline__ float load_q(const void* p, int dt, int64_t k, float scale) {
   float v;
-  if (dt == DT_F32) v = static_cast<const float*>(p)[k];
+  if (dt >= DT_TRUNC) v = trunc_load(p, dt - DT_TRUNC, k);
+  else if (dt == DT_F32) v = static_cast<const float*>(p)[k];
   else if (dt == DT_F16) v = f16_bits_to_f32(static_cast<const uint16_t*>(p)[k]);
   else v = bf16_bits_to_f32(static_cast<const uint16_t*>(p)[k]);
   return v * scale;

@@ -11,7 +11,18 @@
 namespace sph {
 
 enum : int { DT_F64 = SPH_F64, DT_F32 = SPH_F32, DT_F16 = SPH_F16, DT_BF16 = SPH_BF16,
-             DT_I32 = SPH_I32 };
+             DT_I32 = SPH_I32, DT_TRUNC = SPH_TRUNC };
+constexpr int kTruncTile = 256;   // slots whose codes fill whole words (256 T bits)
+constexpr uint32_t kMaxStagedStride = 248;   // largest record staged through LDS by convert
+constexpr uint32_t kMaxPackedStride = 208;   // ... when it also packs truncated codes (9 KiB)
+inline bool is_trunc(int dt) { return dt >= DT_TRUNC + 9 && dt <= DT_TRUNC + 32; }
+// bytes of a field of n values stored in dt (packed codes: whole tiles of
+// 256 values plus two words read past the last value's word)
+inline size_t storage_bytes(int64_t n, int dt) {
+  if (is_trunc(dt))
+    return (size_t)(((n + kTruncTile - 1) / kTruncTile) * 8 * (dt - DT_TRUNC) + 2) * 4;
+  return (size_t)n * (dt == DT_F32 ? 4 : 2);
+}
 constexpr uint32_t kAbsent = SPH_ABSENT;
 
 // AoS layout as passed to kernels (by value)

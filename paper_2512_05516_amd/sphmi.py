@@ -20,7 +20,10 @@ LIB_PATH = os.path.join(HERE, "libsphmi.so")
 SPH_OK, SPH_E_INVALID, SPH_E_RANGE, SPH_E_NOMEM, SPH_E_HIP, SPH_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 FLAG_BAD_POSITION, FLAG_H_TOO_LARGE = 1, 2
 F64, F32, F16, BF16, I32 = 0, 1, 2, 3, 4
+TRUNC = 0x100
 DT = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "i32": I32}
+# truncate_mantissa storage of T bits in total: "t9" ... "t32"
+DT.update({f"t{T}": TRUNC + T for T in range(9, 33)})
 ABSENT = 0xFFFFFFFF
 
 A_FIELDS = ["X", "V", "A", "M", "H", "U", "RHO", "P", "C", "DU", "RHO_DH", "WCOUNT", "F",
@@ -101,7 +104,7 @@ EXPORTS = [
     "sph_worklist", "sph_tune_candidates", "sph_autotune", "sph_task_tile_supported",
     "sph_tasks_run", "sph_now_ns", "sph_server_workspace_size", "sph_server_create",
     "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
-    "sph_server_destroy",
+    "sph_server_destroy", "sph_storage_bytes",
 ]
 
 _lib = None
@@ -145,6 +148,7 @@ def lib():
     L.sph_tasks_run.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, vp, i32, vp, vp,
                                 i32, i32, vp, i32, vp]
     L.sph_now_ns.argtypes = []
+    L.sph_storage_bytes.argtypes = [i32, i32, P(sz)]
     L.sph_server_workspace_size.argtypes = [P(ServerConfig), P(sz)]
     L.sph_server_create.argtypes = [P(ServerConfig), P(Soa), P(Precision), P(Cells), P(Params),
                                     vp, sz, P(vp)]
@@ -271,15 +275,36 @@ class DeviceWork:
         return self._s
 
 
+def storage_bytes(n: int, dtype: int) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_storage_bytes(int(n), int(dtype), C.byref(out)))
+    return out.value
+
+
+def unpack_trunc(words, T: int, n: int) -> np.ndarray:
+    """Host-side reading of n truncated codes of T bits from a packed field
+    (value k at bits [kT, kT + T) of little-endian 32-bit words), widened to
+    FP32 as the kernels read them."""
+    w = np.asarray(words).view(np.uint32).astype(np.uint64)
+    b = np.arange(n, dtype=np.uint64) * np.uint64(T)
+    i = (b >> np.uint64(5)).astype(np.int64)
+    v = w[i] | (w[i + 1] << np.uint64(32))
+    code = (v >> (b & np.uint64(31))) & np.uint64((1 << T) - 1)
+    if T > 16:
+        return (code << np.uint64(32 - T)).astype(np.uint32).view(np.float32)
+    return (code << np.uint64(16 - T)).astype(np.uint16).view(np.float16).astype(np.float32)
+
+
 class DeviceSoa:
-    """SoA arrays (sorted-slot order) for the given storage precision."""
+    """SoA arrays (sorted-slot order) for the given storage precision
+    (truncated formats: packed 32-bit words, see unpack_trunc)."""
 
     def __init__(self, n: int, prec: Precision, device="cuda", fields=None):
         import torch
         self.n = int(n)
         self.prec = prec
         nn = max(self.n, 1)
-        dt = lambda code: getattr(torch, _TORCH_DT[code])
+        dt = lambda code: getattr(torch, _TORCH_DT.get(code, "int32"))
         spec = {}
         for a in ("X", "Y", "Z"):
             spec["OFF_" + a] = dt(prec.pos)
@@ -294,13 +319,25 @@ class DeviceSoa:
         spec["NNGB"] = torch.int32
         spec["NFORCE"] = torch.int32
         want = fields if fields is not None else S_FIELDS
-        self.t = {k: torch.zeros(nn, dtype=spec[k], device=device) for k in want}
+        code = {}
+        for a in ("X", "Y", "Z"):
+            code["OFF_" + a], code["VQ_" + a] = prec.pos, prec.vel
+        for k in ("M", "H", "U"):
+            code[k] = prec.mhu
+        self.packed = {k: c - TRUNC for k, c in code.items() if c >= TRUNC}
+        self.t = {}
+        for k in want:
+            if k in self.packed:
+                words = storage_bytes(nn, code[k]) // 4
+                self.t[k] = torch.zeros(words, dtype=torch.int32, device=device)
+            else:
+                self.t[k] = torch.zeros(nn, dtype=spec[k], device=device)
         self._s = Soa()
         for k, v in self.t.items():
             self._s.f[S[k]] = v.data_ptr()
 
     def __getitem__(self, k):
-        return self.t[k][: self.n]
+        return self.t[k] if k in self.packed else self.t[k][: self.n]
 
     @property
     def struct(self) -> Soa:

@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 3
+    assert sph.abi_version() == 4
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
@@ -240,6 +240,50 @@ def test_task_stream_generator():
     assert abs(gaps.mean() - 1e-4) < 5e-6 and np.all(gaps >= 0)
     req, offs = serve.requests(tasks, np.zeros(2000, np.int64), out_ptr=1 << 20)
     assert req["out"][1] - req["out"][0] == 32 * size[0]
+
+
+def test_truncated_storage_host_side(sph):
+    import math
+    for n in (0, 1, 255, 256, 1000):
+        assert sph.storage_bytes(n, sph.F32) == 4 * n
+        assert sph.storage_bytes(n, sph.F16) == 2 * n
+        for T in (9, 16, 20, 32):
+            assert sph.storage_bytes(n, sph.DT[f"t{T}"]) == (math.ceil(n / 256) * 8 * T + 2) * 4
+    with pytest.raises(sph.SphError):
+        sph.storage_bytes(10, sph.TRUNC + 33)
+    with pytest.raises(sph.SphError):
+        sph.storage_bytes(10, sph.F64)
+    # host unpacking of a bitstream packed here value by value
+    rng = np.random.default_rng(3)
+    for T in (9, 13, 16, 17, 24, 31, 32):
+        n = 700
+        codes = rng.integers(0, 1 << T, n, dtype=np.uint64)
+        bits = np.zeros(((n * T + 31) // 32 + 2) * 32, np.uint8)
+        for k, c in enumerate(codes):
+            for b in range(T):
+                bits[k * T + b] = (int(c) >> b) & 1
+        words = np.packbits(bits.reshape(-1, 8)[:, ::-1]).view(np.uint32)
+        got = sph.unpack_trunc(words, T, n)
+        want = ((codes << np.uint64(32 - T)).astype(np.uint32).view(np.float32) if T > 16 else
+                (codes << np.uint64(16 - T)).astype(np.uint16).view(np.float16).astype(np.float32))
+        assert np.array_equal(got.view(np.uint32), np.asarray(want, np.float32).view(np.uint32)), T
+    # truncated storage is written by sph_convert only
+    L = sph.lib()
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    rec = np.zeros(16, dtype=inputs.AOS_F32)
+    buf = np.zeros(1 << 16, np.uint8)
+    st = L.sph_convert_host(C.c_void_p(rec.ctypes.data), C.byref(lay), C.byref(_fake_cells(sph)),
+                            3, C.byref(sph.precision("t20", "f32", "f32")), C.byref(sph.Soa()),
+                            C.c_void_p(buf.ctypes.data), buf.size, 1, None)
+    assert st == sph.SPH_E_UNSUPPORTED
+    big = sph.layout_from_dtype(inputs.AOS_F32)
+    big.stride = 256
+    soa = sph.Soa()
+    for i in range(len(sph.S_FIELDS)):
+        soa.f[i] = 0x4000 + 256 * i
+    assert L.sph_convert(C.c_void_p(0x3000), C.byref(big), C.byref(_fake_cells(sph)), 3,
+                         C.byref(sph.precision("t20", "t20", "t20")), C.byref(soa),
+                         None) == sph.SPH_E_UNSUPPORTED
 
 
 def test_layout_from_numpy(sph):

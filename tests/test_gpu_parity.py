@@ -601,3 +601,80 @@ def _force_neighbours(ps, n_c, sel, gamma_k):
         r = np.sqrt((d * d).sum(1))
         out.append(cand[r < np.maximum(H[i], H[cand])])
     return np.unique(np.concatenate(out)).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# truncate_mantissa storage (packed T-bit codes)
+# ---------------------------------------------------------------------------
+
+TRUNC_PRECS = [("t20", "t20", "t20", (12, 3, 0)), ("t12", "t14", "t10", (10, 4, 0)),
+               ("t27", "t17", "t31", (0, 0, 0)), ("t16", "t32", "t9", (12, 3, 0))]
+
+
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+@pytest.mark.parametrize("pos,vel,mhu,scales", TRUNC_PRECS)
+def test_convert_truncated_bit_exact(sph, orc, kind, pos, vel, mhu, scales):
+    """Packed codes decode to exactly the oracle's truncated values."""
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(3001, 8, f_blob=0.4, sigma=0.06)   # ragged last tile
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, kind)
+    ref = inputs.unpack_aos(rec)
+    prec = sph.precision(pos, vel, mhu, *scales)
+    pipe = Pipeline(rec, n_c, prec=prec)
+    pipe.bin()
+    pipe.convert("full")
+    torch.cuda.synchronize()
+    perm = pipe.cells.perm.cpu().numpy()
+    _, _, _, off = orc.bin_cells(ref.x, n_c)
+    T = lambda s: int(s[1:])
+    want = {}
+    for a, ax in enumerate("XYZ"):
+        want["OFF_" + ax] = (pos, [orc.roundtrip(v, pos) for v in off[perm, a]], 0)
+        want["VQ_" + ax] = (vel, [orc.roundtrip(v, vel) for v in ref.v[perm, a]], 0)
+    for name, arr, sc in (("M", ref.m, scales[0]), ("H", ref.h, scales[1]), ("U", ref.u, scales[2])):
+        want[name] = (mhu, [orc.roundtrip(v, mhu, sc) for v in arr[perm]], sc)
+    for name, (fmt, vals, sc) in want.items():
+        words = pipe.soa[name].cpu().numpy()
+        got = sph.unpack_trunc(words, T(fmt), ps.n).astype(np.float64) * 2.0 ** -sc
+        assert np.array_equal(got, np.asarray(vals)), (name, fmt)
+
+
+@pytest.mark.parametrize("pos,vel,mhu,scales", TRUNC_PRECS)
+def test_truncated_storage_parity(sph, orc, pos, vel, mhu, scales):
+    """Pair loops on truncated storage: counts from the FP32 test on the
+    stored values, sums against the oracle on the same stored values."""
+    ps = inputs.small_set(3)
+    n_c = 4
+    pipe = run_gpu(ps, n_c, "f32", prec=sph.precision(pos, vel, mhu, *scales))
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    q = orc.dequantise_set(ref, n_c, pos, vel, mhu, scales)
+    got["h"] = q.h
+    nd, nf = orc.count32(ref, n_c, pos=pos, hdt=mhu, h_scale=scales[1])
+    assert np.array_equal(got["nngb"], nd)
+    assert np.array_equal(got["nforce"], nf)
+    dq, fq = oracle_step(orc, q, n_c)
+    check_fp32(got, dq, fq, tol=2e-5, tag=f"{pos}/{vel}/{mhu} vs dequantised")
+
+
+def test_truncation_error_curve_gpu(sph, orc):
+    """Acceleration error of the FP32 kernels on T-bit storage (every field)
+    against FP64 on the unrounded inputs: at 32 bits the FP32 floor; growing
+    as bits are cut within the single and half layouts; lower at exactly 16
+    bits than at 17 (the switch to the half layout)."""
+    ps = inputs.small_set(1)
+    n_c = 4
+    d0, f0 = oracle_step(orc, ps, n_c)
+    e = {}
+    for T in (32, 28, 24, 20, 18, 17, 16, 14, 12, 10):
+        t = f"t{T}"
+        pipe = run_gpu(ps, n_c, "f32", prec=sph.precision(t, t, t, 12, 3, 0))
+        e[T] = rel_rmse(gpu_fields(pipe)["a"], f0["a"])
+    print("RMSE(a) vs bits:", {T: f"{v:.2e}" for T, v in e.items()})
+    assert e[32] < 1e-5
+    for a, b in ((28, 32), (24, 28), (20, 24), (18, 20), (17, 18), (14, 16), (12, 14), (10, 12)):
+        assert e[a] > e[b], (a, b)
+    assert e[16] < e[17]
