@@ -28,6 +28,7 @@ GAMMA_K = 1.825742      # H / h for the 3D cubic spline
 GAMMA = 5.0 / 3.0       # ideal-gas adiabatic index
 ALPHA = 0.8             # artificial-viscosity strength
 BETA = 3.0              # signal-velocity coefficient
+ETA = 1.2348            # h = ETA (m / rho)^(1/3): about 48 neighbours
 
 
 def build(force: bool = True) -> str:
@@ -102,6 +103,9 @@ def lib():
                                          C.c_int, i32, d, d, d, d, d]
         L.orc_num_threads.restype = C.c_int
         L.orc_bin_sub.argtypes = [C.c_int, d, C.c_int, C.c_int, i32, i32, i32]
+        L.orc_smoothing_length.argtypes = [C.c_int, d, d, d, C.c_double, C.POINTER(Params),
+                                           C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+                                           i32, C.c_int, d, i32]
         _lib = L
     return _lib
 
@@ -284,6 +288,31 @@ def dequantise_set(ps, n_c, pos="f32", vel="f32", mhu="f32", scales=(0, 0, 0)):
                              _p(xq, C.c_double), _p(vq, C.c_double), _p(mq, C.c_double),
                              _p(hq, C.c_double), _p(uq, C.c_double))
     return ParticleSet(xq, vq, mq, hq, uq, ps.name + "_dq")
+
+
+def smoothing_length(ps, eta=ETA, h_max=None, tol=1e-4, max_iter=30, prm=None, mode="cells",
+                     n_c=None, sel=None):
+    """Per-particle roots of h = eta (m / rho(h))^(1/3) by limited Newton
+    steps from ps.h. Returns (h, iterations); iterations = max_iter + 1
+    marks a particle that did not converge."""
+    prm = prm or params()
+    x, m, h0 = _f64(ps.x), _f64(ps.m), _f64(ps.h)
+    n = x.shape[0]
+    if h_max is None:
+        h_max = 1.0 / (prm.gamma_k * n_c) if n_c else np.inf
+    if sel is not None:
+        sel = np.ascontiguousarray(sel, dtype=np.int32)
+    cnt = n if sel is None else sel.shape[0]
+    h = np.empty(cnt)
+    it = np.empty(cnt, np.int32)
+    rc = lib().orc_smoothing_length(n, _p(x, C.c_double), _p(m, C.c_double), _p(h0, C.c_double),
+                                    float(eta), C.byref(prm), 0 if mode == "brute" else 1,
+                                    int(n_c or 0), float(h_max), float(tol), int(max_iter),
+                                    _p(sel, C.c_int32), cnt, _p(h, C.c_double),
+                                    _p(it, C.c_int32))
+    if rc != 0:
+        raise ValueError(f"orc_smoothing_length failed ({rc}): gamma_k h_max must fit a cell")
+    return h, it
 
 
 def task_partials(ps, n_c, tasks, dens, prm=None, perm=None, cell=None):

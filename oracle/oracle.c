@@ -403,6 +403,103 @@ int orc_force(int n, const double *x, const double *v, const double *m,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Smoothing lengths adapted to the local density (Sec. 2.1: h follows the   */
+/* density so that the neighbour number stays about constant), from         */
+/* h = eta (m / rho)^(1/3). The density sum gathers with h_i, so rho_i is a  */
+/* function of particle i's own h: each particle solves                      */
+/*   f(h) = h - eta (m / rho(h))^(1/3) = 0                                   */
+/* by Newton steps, f'(h) = 1 + (h_t / (3 rho)) drho/dh with                 */
+/* h_t = eta (m / rho(h))^(1/3); a step that f' <= 0 would make is replaced  */
+/* by h_t; every new h is limited to [h/2, 2h] and to h_max; the iteration   */
+/* stops after the first step with |h_new - h| < tol h (h_new is kept) that  */
+/* the h_max limit did not cut.                                              */
+/* iters[s] = steps taken (max_iter + 1: not converged).                     */
+/* ------------------------------------------------------------------------ */
+
+static void density_at(int i, double hi, int n, const double *x, const double *m,
+                       double gamma_k, int mode, const cellgrid *g, nlist *l, double *rho,
+                       double *drho_dh) {
+  /* neighbours of i for support gamma_k hi: a local h array view */
+  double d[3];
+  double Hi = gamma_k * hi;
+  l->n = 0;
+  if (mode == 0) {
+    for (int j = 0; j < n; ++j) {
+      double r = sqrt(sep2(x, i, j, d));
+      if (r < Hi) nl_push(l, j);
+    }
+  } else {
+    int n_c = g->n_c;
+    int ci = g->cell[i];
+    int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          int cn = ((cx + dx + n_c) % n_c) + n_c * (((cy + dy + n_c) % n_c) +
+                                                     n_c * ((cz + dz + n_c) % n_c));
+          for (int t = g->start[cn]; t < g->start[cn + 1]; ++t) {
+            int j = g->perm[t];
+            double r = sqrt(sep2(x, i, j, d));
+            if (r < Hi) nl_push(l, j);
+          }
+        }
+    qsort(l->idx, (size_t)l->n, sizeof(int32_t), cmp_i32);
+  }
+  double r_sum = 0.0, dh = 0.0;
+  for (int t = 0; t < l->n; ++t) {
+    int j = l->idx[t];
+    double r = sqrt(sep2(x, i, j, d));
+    r_sum += m[j] * orc_W(r, hi, gamma_k);
+    dh += m[j] * orc_dWdh(r, hi, gamma_k);
+  }
+  *rho = r_sum;
+  *drho_dh = dh;
+}
+
+int orc_smoothing_length(int n, const double *x, const double *m, const double *h0,
+                         double eta, const orc_params *p, int mode, int n_c, double h_max,
+                         double tol, int max_iter, const int32_t *sel, int nsel,
+                         double *h_out, int32_t *iters) {
+  cellgrid g;
+  memset(&g, 0, sizeof g);
+  if (mode == 1) {
+    if (n_c < 3 || !(p->gamma_k * h_max <= 1.0 / (double)n_c)) return -2;
+    grid_build(&g, n, x, n_c);
+  }
+  int cnt = sel ? nsel : n;
+#pragma omp parallel
+  {
+    nlist l = {0, 0, 0};
+#pragma omp for schedule(dynamic, 16)
+    for (int s = 0; s < cnt; ++s) {
+      int i = sel ? sel[s] : s;
+      double h = h0[i] < h_max ? h0[i] : h_max;
+      int it = 0;
+      for (; it < max_iter; ++it) {
+        double rho, drho;
+        density_at(i, h, n, x, m, p->gamma_k, mode, &g, &l, &rho, &drho);
+        double ht = eta * cbrt(m[i] / rho);
+        double f = h - ht;
+        double fp = 1.0 + ht / (3.0 * rho) * drho;
+        double hn = fp > 0.0 ? h - f / fp : ht;
+        if (hn < 0.5 * h) hn = 0.5 * h;
+        if (hn > 2.0 * h) hn = 2.0 * h;
+        int capped = hn > h_max;
+        if (capped) hn = h_max;
+        int done = !capped && fabs(hn - h) < tol * h;
+        h = hn;
+        if (done) break;
+      }
+      h_out[s] = h;
+      if (iters) iters[s] = it < max_iter ? it + 1 : max_iter + 1;
+    }
+    free(l.idx);
+  }
+  if (mode == 1) grid_free(&g);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Kick and drift (linear kernels, Alg. 1 CallLinear): kick v and u, then    */
 /* drift x with the kicked velocity and wrap into the periodic box.          */
 /* ------------------------------------------------------------------------ */

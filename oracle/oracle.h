@@ -77,6 +77,12 @@ void orc_reduce(int n, const double *m, const double *v, const double *a,
                 const double *du, double *out);
 
 /* neighbour counts with the support test taken in FP32, as the GPU takes it */
+/* smoothing lengths solving h = eta (m / rho(h))^(1/3) per particle */
+int orc_smoothing_length(int n, const double *x, const double *m, const double *h0,
+                         double eta, const orc_params *p, int mode, int n_c, double h_max,
+                         double tol, int max_iter, const int32_t *sel, int nsel,
+                         double *h_out, int32_t *iters);
+
 int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
                 int pos_dtype, int h_dtype, int h_scale, int mode,
                 const uint8_t *jmask, const int32_t *sel, int nsel, int32_t *nd,

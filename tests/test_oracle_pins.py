@@ -564,3 +564,45 @@ def test_truncation_error_curve_shape(orc):
         for T in range(lo, hi):
             assert e[T] > e[T + 1], T
     assert e[32] < e[33] and e[16] < e[17]
+
+
+def test_smoothing_length_closed_forms(orc):
+    """h = eta (m / rho(h))^(1/3): (1) with equal masses the weighted
+    neighbour number at the root is (4 pi / 3) H^3 rho / m = (4 pi / 3)
+    (gamma_k eta)^3 for every particle; (2) on a perfect lattice the root
+    found by Newton steps equals the root of the direct lattice sum found by
+    bisection; (3) brute force equals the cell list bit for bit; (4) a limit
+    h_max below the root is kept and reported as not converged."""
+    ps = inputs.small_set(4)
+    n_c = 4
+    h_max = 1.0 / (orc.GAMMA_K * n_c)
+    start = ps.subset(np.arange(ps.n))
+    start.h = ps.h * np.random.default_rng(1).uniform(0.7, 1.3, ps.n)
+    h, it = orc.smoothing_length(start, n_c=n_c, tol=1e-10, max_iter=50)
+    assert np.all(it <= 50)
+    assert np.all(h < h_max)
+    ph = ps.subset(np.arange(ps.n))
+    ph.h = h
+    d = orc.density(ph, n_c=n_c)
+    target = 4.0 * np.pi / 3.0 * (orc.GAMMA_K * orc.ETA) ** 3
+    np.testing.assert_allclose(d["wcount"], target, rtol=1e-8)
+    hb, itb = orc.smoothing_length(start, n_c=n_c, tol=1e-10, max_iter=50, mode="brute")
+    assert np.array_equal(h, hb) and np.array_equal(it, itb)
+    # perfect lattice: bisection on rho(h) = m sum_k W(|k| a, h) from the pinned kernel
+    n_side = 16
+    a = 1.0 / n_side
+    lat = inputs.lattice_set(n_side, 0, perfect=True)
+    r = np.sqrt(((np.stack(np.meshgrid(*[np.arange(-4, 5)] * 3, indexing="ij"), -1)
+                  .reshape(-1, 3) * a) ** 2).sum(1))
+    rho = lambda hh: lat.m[0] * sum(orc.W(float(x), hh) for x in r)
+    g = lambda hh: hh - orc.ETA * (lat.m[0] / rho(hh)) ** (1.0 / 3.0)
+    lo, hi = 0.5 * orc.ETA * a, 1.5 * orc.ETA * a
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if g(mid) < 0 else (lo, mid)
+    hl, _ = orc.smoothing_length(lat, n_c=n_c, tol=1e-12, max_iter=60, sel=np.arange(8))
+    np.testing.assert_allclose(hl, 0.5 * (lo + hi), rtol=1e-10)
+    # a limit below the root: kept, and the particle is reported unconverged
+    h2, it2 = orc.smoothing_length(start, n_c=n_c, h_max=0.8 * ps.h.min(), tol=1e-8,
+                                   max_iter=20, sel=np.arange(16))
+    assert np.all(h2 == 0.8 * ps.h.min()) and np.all(it2 == 21)
