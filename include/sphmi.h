@@ -510,6 +510,34 @@ sph_status sph_server_drain(sph_server *srv, int32_t timeout_ms);
  * dropped. */
 sph_status sph_server_destroy(sph_server *srv);
 
+/* Smoothing lengths adapted to the local density (Sec. 2.1: h follows the
+ * density so that the neighbour number stays about constant): for every
+ * slot, the root of h = eta (m / rho(h))^(1/3), rho(h) the density loop's
+ * sum at the particle's own h, by Newton steps with the loop's drho/dh
+ * (f'(h) = 1 + (h_t / (3 rho)) drho/dh, h_t = eta (m / rho(h))^(1/3); a
+ * step f' <= 0 would make is replaced by h_t; each new h is limited to
+ * [h/2, 2h] and to h_max, the largest h whose FP32 support radius fits a
+ * cell), starting from the stored H. A particle is done after the first
+ * step with |h_new - h| < tol h that the h_max limit did not cut; each pass
+ * runs the density loop (tile, work as in sph_density; the work list is
+ * rebuilt for the cells that still hold unfinished particles) and then the
+ * step. H must be stored in SPH_F32 (prec->mhu). Afterwards cells->hmax
+ * (if non-NULL) holds the new per-cell maxima and, if aos is non-NULL, h is
+ * written into the records' H field (layout must have H). The density
+ * outputs are those of the last pass: run sph_density for values at the
+ * final h. *iterations = passes run, *unconverged = particles not done.
+ * work is left holding the last pass's list: rebuild it (sph_worklist)
+ * before using it for another launch.
+ * Blocking: reads the count of unfinished particles after every pass.
+ * workspace: device, sph_smoothing_length_workspace_size(n) bytes. */
+sph_status sph_smoothing_length_workspace_size(int32_t n, size_t *bytes);
+sph_status sph_smoothing_length(const sph_soa *soa, const sph_precision *prec,
+                                const sph_cells *cells, const sph_params *params, double eta,
+                                double tol, int32_t max_iter, sph_tile tile,
+                                const sph_work *work, void *workspace, size_t workspace_bytes,
+                                void *aos, const sph_aos_layout *layout, int32_t *iterations,
+                                int32_t *unconverged, hipStream_t stream);
+
 /* hipStreamSynchronize with the error mapped to sph_status */
 sph_status sph_sync(hipStream_t stream);
 

@@ -423,6 +423,83 @@ sph_status sph_tasks_run(const sph_soa* soa, const sph_precision* prec, const sp
                     "sph_tasks_run");
 }
 
+sph_status sph_smoothing_length_workspace_size(int32_t n, size_t* bytes) {
+  if (!bytes || n < 0) return fail(SPH_E_INVALID, "sph_smoothing_length_workspace_size: bad arguments");
+  *bytes = hiter_workspace_bytes(n);
+  return SPH_OK;
+}
+
+sph_status sph_smoothing_length(const sph_soa* soa, const sph_precision* prec,
+                                const sph_cells* cells, const sph_params* params, double eta,
+                                double tol, int32_t max_iter, sph_tile tile,
+                                const sph_work* work, void* workspace, size_t workspace_bytes,
+                                void* aos, const sph_aos_layout* layout, int32_t* iterations,
+                                int32_t* unconverged, hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  Phys ph;
+  WorkDev w;
+  bool use_w;
+  int ti, k;
+  SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_smoothing_length"));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_params(params, ph));
+  SPH_TRY(resolve_tile(tile, ti, k));
+  SPH_TRY(check_work(work, c, ti, w, use_w));
+  if (p.mhu != SPH_F32)
+    return fail(SPH_E_UNSUPPORTED, "sph_smoothing_length: H must be stored in SPH_F32");
+  if (!(eta > 0.0) || !std::isfinite(eta) || !(tol > 0.0) || !std::isfinite(tol))
+    return fail(SPH_E_INVALID, "sph_smoothing_length: eta and tol must be positive");
+  if (max_iter < 1 || max_iter > 1000)
+    return fail(SPH_E_INVALID, "sph_smoothing_length: max_iter must be 1..1000");
+  if (!iterations || !unconverged)
+    return fail(SPH_E_INVALID, "sph_smoothing_length: NULL result pointer");
+  if (!workspace || workspace_bytes < hiter_workspace_bytes(c.n))
+    return fail(SPH_E_NOMEM, "sph_smoothing_length: workspace too small");
+  AosLayout L{};
+  if (aos) {
+    SPH_TRY(check_layout(layout, bit(SPH_A_H), L));
+    SPH_TRY(check_aos_ptr(aos, c.n));
+  }
+  // largest FP32 h with (gamma_k h)^2 <= (1 / n_c)^2 in the kernels' arithmetic
+  const float s32 = (float)(1.0 / (double)c.n_c);
+  float h_max = s32 / ph.gamma_k;
+  while (h_max > 0.0f) {
+    const float H = ph.gamma_k * h_max;
+    if (H * H <= s32 * s32) break;
+    h_max = std::nextafter(h_max, 0.0f);
+  }
+  *iterations = 0;
+  *unconverged = c.n;
+  if (c.n == 0) {
+    *unconverged = 0;
+    return SPH_OK;
+  }
+  hipError_t e = launch_hiter_init(*soa, p, c.n, h_max, workspace, stream);
+  if (e != hipSuccess) return hip_status(e, "sph_smoothing_length");
+  int32_t left = c.n;
+  int it = 0;
+  while (it < max_iter) {
+    if (use_w) e = launch_worklist_active(c, w, hiter_active(workspace, c.n), stream);
+    if (e == hipSuccess) e = launch_density(*soa, p, c, ph, ti, k, use_w ? &w : nullptr, stream);
+    if (e == hipSuccess)
+      e = launch_hiter_update(*soa, p, c.n, (float)eta, (float)tol, h_max, workspace, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&left, hiter_left(workspace, c.n), sizeof(int32_t),
+                         hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_status(e, "sph_smoothing_length");
+    ++it;
+    if (left == 0) break;
+  }
+  *iterations = it;
+  *unconverged = left;
+  if (c.hmax) e = launch_cell_hmax(*soa, p, c, const_cast<float*>(c.hmax), stream);
+  if (e == hipSuccess && aos) e = launch_write_h(*soa, p, c, aos, L, stream);
+  return hip_status(e, "sph_smoothing_length");
+}
+
 sph_status sph_kick_drift(const sph_soa* soa, const sph_cells* cells, double dt_kick,
                           double dt_drift, int32_t* moved, hipStream_t stream) {
   CellsDev c;

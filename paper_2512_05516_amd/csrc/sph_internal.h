@@ -82,6 +82,22 @@ hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s);
 size_t worklist_bytes(int n, int n_c, int ti);
 int worklist_capacity(int n, int n_c, int ti);
 hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s);
+// work list of the cells that hold at least one slot with active[k] != 0
+hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uint8_t* active,
+                                  hipStream_t s);
+
+// smoothing-length iteration: workspace, init, one update step, cell bounds
+size_t hiter_workspace_bytes(int n);
+hipError_t launch_hiter_init(const sph_soa& soa, const Prec& p, int n, float h_max, void* ws,
+                             hipStream_t s);
+hipError_t launch_hiter_update(const sph_soa& soa, const Prec& p, int n, float eta, float tol,
+                               float h_max, void* ws, hipStream_t s);
+const uint8_t* hiter_active(void* ws, int n);
+const int32_t* hiter_left(void* ws, int n);
+hipError_t launch_cell_hmax(const sph_soa& soa, const Prec& p, const CellsDev& c, float* hmax,
+                            hipStream_t s);
+hipError_t launch_write_h(const sph_soa& soa, const Prec& p, const CellsDev& c, void* aos,
+                          const AosLayout& L, hipStream_t s);
 WorkDev work_view(const sph_work& w, int n, int n_c);
 
 hipError_t launch_convert(const void* aos, const AosLayout& L, const CellsDev& c, int view,

@@ -53,6 +53,7 @@ __device__ __forceinline__ int cell_count(const int32_t* __restrict__ start, int
 // all cells fits in int32.
 __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict__ start, int n_c,
                                                         int n, int ti, int cost_cap,
+                                                        const uint8_t* __restrict__ active,
                                                         int32_t* __restrict__ pos,
                                                         int32_t* __restrict__ cost) {
   const int C = n_c * n_c * n_c;
@@ -63,7 +64,13 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
     cost[C] = 0;
     return;
   }
-  const int cnt = cell_count(start, c, n);
+  int cnt = cell_count(start, c, n);
+  if (active && cnt > 0) {   // only cells that hold an active slot
+    const int a = min(max(start[c], 0), n);
+    bool any = false;
+    for (int k = a; k < a + cnt && !any; ++k) any = active[k] != 0;
+    if (!any) cnt = 0;
+  }
   pos[c] = (cnt + ti - 1) / ti;
   int cx, cy, cz;
   cell_coords(c, n_c, cx, cy, cz);
@@ -91,7 +98,8 @@ __global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict_
   if (c >= C) return;
   const int a = min(max(start[c], 0), n), b = min(max(start[c + 1], a), n);
   int o = pos[c];
-  for (int f = a; f < b && o < capacity; f += ti, ++o) items[o] = make_int2(c, f);
+  const int end = min(pos[c + 1], capacity);   // this cell's items (none if filtered out)
+  for (int f = a; f < b && o < end; f += ti, ++o) items[o] = make_int2(c, f);
 }
 
 // Range boundaries: range q starts at the first item of the first cell
@@ -140,11 +148,16 @@ size_t worklist_bytes(int n, int n_c, int ti) {
 }
 
 hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s) {
+  return launch_worklist_active(c, w, nullptr, s);
+}
+
+hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uint8_t* active,
+                                  hipStream_t s) {
   const int C = c.n_c * c.n_c * c.n_c;
   WlLayout L = wl_layout(reinterpret_cast<char*>(w.counters), C);
   const int cost_cap = (int)((((int64_t)1 << 31) - 1) / ((int64_t)C + 1));
   k_wl_count<<<cdiv(C + 1, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, cost_cap,
-                                                         L.pos, L.cost);
+                                                         active, L.pos, L.cost);
   hipError_t e = scan_i32(L.pos, C + 1, L.partials, s);
   if (e != hipSuccess) return e;
   e = scan_i32(L.cost, C + 1, L.partials, s);

@@ -64,6 +64,20 @@ class Pipeline:
     def convert(self, view="full"):
         sphmi.convert(self.aos, self.layout, self.cells, view, self.soa, self.stream)
 
+    def smoothing_length(self, eta=sphmi.ETA, tol=1e-4, max_iter=30, write_back=True):
+        """Iterate h to the root of h = eta (m / rho(h))^(1/3) for the binned
+        and converted particles (H stored in FP32); with write_back the new
+        h also goes into the AoS records. Returns (passes, not converged)."""
+        if self.work is not None:
+            sphmi.worklist(self.cells, self.work, self.stream)
+        out = sphmi.smoothing_length(self.soa, self.cells, self.prm, eta, tol, max_iter,
+                                     self.til, self.work, None,
+                                     self.aos if write_back else None,
+                                     self.layout if write_back else None, self.stream)
+        for w in self._lists:          # the passes leave a filtered list behind
+            sphmi.worklist(self.cells, w, self.stream)
+        return out
+
     def density(self):
         sphmi.density(self.soa, self.cells, self.prm, self.til, self.stream, self.work)
 

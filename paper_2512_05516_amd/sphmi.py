@@ -104,7 +104,8 @@ EXPORTS = [
     "sph_worklist", "sph_tune_candidates", "sph_autotune", "sph_task_tile_supported",
     "sph_tasks_run", "sph_now_ns", "sph_server_workspace_size", "sph_server_create",
     "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
-    "sph_server_destroy", "sph_storage_bytes",
+    "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
+    "sph_smoothing_length",
 ]
 
 _lib = None
@@ -149,6 +150,10 @@ def lib():
                                 i32, i32, vp, i32, vp]
     L.sph_now_ns.argtypes = []
     L.sph_storage_bytes.argtypes = [i32, i32, P(sz)]
+    L.sph_smoothing_length_workspace_size.argtypes = [i32, P(sz)]
+    L.sph_smoothing_length.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), C.c_double,
+                                       C.c_double, i32, Tile, P(Work), vp, sz, vp,
+                                       P(AosLayout), P(i32), P(i32), vp]
     L.sph_server_workspace_size.argtypes = [P(ServerConfig), P(sz)]
     L.sph_server_create.argtypes = [P(ServerConfig), P(Soa), P(Precision), P(Cells), P(Params),
                                     vp, sz, P(vp)]
@@ -420,6 +425,33 @@ def force(soa: DeviceSoa, cells: DeviceCells, prm=None, til=None, stream=None, w
     _check(lib().sph_force(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
                            C.byref(prm or params()), til or Tile(0, 0), _wk(work),
                            _stream(stream)))
+
+
+ETA = 1.2348
+
+
+def smoothing_length_workspace_size(n: int) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_smoothing_length_workspace_size(int(n), C.byref(out)))
+    return out.value
+
+
+def smoothing_length(soa, cells, prm=None, eta=ETA, tol=1e-4, max_iter=30, til=None,
+                     work=None, ws=None, aos=None, layout=None, stream=None):
+    """Iterate every slot's h to the root of h = eta (m / rho(h))^(1/3)
+    (sph_smoothing_length); returns (passes, particles not converged)."""
+    import torch
+    if ws is None:
+        ws = torch.empty(smoothing_length_workspace_size(cells.n), dtype=torch.uint8,
+                         device=cells.cell_start.device)
+    it, left = C.c_int32(), C.c_int32()
+    _check(lib().sph_smoothing_length(C.byref(soa.struct), C.byref(soa.prec),
+                                      C.byref(cells.struct), C.byref(prm or params()),
+                                      float(eta), float(tol), int(max_iter), til or Tile(0, 0),
+                                      _wk(work), _ptr(ws), int(ws.numel()), _ptr(aos),
+                                      C.byref(layout) if layout is not None else None,
+                                      C.byref(it), C.byref(left), _stream(stream)))
+    return it.value, left.value
 
 
 SCHED_NAMES = {-1: None, 0: "grid", 1: "static", 2: "dynamic"}

@@ -678,3 +678,107 @@ def test_truncation_error_curve_gpu(sph, orc):
     for a, b in ((28, 32), (24, 28), (20, 24), (18, 20), (17, 18), (14, 16), (12, 14), (10, 12)):
         assert e[a] > e[b], (a, b)
     assert e[16] < e[17]
+
+
+# ---------------------------------------------------------------------------
+# smoothing lengths: h = eta (m / rho(h))^(1/3)
+# ---------------------------------------------------------------------------
+
+def _h_max(sph, n_c):
+    """The largest FP32 h with (gamma_k h)^2 <= (1/n_c)^2 in FP32."""
+    gk = np.float32(sph.params().gamma_k)
+    s = np.float32(1.0 / n_c)
+    h = np.float32(s / gk)
+    while (gk * h) * (gk * h) > s * s:
+        h = np.nextafter(h, np.float32(0))
+    return float(h)
+
+
+@pytest.mark.parametrize("which,sched", [("lattice", None), ("clustered", None),
+                                         ("clustered", "grid")])
+def test_smoothing_length_matches_oracle(sph, orc, which, sched):
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    if which == "lattice":
+        ps, n_c = inputs.small_set(2), 4
+    else:
+        ps = inputs.clustered_set(20000, 6, f_blob=0.4, sigma=0.05)
+        n_c = int(np.floor(1.0 / (1.3 * orc.GAMMA_K * ps.h.max())))
+    ps.h = ps.h * np.random.default_rng(3).uniform(0.75, 1.3, ps.n)
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    tol = 1e-5
+    pipe = Pipeline(rec, n_c, sched=sched)
+    pipe.bin()
+    pipe.convert("full")
+    it, left = pipe.smoothing_length(tol=tol, max_iter=40)
+    assert left == 0 and 2 <= it <= 40
+    torch.cuda.synchronize()
+    h_rec = pipe.records()["h"].astype(np.float64)
+    h_max = _h_max(sph, n_c)
+    ho, ito = orc.smoothing_length(ref, n_c=n_c, h_max=h_max, tol=tol, max_iter=40)
+    assert np.all(ito <= 40)
+    assert np.max(np.abs(h_rec / ho - 1)) < 3 * tol + 1e-5
+    assert it >= ito.max() - 1
+    # at the root the weighted neighbour number is (4 pi / 3) (gamma_k eta)^3
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    wc = pipe.records()["wcount"]
+    target = 4.0 * np.pi / 3.0 * (orc.GAMMA_K * orc.ETA) ** 3
+    assert np.max(np.abs(wc / target - 1)) < 10 * tol + 1e-4
+    # the cells' hmax follows the new h
+    cell = pipe.cells.cell.cpu().numpy()
+    hs = pipe.soa["H"].cpu().numpy()
+    want = np.zeros(n_c ** 3, np.float32)
+    np.maximum.at(want, cell, hs)
+    assert np.array_equal(pipe.cells.hmax.cpu().numpy(), want)
+
+
+def test_smoothing_length_capped(sph, orc):
+    """Cells too small for the root: h stops at h_max and the particle is
+    reported as not converged, as in the oracle."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.small_set(2)
+    n_c = 5                                   # cell side below the lattice's support
+    ps.h = np.full(ps.n, 0.8 / (orc.GAMMA_K * n_c))
+    rec = inputs.pack_aos(ps, "f32")
+    pipe = Pipeline(rec, n_c)
+    pipe.bin()
+    pipe.convert("full")
+    it, left = pipe.smoothing_length(tol=1e-5, max_iter=12)
+    assert it == 12 and left == ps.n
+    h_max = _h_max(sph, n_c)
+    assert np.all(pipe.records()["h"] == np.float32(h_max))
+    ho, ito = orc.smoothing_length(inputs.unpack_aos(rec), n_c=n_c, h_max=h_max, tol=1e-5,
+                                   max_iter=12, sel=np.arange(64))
+    assert np.all(ho == h_max) and np.all(ito == 13)
+
+
+def test_smoothing_length_full_size_clustered(sph, orc):
+    """The 4M clustered set from its analytic h, in a 1.25x roomier cell
+    list: every particle converges; a seeded sample (background and blob
+    cells) matches the oracle's iteration."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_k_set(3)
+    n_c = int(np.floor(1.0 / (1.25 * orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    tol = 1e-4
+    pipe = Pipeline(rec, n_c, sched="grid", til=sph.tile(16, 4))
+    pipe.bin()
+    pipe.convert("full")
+    it, left = pipe.smoothing_length(tol=tol, max_iter=30)
+    assert left == 0, left
+    h = pipe.records()["h"].astype(np.float64)
+    rng = np.random.default_rng(21)
+    occ = np.diff(pipe.cells.cell_start.cpu().numpy())
+    cell_of = np.minimum((ref.x * n_c).astype(int), n_c - 1) @ np.array([1, n_c, n_c * n_c])
+    blob = np.nonzero(occ[cell_of] > 400)[0]
+    sel = np.unique(np.concatenate([rng.choice(ps.n, 256, replace=False),
+                                    rng.choice(blob, 128, replace=False)])).astype(np.int32)
+    ho, ito = orc.smoothing_length(ref, n_c=n_c, h_max=_h_max(sph, n_c), tol=tol, max_iter=30,
+                                   sel=sel)
+    assert np.all(ito <= 30)
+    assert np.max(np.abs(h[sel] / ho - 1)) < 3 * tol + 1e-5
+    print(f"h iteration on 4M particles: {it} passes")
