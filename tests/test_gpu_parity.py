@@ -740,8 +740,8 @@ def test_smoothing_length_capped(sph, orc):
     reported as not converged, as in the oracle."""
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.small_set(2)
-    n_c = 5                                   # cell side below the lattice's support
-    ps.h = np.full(ps.n, 0.8 / (orc.GAMMA_K * n_c))
+    n_c = 8                 # h_max = 0.125 / gamma_k = 0.068 < the lattice's root 0.077
+    ps.h = np.full(ps.n, 0.07)
     rec = inputs.pack_aos(ps, "f32")
     pipe = Pipeline(rec, n_c)
     pipe.bin()
