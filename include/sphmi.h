@@ -516,8 +516,9 @@ sph_status sph_server_destroy(sph_server *srv);
  * sum at the particle's own h, by Newton steps with the loop's drho/dh
  * (f'(h) = 1 + (h_t / (3 rho)) drho/dh, h_t = eta (m / rho(h))^(1/3); a
  * step f' <= 0 would make is replaced by h_t; each new h is limited to
- * [h/2, 2h] and to h_max, the largest h whose FP32 support radius fits a
- * cell), starting from the stored H. A particle is done after the first
+ * [h/2, 2h] and to h_max, the largest FP32 h whose support radius fits a
+ * cell both in the kernels' FP32 test and exactly), starting from the
+ * stored H. A particle is done after the first
  * step with |h_new - h| < tol h that the h_max limit did not cut; each pass
  * runs the density loop (tile, work as in sph_density; the work list is
  * rebuilt for the cells that still hold unfinished particles) and then the

@@ -462,12 +462,13 @@ sph_status sph_smoothing_length(const sph_soa* soa, const sph_precision* prec,
     SPH_TRY(check_layout(layout, bit(SPH_A_H), L));
     SPH_TRY(check_aos_ptr(aos, c.n));
   }
-  // largest FP32 h with (gamma_k h)^2 <= (1 / n_c)^2 in the kernels' arithmetic
+  // largest FP32 h whose support fits a cell both in the kernels' FP32 test,
+  // (gamma_k h)^2 <= (1 / n_c)^2, and exactly, gamma_k h <= 1 / n_c
   const float s32 = (float)(1.0 / (double)c.n_c);
   float h_max = s32 / ph.gamma_k;
   while (h_max > 0.0f) {
     const float H = ph.gamma_k * h_max;
-    if (H * H <= s32 * s32) break;
+    if (H * H <= s32 * s32 && params->gamma_k * (double)h_max <= 1.0 / (double)c.n_c) break;
     h_max = std::nextafter(h_max, 0.0f);
   }
   *iterations = 0;

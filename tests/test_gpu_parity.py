@@ -685,11 +685,13 @@ def test_truncation_error_curve_gpu(sph, orc):
 # ---------------------------------------------------------------------------
 
 def _h_max(sph, n_c):
-    """The largest FP32 h with (gamma_k h)^2 <= (1/n_c)^2 in FP32."""
-    gk = np.float32(sph.params().gamma_k)
+    """The largest FP32 h with (gamma_k h)^2 <= (1/n_c)^2 in FP32 and
+    gamma_k h <= 1/n_c exactly."""
+    g64 = sph.params().gamma_k
+    gk = np.float32(g64)
     s = np.float32(1.0 / n_c)
     h = np.float32(s / gk)
-    while (gk * h) * (gk * h) > s * s:
+    while (gk * h) * (gk * h) > s * s or g64 * float(h) > 1.0 / n_c:
         h = np.nextafter(h, np.float32(0))
     return float(h)
 
