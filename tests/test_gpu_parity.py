@@ -726,7 +726,7 @@ def test_smoothing_length_matches_oracle(sph, orc, which, sched):
     pipe.bin()
     pipe.convert("full")
     pipe.density()
-    wc = pipe.records()["wcount"]
+    wc = pipe.soa["WCOUNT"].cpu().numpy()
     target = 4.0 * np.pi / 3.0 * (orc.GAMMA_K * orc.ETA) ** 3
     assert np.max(np.abs(wc / target - 1)) < 10 * tol + 1e-4
     # the cells' hmax follows the new h
