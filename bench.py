@@ -13,8 +13,8 @@ Beside it: per-kernel times (HIP events on the launch stream), HBM GB/s of
 convert / kick-drift / writeback at algorithmic bytes, the plain-AoS step and
 the reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) on the same
 particles, the host-side convert variant, the clustered 4,194,304-particle
-set (occupancy 1..~2,000 per cell) with its own tuned tiling in FP32 and
-FP16 storage, the serving loop on that resident state (Poisson streams of
+set (h from the smoothing-length iteration on the GPU, occupancy up to a few
+thousand per cell) with its own tuned tiling in FP32 and FP16 storage, the serving loop on that resident state (Poisson streams of
 cell-pair tasks, p50/p99 latency), and the FP64 CPU oracle timed on a
 bounded sample (rank 0, N = 1).
 
@@ -123,6 +123,8 @@ def cpu_baseline(ps):
 
 SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
 SERVE_SECONDS = 1.0                    # arrivals per rate
+H_ROOM = 1.6      # clustered set: cell size / background support radius while h iterates
+H_TOL = 1e-4      # relative h change that ends a particle's iteration
 
 
 def serving_variant(pipe, n_c, seed=4):
@@ -179,20 +181,42 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
     and FP16-store steps (FP16 offsets, BF16 v, FP16 m/h/u)."""
     log("generating the clustered 4M set")
     ps = inputs.clustered_k_set(3)
-    n_c = int(np.floor(1.0 / (sphmi.params().gamma_k * ps.h.max())))
+    gk = sphmi.params().gamma_k
     rec = inputs.pack_aos(ps, "f32")
     n = ps.n
+    # h from the density iteration, on the GPU: start from the background h
+    # in a cell list with room for h to grow, then take cells as small as the
+    # largest iterated support radius allows
+    n_c0 = int(np.floor(1.0 / (H_ROOM * gk * ps.h.max())))
     del ps
+    log(f"clustered: smoothing-length iteration (n_c = {n_c0})")
+    p0 = Pipeline(rec, n_c0, sched="grid", til=sphmi.tile(16, 4))
+    p0.bin()
+    p0.convert("full")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    passes, left = p0.smoothing_length(tol=H_TOL, max_iter=30)
+    torch.cuda.synchronize()
+    t_h = time.perf_counter() - t0
+    rec = p0.records()
+    del p0
+    torch.cuda.empty_cache()
+    h = rec["h"].astype(np.float64)
+    n_c = int(np.floor(1.0 / (gk * h.max())))
+    h_iter = {"passes": passes, "not_converged": left, "ms": round(1e3 * t_h, 3), "tol": H_TOL,
+              "n_c_during": n_c0,
+              "h": {"min": float(h.min()), "p50": float(np.median(h)), "max": float(h.max())}}
+    log(f"clustered: {passes} passes, {left} not converged, {1e3 * t_h:.1f} ms; n_c = {n_c}")
     steps = max(1, min(args.steps, 10))
     warm = max(1, min(args.warmup, 2))
     out = {"workload": f"clustered: {n} particles, 37% in 8 Gaussian blobs (sigma 0.03) over "
-                       f"a uniform background, n_c = {n_c}", "particles": n, "n_c": n_c,
-           "steps": steps}
+                       f"a uniform background, h from the density iteration, n_c = {n_c}",
+           "particles": n, "n_c": n_c, "steps": steps, "h_iteration": h_iter}
     for name, prec in (("fp32", sphmi.precision()),
                        ("fp16_store", sphmi.precision("f16", "bf16", "f16", scale_m=22,
                                                       scale_h=7, scale_u=0))):
         log(f"clustered {name}: autotuning")
-        sub = (0, 1, 2) if name == "fp32" else (out["fp32"]["sub_bits"],)
+        sub = (0, 1, 2, 3) if name == "fp32" else (out["fp32"]["sub_bits"],)
         ch = tune.tune(rec, n_c, prec=prec, sub_bits=sub, reps=2, cache_path=args.tune_cache,
                        log=log)
         pipe = Pipeline(rec, n_c, prec=prec, **tune.pipeline_kwargs(ch))
