@@ -517,18 +517,21 @@ __device__ __forceinline__ ChunkBox chunk_box(bool vi, float xi, float yi, float
 
 // Phase A over the staged candidates [0, nj) (nj a multiple of K * kUnroll,
 // padded with entries nobody accepts): lane kk of its particle tests
-// candidates kk, kk + K, ... and appends the accepted ones to its list;
-// `consume(lo)` runs phase B over list entries [tid, lo) whenever the lists
-// may fill up and at the end.
+// candidates kk, kk + K, ... (`accept(q, index)`) and appends the accepted
+// ones to its list; `consume(lo)` runs phase B over list entries [tid, lo)
+// whenever the lists may fill up and at the end. The list position is kept
+// as a byte offset, so appending costs a select and an add.
 template <int NT, int K, int LCAP, class Accept, class Consume>
 __device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst, int nj, int kk,
                                                  Accept accept, Consume consume) {
   const int tid = threadIdx.x;
   const int nit = nj / K;
+  char* const lb = reinterpret_cast<char*>(lst);
+  constexpr int kStep = 2 * NT;     // bytes between a lane's consecutive entries
   int it = 0;
   while (it < nit) {
-    int lo = tid;
-    const int lim = tid + (LCAP - kUnroll) * NT;
+    int lo = 2 * tid;
+    const int lim = 2 * tid + (LCAP - kUnroll) * kStep;
     while (it < nit) {
       const float4* cq = cp + kk + K * it;
       float4 qv[kUnroll];
@@ -536,15 +539,56 @@ __device__ __forceinline__ void test_and_consume(const float4* cp, uint16_t* lst
       for (int u = 0; u < kUnroll; ++u) qv[u] = cq[K * u];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const bool acc = accept(qv[u]);
-        lst[lo] = (uint16_t)(kk + K * (it + u));
-        lo += acc ? NT : 0;
+        const int idx = kk + K * (it + u);
+        const bool acc = accept(qv[u], idx);
+        *reinterpret_cast<uint16_t*>(lb + lo) = (uint16_t)idx;
+        lo += acc ? kStep : 0;
       }
       it += kUnroll;
       if (__any(lo > lim)) break;
     }
-    consume(lo);
+    consume(lo >> 1);
   }
+}
+
+// Candidate prefilter of phase A. With p = x_i and q = x_j relative to the
+// chunk's cell, r^2 = |p|^2 - 2 p.q + |q|^2: staging stores n2 = |q|^2 as
+// q's fourth component, each lane keeps c = H^2 - |p|^2 + M and -2p, and
+// the test is t = n2 - 2 p.q < c, three FMAs and a compare. Phase B takes
+// the exact FP32 support test (dist2) again on the accepted pairs, so the
+// prefilter only has to accept a superset of it; M bounds the rounding of
+// t, of c and of dist2. With |p|^2 <= Bi, |q|^2 <= Bj and H^2 <= Bj those
+// errors add up to less than 19 * 2^-24 * (Bi + Bj); M = 2^-16 (Bi + Bj)
+// leaves a factor 13. Bi, Bj follow from the chunk box: the candidates
+// lie within one cell side s of it (H <= s, else the status flag is set).
+__device__ __forceinline__ float prefilter_margin(const ChunkBox& b, float s) {
+  const float ex = fmaxf(fabsf(b.lox), fabsf(b.hix));
+  const float ey = fmaxf(fabsf(b.loy), fabsf(b.hiy));
+  const float ez = fmaxf(fabsf(b.loz), fabsf(b.hiz));
+  const float bi = ex * ex + ey * ey + ez * ez;
+  const float bj = (ex + s) * (ex + s) + (ey + s) * (ey + s) + (ez + s) * (ez + s);
+  return 0x1p-16f * (bi + bj);
+}
+
+__device__ __forceinline__ float norm2(float x, float y, float z) {
+  return __builtin_fmaf(z, z, __builtin_fmaf(y, y, x * x));
+}
+
+// t = n2 - 2 p.q for a staged candidate q = (x, y, z, n2); m2x = -2 p.x ...
+__device__ __forceinline__ float prefilter_t(float m2x, float m2y, float m2z, const float4& q) {
+  return __builtin_fmaf(m2z, q.z, __builtin_fmaf(m2y, q.y, __builtin_fmaf(m2x, q.x, q.w)));
+}
+
+// dist2 with p given as -2p: fma(-2p, -1/2, -q) is p - q rounded once, the
+// same value as dist2's subtraction, so the lanes need not keep p itself.
+__device__ __forceinline__ float dist2_m2(float m2x, float m2y, float m2z, float qx, float qy,
+                                          float qz, float& dx, float& dy, float& dz) {
+#pragma clang fp contract(off)
+  dx = __builtin_fmaf(m2x, -0.5f, -qx);
+  dy = __builtin_fmaf(m2y, -0.5f, -qy);
+  dz = __builtin_fmaf(m2z, -0.5f, -qz);
+  float xx = dx * dx;
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, xx));
 }
 
 // Work distribution. No work list: one workgroup per cell, taking the
@@ -682,7 +726,8 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
   constexpr int CAP = 4 * NT;
   constexpr int LCAP = 32;
   constexpr int kPad = K * kUnroll;
-  __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, m_j
+  __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, |x|^2
+  __shared__ float cmass[CAP];                 // m_j
   __shared__ uint16_t lst[LCAP * NT];
   __shared__ NbrCells T;
   __shared__ RangeTab<NT> tab;
@@ -712,6 +757,9 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
     const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2, red);
     if (vi && cd.status && H2 > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
     const float bext = sqrtf(bx.h2max);
+    const float m2x = -2.0f * xi, m2y = -2.0f * yi, m2z = -2.0f * zi;
+    const float cpre = vi ? H2 - norm2(xi, yi, zi) + prefilter_margin(bx, s32)
+                          : -__builtin_inff();
 
     float rho = 0.f, wsum = 0.f, dh = 0.f;
     int nn = 0;
@@ -719,27 +767,29 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
     auto pair_phase = [&](int nj) {
       // pad [nj, roundup(nj, kPad)) with entries no particle accepts
       const int njp = (nj + kPad - 1) / kPad * kPad;
-      if (tid < njp - nj) cand[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+      if (tid < njp - nj) cand[nj + tid] = make_float4(0.f, 0.f, 0.f, 1e30f);
       __syncthreads();
       test_and_consume<NT, K, LCAP>(
           cand, lst, njp, kk,
-          [&](const float4& q) {
-            float dx, dy, dz;
-            return dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz) < H2;
-          },
+          [&](const float4& q, int) { return prefilter_t(m2x, m2y, m2z, q) < cpre; },
           [&](int lo) {
             for (int e = tid; e < lo; e += NT) {
-              const float4 q = cand[lst[e]];
+              const int t = lst[e];
+              const float4 q = cand[t];
               float dx, dy, dz;
-              const float r2 = dist2(xi, yi, zi, q.x, q.y, q.z, dx, dy, dz);
+              const float r2 = dist2_m2(m2x, m2y, m2z, q.x, q.y, q.z, dx, dy, dz);
+              const bool in = r2 < H2;       // the exact support test
               const float u = fast_sqrt(r2) * Hinv;
               float w, dw;
               kernel_w_dw(u, w, dw);
-              rho = fmaf(q.w, w, rho);
+              w = in ? w : 0.0f;
+              dw = in ? dw : 0.0f;
+              const float mj = cmass[t];
+              rho = fmaf(mj, w, rho);
               wsum += w;
-              dh = fmaf(q.w, fmaf(u, dw, 3.0f * w), dh);
+              dh = fmaf(mj, fmaf(u, dw, 3.0f * w), dh);
+              nn += in ? 1 : 0;
             }
-            nn += (lo - tid) / NT;
           });
       __syncthreads();
     };
@@ -785,7 +835,10 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
                 njn -= nj;
                 nj = 0;
               }
-              if (ok) cand[nj + slot] = c[r];
+              if (ok) {
+                cand[nj + slot] = make_float4(c[r].x, c[r].y, c[r].z, norm2(c[r].x, c[r].y, c[r].z));
+                cmass[nj + slot] = c[r].w;
+              }
               nj = njn;
             }
           }
@@ -825,7 +878,8 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
   constexpr int CAP = 2 * NT;
   constexpr int LCAP = 32;
   constexpr int kPad = K * kUnroll;
-  __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), H_j^2
+  __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), |x|^2
+  __shared__ float ch2[CAP];      // H_j^2
   __shared__ float4 cv[CAP];      // v_j, m_j
   __shared__ float4 cs4[CAP];     // 1/H_j, A_j, c_j, rho_j
   __shared__ int cid[CAP];        // sorted slot of j
@@ -865,6 +919,13 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     const ChunkBox bx = chunk_box<NT>(vi, xi, yi, zi, H2i, red);
     if (vi && cd.status && H2i > s32 * s32) atomicOr(cd.status, SPH_FLAG_H_TOO_LARGE);
     const float bi = sqrtf(bx.h2max);
+    // prefilter constants: r^2 < max(H_i^2, H_j^2) becomes
+    // t < max(H_i^2 - |p|^2 + M, H_j^2 - (|p|^2 - M))
+    const float m2x = -2.0f * xi, m2y = -2.0f * yi, m2z = -2.0f * zi;
+    const float mrg = prefilter_margin(bx, s32);
+    const float pp = norm2(xi, yi, zi);
+    const float cpre = vi ? H2i - pp + mrg : -__builtin_inff();
+    const float ppm = vi ? pp - mrg : __builtin_inff();
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
     int nf = 0;
@@ -906,25 +967,26 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     auto pair_phase = [&](int nj) {
       const int njp = (nj + kPad - 1) / kPad * kPad;
       if (tid < njp - nj) {
-        cp[nj + tid] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+        cp[nj + tid] = make_float4(0.f, 0.f, 0.f, 1e30f);
+        ch2[nj + tid] = 0.f;
         cid[nj + tid] = -1;
       }
       __syncthreads();
       test_and_consume<NT, K, LCAP>(
           cp, lst, njp, kk,
-          [&](const float4& q0) {
-            float dx, dy, dz;
-            return dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz) < fmaxf(H2i, q0.w);
+          [&](const float4& q0, int idx) {
+            return prefilter_t(m2x, m2y, m2z, q0) < fmaxf(cpre, ch2[idx] - ppm);
           },
           [&](int lo) {
             for (int e = tid; e < lo; e += NT) {
               const int t = lst[e];
               const float4 q0 = cp[t];
               float dx, dy, dz;
-              const float r2 = dist2(xi, yi, zi, q0.x, q0.y, q0.z, dx, dy, dz);
-              // the self pair has r2 = 0 exactly; so may coincident stored
-              // positions, for which w'(0) = 0 makes the pair's terms vanish
-              if (r2 == 0.0f && cid[t] == i) continue;
+              const float r2 = dist2_m2(m2x, m2y, m2z, q0.x, q0.y, q0.z, dx, dy, dz);
+              // the exact support test; the self pair has r2 = 0 exactly, so
+              // may coincident stored positions, for which w'(0) = 0 makes the
+              // pair's terms vanish
+              if (!(r2 < fmaxf(H2i, ch2[t])) || (r2 == 0.0f && cid[t] == i)) continue;
               const float4 q1 = cv[t];
               const float4 q2 = cs4[t];
               const float r = fast_sqrt(r2);
@@ -962,7 +1024,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) {
               const int idx = sbase + r * NT + tid;
-              c[r] = make_float4(0.f, 0.f, 0.f, 1.f);
+              c[r] = make_float4(0.f, 0.f, 0.f, 1.f);   // w: h_j, then H_j^2
               qq[r] = 0;
               jj[r] = 0;
               if (idx < total) {
@@ -996,7 +1058,8 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
                 filled = 0;
               }
               if (ok) {
-                cp[nj + slot] = c[r];
+                cp[nj + slot] = make_float4(c[r].x, c[r].y, c[r].z, norm2(c[r].x, c[r].y, c[r].z));
+                ch2[nj + slot] = c[r].w;
                 cid[nj + slot] = jj[r];
               }
               nj = njn;
