@@ -123,6 +123,7 @@ def cpu_baseline(ps):
 
 SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
 SERVE_SECONDS = 1.0                    # arrivals per rate
+PIPE_THREADS = 16      # host worker threads of the streaming arrangement
 H_ROOM = 1.6      # clustered set: cell size / background support radius while h iterates
 H_TOL = 1e-4      # relative h change that ends a particle's iteration
 
@@ -173,6 +174,46 @@ def serving_variant(pipe, n_c, seed=4):
             log(f"serving {int(rate)}/s: p50 {out[str(int(rate))]['latency_ms']['p50']:.3f} ms, "
                 f"p99 {out[str(int(rate))]['latency_ms']['p99']:.3f} ms, "
                 f"{nb} batches")
+    return out
+
+
+def pipeline_variant(torch, args, rec, choice, sphmi):
+    """Whole steps with the records in pinned host memory, host<->device
+    traffic included: the plain-AoS baseline, the in-place arrangement
+    (records shipped once, GPU convert) and the streaming arrangement (host
+    cell list, per-kernel host gather of narrowed inputs and host scatter of
+    outputs), each with FP32 and FP16 SoA storage; 4 kernels per step
+    (density, force, kick/drift), the tuned tiles, no sub-cell order."""
+    from paper_2512_05516_amd.hoststep import HostStep, pinned_records
+    from paper_2512_05516_amd import tune
+    kw = tune.pipeline_kwargs(choice)
+    kw.pop("sub_bits")
+    prec16 = sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
+    steps = max(2, min(args.steps, 5))
+    t, _ = pinned_records(rec)
+    out = {"steps": steps, "host_threads": PIPE_THREADS,
+           "note": "ms per step incl. H2D/D2H over PCIe; records in pinned host memory"}
+    base = None
+    for name, kind, prec in (("aos_baseline", "aos", None), ("inplace_fp32", "inplace", None),
+                             ("inplace_fp16", "inplace", prec16),
+                             ("streaming_fp32", "streaming", None),
+                             ("streaming_fp16", "streaming", prec16)):
+        log(f"pipeline: {name}")
+        hs = HostStep(t, rec.dtype, N_C, prec=prec, nthreads=PIPE_THREADS, **kw)
+        hs.step(kind, DT, DT)                      # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            hs.step(kind, DT, DT)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        pb = hs.pcie_bytes(kind)
+        out[name] = {"ms_per_step": round(ms, 3), "h2d_bytes": pb["h2d"], "d2h_bytes": pb["d2h"]}
+        if base is None:
+            base = ms
+        out[name]["speedup_vs_aos_baseline"] = round(base / ms, 3)
+        del hs
+        torch.cuda.empty_cache()
     return out
 
 
@@ -254,6 +295,8 @@ def main():
                     help="skip the clustered 4M-particle variant")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop on the clustered state")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the host-records pipeline comparison (in-place vs streaming)")
     ap.add_argument("--clustered-only", action="store_true",
                     help="time only the clustered variant (profiling runs)")
     ap.add_argument("--tune-cache", default=None,
@@ -399,6 +442,9 @@ def main():
         result["convert_placement"] = variants
         del ph, staging
         torch.cuda.empty_cache()
+
+        if not args.no_pipeline:
+            result["pipeline"] = pipeline_variant(torch, args, rec, choice, sphmi)
 
     if not args.no_clustered:
         result["clustered"] = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)

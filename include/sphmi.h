@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 4
+#define SPH_ABI_VERSION 5
 
 typedef int32_t sph_status;
 enum {
@@ -186,7 +186,12 @@ typedef enum {
   SPH_VIEW_DENSITY = 0,   /* OFF, M, H, U                                 */
   SPH_VIEW_FORCE = 1,     /* OFF, VQ, M, H                                */
   SPH_VIEW_KICK = 2,      /* X, V, UK                                     */
-  SPH_VIEW_FULL = 3       /* all of the above                             */
+  SPH_VIEW_FULL = 3,      /* all of the above                             */
+  /* views of the streaming arrangement (host gather only): the inputs the
+   * in-place arrangement keeps resident on the device come from the
+   * records instead (host gather and sph_convert_host only) */
+  SPH_VIEW_FORCE_IN = 4,  /* FORCE + RHO, F, P, C (FP32)                  */
+  SPH_VIEW_KICK_IN = 5    /* KICK + A, DU (FP32)                          */
 } sph_view;
 
 /* physics constants: H = gamma_k h; P = (gamma - 1) rho u; viscosity
@@ -245,7 +250,7 @@ sph_status sph_convert(const void *aos, const sph_aos_layout *layout, const sph_
 
 /* Host-side variant (Eq. gpu_soa_conversion_cpu_datamanagement; the
  * soa_conversion_handler(host) semantics of Sec. 3.1): the host bins the
- * host AoS (aos_host, n records) with nthreads OpenMP threads and gathers
+ * host AoS (aos_host, n records) with nthreads worker threads and gathers
  * the view into pinned host staging (staging_host, at least
  * sph_host_staging_size bytes, allocated with hipHostMalloc), then copies
  * the cell list (cell_start, perm, cell and, when non-NULL, hmax with the
@@ -259,6 +264,43 @@ sph_status sph_convert_host(const void *aos_host, const sph_aos_layout *layout,
                             const sph_cells *cells, int32_t view, const sph_precision *prec,
                             const sph_soa *out, void *staging_host, size_t staging_bytes,
                             int32_t nthreads, hipStream_t stream);
+
+/* Streaming arrangement (Sec. 6, the pipeline comparison): every kernel
+ * call ships only the fields it needs, and all reorganisation happens on
+ * the host. A step is sph_bin_host; H2D of the cell list; then per kernel
+ * sph_gather_host (view DENSITY, FORCE_IN, KICK_IN), the kernel, and
+ * sph_writeback_host of its outputs (view DENSITY, FORCE, KICK).
+ *
+ * sph_bin_host: the cell list of the host records with the definition of
+ * sph_bin for sub_bits = 0 (stable order by (cell id, input index)) into
+ * caller-owned host arrays: cell_start[n_c^3 + 1], perm[n], cell[n] and,
+ * when non-NULL, hmax[n_c^3] (0 for every cell if the layout has no H).
+ * nthreads <= 0: one per hardware thread.
+ *
+ * sph_gather_host: the view's fields of records perm[k], quantised as in
+ * sph_convert (same values bit for bit) into pinned staging (at least
+ * sph_host_staging_size bytes, hipHostMalloc), then enqueues their H2D
+ * copies into out on stream and returns; staging must stay alive and
+ * unchanged until the stream reaches the copies. perm and cell must be a
+ * cell list of these records (entries out of range: SPH_E_RANGE).
+ *
+ * sph_writeback_host: the outputs of a view (DENSITY: rho, wcount, rho_dh,
+ * f, P, c, nngb; FORCE: a, du, vsig, nforce; KICK: X, V, UK -> x, v, u) are
+ * copied D2H into pinned staging (sph_writeback_host_size bytes) on stream;
+ * the call waits for the stream and scatters them into host records
+ * perm[k] (FP32 values widened to the record's FP64 fields where the layout
+ * says so). Blocking. */
+sph_status sph_bin_host(const void *aos_host, const sph_aos_layout *layout, int32_t n, int32_t n_c,
+                        int32_t *cell_start, int32_t *perm, int32_t *cell, float *hmax,
+                        int32_t nthreads);
+sph_status sph_gather_host(const void *aos_host, const sph_aos_layout *layout, int32_t n,
+                           int32_t n_c, const int32_t *perm, const int32_t *cell, int32_t view,
+                           const sph_precision *prec, const sph_soa *out, void *staging_host,
+                           size_t staging_bytes, int32_t nthreads, hipStream_t stream);
+sph_status sph_writeback_host_size(int32_t n, int32_t view, size_t *bytes);
+sph_status sph_writeback_host(const sph_soa *soa, int32_t n, const int32_t *perm, int32_t view,
+                              void *aos_host, const sph_aos_layout *layout, void *staging_host,
+                              size_t staging_bytes, int32_t nthreads, hipStream_t stream);
 
 /* SoA->AoS writeback C^AoS_SoA o N^T o U^T (Sec. 4.1): writes the view's
  * state (KICK: X, V, UK -> x, v, u) and the kernel outputs present in soa

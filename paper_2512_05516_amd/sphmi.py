@@ -37,7 +37,9 @@ S_FIELDS = ["OFF_X", "OFF_Y", "OFF_Z", "VQ_X", "VQ_Y", "VQ_Z", "M", "H", "U",
 S = {name: i for i, name in enumerate(S_FIELDS)}
 
 VIEW_DENSITY, VIEW_FORCE, VIEW_KICK, VIEW_FULL = 0, 1, 2, 3
-VIEWS = {"density": VIEW_DENSITY, "force": VIEW_FORCE, "kick": VIEW_KICK, "full": VIEW_FULL}
+VIEW_FORCE_IN, VIEW_KICK_IN = 4, 5
+VIEWS = {"density": VIEW_DENSITY, "force": VIEW_FORCE, "kick": VIEW_KICK, "full": VIEW_FULL,
+         "force_in": VIEW_FORCE_IN, "kick_in": VIEW_KICK_IN}
 
 
 class SphError(RuntimeError):
@@ -105,7 +107,8 @@ EXPORTS = [
     "sph_tasks_run", "sph_now_ns", "sph_server_workspace_size", "sph_server_create",
     "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
-    "sph_smoothing_length",
+    "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
+    "sph_writeback_host",
 ]
 
 _lib = None
@@ -133,6 +136,11 @@ def lib():
     L.sph_convert_host.argtypes = [vp, P(AosLayout), P(Cells), i32, P(Precision), P(Soa), vp, sz,
                                    i32, vp]
     L.sph_writeback.argtypes = [P(Soa), P(Cells), i32, vp, P(AosLayout), vp]
+    L.sph_bin_host.argtypes = [vp, P(AosLayout), i32, i32, vp, vp, vp, vp, i32]
+    L.sph_gather_host.argtypes = [vp, P(AosLayout), i32, i32, vp, vp, i32, P(Precision), P(Soa),
+                                  vp, sz, i32, vp]
+    L.sph_writeback_host_size.argtypes = [i32, i32, P(sz)]
+    L.sph_writeback_host.argtypes = [P(Soa), i32, vp, i32, vp, P(AosLayout), vp, sz, i32, vp]
     L.sph_worklist_size.argtypes = [i32, i32, i32, P(sz)]
     L.sph_worklist.argtypes = [P(Cells), P(Work), vp]
     L.sph_density.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, P(Work), vp]
@@ -408,6 +416,51 @@ def convert_host(aos_np: np.ndarray, layout, cells: DeviceCells, view, soa: Devi
                                   C.byref(cells.struct), VIEWS.get(view, view), C.byref(soa.prec),
                                   C.byref(soa.struct), C.c_void_p(staging.data_ptr()),
                                   staging.numel(), int(nthreads), _stream(stream)))
+
+
+def _np_ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def bin_host(aos_np: np.ndarray, layout, n_c: int, nthreads=0, out=None, hmax=True):
+    """Host cell list of the records (sph_bin_host): (cell_start, perm, cell,
+    hmax or None) as int32/float32 numpy arrays, or filled into `out`."""
+    n = int(aos_np.shape[0])
+    Cn = n_c ** 3
+    if out is None:
+        out = (np.empty(Cn + 1, np.int32), np.empty(n, np.int32), np.empty(n, np.int32),
+               np.empty(Cn, np.float32) if hmax else None)
+    start, perm, cell, hm = out
+    _check(lib().sph_bin_host(C.c_void_p(aos_np.ctypes.data), C.byref(layout), n, int(n_c),
+                              _np_ptr(start), _np_ptr(perm), _np_ptr(cell), _np_ptr(hm),
+                              int(nthreads)))
+    return out
+
+
+def gather_host(aos_np: np.ndarray, layout, n_c, perm, cell, view, soa: DeviceSoa, staging,
+                nthreads=0, stream=None):
+    """sph_gather_host: staging is a pinned host uint8 tensor of at least
+    host_staging_size bytes; the H2D copies are enqueued on `stream`."""
+    _check(lib().sph_gather_host(C.c_void_p(aos_np.ctypes.data), C.byref(layout),
+                                 int(aos_np.shape[0]), int(n_c), _np_ptr(perm), _np_ptr(cell),
+                                 VIEWS.get(view, view), C.byref(soa.prec), C.byref(soa.struct),
+                                 C.c_void_p(staging.data_ptr()), staging.numel(), int(nthreads),
+                                 _stream(stream)))
+
+
+def writeback_host_size(n, view) -> int:
+    out = C.c_size_t()
+    _check(lib().sph_writeback_host_size(int(n), VIEWS.get(view, view), C.byref(out)))
+    return out.value
+
+
+def writeback_host(soa: DeviceSoa, perm, view, aos_np: np.ndarray, layout, staging, nthreads=0,
+                   stream=None):
+    """sph_writeback_host (blocking): the view's outputs into the host records."""
+    _check(lib().sph_writeback_host(C.byref(soa.struct), int(aos_np.shape[0]), _np_ptr(perm),
+                                    VIEWS.get(view, view), C.c_void_p(aos_np.ctypes.data),
+                                    C.byref(layout), C.c_void_p(staging.data_ptr()),
+                                    staging.numel(), int(nthreads), _stream(stream)))
 
 
 def writeback(soa: DeviceSoa, cells: DeviceCells, view, aos, layout, stream=None):

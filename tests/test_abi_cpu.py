@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 4
+    assert sph.abi_version() == 5
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
@@ -311,3 +311,54 @@ def test_inputs_recipe():
     blk = np.floor(pb.x * 4).astype(int)
     key = blk[:, 0] + 4 * (blk[:, 1] + 4 * blk[:, 2])
     assert np.all(key.reshape(-1, 64) == key.reshape(-1, 64)[:, :1])
+
+
+def test_host_binning_and_streaming_checks(sph, orc):
+    """sph_bin_host follows the binning definition (numpy floor + stable
+    lexsort, per-cell largest h); the streaming gather and writeback reject
+    bad views, short staging and out-of-range cell lists on the host."""
+    ps = inputs.small_set(5)
+    rec = inputs.pack_aos(ps, "f32")
+    lay = sph.layout_from_dtype(rec.dtype)
+    n_c = 4
+    start, perm, cell, hmax = sph.bin_host(rec, lay, n_c, nthreads=3)
+    x = ps.x - np.floor(ps.x)
+    c3 = np.minimum(np.floor(x * n_c).astype(np.int64), n_c - 1)
+    ref_cell = c3[:, 0] + n_c * (c3[:, 1] + n_c * c3[:, 2])
+    ref_perm = np.lexsort((np.arange(ps.n), ref_cell))
+    assert np.array_equal(perm, ref_perm)
+    assert np.array_equal(cell, ref_cell[ref_perm])
+    assert np.array_equal(start, np.searchsorted(ref_cell[ref_perm], np.arange(n_c ** 3 + 1)))
+    hm = np.zeros(n_c ** 3, np.float32)
+    np.maximum.at(hm, ref_cell, rec["h"].astype(np.float32))
+    assert np.array_equal(hmax, hm)
+    # more threads than one give the same list (stable by input index)
+    big = np.concatenate([rec] * 2)
+    a = sph.bin_host(big, lay, n_c, nthreads=1)
+    b = sph.bin_host(big, lay, n_c, nthreads=7)
+    assert all(np.array_equal(u, v) for u, v in zip(a, b))
+
+    L = sph.lib()
+    soa = sph.Soa()
+    prec = sph.precision()
+    buf = np.zeros(1 << 20, np.uint8)
+    bad = perm.copy()
+    bad[3] = ps.n
+    args = lambda view, p_, nbytes: L.sph_gather_host(
+        C.c_void_p(rec.ctypes.data), C.byref(lay), ps.n, n_c, C.c_void_p(p_.ctypes.data),
+        C.c_void_p(cell.ctypes.data), view, C.byref(prec), C.byref(soa),
+        C.c_void_p(buf.ctypes.data), nbytes, 1, None)
+    assert args(9, perm, buf.size) == sph.SPH_E_INVALID            # unknown view
+    assert args(4, perm, buf.size) == sph.SPH_E_INVALID            # soa fields are NULL
+    for f in range(len(sph.S_FIELDS)):                             # any non-NULL pointer
+        soa.f[f] = buf.ctypes.data
+    assert args(4, bad, buf.size) == sph.SPH_E_RANGE
+    assert args(4, perm, 16) == sph.SPH_E_NOMEM
+    out = C.c_size_t()
+    assert L.sph_writeback_host_size(ps.n, 4, C.byref(out)) == sph.SPH_E_INVALID
+    assert L.sph_writeback_host_size(ps.n, 2, C.byref(out)) == sph.SPH_OK
+    assert out.value >= ps.n * (3 * 8 + 4 * 4)
+    st = L.sph_writeback_host(C.byref(soa), ps.n, C.c_void_p(bad.ctypes.data), 2,
+                              C.c_void_p(rec.ctypes.data), C.byref(lay),
+                              C.c_void_p(buf.ctypes.data), buf.size, 1, None)
+    assert st == sph.SPH_E_RANGE
