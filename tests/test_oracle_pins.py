@@ -606,3 +606,90 @@ def test_smoothing_length_closed_forms(orc):
     h2, it2 = orc.smoothing_length(start, n_c=n_c, h_max=0.8 * ps.h.min(), tol=1e-8,
                                    max_iter=20, sel=np.arange(16))
     assert np.all(h2 == 0.8 * ps.h.min()) and np.all(it2 == 21)
+
+
+# ---------------------------------------------------------------------------
+# time integration: CFL step and leapfrog kick-drift-kick
+# ---------------------------------------------------------------------------
+
+def _moving_set(seed, v_sigma=0.3):
+    ps = inputs.small_set(seed)
+    ps.v = np.random.default_rng(seed).normal(0.0, v_sigma, ps.v.shape)
+    return ps
+
+
+def test_cfl_timestep_closed_form(orc):
+    """Perfect lattice at rest: every signal velocity is 2c, so the step is
+    c_cfl gamma_k h / (2 c), c = sqrt(gamma (gamma - 1) u); a particle with
+    no neighbour (vsig = 0) sets no limit."""
+    lat = inputs.lattice_set(16, 0, perfect=True)
+    lat.v[:] = 0.0
+    d = orc.density(lat, n_c=4)
+    f = orc.force(lat, d, n_c=4)
+    c = np.sqrt(orc.GAMMA * (orc.GAMMA - 1.0) * lat.u)
+    np.testing.assert_allclose(f["vsig"], 2.0 * c, rtol=1e-14)
+    dt, dmin = orc.timestep(lat.h, f["vsig"])
+    np.testing.assert_allclose(dt, orc.C_CFL * orc.GAMMA_K * lat.h / (2.0 * c), rtol=1e-14)
+    assert dmin == dt.min()
+    dt2, dmin2 = orc.timestep(np.array([0.1, 0.2]), np.array([0.0, 4.0]))
+    assert dt2[0] == np.inf and dmin2 == dt2[1] == orc.C_CFL * orc.GAMMA_K * 0.2 / 4.0
+
+
+def test_kdk_energy_second_order(orc):
+    """Total energy sum m (|v|^2 / 2 + u) is conserved by the equations;
+    the leapfrog error over a fixed time falls with the square of the step
+    (halving dt cuts it by about 4) without viscosity, where the flow is
+    smooth. A first-order arrangement (forces taken with the half-step v
+    and u instead of the predicted ones) only halves it. Momentum is
+    conserved to rounding, viscosity included."""
+    ps = _moving_set(22)
+    for prm in (orc.params(alpha=0.0), orc.params()):
+        err = {}
+        for dt, n in ((4e-3, 6), (2e-3, 12), (1e-3, 24)):
+            _, hist = orc.kdk_run(ps, 4, n, dt=dt, prm=prm)
+            e = np.array([h["ekin"] + h["eth"] for h in hist])
+            err[dt] = np.abs(e - e[0]).max() / e[0]
+            p = np.array([h["p"] for h in hist])
+            assert np.abs(p - p[0]).max() < 1e-13
+        if prm.alpha == 0.0:
+            assert 1e-8 < err[1e-3] < 1e-5, err
+            assert 3.5 < err[4e-3] / err[2e-3] < 5.0, err
+            assert 3.5 < err[2e-3] / err[1e-3] < 5.0, err
+        else:
+            # the viscosity switch min(w, 0) is not smooth: bounded and
+            # falling with dt, but not by a clean power
+            assert err[1e-3] < 1e-5 and err[4e-3] / err[1e-3] > 2.0, err
+    # the same run with forces from the half-step v and u: first order
+    prm = orc.params(alpha=0.0)
+    err = {}
+    for dt, n in ((2e-3, 12), (1e-3, 24)):
+        x, v, u = ps.x.copy(), ps.v.copy(), ps.u.copy()
+        at = lambda: inputs.ParticleSet(x, v, ps.m, ps.h, u)
+        f = orc.force(at(), orc.density(at(), prm, n_c=4), prm, n_c=4)
+        e0 = orc.totals(ps.m, v, u)
+        for _ in range(n):
+            x, v, u = orc.kick_drift(x, v, u, f["a"], f["du"], dt / 2, dt)
+            f = orc.force(at(), orc.density(at(), prm, n_c=4), prm, n_c=4)
+            x, v, u = orc.kick_drift(x, v, u, f["a"], f["du"], dt / 2, 0.0)
+        e1 = orc.totals(ps.m, v, u)
+        err[dt] = abs(e1["ekin"] + e1["eth"] - e0["ekin"] - e0["eth"])
+    assert err[2e-3] / err[1e-3] < 2.5, err
+
+
+def test_kdk_free_particles(orc):
+    """Particles farther apart than their supports feel no force: x moves
+    by v t exactly (modulo the box), v and u stay, and the CFL step sets no
+    limit (no neighbour, vsig = 0)."""
+    g = np.arange(4) / 4.0 + 0.125
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    n = x.shape[0]
+    rng = np.random.default_rng(5)
+    ps = inputs.ParticleSet(x, rng.normal(0, 0.5, (n, 3)), np.full(n, 1.0 / n),
+                            np.full(n, 0.05), np.ones(n))
+    out, hist = orc.kdk_run(ps, 4, 5, dt=0.01)
+    want = ps.x + 0.05 * ps.v
+    want -= np.floor(want)
+    np.testing.assert_allclose(out.x, want, atol=1e-15)
+    assert np.array_equal(out.v, ps.v) and np.array_equal(out.u, ps.u)
+    f = orc.force(ps, orc.density(ps, n_c=4), n_c=4)
+    assert np.all(f["vsig"] == 0.0) and orc.timestep(ps.h, f["vsig"])[1] == np.inf
