@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 5
+#define SPH_ABI_VERSION 6
 
 typedef int32_t sph_status;
 enum {
@@ -368,6 +368,34 @@ sph_status sph_kick_drift(const sph_soa *soa, const sph_cells *cells, double dt_
 sph_status sph_reduce_workspace_size(int32_t n, size_t *bytes);
 sph_status sph_reduce(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
                       double *out, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Leapfrog kick-drift-kick over several steps (the Kick and Drift kernels
+ * of Sec. 6 arranged as the second-order integrator; the paper gives no
+ * scheme). A step of size dt: sph_kick_drift(dt/2, dt) and the kick view
+ * written back; rebin and convert; sph_predict(dt/2); density and force;
+ * sph_kick_drift(dt/2, 0); full writeback (which keeps the rates a, du in
+ * the records for the next prediction).
+ *
+ * sph_predict: the force depends on v (viscosity) and, through the
+ * pressure, on u, so the forces at the end of the step are evaluated with
+ * v and u predicted by the last rates: for every slot k, with the record
+ * perm[k]'s A and DU, VQ = Q_vel(V + a dt_half) and U = Q_mhu((UK + du
+ * dt_half) 2^scale_u) in FP32 (fma), where V, UK (the kick view) hold the
+ * half-step values. Writes VQ and U only; IEEE storage formats only
+ * (SPH_E_UNSUPPORTED for truncated ones).
+ *
+ * sph_step_totals: out[0..2] = sum m v, out[3] = sum m |v|^2 / 2,
+ * out[4] = sum m u, out[5] = sum m (FP64, deterministic order, m and h as
+ * stored with their scales, v and u from V and UK), out[6] = the Courant
+ * step min over slots with vsig > 0 of c_cfl (gamma_k h) / vsig in FP64
+ * (+inf if none), out[7] = number of such slots. workspace: at least
+ * sph_reduce_workspace_size bytes; out: 8 doubles on the device. */
+sph_status sph_predict(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                       const void *aos, const sph_aos_layout *layout, double dt_half,
+                       hipStream_t stream);
+sph_status sph_step_totals(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
+                           const sph_params *params, double c_cfl, double *out, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream);
 
 /* Plain-AoS forms (Eq. gpu_native): the same kernels reading and writing
  * the AoS records through the cell list (record perm[k] for slot k),

@@ -533,6 +533,49 @@ sph_status sph_reduce(const sph_soa* soa, const sph_precision* prec, const sph_c
   return hip_status(launch_reduce(*soa, p, c.n, out, workspace, stream), "sph_reduce");
 }
 
+sph_status sph_predict(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                       const void* aos, const sph_aos_layout* layout, double dt_half,
+                       hipStream_t stream) {
+  static const int kPredIn[] = {SPH_S_V_X, SPH_S_V_Y, SPH_S_V_Z, SPH_S_UK,
+                                SPH_S_VQ_X, SPH_S_VQ_Y, SPH_S_VQ_Z, SPH_S_U};
+  CellsDev c;
+  Prec p;
+  AosLayout L;
+  SPH_TRY(check_soa(soa, kPredIn, len(kPredIn), "sph_predict"));
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_layout(layout, bit(SPH_A_A) | bit(SPH_A_DU), L));
+  SPH_TRY(check_aos_ptr(aos, c.n));
+  if (is_trunc(p.vel) || is_trunc(p.mhu))
+    return fail(SPH_E_UNSUPPORTED, "sph_predict: truncated storage is written by sph_convert only");
+  if (!std::isfinite(dt_half)) return fail(SPH_E_INVALID, "sph_predict: dt_half must be finite");
+  return hip_status(launch_predict(*soa, p, c, aos, L, dt_half, stream), "sph_predict");
+}
+
+sph_status sph_step_totals(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
+                           const sph_params* params, double c_cfl, double* out, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
+  static const int kTotIn[] = {SPH_S_M, SPH_S_H, SPH_S_V_X, SPH_S_V_Y, SPH_S_V_Z, SPH_S_UK,
+                               SPH_S_VSIG};
+  CellsDev c;
+  Prec p;
+  Phys ph;
+  SPH_TRY(check_soa(soa, kTotIn, len(kTotIn), "sph_step_totals"));
+  SPH_TRY(check_cells(cells, false, c));
+  SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_params(params, ph));
+  if (!(c_cfl > 0.0) || !std::isfinite(c_cfl))
+    return fail(SPH_E_INVALID, "sph_step_totals: c_cfl must be positive and finite");
+  if (!out) return fail(SPH_E_INVALID, "sph_step_totals: out is NULL");
+  if (!workspace) return fail(SPH_E_INVALID, "sph_step_totals: workspace is NULL");
+  if (workspace_bytes < reduce_workspace_bytes(c.n))
+    return fail(SPH_E_NOMEM, "sph_step_totals: workspace has %zu bytes, needs %zu",
+                workspace_bytes, reduce_workspace_bytes(c.n));
+  return hip_status(launch_step_totals(*soa, p, c.n, params->gamma_k, c_cfl, out, workspace,
+                                       stream),
+                    "sph_step_totals");
+}
+
 sph_status sph_density_aos(void* aos, const sph_aos_layout* layout, const sph_cells* cells,
                            const sph_params* params, sph_tile tile, const sph_work* work,
                            hipStream_t stream) {

@@ -168,7 +168,161 @@ __global__ __launch_bounds__(kThreads) void k_reduce_final(const double* __restr
   }
 }
 
+// --- leapfrog support: predicted v, u; time step and conserved totals -----
+
+struct PredIn {
+  const float* v[3];      // kick view V (half-step values)
+  const float* u;         // kick view UK
+  void* vq[3];            // force view VQ (stored format)
+  void* uq;               // U (stored format)
+  int vel_dt, mhu_dt;
+  float store_u;
+  const int32_t* perm;
+  const char* aos;
+  AosLayout L;
+};
+
+// v and u predicted to the end of the step with the last rates (record
+// fields A, DU of the slot's record), stored in the force/density formats.
+__global__ __launch_bounds__(kThreads) void k_predict(PredIn s, int n, float dth) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= n) return;
+  const char* rec = s.aos + (size_t)min(max(s.perm[k], 0), n - 1) * s.L.stride;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float a = rec_load32(rec, s.L.off[SPH_A_A], s.L.dt[SPH_A_A], c);
+    store_q32(s.vq[c], s.vel_dt, k, __builtin_fmaf(a, dth, s.v[c][k]), 1.0f);
+  }
+  const float du = rec_load32(rec, s.L.off[SPH_A_DU], s.L.dt[SPH_A_DU]);
+  store_q32(s.uq, s.mhu_dt, k, __builtin_fmaf(du, dth, s.u[k]), s.store_u);
+}
+
+struct TotIn {
+  const void* m;
+  const void* h;
+  int mhu_dt;
+  float lm, lh;
+  const float* v[3];
+  const float* u;
+  const float* vsig;
+  double gk, cfl;
+};
+
+// Per-block partials: sums of m v (3), m |v|^2 / 2, m u, m, the count of
+// slots with vsig > 0 (slot 7) and the minimum CFL step (slot 6).
+__global__ __launch_bounds__(kThreads) void k_totals_partial(TotIn s, int n,
+                                                             double* __restrict__ part) {
+  __shared__ double lds[kThreads / 64][kReduceVals];
+  double acc[kReduceVals];
+#pragma unroll
+  for (int q = 0; q < kReduceVals; ++q) acc[q] = 0.0;
+  acc[6] = __builtin_inf();
+  for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) {
+    const double m = (double)load_q(s.m, s.mhu_dt, k, s.lm);
+    double v2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double v = s.v[c][k];
+      acc[c] += m * v;
+      v2 += v * v;
+    }
+    acc[3] += 0.5 * m * v2;
+    acc[4] += m * (double)s.u[k];
+    acc[5] += m;
+    const double vs = s.vsig[k];
+    if (vs > 0.0) {
+      const double h = (double)load_q(s.h, s.mhu_dt, k, s.lh);
+      acc[6] = fmin(acc[6], s.cfl * (s.gk * h) / vs);
+      acc[7] += 1.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kReduceVals; ++q) {
+    double v = acc[q];
+    for (int o = 32; o > 0; o >>= 1) {
+      const double w = __shfl_xor(v, o);
+      v = (q == 6) ? fmin(v, w) : v + w;
+    }
+    acc[q] = v;
+  }
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < kReduceVals; ++q) lds[threadIdx.x >> 6][q] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < kReduceVals) {
+    const int q = threadIdx.x;
+    double t = (q == 6) ? __builtin_inf() : 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) t = (q == 6) ? fmin(t, lds[w][q]) : t + lds[w][q];
+    part[blockIdx.x * kReduceVals + q] = t;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_totals_final(const double* __restrict__ part, int nb,
+                                                           double* __restrict__ out) {
+  __shared__ double lds[kThreads / 64];
+  for (int q = 0; q < kReduceVals; ++q) {
+    const bool mn = q == 6;
+    double t = mn ? __builtin_inf() : 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) {
+      const double x = part[b * kReduceVals + q];
+      t = mn ? fmin(t, x) : t + x;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double w = __shfl_xor(t, o);
+      t = mn ? fmin(t, w) : t + w;
+    }
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r = mn ? __builtin_inf() : 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) r = mn ? fmin(r, lds[w]) : r + lds[w];
+      out[q] = r;
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_predict(const sph_soa& soa, const Prec& p, const CellsDev& c, const void* aos,
+                          const AosLayout& L, double dth, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  PredIn in;
+  for (int a = 0; a < 3; ++a) {
+    in.v[a] = static_cast<const float*>(soa.f[SPH_S_V_X + a]);
+    in.vq[a] = soa.f[SPH_S_VQ_X + a];
+  }
+  in.u = static_cast<const float*>(soa.f[SPH_S_UK]);
+  in.uq = soa.f[SPH_S_U];
+  in.vel_dt = p.vel;
+  in.mhu_dt = p.mhu;
+  in.store_u = p.store_u;
+  in.perm = c.perm;
+  in.aos = static_cast<const char*>(aos);
+  in.L = L;
+  k_predict<<<(c.n + kThreads - 1) / kThreads, kThreads, 0, s>>>(in, c.n, (float)dth);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_totals(const sph_soa& soa, const Prec& p, int n, double gamma_k,
+                              double c_cfl, double* out, void* ws, hipStream_t s) {
+  TotIn t;
+  t.m = soa.f[SPH_S_M];
+  t.h = soa.f[SPH_S_H];
+  t.mhu_dt = p.mhu;
+  t.lm = p.load_m;
+  t.lh = p.load_h;
+  for (int a = 0; a < 3; ++a) t.v[a] = static_cast<const float*>(soa.f[SPH_S_V_X + a]);
+  t.u = static_cast<const float*>(soa.f[SPH_S_UK]);
+  t.vsig = static_cast<const float*>(soa.f[SPH_S_VSIG]);
+  t.gk = gamma_k;
+  t.cfl = c_cfl;
+  double* part = static_cast<double*>(ws);
+  k_totals_partial<<<kReduceBlocks, kThreads, 0, s>>>(t, n, part);
+  k_totals_final<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_kick_drift(const sph_soa& soa, const CellsDev& c, double dtk, double dtd,
                              int32_t* moved, hipStream_t s) {

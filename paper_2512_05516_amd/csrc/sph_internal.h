@@ -127,6 +127,10 @@ hipError_t launch_kick_drift_aos(void* aos, const AosLayout& L, int n, int n_c, 
                                  double dtd, int32_t* moved, hipStream_t s);
 
 size_t reduce_workspace_bytes(int n);
+hipError_t launch_predict(const sph_soa& soa, const Prec& p, const CellsDev& c, const void* aos,
+                          const AosLayout& L, double dth, hipStream_t s);
+hipError_t launch_step_totals(const sph_soa& soa, const Prec& p, int n, double gamma_k,
+                              double c_cfl, double* out, void* ws, hipStream_t s);
 hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,
                          hipStream_t s);
 

@@ -123,6 +123,44 @@ class Pipeline:
         self.force_aos()
         self.kick_drift_aos(dt_kick, dt_drift)
 
+    def kdk_run(self, steps, dt=None, c_cfl=sphmi.C_CFL, dt_max=float("inf")):
+        """Leapfrog kick-drift-kick over `steps` steps with h held fixed
+        (the sequence of sph_predict / sph_step_totals in the header). dt:
+        fixed step size, or None for the Courant step from the last forces
+        (capped at dt_max). Returns the history: per step the step size and
+        the totals before it, then the totals after the run (dt None)."""
+        torch = self.torch
+        tot = torch.zeros(8, dtype=torch.float64, device=self.aos.device)
+
+        def totals():
+            sphmi.step_totals(self.soa, self.cells, tot, self.red_ws, self.prm, c_cfl,
+                              self.stream)
+            t = tot.cpu().numpy()
+            return {"p": t[0:3].copy(), "ekin": float(t[3]), "eth": float(t[4]),
+                    "mass": float(t[5]), "dt_cfl": float(t[6]), "n_vsig": int(t[7])}
+
+        self.bin()
+        self.convert("full")
+        self.density()
+        self.force()
+        self.writeback("full")
+        hist = []
+        for _ in range(steps):
+            t = totals()
+            step = dt if dt is not None else min(t["dt_cfl"], dt_max)
+            hist.append(dict(t, dt=step))
+            self.kick_drift(0.5 * step, step)
+            self.writeback("kick")
+            self.bin()
+            self.convert("full")
+            sphmi.predict(self.soa, self.cells, self.aos, self.layout, 0.5 * step, self.stream)
+            self.density()
+            self.force()
+            self.kick_drift(0.5 * step, 0.0)
+            self.writeback("full")
+        hist.append(dict(totals(), dt=None))
+        return hist
+
     # --- readback ---------------------------------------------------------------
     def records(self) -> np.ndarray:
         self.torch.cuda.synchronize()

@@ -108,7 +108,7 @@ EXPORTS = [
     "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
     "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
-    "sph_writeback_host",
+    "sph_writeback_host", "sph_predict", "sph_step_totals",
 ]
 
 _lib = None
@@ -140,6 +140,9 @@ def lib():
     L.sph_gather_host.argtypes = [vp, P(AosLayout), i32, i32, vp, vp, i32, P(Precision), P(Soa),
                                   vp, sz, i32, vp]
     L.sph_writeback_host_size.argtypes = [i32, i32, P(sz)]
+    L.sph_predict.argtypes = [P(Soa), P(Precision), P(Cells), vp, P(AosLayout), C.c_double, vp]
+    L.sph_step_totals.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), C.c_double, vp, vp,
+                                  sz, vp]
     L.sph_writeback_host.argtypes = [P(Soa), i32, vp, i32, vp, P(AosLayout), vp, sz, i32, vp]
     L.sph_worklist_size.argtypes = [i32, i32, i32, P(sz)]
     L.sph_worklist.argtypes = [P(Cells), P(Work), vp]
@@ -544,6 +547,24 @@ def autotune(loop: str, soa: "DeviceSoa", cells: "DeviceCells", prm=None, cand=N
 def kick_drift(soa: DeviceSoa, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):
     _check(lib().sph_kick_drift(C.byref(soa.struct), C.byref(cells.struct), float(dt_kick),
                                 float(dt_drift), _ptr(moved), _stream(stream)))
+
+
+C_CFL = 0.1    # Courant factor of the leapfrog runs' time step
+
+
+def predict(soa: DeviceSoa, cells: DeviceCells, aos, layout, dt_half, stream=None):
+    _check(lib().sph_predict(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                             _ptr(aos), C.byref(layout), float(dt_half), _stream(stream)))
+
+
+def step_totals(soa: DeviceSoa, cells: DeviceCells, out, workspace, prm=None, c_cfl=C_CFL,
+                stream=None):
+    """out (8 doubles on the device): sum m v (3), sum m |v|^2/2, sum m u,
+    sum m, the Courant step, the number of slots with vsig > 0."""
+    _check(lib().sph_step_totals(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                                 C.byref(prm or params()), float(c_cfl), _ptr(out),
+                                 _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                 _stream(stream)))
 
 
 def reduce(soa: DeviceSoa, cells: DeviceCells, out, workspace, stream=None):

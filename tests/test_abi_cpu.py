@@ -39,7 +39,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 5
+    assert sph.abi_version() == 6
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
@@ -362,3 +362,30 @@ def test_host_binning_and_streaming_checks(sph, orc):
                               C.c_void_p(rec.ctypes.data), C.byref(lay),
                               C.c_void_p(buf.ctypes.data), buf.size, 1, None)
     assert st == sph.SPH_E_RANGE
+
+
+def test_leapfrog_entry_points_host_side(sph):
+    """sph_predict / sph_step_totals reject bad arguments before any launch."""
+    L = sph.lib()
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    cells = _fake_cells(sph)
+    soa = sph.Soa()
+    for f in range(len(sph.S_FIELDS)):
+        soa.f[f] = 0x4000
+    prec = sph.precision()
+    aos = C.c_void_p(0x8000)
+    pred = lambda s, p, l, dth: L.sph_predict(s, C.byref(p), C.byref(cells), aos, l, dth, None)
+    assert pred(None, prec, C.byref(lay), 1e-3) == sph.SPH_E_INVALID
+    assert pred(C.byref(soa), sph.precision("t20", "t20", "t20"), C.byref(lay),
+                1e-3) == sph.SPH_E_UNSUPPORTED
+    assert pred(C.byref(soa), prec, C.byref(lay), float("nan")) == sph.SPH_E_INVALID
+    no_a = sph.layout_from_dtype(inputs.AOS_F32)
+    no_a.offset[sph.A["A"]] = sph.ABSENT
+    assert pred(C.byref(soa), prec, C.byref(no_a), 1e-3) == sph.SPH_E_INVALID
+    out = C.c_void_p(0x9000)
+    tot = lambda c, ws, nb: L.sph_step_totals(C.byref(soa), C.byref(prec), C.byref(cells),
+                                              C.byref(sph.params()), c, out, ws, nb, None)
+    need = sph.reduce_workspace_size(16)
+    assert tot(0.0, C.c_void_p(0xa000), need) == sph.SPH_E_INVALID
+    assert tot(0.1, None, need) == sph.SPH_E_INVALID
+    assert tot(0.1, C.c_void_p(0xa000), need - 8) == sph.SPH_E_NOMEM

@@ -1,0 +1,134 @@
+"""Leapfrog runs on the device (sph_predict, sph_step_totals and the
+kick-drift-kick sequence) against the oracle's kdk_run.
+
+Bars: the Courant step and the totals are FP64 reductions of the stored
+FP32 values, so they match the same formulas evaluated by numpy on those
+values (step bit for bit, sums to 1e-12). A run of S steps evaluates the
+forces S + 1 times at FP32 (1e-5 each), so the changes of x, v and u over
+the run match the oracle's within (S + 1) x 1e-5 (relative RMSE); the
+energies match within the FP32 storage of v and u (1e-6)."""
+import numpy as np
+import pytest
+
+from paper_2512_05516_amd import inputs
+
+from helpers import rel_rmse
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sph():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2512_05516_amd import sphmi
+    sphmi.lib()
+    return sphmi
+
+
+def _moving(n, seed, v_sigma=0.3):
+    ps = inputs.clustered_set(n, seed)
+    ps.v = np.random.default_rng(seed).normal(0.0, v_sigma, ps.v.shape)
+    return ps
+
+
+def _pdiff(a, b):
+    d = a - b
+    return d - np.round(d)
+
+
+def test_step_totals_exact(sph, orc):
+    """Totals and Courant step of the device state equal numpy's on the
+    same stored values."""
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = _moving(30000, 3)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    pipe = Pipeline(inputs.pack_aos(ps, "f32"), n_c, sched="grid", til=sph.tile(32, 2))
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    out = torch.zeros(8, dtype=torch.float64, device="cuda")
+    sph.step_totals(pipe.soa, pipe.cells, out, pipe.red_ws, c_cfl=0.1)
+    got = out.cpu().numpy()
+    m = pipe.slot("M").astype(np.float64)
+    v = np.stack([pipe.slot(f"V_{a}") for a in "XYZ"], 1).astype(np.float64)
+    u = pipe.slot("UK").astype(np.float64)
+    h = pipe.slot("H").astype(np.float64)
+    vs = pipe.slot("VSIG").astype(np.float64)
+    ref = orc.totals(m, v, u)
+    np.testing.assert_allclose(got[0:3], ref["p"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(got[3:6], [ref["ekin"], ref["eth"], ref["mass"]], rtol=1e-12)
+    assert got[6] == orc.timestep(h, vs, 0.1, sph.params().gamma_k)[1]
+    assert got[7] == np.count_nonzero(vs > 0)
+
+
+@pytest.mark.parametrize("steps", [1, 4])
+def test_kdk_matches_oracle(sph, orc, steps):
+    """Fixed-step run on a clustered set (uneven cells, ragged chunks)."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = _moving(20000, 5)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref0 = inputs.unpack_aos(rec)
+    dt = 1e-3
+    pipe = Pipeline(rec, n_c, sched="grid", til=sph.tile(32, 2))
+    hist = pipe.kdk_run(steps, dt=dt)
+    assert pipe.status() == 0
+    r = pipe.records()
+    fin, ohist = orc.kdk_run(ref0, n_c, steps, dt=dt)
+    bar = (steps + 1) * 1e-5
+    dx_g = _pdiff(r["x"], ref0.x)
+    dx_o = _pdiff(fin.x, ref0.x)
+    errs = {"dx": rel_rmse(dx_g, dx_o),
+            "dv": rel_rmse(r["v"].astype(np.float64) - ref0.v, fin.v - ref0.v),
+            "du": rel_rmse((r["u"].astype(np.float64) - ref0.u)[:, None],
+                           (fin.u - ref0.u)[:, None])}
+    print(steps, {k: f"{e:.2e}" for k, e in errs.items()})
+    for k, e in errs.items():
+        assert e < bar, (k, e)
+    for hg, ho in zip(hist, ohist):
+        for k in ("ekin", "eth"):
+            assert abs(hg[k] - ho[k]) <= 1e-6 * (ho["ekin"] + ho["eth"]), (k, hg[k], ho[k])
+        np.testing.assert_allclose(hg["p"], ho["p"], atol=1e-6 * np.abs(ref0.v).max())
+
+
+def test_kdk_courant_steps(sph, orc):
+    """dt from the Courant condition: each step's size matches the
+    oracle's within the FP32 bar, and the energy stays conserved."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = _moving(20000, 6)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    pipe = Pipeline(rec, n_c, sched="grid", til=sph.tile(32, 2))
+    hist = pipe.kdk_run(3)
+    _, ohist = orc.kdk_run(inputs.unpack_aos(rec), n_c, 3)
+    for hg, ho in zip(hist[:-1], ohist[:-1]):
+        assert abs(hg["dt"] / ho["dt"] - 1.0) < 4e-5, (hg["dt"], ho["dt"])
+    e = np.array([h["ekin"] + h["eth"] for h in hist])
+    eo = np.array([h["ekin"] + h["eth"] for h in ohist])
+    assert abs((e[-1] - e[0]) - (eo[-1] - eo[0])) < 1e-6 * e[0]
+
+
+def test_kdk_reduced_storage(sph, orc):
+    """FP16 offsets / BF16 v / FP16 m, h, u: the predicted v, u are stored
+    in those formats; the run stays within the storage error of the FP32
+    run."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = _moving(20000, 7)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    prec = sph.precision("f16", "bf16", "f16", scale_m=14, scale_h=5, scale_u=0)
+    p16 = Pipeline(rec, n_c, prec=prec, sched="grid", til=sph.tile(32, 2))
+    h16 = p16.kdk_run(3, dt=1e-3)
+    p32 = Pipeline(rec, n_c, sched="grid", til=sph.tile(32, 2))
+    h32 = p32.kdk_run(3, dt=1e-3)
+    assert p16.status() == 0
+    r16, r32 = p16.records(), p32.records()
+    ref0 = inputs.unpack_aos(rec)
+    e = rel_rmse(_pdiff(r16["x"], ref0.x), _pdiff(r32["x"], ref0.x))
+    assert e < 2e-2, e
+    e0 = h32[0]["ekin"] + h32[0]["eth"]
+    assert abs((h16[-1]["ekin"] + h16[-1]["eth"]) - (h32[-1]["ekin"] + h32[-1]["eth"])) < 1e-3 * e0
