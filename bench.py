@@ -123,6 +123,7 @@ def cpu_baseline(ps):
 
 SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
 SERVE_SECONDS = 1.0                    # arrivals per rate
+KDK_STEPS = 10         # leapfrog steps of the multi-step run
 PIPE_THREADS = 16      # host worker threads of the streaming arrangement
 H_ROOM = 1.6      # clustered set: cell size / background support radius while h iterates
 H_TOL = 1e-4      # relative h change that ends a particle's iteration
@@ -214,6 +215,31 @@ def pipeline_variant(torch, args, rec, choice, sphmi):
         out[name]["speedup_vs_aos_baseline"] = round(base / ms, 3)
         del hs
         torch.cuda.empty_cache()
+    return out
+
+
+def kdk_variant(torch, rec, kw, Pipeline, steps=KDK_STEPS):
+    """Leapfrog kick-drift-kick run of `steps` steps with the Courant step
+    (h fixed), tuned tiling: wall time per step (bin, convert, predict,
+    density, force, two kicks, writebacks, totals readback) and the drift
+    of the conserved totals."""
+    pipe = Pipeline(rec, N_C, **kw)
+    pipe.kdk_run(1)                              # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = pipe.kdk_run(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    e = np.array([h["ekin"] + h["eth"] for h in hist])
+    p = np.array([h["p"] for h in hist])
+    out = {"steps": steps, "c_cfl": 0.1,
+           "ms_per_step": round(1e3 * secs / steps, 3),
+           "dt": [float(h["dt"]) for h in hist[:-1]],
+           "energy_rel_drift": float(np.abs(e - e[0]).max() / e[0]),
+           "momentum_abs_drift": float(np.abs(p - p[0]).max()),
+           "status_flags": pipe.status()}
+    del pipe
+    torch.cuda.empty_cache()
     return out
 
 
@@ -443,6 +469,8 @@ def main():
         del ph, staging
         torch.cuda.empty_cache()
 
+        log("leapfrog run")
+        result["kdk_run"] = kdk_variant(torch, rec, kw, Pipeline)
         if not args.no_pipeline:
             result["pipeline"] = pipeline_variant(torch, args, rec, choice, sphmi)
 
