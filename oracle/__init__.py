@@ -47,11 +47,21 @@ def build(force: bool = True) -> str:
 
 class Params(C.Structure):
     _fields_ = [("gamma_k", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gradh", C.c_int32)]
+                ("beta", C.c_double), ("gradh", C.c_int32), ("kernel", C.c_int32)]
 
 
-def params(gamma_k=GAMMA_K, gamma=GAMMA, alpha=ALPHA, beta=BETA, gradh=True) -> Params:
-    return Params(gamma_k, gamma, alpha, beta, 1 if gradh else 0)
+KERNEL_M4, KERNEL_WENDLAND_C2 = 0, 1
+KERNELS = {"m4": KERNEL_M4, "wendland_c2": KERNEL_WENDLAND_C2}
+# support radius over smoothing length of the Wendland C2 function: the
+# kernel's standard deviation matches the M4 spline's at equal h
+GAMMA_K_WENDLAND_C2 = 1.936492
+
+
+def params(gamma_k=None, gamma=GAMMA, alpha=ALPHA, beta=BETA, gradh=True, kernel="m4") -> Params:
+    k = KERNELS.get(kernel, kernel)
+    if gamma_k is None:
+        gamma_k = GAMMA_K_WENDLAND_C2 if k == KERNEL_WENDLAND_C2 else GAMMA_K
+    return Params(gamma_k, gamma, alpha, beta, 1 if gradh else 0, k)
 
 
 _lib = None
@@ -73,6 +83,10 @@ def lib():
         L.orc_W.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_dWdh.restype = C.c_double
         L.orc_dWdh.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_kernel_w.restype = C.c_double
+        L.orc_kernel_w.argtypes = [C.c_int, C.c_double]
+        L.orc_kernel_dw.restype = C.c_double
+        L.orc_kernel_dw.argtypes = [C.c_int, C.c_double]
         L.orc_bin.argtypes = [C.c_int, d, C.c_int, i32, i32, i32, d]
         u8 = C.POINTER(C.c_uint8)
         L.orc_density.argtypes = [C.c_int, d, d, d, d, C.POINTER(Params), C.c_int, C.c_int,
@@ -123,12 +137,12 @@ def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def w_hat(u: float) -> float:
-    return lib().orc_w_hat(float(u))
+def w_hat(u: float, kernel="m4") -> float:
+    return lib().orc_kernel_w(KERNELS.get(kernel, kernel), float(u))
 
 
-def dw_hat(u: float) -> float:
-    return lib().orc_dw_hat(float(u))
+def dw_hat(u: float, kernel="m4") -> float:
+    return lib().orc_kernel_dw(KERNELS.get(kernel, kernel), float(u))
 
 
 def W(r, h, gamma_k=GAMMA_K):

@@ -39,44 +39,50 @@
 /* Kernel (Sec. 2.1: cubic spline, compact support)                          */
 /* ------------------------------------------------------------------------ */
 
-/* Normalised 3D M4 cubic spline on the unit support, u = r / H. */
-double orc_w_hat(double u) {
+/* Normalised 3D kernels on the unit support, u = r / H (Sec. 2.1 names the
+ * cubic spline and Wendland families): kernel ORC_KERNEL_M4, the M4 cubic
+ * spline; ORC_KERNEL_WENDLAND_C2, the Wendland C2 function
+ * (21 / 2 pi) (1 - u)^4 (1 + 4 u). */
+double orc_kernel_w(int kernel, double u) {
+  if (!(u < 1.0)) return 0.0;
+  double t = 1.0 - u;
+  if (kernel == ORC_KERNEL_WENDLAND_C2) return (21.0 / (2.0 * ORC_PI)) * t * t * t * t * (1.0 + 4.0 * u);
   if (u < 0.5) return (8.0 / ORC_PI) * (1.0 - 6.0 * u * u + 6.0 * u * u * u);
-  if (u < 1.0) {
-    double t = 1.0 - u;
-    return (16.0 / ORC_PI) * t * t * t;
-  }
-  return 0.0;
+  return (16.0 / ORC_PI) * t * t * t;
 }
 
 /* d(w_hat)/du */
-double orc_dw_hat(double u) {
+double orc_kernel_dw(int kernel, double u) {
+  if (!(u < 1.0)) return 0.0;
+  double t = 1.0 - u;
+  if (kernel == ORC_KERNEL_WENDLAND_C2) return -(210.0 / ORC_PI) * u * t * t * t;
   if (u < 0.5) return (8.0 / ORC_PI) * (-12.0 * u + 18.0 * u * u);
-  if (u < 1.0) {
-    double t = 1.0 - u;
-    return -(48.0 / ORC_PI) * t * t;
-  }
-  return 0.0;
+  return -(48.0 / ORC_PI) * t * t;
 }
 
+double orc_w_hat(double u) { return orc_kernel_w(ORC_KERNEL_M4, u); }
+double orc_dw_hat(double u) { return orc_kernel_dw(ORC_KERNEL_M4, u); }
+
 /* W(r, h) = w_hat(r / H) / H^3 with H = gamma_k h (Eq. interpolant, Eq. density) */
-double orc_W(double r, double h, double gamma_k) {
+double orc_W(double r, double h, double gamma_k) { return orc_W_k(ORC_KERNEL_M4, r, h, gamma_k); }
+double orc_W_k(int kernel, double r, double h, double gamma_k) {
   double H = gamma_k * h;
-  return orc_w_hat(r / H) / (H * H * H);
+  return orc_kernel_w(kernel, r / H) / (H * H * H);
 }
 
 /* dW/dh at fixed r: -gamma_k (3 w_hat(u) + u w_hat'(u)) / H^4 */
-double orc_dWdh(double r, double h, double gamma_k) {
+double orc_dWdh(double r, double h, double gamma_k) { return orc_dWdh_k(ORC_KERNEL_M4, r, h, gamma_k); }
+double orc_dWdh_k(int kernel, double r, double h, double gamma_k) {
   double H = gamma_k * h;
   double u = r / H;
-  return -gamma_k * (3.0 * orc_w_hat(u) + u * orc_dw_hat(u)) / (H * H * H * H);
+  return -gamma_k * (3.0 * orc_kernel_w(kernel, u) + u * orc_kernel_dw(kernel, u)) / (H * H * H * H);
 }
 
 /* |grad_i W(r_ij, h)| along e_ij = (x_i - x_j)/r: w_hat'(u) / H^4 (Eq. gradient) */
-static double orc_gradW(double r, double h, double gamma_k) {
+static double orc_gradW(int kernel, double r, double h, double gamma_k) {
   double H = gamma_k * h;
   if (!(r < H)) return 0.0;
-  return orc_dw_hat(r / H) / (H * H * H * H);
+  return orc_kernel_dw(kernel, r / H) / (H * H * H * H);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -318,9 +324,9 @@ int orc_density(int n, const double *x, const double *m, const double *h,
         int j = l.idx[t];
         double r = sqrt(sep2(x, i, j, d));
         double Hi = p->gamma_k * h[i];
-        rho_i += m[j] * orc_W(r, h[i], p->gamma_k);
-        S += orc_w_hat(r / Hi);
-        dh += m[j] * orc_dWdh(r, h[i], p->gamma_k);
+        rho_i += m[j] * orc_W_k(p->kernel, r, h[i], p->gamma_k);
+        S += orc_kernel_w(p->kernel, r / Hi);
+        dh += m[j] * orc_dWdh_k(p->kernel, r, h[i], p->gamma_k);
       }
       /* grad-h term Omega_i = 1 + (h_i / (3 rho_i)) d rho_i / d h_i,
        * from h = eta (m / rho)^(1/3) */
@@ -377,8 +383,8 @@ int orc_force(int n, const double *x, const double *v, const double *m,
         double e[3] = {d[0] / r, d[1] / r, d[2] / r};
         double fj = p->gradh ? f[j] : 1.0;
         double Aj = fj * P[j] / (rho[j] * rho[j]);
-        double gi = orc_gradW(r, h[i], p->gamma_k);
-        double gj = orc_gradW(r, h[j], p->gamma_k);
+        double gi = orc_gradW(p->kernel, r, h[i], p->gamma_k);
+        double gj = orc_gradW(p->kernel, r, h[j], p->gamma_k);
         double w = (v[3 * i + 0] - v[3 * j + 0]) * e[0] +
                    (v[3 * i + 1] - v[3 * j + 1]) * e[1] +
                    (v[3 * i + 2] - v[3 * j + 2]) * e[2];
@@ -417,8 +423,8 @@ int orc_force(int n, const double *x, const double *v, const double *m,
 /* ------------------------------------------------------------------------ */
 
 static void density_at(int i, double hi, int n, const double *x, const double *m,
-                       double gamma_k, int mode, const cellgrid *g, nlist *l, double *rho,
-                       double *drho_dh) {
+                       double gamma_k, int kernel, int mode, const cellgrid *g, nlist *l,
+                       double *rho, double *drho_dh) {
   /* neighbours of i for support gamma_k hi: a local h array view */
   double d[3];
   double Hi = gamma_k * hi;
@@ -449,8 +455,8 @@ static void density_at(int i, double hi, int n, const double *x, const double *m
   for (int t = 0; t < l->n; ++t) {
     int j = l->idx[t];
     double r = sqrt(sep2(x, i, j, d));
-    r_sum += m[j] * orc_W(r, hi, gamma_k);
-    dh += m[j] * orc_dWdh(r, hi, gamma_k);
+    r_sum += m[j] * orc_W_k(kernel, r, hi, gamma_k);
+    dh += m[j] * orc_dWdh_k(kernel, r, hi, gamma_k);
   }
   *rho = r_sum;
   *drho_dh = dh;
@@ -477,7 +483,7 @@ int orc_smoothing_length(int n, const double *x, const double *m, const double *
       int it = 0;
       for (; it < max_iter; ++it) {
         double rho, drho;
-        density_at(i, h, n, x, m, p->gamma_k, mode, &g, &l, &rho, &drho);
+        density_at(i, h, n, x, m, p->gamma_k, p->kernel, mode, &g, &l, &rho, &drho);
         double ht = eta * cbrt(m[i] / rho);
         double f = h - ht;
         double fp = 1.0 + ht / (3.0 * rho) * drho;

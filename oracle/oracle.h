@@ -31,7 +31,11 @@ typedef struct {
   double alpha;     /* artificial-viscosity strength                        */
   double beta;      /* signal-velocity coefficient of the viscosity         */
   int32_t gradh;    /* 1: grad-h correction factor f_i; 0: f_i = 1          */
+  int32_t kernel;   /* ORC_KERNEL_M4 or ORC_KERNEL_WENDLAND_C2              */
 } orc_params;
+
+#define ORC_KERNEL_M4 0
+#define ORC_KERNEL_WENDLAND_C2 1
 
 /* dtype codes shared with the quantiser entry points */
 enum { ORC_F32 = 0, ORC_F16 = 1, ORC_BF16 = 2, ORC_F64 = 3 };
@@ -44,6 +48,10 @@ double orc_w_hat(double u);
 double orc_dw_hat(double u);
 double orc_W(double r, double h, double gamma_k);
 double orc_dWdh(double r, double h, double gamma_k);
+double orc_kernel_w(int kernel, double u);
+double orc_kernel_dw(int kernel, double u);
+double orc_W_k(int kernel, double r, double h, double gamma_k);
+double orc_dWdh_k(int kernel, double r, double h, double gamma_k);
 
 /* binning: wrap, integer cell, stable order by (cell, input index) */
 int orc_bin(int n, const double *x, int n_c, int32_t *cell, int32_t *cell_start,

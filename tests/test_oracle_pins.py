@@ -59,6 +59,59 @@ def test_dWdh_matches_finite_difference(orc):
         assert abs(fd - got) <= 1e-6 * max(abs(fd), 1.0)
 
 
+def test_wendland_c2_kernel(orc):
+    # The Wendland C2 variant: normalised over the unit support, zero value
+    # and slope at the edge, zero slope at the origin, derivative against a
+    # central difference; and for both kernels H / h = 1 / (2 sigma) with
+    # sigma the per-axis standard deviation of the unit-support kernel,
+    # which fixes the two gamma_k constants (1.825742 for M4, 1.936492 for
+    # C2) from the kernel shapes alone.
+    k = "wendland_c2"
+    val, _ = integrate.quad(lambda u: 4.0 * math.pi * u * u * orc.w_hat(u, k), 0.0, 1.0,
+                            epsabs=1e-14, epsrel=1e-14)
+    assert abs(val - 1.0) < 1e-12
+    assert orc.w_hat(1.0, k) == 0.0 and orc.dw_hat(1.0, k) == 0.0 and orc.dw_hat(0.0, k) == 0.0
+    assert orc.w_hat(1.2, k) == 0.0 and abs(orc.dw_hat(1.0 - 1e-6, k)) < 1e-15
+    for u in np.linspace(0.01, 0.99, 99):
+        d = 1e-6
+        fd = (orc.w_hat(u + d, k) - orc.w_hat(u - d, k)) / (2 * d)
+        assert abs(fd - orc.dw_hat(u, k)) < 1e-7 * max(1.0, abs(fd))
+    for kern, g in (("m4", orc.GAMMA_K), (k, orc.GAMMA_K_WENDLAND_C2)):
+        m2, _ = integrate.quad(lambda u: 4.0 * math.pi * u ** 4 * orc.w_hat(u, kern), 0.0, 1.0,
+                               points=[0.5], epsabs=1e-15, epsrel=1e-14)
+        assert abs(1.0 / (2.0 * math.sqrt(m2 / 3.0)) - g) < 1e-6, kern
+
+
+@pytest.mark.parametrize("kernel", ["m4", "wendland_c2"])
+def test_lattice_and_conservation_per_kernel(orc, kernel):
+    # Both kernels: the perfect-lattice density equals the direct lattice
+    # sum of the kernel (independent of the cell list), the lattice at rest
+    # feels no force, and a jittered set conserves momentum and energy.
+    prm = orc.params(kernel=kernel)
+    ps = inputs.lattice_set(16, 0, perfect=True, order="shuffled")
+    a = prm.gamma_k * inputs.ETA
+    K = int(math.ceil(a)) + 1
+    r = np.arange(-K, K + 1)
+    kx, ky, kz = np.meshgrid(r, r, r, indexing="ij")
+    dist = np.sqrt(kx ** 2 + ky ** 2 + kz ** 2).ravel()
+    dist = dist[dist < a]
+    S = sum(orc.w_hat(t / a, kernel) for t in dist)
+    d = orc.density(ps, prm, n_c=4)
+    assert np.all(d["nngb"] == len(dist))
+    assert np.max(np.abs(d["rho"] * a ** 3 / S - 1.0)) < 1e-13
+    assert np.max(np.abs(d["wcount"] - 4.0 * math.pi / 3.0 * S)) < 1e-11
+    f = orc.force(ps, d, prm, n_c=4)
+    assert np.max(np.abs(f["a"])) < 1e-7 and np.max(np.abs(f["du"])) == 0.0
+    js = inputs.small_set(1)
+    d = orc.density(js, prm, n_c=4)
+    f = orc.force(js, d, prm, n_c=4)
+    red = orc.reduce(js.m, js.v, f["a"], f["du"])
+    assert np.linalg.norm(red[:3]) / red[4] <= 1e-12 and abs(red[3]) / red[5] <= 1e-12
+    assert red[4] > 1e-3
+    db = orc.density(js, prm, mode="brute")
+    assert all(np.array_equal(db[q], d[q]) for q in d)
+
+
 def test_neighbour_number_convention(orc):
     # (4 pi / 3)(gamma_k eta)^3 ~ 48 neighbours at eta = 1.2348: pins the
     # H = gamma_k h convention (H = 2h would give ~63).
@@ -260,9 +313,10 @@ def _solve_h(orc, ps, prm, eta=inputs.ETA, iters=60):
     return q, orc.density(q, prm, mode="brute")
 
 
-def test_gradh_force_is_energy_gradient(orc):
+@pytest.mark.parametrize("kernel", ["m4", "wendland_c2"])
+def test_gradh_force_is_energy_gradient(orc, kernel):
     gam = 5.0 / 3.0
-    prm = orc.params(alpha=0.0)
+    prm = orc.params(alpha=0.0, kernel=kernel)
     ps0 = inputs.lattice_set(6, 11, jitter=0.15, order="shuffled")
     rng = np.random.default_rng(5)
     ps0.m = ps0.m * rng.uniform(0.7, 1.3, ps0.n)        # uneven masses -> uneven h
