@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 6
+#define SPH_ABI_VERSION 7
 
 typedef int32_t sph_status;
 enum {
@@ -196,11 +196,20 @@ typedef enum {
 
 /* physics constants: H = gamma_k h; P = (gamma - 1) rho u; viscosity
  * strength alpha and signal-velocity coefficient beta; gradh = 1 applies
- * the grad-h factor f_i, 0 sets f_i = 1. */
+ * the grad-h factor f_i, 0 sets f_i = 1; kernel picks the smoothing kernel
+ * (Sec. 2.1 names the cubic-spline and Wendland families): SPH_KERNEL_M4,
+ * w(u) = 8/pi (1 - 6u^2 + 6u^3) for u < 1/2, 16/pi (1-u)^3 for u < 1
+ * (gamma_k = 1.825742), or SPH_KERNEL_WENDLAND_C2,
+ * w(u) = 21/(2 pi) (1-u)^4 (1 + 4u) for u < 1 (gamma_k = 1.936492); both
+ * normalised on the unit support u = r / H. */
 typedef struct {
   double gamma_k, gamma, alpha, beta;
   int32_t gradh;
+  int32_t kernel;
 } sph_params;
+
+#define SPH_KERNEL_M4 0
+#define SPH_KERNEL_WENDLAND_C2 1
 
 /* pair-kernel tiling: ti particles i per work item, k lanes per particle
  * (ti * k threads per workgroup). {0, 0} picks the default. Supported

@@ -167,6 +167,9 @@ sph_status check_params(const sph_params* p, Phys& out) {
   out.alpha = (float)p->alpha;
   out.beta = (float)p->beta;
   out.gradh = p->gradh ? 1 : 0;
+  if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_WENDLAND_C2)
+    return fail(SPH_E_INVALID, "params->kernel = %d is not a known kernel", p->kernel);
+  out.kernel = p->kernel;
   return SPH_OK;
 }
 

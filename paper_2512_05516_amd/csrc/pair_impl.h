@@ -719,9 +719,10 @@ struct TaskItems {
 // --------------------------------------------------------------------------
 // Density
 // --------------------------------------------------------------------------
-template <int TI, int K, class Src, class Items>
+template <int TI, int K, class Src, class Items, int KS>
 __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, CellsDev cd, Phys ph,
                                                                     float s32, Items items) {
+  using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
   constexpr int CAP = 4 * NT;
   constexpr int LCAP = 32;
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
               const bool in = r2 < H2;       // the exact support test
               const float u = fast_sqrt(r2) * Hinv;
               float w, dw;
-              kernel_w_dw(u, w, dw);
+              Shape::w_dw(u, w, dw);
               w = in ? w : 0.0f;
               dw = in ? dw : 0.0f;
               const float mj = cmass[t];
@@ -871,9 +872,10 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
 // --------------------------------------------------------------------------
 // Force
 // --------------------------------------------------------------------------
-template <int TI, int K, class Src, class Items>
+template <int TI, int K, class Src, class Items, int KS>
 __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsDev cd, Phys ph,
                                                                  float s32, Items items) {
+  using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
   constexpr int CAP = 2 * NT;
   constexpr int LCAP = 32;
@@ -992,9 +994,9 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
               const float r = fast_sqrt(r2);
               const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
               const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
-              const float gi_ = kernel_dw(r * Hinvi) * Hinv4i;
+              const float gi_ = Shape::dw(r * Hinvi) * Hinv4i;
               const float hj2 = q2.x * q2.x;
-              const float gj_ = kernel_dw(r * q2.x) * (hj2 * hj2);
+              const float gj_ = Shape::dw(r * q2.x) * (hj2 * hj2);
               const float w = (vxi - q1.x) * ex + (vyi - q1.y) * ey + (vzi - q1.z) * ez;
               const float mu = fminf(w, 0.0f);
               const float vs = ci + q2.z - beta * mu;
@@ -1158,7 +1160,9 @@ hipError_t run_density(const S& src, const CellsDev& c, const Phys& ph, int ti, 
   if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_DENS_CASE(TI_, K_)                                                        \
   if (ti == TI_ && k == K_) {                                                         \
-    auto kern = k_density<TI_, K_, S, LoopItems>;                                     \
+    auto kern = ph.kernel == SPH_KERNEL_WENDLAND_C2                                   \
+                    ? k_density<TI_, K_, S, LoopItems, SPH_KERNEL_WENDLAND_C2>        \
+                    : k_density<TI_, K_, S, LoopItems, SPH_KERNEL_M4>;                \
     const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
     kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, LoopItems{wv});                      \
     return hipGetLastError();                                                         \
@@ -1185,7 +1189,9 @@ hipError_t run_force(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   if (w && w->sched == SPH_SCHED_DYNAMIC) k_reset_queues<<<1, 64, 0, s>>>(*w);
 #define SPH_FORCE_CASE(TI_, K_)                                                       \
   if (ti == TI_ && k == K_) {                                                         \
-    auto kern = k_force<TI_, K_, S, LoopItems>;                                       \
+    auto kern = ph.kernel == SPH_KERNEL_WENDLAND_C2                                   \
+                    ? k_force<TI_, K_, S, LoopItems, SPH_KERNEL_WENDLAND_C2>          \
+                    : k_force<TI_, K_, S, LoopItems, SPH_KERNEL_M4>;                  \
     const int G = pair_grid((const void*)kern, TI_ * K_, C, w);                       \
     kern<<<G, TI_ * K_, 0, s>>>(src, c, ph, s32, LoopItems{wv});                      \
     return hipGetLastError();                                                         \
@@ -1209,10 +1215,13 @@ hipError_t run_tasks(const S& src, const CellsDev& c, const Phys& ph, int ti, in
   const float s32 = (float)(1.0 / (double)c.n_c);
 #define SPH_TASK_CASE(TI_, K_)                                                         \
   if (ti == TI_ && k == K_) {                                                          \
-    if (dens.nitems > 0)                                                               \
-      k_density<TI_, K_, S, TaskItems><<<dens.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, dens); \
-    if (force.nitems > 0)                                                              \
-      k_force<TI_, K_, S, TaskItems><<<force.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, force); \
+    const bool wc2 = ph.kernel == SPH_KERNEL_WENDLAND_C2;                                \
+    auto kd = wc2 ? k_density<TI_, K_, S, TaskItems, SPH_KERNEL_WENDLAND_C2>             \
+                  : k_density<TI_, K_, S, TaskItems, SPH_KERNEL_M4>;                     \
+    auto kf = wc2 ? k_force<TI_, K_, S, TaskItems, SPH_KERNEL_WENDLAND_C2>               \
+                  : k_force<TI_, K_, S, TaskItems, SPH_KERNEL_M4>;                       \
+    if (dens.nitems > 0) kd<<<dens.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, dens);    \
+    if (force.nitems > 0) kf<<<force.nitems, TI_ * K_, 0, s>>>(src, c, ph, s32, force); \
     return hipGetLastError();                                                          \
   }
   SPH_TASK_CASE(64, 4)

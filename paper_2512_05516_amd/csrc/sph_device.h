@@ -173,6 +173,37 @@ __device__ __forceinline__ float kernel_dw(float u) {
   return u < 1.0f ? d : 0.0f;
 }
 
+// Wendland C2 on the unit support, FP32: w(u) = 21/(2 pi) (1-u)^4 (1+4u),
+// w'(u) = -210/pi u (1-u)^3, both zero for u >= 1.
+constexpr float kCW = 3.3422538049298023f;    // 21/(2 pi)
+constexpr float kCWd = 66.84507609859604f;    // 210/pi
+
+__device__ __forceinline__ void wendland_w_dw(float u, float& w, float& dw) {
+  const float t = fmaxf(1.0f - u, 0.0f);
+  const float t3 = t * t * t;
+  w = kCW * (t3 * t) * (1.0f + 4.0f * u);
+  dw = -kCWd * u * t3;
+}
+
+__device__ __forceinline__ float wendland_dw(float u) {
+  const float t = fmaxf(1.0f - u, 0.0f);
+  return -kCWd * u * (t * t * t);
+}
+
+// Kernel shape as a compile-time tag: the loops branch once per batch on
+// the launch's (uniform) kernel choice and run a specialised body.
+template <int KS>
+struct KernelShape {
+  static constexpr int value = KS;
+  __device__ __forceinline__ static void w_dw(float u, float& w, float& dw) {
+    if (KS == SPH_KERNEL_WENDLAND_C2) wendland_w_dw(u, w, dw);
+    else kernel_w_dw(u, w, dw);
+  }
+  __device__ __forceinline__ static float dw(float u) {
+    return KS == SPH_KERNEL_WENDLAND_C2 ? wendland_dw(u) : kernel_dw(u);
+  }
+};
+
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 

@@ -42,6 +42,7 @@ struct Prec {
 struct Phys {
   float gamma_k, gamma, alpha, beta;
   int gradh;
+  int kernel;   // SPH_KERNEL_*
 };
 
 struct CellsDev {

@@ -76,7 +76,12 @@ class Precision(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("gamma_k", C.c_double), ("gamma", C.c_double), ("alpha", C.c_double),
-                ("beta", C.c_double), ("gradh", C.c_int32)]
+                ("beta", C.c_double), ("gradh", C.c_int32), ("kernel", C.c_int32)]
+
+
+KERNEL_M4, KERNEL_WENDLAND_C2 = 0, 1
+KERNELS = {"m4": KERNEL_M4, "wendland_c2": KERNEL_WENDLAND_C2}
+GAMMA_K = {KERNEL_M4: 1.825742, KERNEL_WENDLAND_C2: 1.936492}   # H / h per kernel
 
 
 class Tile(C.Structure):
@@ -220,8 +225,11 @@ def precision(pos="f32", vel="f32", mhu="f32", scale_m=0, scale_h=0, scale_u=0) 
     return Precision(DT[pos], DT[vel], DT[mhu], scale_m, scale_h, scale_u)
 
 
-def params(gamma_k=1.825742, gamma=5.0 / 3.0, alpha=0.8, beta=3.0, gradh=True) -> Params:
-    return Params(gamma_k, gamma, alpha, beta, 1 if gradh else 0)
+def params(gamma_k=None, gamma=5.0 / 3.0, alpha=0.8, beta=3.0, gradh=True,
+           kernel="m4") -> Params:
+    k = KERNELS.get(kernel, kernel)
+    return Params(GAMMA_K[k] if gamma_k is None else gamma_k, gamma, alpha, beta,
+                  1 if gradh else 0, k)
 
 
 def tile(ti=0, k=0) -> Tile:

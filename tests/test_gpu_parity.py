@@ -786,3 +786,73 @@ def test_smoothing_length_full_size_clustered(sph, orc):
     assert np.all((ito <= 30) | (ho == h_max))
     assert np.max(np.abs(h[sel] / ho - 1)) < 3 * tol + 1e-5
     print(f"h iteration on 4M particles: {it} passes, {left} held at h_max")
+
+
+# ---------------------------------------------------------------------------
+# Wendland C2 kernel variant
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("til,sched,sub_bits", [((64, 4), None, 0), ((32, 2), "grid", 1),
+                                                ((16, 4), "static", 2)])
+def test_wendland_matches_oracle(sph, orc, til, sched, sub_bits):
+    """Density and force with the Wendland C2 kernel (gamma_k 1.936492) on a
+    clustered set: counts bit-exact with the FP32 replica, values at the
+    FP32 bar; AoS == SoA bit for bit."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    prm_o, prm_g = orc.params(kernel="wendland_c2"), sph.params(kernel="wendland_c2")
+    assert prm_o.gamma_k == prm_g.gamma_k
+    ps = inputs.clustered_set(20000, 9)
+    n_c = int(np.floor(1.0 / (prm_o.gamma_k * ps.h.max())))
+    pipe = run_gpu(ps, n_c, prm=prm_g, til=sph.tile(*til), sched=sched, sub_bits=sub_bits)
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    d, f = oracle_step(orc, ref, n_c, prm=prm_o)
+    nd, nf = orc.count32(ref, n_c, gamma_k=prm_o.gamma_k)
+    assert np.array_equal(got["nngb"], nd) and np.array_equal(got["nforce"], nf)
+    got["h"] = ref.h
+    check_fp32(got, d, f, tag=f"wendland {til} {sched}")
+    # the M4 run differs: the kernel choice reaches the loops
+    m4 = gpu_fields(run_gpu(ps, n_c, til=sph.tile(*til), sched=sched, sub_bits=sub_bits))
+    assert not np.array_equal(m4["rho"], got["rho"])
+    if sub_bits == 0:
+        pa = Pipeline(inputs.pack_aos(ps, "f32"), n_c, prm=prm_g, til=sph.tile(*til), sched=sched)
+        pa.bin()
+        pa.density_aos()
+        pa.force_aos()
+        ra = pa.records()
+        for k in ("rho", "wcount", "rho_dh", "f", "P", "c", "nngb", "a", "du", "vsig", "nforce"):
+            assert np.array_equal(np.asarray(ra[k]), pipe.records()[k]), k
+
+
+def test_wendland_smoothing_length(sph, orc):
+    """The h iteration with the Wendland kernel reaches the oracle's roots and
+    the weighted neighbour number (4 pi / 3)(gamma_k eta)^3 of that kernel."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    prm_o, prm_g = orc.params(kernel="wendland_c2"), sph.params(kernel="wendland_c2")
+    ps = inputs.small_set(2)
+    ps.h = ps.h * np.random.default_rng(4).uniform(0.8, 1.2, ps.n)
+    n_c = 4
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    pipe = Pipeline(rec, n_c, prm=prm_g)
+    pipe.bin()
+    pipe.convert("full")
+    tol = 1e-5
+    it, left = pipe.smoothing_length(tol=tol, max_iter=40)
+    assert left == 0
+    g64 = prm_g.gamma_k
+    gk, s = np.float32(g64), np.float32(1.0 / n_c)
+    h_max = np.float32(s / gk)
+    while (gk * h_max) * (gk * h_max) > s * s or g64 * float(h_max) > 1.0 / n_c:
+        h_max = np.nextafter(h_max, np.float32(0))
+    ho, _ = orc.smoothing_length(ref, n_c=n_c, h_max=float(h_max), tol=tol, max_iter=40,
+                                 prm=prm_o)
+    h = pipe.records()["h"].astype(np.float64)
+    assert np.max(np.abs(h / ho - 1)) < 3 * tol + 1e-5
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    wc = pipe.soa["WCOUNT"].cpu().numpy()
+    target = 4.0 * np.pi / 3.0 * (g64 * orc.ETA) ** 3
+    assert np.max(np.abs(wc / target - 1)) < 10 * tol + 1e-4
