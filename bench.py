@@ -469,6 +469,20 @@ def main():
         del ph, staging
         torch.cuda.empty_cache()
 
+        # ---- Wendland C2 kernel variant, FP32 SoA step, same tiling ---------------
+        log("Wendland C2 step")
+        pw = Pipeline(rec, N_C, prm=sphmi.params(kernel="wendland_c2"), **kw)
+        s_w, per_w = timed_steps(torch, pw, "soa", args.steps, args.warmup)
+        red_w = pw.red_out.cpu().numpy()
+        result["wendland_c2"] = {"ms_per_step": 1e3 * s_w / args.steps,
+                                 "value": float(red_w[6] + red_w[7]) * args.steps / s_w,
+                                 "pairs_per_step": {"density": float(red_w[6]),
+                                                    "force": float(red_w[7])},
+                                 "kernels_ms": {k: round(v, 4) for k, v in per_w.items()},
+                                 "gamma_k": sphmi.params(kernel="wendland_c2").gamma_k,
+                                 "status_flags": pw.status()}
+        del pw
+        torch.cuda.empty_cache()
         log("leapfrog run")
         result["kdk_run"] = kdk_variant(torch, rec, kw, Pipeline)
         if not args.no_pipeline:
