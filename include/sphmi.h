@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 7
+#define SPH_ABI_VERSION 8
 
 typedef int32_t sph_status;
 enum {
@@ -327,6 +327,12 @@ sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t vie
  * the schedule. work->sched is not used here. */
 sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t *bytes);
 sph_status sph_worklist(const sph_cells *cells, sph_work *work, hipStream_t stream);
+/* The same list restricted to the cells holding occ_lo <= count < occ_hi
+ * particles: a loop over all cells can run as several launches, each with
+ * the tile that suits its occupancy class (results do not depend on the
+ * split). Empty or negative ranges: SPH_E_INVALID. */
+sph_status sph_worklist_occupancy(const sph_cells *cells, sph_work *work, int32_t occ_lo,
+                                  int32_t occ_hi, hipStream_t stream);
 
 /* Density loop (Eq. density; Alg. 1 CallQuadratic over the 27 cells
  * around each particle's cell). For every slot i, over every j with

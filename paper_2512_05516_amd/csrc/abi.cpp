@@ -279,6 +279,11 @@ sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t* bytes) 
 }
 
 sph_status sph_worklist(const sph_cells* cells, sph_work* work, hipStream_t stream) {
+  return sph_worklist_occupancy(cells, work, 0, 0x7fffffff, stream);
+}
+
+sph_status sph_worklist_occupancy(const sph_cells* cells, sph_work* work, int32_t occ_lo,
+                                  int32_t occ_hi, hipStream_t stream) {
   CellsDev c;
   SPH_TRY(check_cells(cells, true, c));
   if (!work || !work->buf) return fail(SPH_E_INVALID, "work or work->buf is NULL");
@@ -288,8 +293,10 @@ sph_status sph_worklist(const sph_cells* cells, sph_work* work, hipStream_t stre
   if (work->bytes < worklist_bytes(c.n, c.n_c, work->ti))
     return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", work->bytes,
                 worklist_bytes(c.n, c.n_c, work->ti));
+  if (occ_lo < 0 || occ_hi <= occ_lo)
+    return fail(SPH_E_INVALID, "occupancy range [%d, %d) is empty or negative", occ_lo, occ_hi);
   WorkDev w = work_view(*work, c.n, c.n_c);
-  return hip_status(launch_worklist(c, w, stream), "sph_worklist");
+  return hip_status(launch_worklist_range(c, w, nullptr, occ_lo, occ_hi, stream), "sph_worklist");
 }
 
 sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,

@@ -83,6 +83,8 @@ hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s);
 size_t worklist_bytes(int n, int n_c, int ti);
 int worklist_capacity(int n, int n_c, int ti);
 hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s);
+hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint8_t* active,
+                                 int occ_lo, int occ_hi, hipStream_t s);
 // work list of the cells that hold at least one slot with active[k] != 0
 hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uint8_t* active,
                                   hipStream_t s);

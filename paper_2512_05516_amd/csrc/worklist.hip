@@ -54,6 +54,7 @@ __device__ __forceinline__ int cell_count(const int32_t* __restrict__ start, int
 __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict__ start, int n_c,
                                                         int n, int ti, int cost_cap,
                                                         const uint8_t* __restrict__ active,
+                                                        int occ_lo, int occ_hi,
                                                         int32_t* __restrict__ pos,
                                                         int32_t* __restrict__ cost) {
   const int C = n_c * n_c * n_c;
@@ -65,6 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
     return;
   }
   int cnt = cell_count(start, c, n);
+  if (cnt < occ_lo || cnt >= occ_hi) cnt = 0;   // only cells of this occupancy class
   if (active && cnt > 0) {   // only cells that hold an active slot
     const int a = min(max(start[c], 0), n);
     bool any = false;
@@ -153,11 +155,16 @@ hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s) {
 
 hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uint8_t* active,
                                   hipStream_t s) {
+  return launch_worklist_range(c, w, active, 0, 0x7fffffff, s);
+}
+
+hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint8_t* active,
+                                 int occ_lo, int occ_hi, hipStream_t s) {
   const int C = c.n_c * c.n_c * c.n_c;
   WlLayout L = wl_layout(reinterpret_cast<char*>(w.counters), C);
   const int cost_cap = (int)((((int64_t)1 << 31) - 1) / ((int64_t)C + 1));
   k_wl_count<<<cdiv(C + 1, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, cost_cap,
-                                                         active, L.pos, L.cost);
+                                                         active, occ_lo, occ_hi, L.pos, L.cost);
   hipError_t e = scan_i32(L.pos, C + 1, L.partials, s);
   if (e != hipSuccess) return e;
   e = scan_i32(L.cost, C + 1, L.partials, s);

@@ -94,8 +94,7 @@ class HostStep:
         c.perm.copy_(self._perm, non_blocking=True)
         c.cell.copy_(self._cell, non_blocking=True)
         c.hmax.copy_(self._hmax, non_blocking=True)
-        for w in p._lists:
-            sphmi.worklist(c, w, p.stream)
+        p.build_lists()
         args = (self.layout, self.n_c, perm, cell)
         sphmi.gather_host(self.rec, *args, "density", p.soa, self.staging, self.nthreads, p.stream)
         p.density()

@@ -15,7 +15,7 @@ from . import sphmi
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
                  prm=None, stream=None, sub_bits: int = 0, sched=None,
-                 til_force=None):
+                 til_force=None, split=None):
         import torch
         self.torch = torch
         self.n = int(aos_np.shape[0])
@@ -47,6 +47,22 @@ class Pipeline:
             else:
                 self.work_force = sphmi.DeviceWork(self.n, self.n_c, ti_f, device, sf)
                 self._lists.append(self.work_force)
+        # split: per loop ("density" / "force") None or (T, (ti, k), sched):
+        # cells with fewer than T particles run as a launch of their own with
+        # that tile and schedule, the other cells with the loop's own tile and
+        # schedule (which must then be a work-list schedule)
+        self.split = dict(split or {})
+        self._parts = {}
+        for loop, main_til, main_sched in (("density", self.til, sd), ("force", self.til_force, sf)):
+            sp = self.split.get(loop)
+            if not sp:
+                continue
+            T, (ti, k), small_sched = sp
+            big_sched = main_sched or "grid"
+            ws = sphmi.DeviceWork(self.n, self.n_c, ti, device, small_sched)
+            wl = sphmi.DeviceWork(self.n, self.n_c, main_til.ti or 64, device, big_sched)
+            self._parts[loop] = [(sphmi.tile(ti, k), ws, (0, int(T))),
+                                 (main_til, wl, (int(T), 2 ** 31 - 1))]
         self.bin_ws = torch.empty(sphmi.bin_workspace_size(self.n, self.n_c), dtype=torch.uint8,
                                   device=device)
         self.soa = sphmi.DeviceSoa(self.n, self.prec, device)
@@ -58,8 +74,15 @@ class Pipeline:
     # --- individual stages -------------------------------------------------
     def bin(self):
         sphmi.bin(self.aos, self.layout, self.cells, self.bin_ws, self.stream)
+        self.build_lists()
+
+    def build_lists(self):
+        """(Re)build every work list from the current cell list."""
         for w in self._lists:
             sphmi.worklist(self.cells, w, self.stream)
+        for parts in self._parts.values():
+            for _, w, occ in parts:
+                sphmi.worklist(self.cells, w, self.stream, occ)
 
     def convert(self, view="full"):
         sphmi.convert(self.aos, self.layout, self.cells, view, self.soa, self.stream)
@@ -74,14 +97,21 @@ class Pipeline:
                                      self.til, self.work, None,
                                      self.aos if write_back else None,
                                      self.layout if write_back else None, self.stream)
-        for w in self._lists:          # the passes leave a filtered list behind
-            sphmi.worklist(self.cells, w, self.stream)
+        self.build_lists()             # the passes leave a filtered list behind
         return out
 
     def density(self):
+        if "density" in self._parts:
+            for til, w, _ in self._parts["density"]:
+                sphmi.density(self.soa, self.cells, self.prm, til, self.stream, w)
+            return
         sphmi.density(self.soa, self.cells, self.prm, self.til, self.stream, self.work)
 
     def force(self):
+        if "force" in self._parts:
+            for til, w, _ in self._parts["force"]:
+                sphmi.force(self.soa, self.cells, self.prm, til, self.stream, w)
+            return
         sphmi.force(self.soa, self.cells, self.prm, self.til_force, self.stream, self.work_force)
 
     def reduce(self):
@@ -94,12 +124,12 @@ class Pipeline:
         sphmi.writeback(self.soa, self.cells, view, self.aos, self.layout, self.stream)
 
     def density_aos(self):
-        sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, self.til, self.stream,
-                          self.work)
+        for til, w, _ in self._parts.get("density", [(self.til, self.work, None)]):
+            sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, til, self.stream, w)
 
     def force_aos(self):
-        sphmi.force_aos(self.aos, self.layout, self.cells, self.prm, self.til_force, self.stream,
-                        self.work_force)
+        for til, w, _ in self._parts.get("force", [(self.til_force, self.work_force, None)]):
+            sphmi.force_aos(self.aos, self.layout, self.cells, self.prm, til, self.stream, w)
 
     def kick_drift_aos(self, dt_kick, dt_drift):
         sphmi.kick_drift_aos(self.aos, self.layout, self.cells, dt_kick, dt_drift, self.moved,

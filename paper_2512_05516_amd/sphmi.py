@@ -113,7 +113,7 @@ EXPORTS = [
     "sph_server_submit", "sph_server_poll", "sph_server_get_stats", "sph_server_drain",
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
     "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
-    "sph_writeback_host", "sph_predict", "sph_step_totals",
+    "sph_writeback_host", "sph_predict", "sph_step_totals", "sph_worklist_occupancy",
 ]
 
 _lib = None
@@ -151,6 +151,7 @@ def lib():
     L.sph_writeback_host.argtypes = [P(Soa), i32, vp, i32, vp, P(AosLayout), vp, sz, i32, vp]
     L.sph_worklist_size.argtypes = [i32, i32, i32, P(sz)]
     L.sph_worklist.argtypes = [P(Cells), P(Work), vp]
+    L.sph_worklist_occupancy.argtypes = [P(Cells), P(Work), i32, i32, vp]
     L.sph_density.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_force.argtypes = [P(Soa), P(Precision), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift.argtypes = [P(Soa), P(Cells), C.c_double, C.c_double, vp, vp]
@@ -395,8 +396,15 @@ def worklist_size(n, n_c, ti) -> int:
     return out.value
 
 
-def worklist(cells: DeviceCells, work: DeviceWork, stream=None):
-    _check(lib().sph_worklist(C.byref(cells.struct), C.byref(work.struct), _stream(stream)))
+def worklist(cells: DeviceCells, work: DeviceWork, stream=None, occupancy=None):
+    """Build `work` from the cell list; occupancy=(lo, hi) keeps only the
+    cells holding lo <= count < hi particles."""
+    if occupancy is None:
+        _check(lib().sph_worklist(C.byref(cells.struct), C.byref(work.struct), _stream(stream)))
+    else:
+        lo, hi = occupancy
+        _check(lib().sph_worklist_occupancy(C.byref(cells.struct), C.byref(work.struct), int(lo),
+                                            int(min(hi, 2 ** 31 - 1)), _stream(stream)))
 
 
 def _wk(work):

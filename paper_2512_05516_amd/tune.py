@@ -10,8 +10,12 @@ set; this driver repeats that for each sub-cell depth (which needs a
 re-bin), picks the depth with the smallest density + force time and the
 fastest candidate of each loop, and keeps the result in a JSON cache keyed
 by the workload's signature (particle count, cells, occupancy statistics,
-storage formats, device). The choice changes only timings: every
-candidate computes the same interactions.
+storage formats, device). On cells of very uneven occupancy it then tries
+splitting each loop into two launches by an occupancy threshold T: the
+cells with fewer than T particles with a tile of their own, the others with
+the loop's tile, and keeps a split that is faster than the single launch.
+The choice changes only timings: every candidate computes the same
+interactions.
 """
 import json
 import os
@@ -62,8 +66,73 @@ def _store(path, cache):
     os.replace(tmp, path)
 
 
+SPLIT_THRESHOLDS = (32, 48, 64)
+SPLIT_SMALL = ((32, 2, "grid"), (32, 8, "grid"), (16, 4, "grid"), (64, 1, "grid"))
+SPLIT_LARGE = ((64, 4, "dynamic"), (32, 2, "grid"), (64, 4, "static"))
+
+
+def _time_parts(pipe, loop, parts, reps):
+    """Mean time (ms) of one pass of `loop` as the given launches."""
+    import torch
+    fn = sphmi.density if loop == "density" else sphmi.force
+
+    def once():
+        for til, w in parts:
+            fn(pipe.soa, pipe.cells, pipe.prm, til, None, w)
+    once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_split(pipe, single: dict, reps: int = 3, log=None) -> dict:
+    """For each loop, the best two-launch split (threshold T, small tile and
+    schedule, large tile and schedule) on the binned and converted `pipe`,
+    kept when it beats the single launch `single[loop]["ms"]` by 3 %."""
+    occ = np.diff(pipe.cells.cell_start.cpu().numpy())
+    out = {}
+    works = {}
+
+    def work(ti, sched, rng):
+        key = (ti, sched, rng)
+        if key not in works:
+            w = sphmi.DeviceWork(pipe.n, pipe.n_c, ti, pipe.aos.device, sched)
+            sphmi.worklist(pipe.cells, w, None, rng)
+            works[key] = w
+        return works[key]
+
+    for loop in ("density", "force"):
+        s = single[loop]
+        large = {(s["ti"], s["k"], s["sched"] or "grid")} | set(SPLIT_LARGE)
+        best = None
+        for T in SPLIT_THRESHOLDS:
+            frac = occ[occ < T].sum() / max(occ.sum(), 1)
+            if not 0.05 < frac < 0.95:
+                continue
+            for (ts, ks, ss) in SPLIT_SMALL:
+                for (tl, kl, sl) in sorted(large):
+                    parts = [(sphmi.tile(ts, ks), work(ts, ss, (0, T))),
+                             (sphmi.tile(tl, kl), work(tl, sl, (T, 2 ** 31 - 1)))]
+                    ms = _time_parts(pipe, loop, parts, reps)
+                    if best is None or ms < best[0]:
+                        best = (ms, T, (ts, ks, ss), (tl, kl, sl))
+        if best is not None and best[0] < 0.97 * s["ms"]:
+            ms, T, sm, lg = best
+            out[loop] = {"threshold": T, "small": list(sm), "large": list(lg), "ms": ms}
+            if log:
+                log(f"tune split {loop}: cells < {T} {sm[0]}x{sm[1]} {sm[2]}, others "
+                    f"{lg[0]}x{lg[1]} {lg[2]}: {ms:.3f} ms (single {s['ms']:.3f} ms)")
+    del works
+    return out
+
+
 def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), cand=None,
-         reps: int = 3, cache_path=DEFAULT_CACHE, refresh: bool = False, log=None) -> dict:
+         reps: int = 3, cache_path=DEFAULT_CACHE, refresh: bool = False, log=None,
+         split: bool = True) -> dict:
     """Choose sub_bits and each loop's (tile, schedule) for the AoS records
     `rec` binned with n_c cells per axis. Returns {"sub_bits", "density":
     {ti, k, sched, ms}, "force": {...}, "table": [...], "signature", "cached"}."""
@@ -74,6 +143,7 @@ def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), can
     sig["sub_bits"] = list(sub_bits)
     sig["reps"] = reps
     sig["candidates"] = cand if cand is None else [list(c) for c in cand]
+    sig["split"] = bool(split)
     cache = _load(cache_path) if cache_path else {}
     if not refresh and _key(sig) in cache:
         out = dict(cache[_key(sig)])
@@ -108,7 +178,14 @@ def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), can
     out = {"sub_bits": sb,
            "density": {"ti": d[0], "k": d[1], "sched": d[2], "ms": d[3]},
            "force": {"ti": f[0], "k": f[1], "sched": f[2], "ms": f[3]},
-           "table": table, "signature": sig}
+           "table": table, "signature": sig, "split": {}}
+    if split:
+        pipe = Pipeline(rec, n_c, prec=prec, prm=prm, sub_bits=sb)
+        pipe.bin()
+        pipe.convert("full")
+        out["split"] = tune_split(pipe, out, reps, log)
+        del pipe
+        torch.cuda.empty_cache()
     if cache_path:
         cache = _load(cache_path)
         cache[_key(sig)] = out
@@ -120,12 +197,28 @@ def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), can
 
 def pipeline_kwargs(choice: dict) -> dict:
     """Pipeline keyword arguments that apply a tuner choice."""
-    d, f = choice["density"], choice["force"]
+    d, f = dict(choice["density"]), dict(choice["force"])
+    sp = choice.get("split") or {}
+    split = {}
+    for loop, c in (("density", d), ("force", f)):
+        if loop in sp:
+            s = sp[loop]
+            c["ti"], c["k"], c["sched"] = s["large"]
+            split[loop] = (s["threshold"], (s["small"][0], s["small"][1]), s["small"][2])
     return {"sub_bits": choice["sub_bits"], "til": sphmi.tile(d["ti"], d["k"]),
-            "til_force": sphmi.tile(f["ti"], f["k"]), "sched": (d["sched"], f["sched"])}
+            "til_force": sphmi.tile(f["ti"], f["k"]), "sched": (d["sched"], f["sched"]),
+            "split": split}
 
 
 def describe(choice: dict) -> str:
-    d, f = choice["density"], choice["force"]
-    return (f"sub_bits {choice['sub_bits']}; density {d['ti']}x{d['k']} "
-            f"{d['sched'] or 'per-cell'}; force {f['ti']}x{f['k']} {f['sched'] or 'per-cell'}")
+    out = [f"sub_bits {choice['sub_bits']}"]
+    sp = choice.get("split") or {}
+    for loop in ("density", "force"):
+        if loop in sp:
+            s = sp[loop]
+            out.append(f"{loop} cells < {s['threshold']}: {s['small'][0]}x{s['small'][1]} "
+                       f"{s['small'][2]}, others {s['large'][0]}x{s['large'][1]} {s['large'][2]}")
+        else:
+            c = choice[loop]
+            out.append(f"{loop} {c['ti']}x{c['k']} {c['sched'] or 'per-cell'}")
+    return "; ".join(out)

@@ -856,3 +856,35 @@ def test_wendland_smoothing_length(sph, orc):
     wc = pipe.soa["WCOUNT"].cpu().numpy()
     target = 4.0 * np.pi / 3.0 * (g64 * orc.ETA) ** 3
     assert np.max(np.abs(wc / target - 1)) < 10 * tol + 1e-4
+
+
+def test_occupancy_split_launches(sph, orc):
+    """A loop run as two launches over occupancy classes (sparse cells with
+    one tile, crowded cells with another, sph_worklist_occupancy) gives the
+    oracle's results: counts bit-exact, values at the FP32 bar; the two
+    classes partition the cells (every particle's outputs are written)."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(30000, 12, f_blob=0.4)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref = inputs.unpack_aos(rec)
+    pipe = Pipeline(rec, n_c, sub_bits=1, til=sph.tile(64, 4), til_force=sph.tile(64, 4),
+                    sched=("grid", "dynamic"),
+                    split={"density": (24, (32, 2), "grid"), "force": (24, (16, 4), "static")})
+    occ = None
+    pipe.bin()
+    occ = np.diff(pipe.cells.cell_start.cpu().numpy())
+    assert (occ[occ > 0] < 24).any() and (occ >= 24).any()
+    pipe.soa["RHO"].fill_(float("nan"))
+    pipe.soa["A_X"].fill_(float("nan"))
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    pipe.writeback("full")
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    got["h"] = ref.h
+    d, f = oracle_step(orc, ref, n_c)
+    nd, nf = orc.count32(ref, n_c)
+    assert np.array_equal(got["nngb"], nd) and np.array_equal(got["nforce"], nf)
+    check_fp32(got, d, f, tag="split")
