@@ -78,17 +78,25 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
   if (hmax && offh != kAbsent) {
     const float h = valid ? rec_load32(rec, rh, dth) : 0.0f;
     const bool contrib = valid && h > 0.0f;
-    // input in cell order (buffers of co-located particles): when every
-    // contributing lane of the wave has the same cell, one atomic per wave
-    const int lead = __shfl(cell, __ffsll((long long)__ballot(contrib)) - 1);
-    if (__all(!contrib || cell == lead)) {
-      float m = contrib ? h : 0.0f;
+    // one atomic per distinct cell of the wave for its first eight cells:
+    // the lanes of the first remaining lane's cell take their maximum
+    // together, then drop out (per-lane atomics on the words of crowded
+    // cells serialise); lanes of further cells use their own atomics
+    uint64_t todo = __ballot(contrib);
+    for (int round = 0; round < 8 && todo; ++round) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int lc = __shfl(cell, leader);
+      const bool mine = contrib && cell == lc;
+      const uint64_t grp = __ballot(mine);
+      float m = mine ? h : 0.0f;
       for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-      if ((threadIdx.x & 63) == 0 && m > 0.0f)
-        atomicMax(reinterpret_cast<int*>(hmax) + lead, __float_as_int(m));
-    } else if (contrib) {
-      atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
+      // positive floats order like their bit patterns, so an integer max works
+      if ((int)(threadIdx.x & 63) == leader)
+        atomicMax(reinterpret_cast<int*>(hmax) + lc, __float_as_int(m));
+      todo &= ~grp;
     }
+    if ((todo >> (threadIdx.x & 63)) & 1)
+      atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
   }
   if (valid && bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
 }

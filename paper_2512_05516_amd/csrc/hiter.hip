@@ -102,17 +102,20 @@ __global__ __launch_bounds__(kThreads) void k_sum_partials(const int32_t* __rest
   if (threadIdx.x == 0) *out = red[0];
 }
 
-// largest h of each cell, from the SoA values
+// largest h of each cell, from the SoA values: one wave per cell, so a
+// crowded cell's slots are read 64 at a time
 __global__ __launch_bounds__(kThreads) void k_cell_hmax(const int32_t* __restrict__ start, int C,
                                                          int n, const void* __restrict__ H,
                                                          int hdt, float lh,
                                                          float* __restrict__ hmax) {
-  const int c = blockIdx.x * kThreads + threadIdx.x;
-  if (c >= C) return;
+  const int c = blockIdx.x * (kThreads / 64) + (int)(threadIdx.x >> 6);
+  if (c >= C) return;                       // whole waves leave together
+  const int lane = threadIdx.x & 63;
   const int a = min(max(start[c], 0), n), b = min(max(start[c + 1], a), n);
   float m = 0.0f;
-  for (int k = a; k < b; ++k) m = fmaxf(m, load_q(H, hdt, k, lh));
-  hmax[c] = m;
+  for (int k = a + lane; k < b; k += 64) m = fmaxf(m, load_q(H, hdt, k, lh));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) hmax[c] = m;
 }
 
 // h of slot k into the H field of record perm[k]
@@ -163,8 +166,8 @@ const int32_t* hiter_left(void* ws, int n) { return carve(ws, n).left; }
 hipError_t launch_cell_hmax(const sph_soa& soa, const Prec& p, const CellsDev& c, float* hmax,
                             hipStream_t s) {
   const int C = c.n_c * c.n_c * c.n_c;
-  k_cell_hmax<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, C, c.n, soa.f[SPH_S_H], p.mhu,
-                                                      p.load_h, hmax);
+  k_cell_hmax<<<cdiv(C, kThreads / 64), kThreads, 0, s>>>(c.start, C, c.n, soa.f[SPH_S_H], p.mhu,
+                                                           p.load_h, hmax);
   return hipGetLastError();
 }
 
