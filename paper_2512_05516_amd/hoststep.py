@@ -36,7 +36,7 @@ class HostStep:
     tiling (sub-cell order is not used: the host cell list has none)."""
 
     def __init__(self, host_t, dtype, n_c, prec=None, til=None, sched=None, prm=None,
-                 nthreads=0, device="cuda", til_force=None):
+                 nthreads=0, device="cuda", til_force=None, split=None):
         import torch
         self.torch = torch
         self.host_t = host_t
@@ -46,7 +46,7 @@ class HostStep:
         self.nthreads = int(nthreads)
         # device side: the same buffers the resident pipeline uses
         self.pipe = Pipeline(self.rec, n_c, prec=prec, device=device, til=til, prm=prm,
-                             sched=sched, til_force=til_force)
+                             sched=sched, til_force=til_force, split=split)
         self.layout = self.pipe.layout
         n, C = self.n, self.n_c ** 3
         pin = dict(pin_memory=True)
