@@ -101,9 +101,14 @@ def force_traffic(choice):
     return int(t["fetch_bytes"]) + int(t["write_bytes"])
 
 
-def cpu_baseline(ps):
+def cpu_baseline(ps, gpu_records=None):
     """FP64 oracle (cells mode, OpenMP) on a bounded sample of the workload:
-    density over all particles and force over every 8th particle."""
+    density over all particles and force over every 8th particle. With
+    gpu_records ({storage: records of one GPU evaluation of the same
+    particles}) the same oracle values give each storage format's error
+    against FP64: max relative error of rho over all particles, relative
+    RMSE (normalised by the mean magnitude) and max normalised error of a
+    and du/dt over the force sample."""
     import oracle
     oracle.lib()
     n = ps.n
@@ -114,16 +119,31 @@ def cpu_baseline(ps):
     f = oracle.force(ps, d, n_c=N_C, sel=sel)
     t2 = time.perf_counter()
     pairs = float(d["nngb"].sum() + f["nforce"].sum())
-    return {"value": pairs / (t2 - t0), "unit": "pair-interactions/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, cell-list mode: density over all {n} particles "
-                      f"({t1 - t0:.2f} s) + force over {len(sel)} (every 8th) "
-                      f"({t2 - t1:.2f} s)"}
+    out = {"value": pairs / (t2 - t0), "unit": "pair-interactions/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"FP64 oracle, cell-list mode: density over all {n} particles "
+                     f"({t1 - t0:.2f} s) + force over {len(sel)} (every 8th) "
+                     f"({t2 - t1:.2f} s)"}
+    if gpu_records:
+        def rel_rmse(g, r):
+            dn = np.linalg.norm(np.atleast_2d((g - r).T).T, axis=1)
+            rn = np.linalg.norm(np.atleast_2d(r.T).T, axis=1)
+            return float(np.sqrt((dn ** 2).mean()) / rn.mean()), float(dn.max() / rn.mean())
+        errs = {}
+        for name, r in gpu_records.items():
+            a_rm, a_mx = rel_rmse(r["a"][sel].astype(np.float64), f["a"])
+            u_rm, u_mx = rel_rmse(r["du"][sel].astype(np.float64)[:, None], f["du"][:, None])
+            errs[name] = {"rho_max_rel": float(np.max(np.abs(r["rho"] / d["rho"] - 1.0))),
+                          "a_rel_rmse": a_rm, "a_max_norm": a_mx,
+                          "du_rel_rmse": u_rm, "du_max_norm": u_mx}
+        out["errors_vs_fp64"] = errs
+    return out
 
 
 SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
 SERVE_SECONDS = 1.0                    # arrivals per rate
 KDK_STEPS = 10         # leapfrog steps of the multi-step run
+PREC16 = lambda sphmi: sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
 PIPE_THREADS = 16      # host worker threads of the streaming arrangement
 H_ROOM = 1.6      # clustered set: cell size / background support radius while h iterates
 H_TOL = 1e-4      # relative h change that ends a particle's iteration
@@ -502,7 +522,18 @@ def main():
 
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(ps)
+        gpu_records = {}
+        for name, prec in (("fp32", sphmi.precision()), ("fp16_store", PREC16(sphmi))):
+            pe = Pipeline(rec, N_C, prec=prec, **kw)
+            pe.bin()
+            pe.convert("full")
+            pe.density()
+            pe.force()
+            pe.writeback("full")
+            gpu_records[name] = pe.records()
+            del pe
+        torch.cuda.empty_cache()
+        result["cpu_baseline"] = cpu_baseline(ps, gpu_records)
     print(json.dumps(result), flush=True)
 
 
