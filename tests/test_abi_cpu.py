@@ -389,3 +389,18 @@ def test_leapfrog_entry_points_host_side(sph):
     assert tot(0.0, C.c_void_p(0xa000), need) == sph.SPH_E_INVALID
     assert tot(0.1, None, need) == sph.SPH_E_INVALID
     assert tot(0.1, C.c_void_p(0xa000), need - 8) == sph.SPH_E_NOMEM
+
+
+def test_worklist_occupancy_host_side(sph):
+    """sph_worklist_occupancy rejects empty or negative occupancy ranges and
+    bad work buffers before any launch."""
+    L = sph.lib()
+    cells = _fake_cells(sph, 16, 4)
+    need = sph.worklist_size(16, 4, 64)
+    work = sph.Work(64, 0, C.c_void_p(0x2000), need)
+    assert L.sph_worklist_occupancy(C.byref(cells), C.byref(work), 5, 5, None) == sph.SPH_E_INVALID
+    assert L.sph_worklist_occupancy(C.byref(cells), C.byref(work), -1, 8, None) == sph.SPH_E_INVALID
+    small = sph.Work(64, 0, C.c_void_p(0x2000), need - 1)
+    assert L.sph_worklist_occupancy(C.byref(cells), C.byref(small), 0, 8, None) == sph.SPH_E_NOMEM
+    bad = sph.Work(64, 7, C.c_void_p(0x2000), need)
+    assert L.sph_worklist_occupancy(C.byref(cells), C.byref(bad), 0, 8, None) == sph.SPH_E_INVALID

@@ -132,3 +132,26 @@ def test_kdk_reduced_storage(sph, orc):
     assert e < 2e-2, e
     e0 = h32[0]["ekin"] + h32[0]["eth"]
     assert abs((h16[-1]["ekin"] + h16[-1]["eth"]) - (h32[-1]["ekin"] + h32[-1]["eth"])) < 1e-3 * e0
+
+
+def test_kdk_wendland(sph, orc):
+    """Leapfrog run with the Wendland C2 kernel against the oracle's run
+    with the same kernel (fixed step)."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    prm_o, prm_g = orc.params(kernel="wendland_c2"), sph.params(kernel="wendland_c2")
+    ps = _moving(20000, 8)
+    n_c = int(np.floor(1.0 / (prm_o.gamma_k * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    ref0 = inputs.unpack_aos(rec)
+    steps = 3
+    pipe = Pipeline(rec, n_c, prm=prm_g, sched="grid", til=sph.tile(32, 2))
+    hist = pipe.kdk_run(steps, dt=1e-3)
+    assert pipe.status() == 0
+    r = pipe.records()
+    fin, ohist = orc.kdk_run(ref0, n_c, steps, dt=1e-3, prm=prm_o)
+    bar = (steps + 1) * 1e-5
+    assert rel_rmse(_pdiff(r["x"], ref0.x), _pdiff(fin.x, ref0.x)) < bar
+    assert rel_rmse(r["v"].astype(np.float64) - ref0.v, fin.v - ref0.v) < bar
+    e_g = hist[-1]["ekin"] + hist[-1]["eth"]
+    e_o = ohist[-1]["ekin"] + ohist[-1]["eth"]
+    assert abs(e_g - e_o) < 1e-6 * e_o
