@@ -322,7 +322,9 @@ sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t vie
  * uneven occupancy in one launch): one item per chunk of at most ti
  * consecutive slots of a cell, in cell order. The cost of an item is
  * estimated as its particle count times the particle count of the 27 cells
- * around its cell; the 8 XCD ranges split the total cost evenly. Items are
+ * around its cell, capped at 27 x 64 (h follows the density, so the
+ * candidates a chunk stages stay bounded next to crowded cells); the 8 XCD
+ * ranges split the total cost evenly. Items are
  * independent (each writes only its own particles), so no result depends on
  * the schedule. work->sched is not used here. */
 sph_status sph_worklist_size(int32_t n, int32_t n_c, int32_t ti, size_t *bytes);

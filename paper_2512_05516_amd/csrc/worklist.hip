@@ -4,8 +4,8 @@
 // contiguous ranges, one per XCD, so neighbouring cells are processed on the
 // same XCD and share its L2. The ranges balance an estimated cost rather
 // than the item count: a chunk of a cell costs about (its particle count) x
-// (the particle count of the 27 cells around it) candidate tests, so a few
-// crowded cells weigh as much as many sparse ones. Each item writes only its
+// (the particle count of the 27 cells around it, capped at 27 x 64)
+// candidate tests, so a few crowded cells weigh as much as many sparse ones. Each item writes only its
 // own particles' outputs, so no result depends on the split or the schedule.
 //
 // Buffer layout: [0, kWorkHeader) queue counters[8] and meta (item count,
@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kCostShift = 12;   // cost unit: 4096 candidate tests
+constexpr int kNbCap = 27 * 64;  // neighbour-count cap of the cost estimate
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -87,7 +88,10 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
       }
     }
   }
-  const int64_t raw = (int64_t)cnt * nb;
+  // a chunk stages about the particles within a support radius of it; with
+  // h following the density that is a bounded number even next to crowded
+  // cells, so the neighbour count is capped at that of a 64-per-cell lattice
+  const int64_t raw = (int64_t)cnt * min(nb, (int64_t)kNbCap);
   const int64_t units = (raw + (1 << kCostShift) - 1) >> kCostShift;
   cost[c] = (int32_t)min(units, (int64_t)cost_cap);
 }

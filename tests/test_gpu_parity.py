@@ -210,9 +210,9 @@ def test_host_convert_matches_device(sph, kind):
 def _worklist_reference(start, n, n_c, ti):
     """Items and XCD range boundaries of the work list, rebuilt on the host
     from the cell table: items (cell, first slot) in cell order; the cost of
-    a cell is ceil(count * (count of its 27 cells) / 4096), clamped so the
-    sum fits in int32; range q starts at the first item of the first cell
-    whose cost prefix reaches ceil(q * total / 8)."""
+    a cell is ceil(count * min(count of its 27 cells, 27 * 64) / 4096),
+    clamped so the sum fits in int32; range q starts at the first item of the
+    first cell whose cost prefix reaches ceil(q * total / 8)."""
     C = n_c ** 3
     counts = np.diff(start).astype(np.int64)
     items = [(c, f) for c in range(C) for f in range(start[c], start[c + 1], ti)]
@@ -220,7 +220,7 @@ def _worklist_reference(start, n, n_c, ti):
     nb = sum(np.roll(grid, (dz, dy, dx), axis=(0, 1, 2))
              for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)).reshape(-1)
     cap = (2 ** 31 - 1) // (C + 1)
-    cost = np.minimum((counts * nb + 4095) >> 12, cap)
+    cost = np.minimum((counts * np.minimum(nb, 27 * 64) + 4095) >> 12, cap)
     prefix = np.concatenate([[0], np.cumsum(cost)])
     pos = np.concatenate([[0], np.cumsum((counts + ti - 1) // ti)])
     total = len(items)
