@@ -511,6 +511,20 @@ def main():
     if not args.no_clustered:
         result["clustered"] = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)
 
+    # practical HBM ceiling: a plain 1 GiB device-to-device copy (read + write)
+    cp_a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    cp_b = torch.empty_like(cp_a)
+    cp_b.copy_(cp_a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        cp_b.copy_(cp_a)
+    e1.record()
+    torch.cuda.synchronize()
+    result["hbm_copy_gbs"] = round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del cp_a, cp_b
+    torch.cuda.empty_cache()
+
     if args.copy_probe_mib:
         log("device copy probe")
         nb = args.copy_probe_mib << 20
