@@ -277,7 +277,7 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
     n_c0 = int(np.floor(1.0 / (H_ROOM * gk * ps.h.max())))
     del ps
     log(f"clustered: smoothing-length iteration (n_c = {n_c0})")
-    p0 = Pipeline(rec, n_c0, sched="grid", til=sphmi.tile(16, 4))
+    p0 = Pipeline(rec, n_c0, sched="grid", til=sphmi.tile(32, 2), sub_bits=2)
     p0.bin()
     p0.convert("full")
     torch.cuda.synchronize()

@@ -696,9 +696,10 @@ def _h_max(sph, n_c):
     return float(h)
 
 
-@pytest.mark.parametrize("which,sched", [("lattice", None), ("clustered", None),
-                                         ("clustered", "grid")])
-def test_smoothing_length_matches_oracle(sph, orc, which, sched):
+@pytest.mark.parametrize("which,sched,sub_bits", [("lattice", None, 0), ("clustered", None, 0),
+                                                  ("clustered", "grid", 0),
+                                                  ("clustered", "grid", 2)])
+def test_smoothing_length_matches_oracle(sph, orc, which, sched, sub_bits):
     import torch
     from paper_2512_05516_amd.pipeline import Pipeline
     if which == "lattice":
@@ -710,7 +711,7 @@ def test_smoothing_length_matches_oracle(sph, orc, which, sched):
     rec = inputs.pack_aos(ps, "f32")
     ref = inputs.unpack_aos(rec)
     tol = 1e-5
-    pipe = Pipeline(rec, n_c, sched=sched)
+    pipe = Pipeline(rec, n_c, sched=sched, sub_bits=sub_bits)
     pipe.bin()
     pipe.convert("full")
     it, left = pipe.smoothing_length(tol=tol, max_iter=40)
