@@ -11,6 +11,7 @@ constexpr int kRounds = 8;
 constexpr int kTile = kThreads * kRounds;     // keys per radix block
 constexpr int kScanPer = 16;                  // elements per thread in scans
 constexpr int kScanTile = kThreads * kScanPer;
+constexpr int kMaxBuckets = 512;             // radix buckets of the widest digit (9 bits)
 
 // Morton code of a sub-cell (bit b of sx at 3b, sy at 3b+1, sz at 3b+2)
 __device__ __forceinline__ int morton3(int sx, int sy, int sz, int bits) {
@@ -106,44 +107,45 @@ __global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, in
   if (i < n) p[i] = v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_key_to_cell(const int32_t* __restrict__ keys, int n,
-                                                           int sub_bits,
-                                                           int32_t* __restrict__ cell) {
-  int i = blockIdx.x * kThreads + threadIdx.x;
-  if (i < n) cell[i] = keys[i] >> (3 * sub_bits);
-}
-
+// Per-block digit counts of one pass (D-bit digits, 2^D buckets), stored
+// digit-major so that one exclusive scan gives every block's base offsets.
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restrict__ kin,
                                                           int32_t* __restrict__ hist, int n,
                                                           int nblk, int shift) {
-  __shared__ int h[256];
-  int tid = threadIdx.x;
-  h[tid] = 0;
+  constexpr int NB = 1 << D;
+  __shared__ int h[NB];
+  const int tid = threadIdx.x;
+  for (int d = tid; d < NB; d += kThreads) h[d] = 0;
   __syncthreads();
-  int b = blockIdx.x;
+  const int b = blockIdx.x;
   for (int r = 0; r < kRounds; ++r) {
     int idx = b * kTile + r * kThreads + tid;
-    if (idx < n) atomicAdd(&h[(kin[idx] >> shift) & 255], 1);
+    if (idx < n) atomicAdd(&h[(kin[idx] >> shift) & (NB - 1)], 1);
   }
   __syncthreads();
-  hist[tid * nblk + b] = h[tid];
+  for (int d = tid; d < NB; d += kThreads) hist[d * nblk + b] = h[d];
 }
 
 // Stable scatter: in round r the block ranks keys b*kTile + r*256 + tid in
-// index order. Lanes with equal digits are found with 8 ballots; earlier
+// index order. Lanes with equal digits are found with D ballots; earlier
 // waves and earlier rounds are counted in LDS.
+template <int D>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
     int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift) {
-  __shared__ int wcnt[kThreads / 64][256];
-  __shared__ int run[256];
-  __shared__ int base[256];
+  constexpr int NB = 1 << D;
+  __shared__ int wcnt[kThreads / 64][NB];
+  __shared__ int run[NB];
+  __shared__ int base[NB];
   const int tid = threadIdx.x, wave = tid >> 6;
   const int b = blockIdx.x;
-  base[tid] = offsets[tid * nblk + b];
-  run[tid] = 0;
+  for (int d = tid; d < NB; d += kThreads) {
+    base[d] = offsets[d * nblk + b];
+    run[d] = 0;
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) wcnt[w][tid] = 0;
+    for (int w = 0; w < kThreads / 64; ++w) wcnt[w][d] = 0;
+  }
   __syncthreads();
   for (int r = 0; r < kRounds; ++r) {
     int idx = b * kTile + r * kThreads + tid;
@@ -151,10 +153,10 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     bool valid = idx < n;
     int key = valid ? kin[idx] : 0;
     int val = valid ? vin[idx] : 0;
-    int d = (key >> shift) & 255;
+    int d = (key >> shift) & (NB - 1);
     uint64_t m = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < D; ++bit) {
       uint64_t bl = __ballot((d >> bit) & 1);
       m &= ((d >> bit) & 1) ? bl : ~bl;
     }
@@ -169,13 +171,15 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
       vout[pos] = val;
     }
     __syncthreads();
-    int tot = 0;
+    for (int dd = tid; dd < NB; dd += kThreads) {
+      int tot = 0;
 #pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-      tot += wcnt[w][tid];
-      wcnt[w][tid] = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        tot += wcnt[w][dd];
+        wcnt[w][dd] = 0;
+      }
+      run[dd] += tot;
     }
-    run[tid] += tot;
     __syncthreads();
   }
 }
@@ -242,13 +246,29 @@ __global__ __launch_bounds__(kThreads) void k_scan_add(int32_t* __restrict__ dat
     if (base + e < len) data[base + e] += add;
 }
 
-__global__ __launch_bounds__(kThreads) void k_cell_start(const int32_t* __restrict__ skeys, int n,
-                                                          int C, int32_t* __restrict__ start) {
-  int k = blockIdx.x * kThreads + threadIdx.x;
-  if (k > n) return;
-  int cur = k < n ? skeys[k] : C;
-  int prev = k > 0 ? skeys[k - 1] : -1;
+// CSR starts of the sorted keys: start[c] = first slot whose key is >= c,
+// for c = 0 .. C (start[C] = n). Slot k writes the starts of the keys
+// between its predecessor's key and its own.
+__device__ __forceinline__ void fill_starts(int prev, int cur, int k, int32_t* __restrict__ start) {
   for (int c = prev + 1; c <= cur; ++c) start[c] = k;
+}
+
+// Cell ids of the sorted slots (key >> 3 sub_bits) and the CSR tables of
+// cells and, with sub_bits > 0, of sub-cells, in one pass over the keys.
+__global__ __launch_bounds__(kThreads) void k_cell_tables(const int32_t* __restrict__ skeys,
+                                                           int n, int sub_bits, int C,
+                                                           int32_t* __restrict__ cell,
+                                                           int32_t* __restrict__ cell_start,
+                                                           int32_t* __restrict__ sub_start) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k > n) return;
+  const int sh = 3 * sub_bits;
+  const int key = k < n ? skeys[k] : (C << sh);
+  const int pkey = k > 0 ? skeys[k - 1] : -1;
+  const int cur = key >> sh, prev = k > 0 ? (pkey >> sh) : -1;
+  if (k < n && sub_bits) cell[k] = cur;
+  fill_starts(prev, cur, k, cell_start);
+  if (sub_bits) fill_starts(pkey, key, k, sub_start);
 }
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -266,7 +286,7 @@ BinWs carve(void* ws, int n, int nblk) {
   w.va = reinterpret_cast<int32_t*>(p); p += nb;
   w.kb = reinterpret_cast<int32_t*>(p); p += nb;
   w.vb = reinterpret_cast<int32_t*>(p); p += nb;
-  size_t hl = (size_t)256 * (size_t)(nblk > 0 ? nblk : 1);
+  size_t hl = (size_t)kMaxBuckets * (size_t)(nblk > 0 ? nblk : 1);
   w.hist = reinterpret_cast<int32_t*>(p); p += al(sizeof(int32_t) * hl);
   w.partials = reinterpret_cast<int32_t*>(p);
   return w;
@@ -294,7 +314,7 @@ size_t bin_workspace_bytes(int n, int n_c, int sub_bits) {
   (void)sub_bits;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   int nblk = cdiv(n, kTile);
-  size_t hl = (size_t)256 * (size_t)(nblk > 0 ? nblk : 1);
+  size_t hl = (size_t)kMaxBuckets * (size_t)(nblk > 0 ? nblk : 1);
   return 4 * al(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) + al(sizeof(int32_t) * hl) +
          al(sizeof(int32_t) * ((size_t)cdiv((int64_t)hl, kScanTile) + 1));
 }
@@ -322,7 +342,10 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
         w.va, want_h ? hmax : nullptr, c.status);
     int bits = 1;
     while ((1 << bits) < S) ++bits;
-    int passes = (bits + 7) / 8;
+    // 9-bit digits where they need fewer passes than 8-bit ones (keys of
+    // 9, 17-18, 25-27 bits), else 8-bit digits
+    const int passes = (bits + 8) / 9 < (bits + 7) / 8 ? (bits + 8) / 9 : (bits + 7) / 8;
+    const int D = passes * 8 >= bits ? 8 : 9;
     int32_t *ks = w.ka, *vs = w.va;
     for (int p = 0; p < passes; ++p) {
       int32_t *kd, *vd;
@@ -333,18 +356,25 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
         kd = (ks == w.ka) ? w.kb : w.ka;
         vd = (vs == w.va) ? w.vb : w.va;
       }
-      k_radix_hist<<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p);
-      hipError_t e = scan_local(w.hist, 256 * nblk, w.partials, s);
+      if (D == 8) {
+        k_radix_hist<8><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p);
+      } else {
+        k_radix_hist<9><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 9 * p);
+      }
+      hipError_t e = scan_local(w.hist, (1 << D) * nblk, w.partials, s);
       if (e != hipSuccess) return e;
-      k_radix_scatter<<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p);
+      if (D == 8) {
+        k_radix_scatter<8><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p);
+      } else {
+        k_radix_scatter<9><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 9 * p);
+      }
       ks = kd;
       vs = vd;
     }
     skeys = ks;
-    if (sb) k_key_to_cell<<<cdiv(n, kThreads), kThreads, 0, s>>>(skeys, n, sb, cell);
   }
-  k_cell_start<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(cell, n, C, cell_start);
-  if (sb) k_cell_start<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(skeys, n, S, sub_start);
+  k_cell_tables<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(skeys, n, sb, C, cell, cell_start,
+                                                           sub_start);
   return hipGetLastError();
 }
 

@@ -494,6 +494,7 @@ __device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int r
 constexpr int kUnroll = 8;
 constexpr int kRounds = 4;      // gather rounds whose loads are issued together
 constexpr int kFillRounds = 4;  // force-only fields: rounds issued together
+constexpr float kFlatRatio = 1.02f;   // force: neighbour support bound^2 / chunk's largest H^2
 
 // Chunk bounding box of the valid particles and the largest H^2
 struct ChunkBox {
@@ -928,6 +929,17 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     const float pp = norm2(xi, yi, zi);
     const float cpre = vi ? H2i - pp + mrg : -__builtin_inff();
     const float ppm = vi ? pp - mrg : __builtin_inff();
+    // Where no neighbour cell's support bound exceeds the chunk's largest
+    // support by much, one threshold per lane replaces the per-candidate
+    // max: t < max(H_i^2, Hn^2) - |p|^2 + M, with Hn bounding every H_j of
+    // the 27 cells, accepts a superset of the pairs at a few extra entries,
+    // and the consume phase applies the exact test to each of them.
+    float hn = 0.0f;
+    for (int q = 0; q < 27; ++q)
+      if (only_q == -1 || q == only_q) hn = fmaxf(hn, T.hb[q]);
+    const float hn2 = hn * hn;
+    const bool flat = hn2 <= kFlatRatio * bx.h2max;   // uniform over the block
+    const float cflat = vi ? fmaxf(H2i, hn2) - pp + mrg : -__builtin_inff();
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
     int nf = 0;
@@ -974,12 +986,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
         cid[nj + tid] = -1;
       }
       __syncthreads();
-      test_and_consume<NT, K, LCAP>(
-          cp, lst, njp, kk,
-          [&](const float4& q0, int idx) {
-            return prefilter_t(m2x, m2y, m2z, q0) < fmaxf(cpre, ch2[idx] - ppm);
-          },
-          [&](int lo) {
+      auto consume = [&](int lo) {
             for (int e = tid; e < lo; e += NT) {
               const int t = lst[e];
               const float4 q0 = cp[t];
@@ -1010,7 +1017,19 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
               vsig = fmaxf(vsig, vs);
               ++nf;
             }
-          });
+          };
+      if (flat)
+        test_and_consume<NT, K, LCAP>(
+            cp, lst, njp, kk,
+            [&](const float4& q0, int) { return prefilter_t(m2x, m2y, m2z, q0) < cflat; },
+            consume);
+      else
+        test_and_consume<NT, K, LCAP>(
+            cp, lst, njp, kk,
+            [&](const float4& q0, int idx) {
+              return prefilter_t(m2x, m2y, m2z, q0) < fmaxf(cpre, ch2[idx] - ppm);
+            },
+            consume);
       __syncthreads();
     };
 

@@ -74,8 +74,9 @@ def _bin_gpu(sph, x, n_c, sub_bits=0, h=None):
     return out
 
 
+# cell ids of 5 to 19 bits: one, two and three radix passes, 8- and 9-bit digits
 @pytest.mark.parametrize("n,n_c", [(0, 3), (1, 3), (4096, 4), (20000, 7), (100003, 23),
-                                    (300000, 70)])
+                                    (150001, 50), (300000, 70)])
 def test_bin_bit_exact(sph, orc, n, n_c):
     rng = np.random.default_rng(n + n_c)
     x = rng.uniform(-0.5, 1.5, size=(n, 3))
@@ -91,8 +92,9 @@ def test_bin_bit_exact(sph, orc, n, n_c):
     assert np.array_equal(cell, ocell[operm])
 
 
+# keys of 8 to 25 bits, including 9-bit digits in one, two and three passes
 @pytest.mark.parametrize("n,n_c,bits", [(4096, 4, 1), (30011, 7, 2), (200000, 23, 3),
-                                         (1, 3, 2), (0, 3, 1)])
+                                         (200000, 32, 1), (300000, 70, 2), (1, 3, 2), (0, 3, 1)])
 def test_bin_sub_cells_bit_exact(sph, orc, n, n_c, bits):
     rng = np.random.default_rng(n + 7 * bits)
     x = rng.uniform(-0.5, 1.5, size=(n, 3))
