@@ -25,7 +25,8 @@ __device__ __forceinline__ int morton3(int sx, int sy, int sz, int bits) {
 // Largest record span staged through LDS by k_bin_keys (8-byte words)
 constexpr int kSpanWords = 16;
 
-// key = cell * R^3 + Morton(sub-cell); also the per-cell max of h.
+// key = cell * R^3 + Morton(sub-cell); also h of each record for the
+// per-cell maximum.
 // nw > 0: the block first copies bytes [lo, lo + 8 nw) of each of its
 // records into LDS with consecutive threads on consecutive words (x and h
 // read from there), so every record line is fetched once and the loads
@@ -36,12 +37,12 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
                                                         int nw, int n, int n_c, int sub_bits,
                                                         int32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
-                                                        float* __restrict__ hmax,
+                                                        float* __restrict__ hin,
                                                         int32_t* status) {
   __shared__ uint2 span[kThreads * kSpanWords];
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + threadIdx.x;
-  const bool valid = i < n;   // no early exit: the whole wave takes part in the h reduction
+  const bool valid = i < n;   // no early exit: the whole block stages the records
   const char* rec;            // record bytes as seen at offsets offx, offh
   uint32_t rx = offx, rh = offh;
   if (nw > 0) {
@@ -76,28 +77,11 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
     keys[i] = (cell << (3 * sub_bits)) + morton3(sc[0], sc[1], sc[2], sub_bits);
     vals[i] = i;
   }
-  if (hmax && offh != kAbsent) {
-    const float h = valid ? rec_load32(rec, rh, dth) : 0.0f;
-    const bool contrib = valid && h > 0.0f;
-    // one atomic per distinct cell of the wave for its first eight cells:
-    // the lanes of the first remaining lane's cell take their maximum
-    // together, then drop out (per-lane atomics on the words of crowded
-    // cells serialise); lanes of further cells use their own atomics
-    uint64_t todo = __ballot(contrib);
-    for (int round = 0; round < 8 && todo; ++round) {
-      const int leader = __ffsll((long long)todo) - 1;
-      const int lc = __shfl(cell, leader);
-      const bool mine = contrib && cell == lc;
-      const uint64_t grp = __ballot(mine);
-      float m = mine ? h : 0.0f;
-      for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-      // positive floats order like their bit patterns, so an integer max works
-      if ((int)(threadIdx.x & 63) == leader)
-        atomicMax(reinterpret_cast<int*>(hmax) + lc, __float_as_int(m));
-      todo &= ~grp;
-    }
-    if ((todo >> (threadIdx.x & 63)) & 1)
-      atomicMax(reinterpret_cast<int*>(hmax) + cell, __float_as_int(h));
+  // h of each input slot (0 where not positive): the per-cell maximum is
+  // taken after the sort, without atomics on the words of crowded cells
+  if (hin && valid) {
+    const float h = rec_load32(rec, rh, dth);
+    hin[i] = h > 0.0f ? h : 0.0f;
   }
   if (valid && bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
 }
@@ -271,10 +255,27 @@ __global__ __launch_bounds__(kThreads) void k_cell_tables(const int32_t* __restr
   if (sub_bits) fill_starts(pkey, key, k, sub_start);
 }
 
+// Largest h of each cell over its sorted slots: one wave per cell, the
+// lanes striding over the cell's slots (h read through perm), then a wave
+// maximum; empty cells get 0.
+__global__ __launch_bounds__(kThreads) void k_cell_hmax_sorted(const int32_t* __restrict__ start,
+                                                                const int32_t* __restrict__ perm,
+                                                                const float* __restrict__ hin,
+                                                                int C, float* __restrict__ hmax) {
+  const int c = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+  if (c >= C) return;                          // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  float m = 0.0f;
+  for (int k = start[c] + lane; k < start[c + 1]; k += 64) m = fmaxf(m, hin[perm[k]]);
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) hmax[c] = m;
+}
+
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 struct BinWs {
   int32_t *ka, *va, *kb, *vb, *hist, *partials;
+  float* hin;   // h per input slot
 };
 
 BinWs carve(void* ws, int n, int nblk) {
@@ -288,6 +289,7 @@ BinWs carve(void* ws, int n, int nblk) {
   w.vb = reinterpret_cast<int32_t*>(p); p += nb;
   size_t hl = (size_t)kMaxBuckets * (size_t)(nblk > 0 ? nblk : 1);
   w.hist = reinterpret_cast<int32_t*>(p); p += al(sizeof(int32_t) * hl);
+  w.hin = reinterpret_cast<float*>(p); p += nb;
   w.partials = reinterpret_cast<int32_t*>(p);
   return w;
 }
@@ -315,7 +317,7 @@ size_t bin_workspace_bytes(int n, int n_c, int sub_bits) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   int nblk = cdiv(n, kTile);
   size_t hl = (size_t)kMaxBuckets * (size_t)(nblk > 0 ? nblk : 1);
-  return 4 * al(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) + al(sizeof(int32_t) * hl) +
+  return 5 * al(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)) + al(sizeof(int32_t) * hl) +
          al(sizeof(int32_t) * ((size_t)cdiv((int64_t)hl, kScanTile) + 1));
 }
 
@@ -327,7 +329,6 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
   const int S = C << (3 * sb);
   const int nblk = cdiv(n, kTile);
   BinWs w = carve(ws, n, nblk);
-  if (hmax) k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
   int32_t* skeys = cell;                 // sorted keys (cell ids when sb == 0)
   if (n > 0) {
     // span of the record bytes the keys need: x, and h when hmax is wanted
@@ -339,7 +340,7 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
     const int nw = (hi - lo) / 8 <= (uint32_t)kSpanWords ? (int)((hi - lo) / 8) : 0;
     k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(
         static_cast<const char*>(aos), L.stride, ox, oh, L.dt[SPH_A_H], lo, nw, n, n_c, sb, w.ka,
-        w.va, want_h ? hmax : nullptr, c.status);
+        w.va, want_h ? w.hin : nullptr, c.status);
     int bits = 1;
     while ((1 << bits) < S) ++bits;
     // 9-bit digits where they need fewer passes than 8-bit ones (keys of
@@ -375,6 +376,14 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
   }
   k_cell_tables<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(skeys, n, sb, C, cell, cell_start,
                                                            sub_start);
+  if (hmax) {
+    if (n > 0 && L.off[SPH_A_H] != kAbsent) {
+      k_cell_hmax_sorted<<<cdiv(C, kThreads / 64), kThreads, 0, s>>>(cell_start, perm, w.hin, C,
+                                                                      hmax);
+    } else {
+      k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
+    }
+  }
   return hipGetLastError();
 }
 

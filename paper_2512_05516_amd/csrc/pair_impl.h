@@ -253,11 +253,13 @@ struct NbrCells {
   int cell[27];
   float sh[27][3];
   float hb[27];
+  float hbmax;   // largest hb over the 27 cells
 };
 
 __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int cx, int cy,
                                           int cz, float s32, float gk) {
   const int tid = threadIdx.x;
+  float hbv = 0.0f;
   if (tid < 27) {
     int cn;
     float shx, shy, shz;
@@ -266,7 +268,13 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
     T.sh[tid][0] = shx;
     T.sh[tid][1] = shy;
     T.sh[tid][2] = shz;
-    T.hb[tid] = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
+    hbv = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
+    T.hb[tid] = hbv;
+  }
+  if (tid < 64) {   // first wave: the largest bound
+    float m = hbv;
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (tid == 0) T.hbmax = m;
   }
   __syncthreads();
 }
@@ -934,9 +942,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
     // max: t < max(H_i^2, Hn^2) - |p|^2 + M, with Hn bounding every H_j of
     // the 27 cells, accepts a superset of the pairs at a few extra entries,
     // and the consume phase applies the exact test to each of them.
-    float hn = 0.0f;
-    for (int q = 0; q < 27; ++q)
-      if (only_q == -1 || q == only_q) hn = fmaxf(hn, T.hb[q]);
+    const float hn = only_q == -1 ? T.hbmax : T.hb[only_q];
     const float hn2 = hn * hn;
     const bool flat = hn2 <= kFlatRatio * bx.h2max;   // uniform over the block
     const float cflat = vi ? fmaxf(H2i, hn2) - pp + mrg : -__builtin_inff();
