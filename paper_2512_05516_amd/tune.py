@@ -14,6 +14,11 @@ storage formats, device). On cells of very uneven occupancy it then tries
 splitting each loop into two launches by an occupancy threshold T: the
 cells with fewer than T particles with a tile of their own, the others with
 the loop's tile, and keeps a split that is faster than the single launch.
+Before that, the fastest few candidates of each loop (timed back to back on
+their own) are timed again where the loop runs in a step, right after the
+kernel that precedes it (bin, convert, density, force), and the fastest
+there is kept: a schedule that partitions a resident grid statically can
+lose several per cent in that position while leading in isolation.
 The choice changes only timings: every candidate computes the same
 interactions.
 """
@@ -130,9 +135,64 @@ def tune_split(pipe, single: dict, reps: int = 3, log=None) -> dict:
     return out
 
 
+REFINE_TOP = 3
+
+
+def _in_step_ms(rec, n_c, prec, prm, sb, d, f, reps):
+    """Mean density and force times (ms) inside the sequence bin, convert,
+    density, force, for the tiles d and f = (ti, k, sched)."""
+    import torch
+    pipe = Pipeline(rec, n_c, prec=prec, prm=prm, sub_bits=sb, til=sphmi.tile(d[0], d[1]),
+                    til_force=sphmi.tile(f[0], f[1]), sched=(d[2], f[2]))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(reps + 1)]
+    for r in range(reps + 1):               # the first pass is a warmup
+        pipe.bin()
+        pipe.convert("full")
+        ev[r][0].record()
+        pipe.density()
+        ev[r][1].record()
+        pipe.force()
+        ev[r][2].record()
+    torch.cuda.synchronize()
+    dm = sum(ev[r][0].elapsed_time(ev[r][1]) for r in range(1, reps + 1)) / reps
+    fm = sum(ev[r][1].elapsed_time(ev[r][2]) for r in range(1, reps + 1)) / reps
+    del pipe
+    return dm, fm
+
+
+def refine_in_step(rec, n_c, prec, prm, sb, table, choice, reps=4, log=None):
+    """Re-times the REFINE_TOP fastest isolated candidates of each loop (at
+    sub-cell depth sb) in their place in a step and returns {loop: (ti, k,
+    sched, ms)} of the fastest there."""
+    import torch
+    out = {}
+    for loop in ("density", "force"):
+        rows = sorted((r for r in table if r["sub_bits"] == sb and r["loop"] == loop),
+                      key=lambda r: r["ms"])
+        cands = []
+        for r in rows:
+            c = (r["ti"], r["k"], r["sched"])
+            if c not in cands:
+                cands.append(c)
+            if len(cands) == REFINE_TOP:
+                break
+        best = None
+        for c in cands:
+            d = c if loop == "density" else choice["density"]
+            f = c if loop == "force" else choice["force"]
+            ms = _in_step_ms(rec, n_c, prec, prm, sb, d, f, reps)[0 if loop == "density" else 1]
+            if log:
+                log(f"tune in step {loop}: {c[0]}x{c[1]} {c[2] or 'per-cell'} {ms:.3f} ms")
+            if best is None or ms < best[3]:
+                best = (c[0], c[1], c[2], ms)
+        out[loop] = best
+        torch.cuda.empty_cache()
+    return out
+
+
 def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), cand=None,
          reps: int = 3, cache_path=DEFAULT_CACHE, refresh: bool = False, log=None,
-         split: bool = True) -> dict:
+         split: bool = True, refine: bool = True) -> dict:
     """Choose sub_bits and each loop's (tile, schedule) for the AoS records
     `rec` binned with n_c cells per axis. Returns {"sub_bits", "density":
     {ti, k, sched, ms}, "force": {...}, "table": [...], "signature", "cached"}."""
@@ -144,6 +204,7 @@ def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), can
     sig["reps"] = reps
     sig["candidates"] = cand if cand is None else [list(c) for c in cand]
     sig["split"] = bool(split)
+    sig["refine"] = bool(refine)
     cache = _load(cache_path) if cache_path else {}
     if not refresh and _key(sig) in cache:
         out = dict(cache[_key(sig)])
@@ -175,6 +236,15 @@ def tune(rec: np.ndarray, n_c: int, prec=None, prm=None, sub_bits=(0, 1, 2), can
     del first, wbuf
     torch.cuda.empty_cache()
     _, sb, d, f = best
+    if refine:
+        rf = refine_in_step(rec, n_c, prec, prm, sb, table,
+                            {"density": (d[0], d[1], d[2]), "force": (f[0], f[1], f[2])},
+                            log=log)
+        # the isolated times of the kept candidates (the split search compares
+        # against isolated launches)
+        iso = {(r["loop"], r["ti"], r["k"], r["sched"]): r["ms"] for r in table if r["sub_bits"] == sb}
+        d = rf["density"][:3] + (iso[("density",) + rf["density"][:3]],)
+        f = rf["force"][:3] + (iso[("force",) + rf["force"][:3]],)
     out = {"sub_bits": sb,
            "density": {"ti": d[0], "k": d[1], "sched": d[2], "ms": d[3]},
            "force": {"ti": f[0], "k": f[1], "sched": f[2], "ms": f[3]},
