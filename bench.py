@@ -90,15 +90,19 @@ def timed_steps(torch, pipe, kind, steps, warmup):
 
 def force_traffic(choice):
     """HBM bytes per k_force launch (FETCH_SIZE + WRITE_SIZE, calibrated) from
-    the committed counter profile, if it was taken with the tiling chosen
-    now and the kernel's sources have not changed since; else None."""
+    the committed counter profile and the tiling they were taken with, if
+    they were taken on the kernel instance chosen now (same sub-cell depth
+    and tile; the schedule only changes the order in which workgroups take
+    the chunks) and the kernel's sources have not changed since; else
+    (None, None)."""
     from paper_2512_05516_amd import prof_summary
     t = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "step_lattice128_f32.txt"))
     f = choice["force"]
-    tiling = f"sub_bits{choice['sub_bits']}/force{f['ti']}x{f['k']}{f['sched'] or 'percell'}"
-    if not t or t.get("tiling") != tiling or t.get("source_sha256") != prof_summary.source_hash():
-        return None
-    return int(t["fetch_bytes"]) + int(t["write_bytes"])
+    inst = f"sub_bits{choice['sub_bits']}/force{f['ti']}x{f['k']}"
+    if (not t or not t.get("tiling", "").startswith(inst)
+            or t.get("source_sha256") != prof_summary.source_hash()):
+        return None, None
+    return int(t["fetch_bytes"]) + int(t["write_bytes"]), t["tiling"]
 
 
 def cpu_baseline(ps, gpu_records=None):
@@ -397,10 +401,13 @@ def main():
 
     force_s = per["force"] * 1e-3
     achieved = FLOP_FORCE_PAIR * pairs_f / force_s / 1e12
+    traffic, traffic_tiling = force_traffic(choice)
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": force_traffic(choice), "kernel": "k_force (FP32 SoA)",
+                "traffic": traffic, "kernel": "k_force (FP32 SoA)",
                 "flop_per_unit": FLOP_FORCE_PAIR, "units_per_launch": pairs_f}
+    if traffic is not None:
+        roofline["traffic_tiling"] = traffic_tiling
     dens_tf = FLOP_DENSITY_PAIR * pairs_d / (per["density"] * 1e-3) / 1e12
     gbs = lambda b, ms: b * n / (ms * 1e-3) / 1e9
     hbm = {"convert_full": round(gbs(BYTES_CONVERT_FULL, per["convert"]), 1),
