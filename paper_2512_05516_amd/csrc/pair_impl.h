@@ -620,8 +620,8 @@ struct LoopItems {
 
   template <class Chunk>
   __device__ __forceinline__ void run(const CellsDev& cd, int TI, Chunk chunk) const {
-  if (!wk.items) {
-    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  if (!wk.items) {   // one workgroup per cell, cells in brick order
+    const int cell = brick_cell(xcd_remap(blockIdx.x, gridDim.x), cd.n_c);
     const int cs = clamp_slot(cd.start[cell], cd.n);
     const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
     for (int base = cs; base < ce; base += TI)

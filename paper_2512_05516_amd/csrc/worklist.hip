@@ -1,17 +1,18 @@
 // Work list of the pair kernels for one launch over all cells of uneven
 // occupancy (Alg. 1 CallQuadratic): one item per chunk of at most ti
-// consecutive slots of a cell, in cell order. The items are split into 8
-// contiguous ranges, one per XCD, so neighbouring cells are processed on the
-// same XCD and share its L2. The ranges balance an estimated cost rather
-// than the item count: a chunk of a cell costs about (its particle count) x
-// (the particle count of the 27 cells around it, capped at 27 x 64)
-// candidate tests, so a few crowded cells weigh as much as many sparse ones. Each item writes only its
-// own particles' outputs, so no result depends on the split or the schedule.
+// consecutive slots of a cell, the cells in brick order (brick_cell). The
+// items are split into 8 contiguous ranges, one per XCD, so neighbouring
+// cells are processed on the same XCD and share its L2. The ranges balance
+// an estimated cost rather than the item count: a chunk of a cell costs
+// about (its particle count) x (the particle count of the 27 cells around
+// it, capped at 27 x 64) candidate tests, so a few crowded cells weigh as
+// much as many sparse ones. Each item writes only its own particles'
+// outputs, so no result depends on the split, the order or the schedule.
 //
 // Buffer layout: [0, kWorkHeader) queue counters[8] and meta (item count,
-// range boundaries[9]); then per-cell item offsets [C + 1], per-cell cost
-// prefix [C + 1], one set of scan partials, and the items (int2: cell, first
-// slot).
+// range boundaries[9]); then the item offsets [C + 1] and the cost prefix
+// [C + 1] of the cells in brick order, one set of scan partials, and the
+// items (int2: cell, first slot).
 #include "sph_device.h"
 
 namespace sph {
@@ -24,8 +25,8 @@ constexpr int kNbCap = 27 * 64;  // neighbour-count cap of the cost estimate
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 struct WlLayout {
-  int32_t* pos;       // [C + 1] first item of each cell
-  int32_t* cost;      // [C + 1] exclusive prefix of the cell costs
+  int32_t* pos;       // [C + 1] first item of each cell (brick order)
+  int32_t* cost;      // [C + 1] exclusive prefix of the cell costs (brick order)
   int32_t* partials;
   int2* items;
 };
@@ -59,13 +60,14 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
                                                         int32_t* __restrict__ pos,
                                                         int32_t* __restrict__ cost) {
   const int C = n_c * n_c * n_c;
-  const int c = blockIdx.x * kThreads + threadIdx.x;
-  if (c > C) return;
-  if (c == C) {
+  const int j = blockIdx.x * kThreads + threadIdx.x;   // position in brick order
+  if (j > C) return;
+  if (j == C) {
     pos[C] = 0;
     cost[C] = 0;
     return;
   }
+  const int c = brick_cell(j, n_c);
   int cnt = cell_count(start, c, n);
   if (cnt < occ_lo || cnt >= occ_hi) cnt = 0;   // only cells of this occupancy class
   if (active && cnt > 0) {   // only cells that hold an active slot
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
     for (int k = a; k < a + cnt && !any; ++k) any = active[k] != 0;
     if (!any) cnt = 0;
   }
-  pos[c] = (cnt + ti - 1) / ti;
+  pos[j] = (cnt + ti - 1) / ti;
   int cx, cy, cz;
   cell_coords(c, n_c, cx, cy, cz);
   int64_t nb = 0;
@@ -93,23 +95,25 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
   // cells, so the neighbour count is capped at that of a 64-per-cell lattice
   const int64_t raw = (int64_t)cnt * min(nb, (int64_t)kNbCap);
   const int64_t units = (raw + (1 << kCostShift) - 1) >> kCostShift;
-  cost[c] = (int32_t)min(units, (int64_t)cost_cap);
+  cost[j] = (int32_t)min(units, (int64_t)cost_cap);
 }
 
-__global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict__ start, int C,
+__global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict__ start, int n_c,
                                                        int n, int ti, int capacity,
                                                        const int32_t* __restrict__ pos,
                                                        int2* __restrict__ items) {
-  const int c = blockIdx.x * kThreads + threadIdx.x;
-  if (c >= C) return;
+  const int C = n_c * n_c * n_c;
+  const int j = blockIdx.x * kThreads + threadIdx.x;   // position in brick order
+  if (j >= C) return;
+  const int c = brick_cell(j, n_c);
   const int a = min(max(start[c], 0), n), b = min(max(start[c + 1], a), n);
-  int o = pos[c];
-  const int end = min(pos[c + 1], capacity);   // this cell's items (none if filtered out)
+  int o = pos[j];
+  const int end = min(pos[j + 1], capacity);   // this cell's items (none if filtered out)
   for (int f = a; f < b && o < end; f += ti, ++o) items[o] = make_int2(c, f);
 }
 
-// Range boundaries: range q starts at the first item of the first cell
-// whose cost prefix reaches q/8 of the total.
+// Range boundaries: range q starts at the first item of the first cell (in
+// brick order) whose cost prefix reaches q/8 of the total.
 __global__ void k_wl_meta(const int32_t* __restrict__ pos, const int32_t* __restrict__ cost,
                           int C, int capacity, int32_t* __restrict__ counters,
                           int32_t* __restrict__ meta) {
@@ -173,7 +177,7 @@ hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint
   if (e != hipSuccess) return e;
   e = scan_i32(L.cost, C + 1, L.partials, s);
   if (e != hipSuccess) return e;
-  k_wl_fill<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, C, c.n, w.ti, w.capacity, L.pos,
+  k_wl_fill<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, w.capacity, L.pos,
                                                     w.items);
   k_wl_meta<<<1, 64, 0, s>>>(L.pos, L.cost, C, w.capacity, w.counters, w.meta);
   return hipGetLastError();

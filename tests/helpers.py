@@ -63,3 +63,18 @@ def gpu_fields(pipe):
     return {k: np.asarray(r[k], np.float64) if r[k].dtype.kind == "f" else r[k].copy()
             for k in ("rho", "wcount", "rho_dh", "f", "P", "c", "nngb", "a", "du", "vsig",
                       "nforce", "x", "v", "u", "cell")}
+
+
+def brick_order(n_c, b=4):
+    """Cell ids in the order the pair launches visit them, enumerated
+    directly: bricks of b x b x b cells (thinner at the upper box edge) with
+    x the fastest brick index, then y, then z; inside a brick x fastest."""
+    out = []
+    for z0 in range(0, n_c, b):
+        for y0 in range(0, n_c, b):
+            for x0 in range(0, n_c, b):
+                for z in range(z0, min(z0 + b, n_c)):
+                    for y in range(y0, min(y0 + b, n_c)):
+                        for x in range(x0, min(x0 + b, n_c)):
+                            out.append(x + n_c * (y + n_c * z))
+    return np.array(out, dtype=np.int64)

@@ -404,3 +404,36 @@ def test_worklist_occupancy_host_side(sph):
     assert L.sph_worklist_occupancy(C.byref(cells), C.byref(small), 0, 8, None) == sph.SPH_E_NOMEM
     bad = sph.Work(64, 7, C.c_void_p(0x2000), need)
     assert L.sph_worklist_occupancy(C.byref(cells), C.byref(bad), 0, 8, None) == sph.SPH_E_INVALID
+
+
+def _brick_cell(j, n_c, b=4):
+    """The closed form the launches use to map a position j in brick order
+    to a cell id (mixed radix over z-layers, rows and bricks of b cells,
+    thinner at the upper edge)."""
+    nb = (n_c + b - 1) // b
+    last = n_c - b * (nb - 1)
+    layer = b * n_c * n_c
+    bz = min(j // layer, nb - 1)
+    r = j - bz * layer
+    tz = last if bz == nb - 1 else b
+    row = tz * b * n_c
+    by = min(r // row, nb - 1)
+    r -= by * row
+    ty = last if by == nb - 1 else b
+    col = tz * ty * b
+    bx = min(r // col, nb - 1)
+    r -= bx * col
+    tx = last if bx == nb - 1 else b
+    lx, ly, lz = r % tx, (r // tx) % ty, r // (tx * ty)
+    return (b * bx + lx) + n_c * ((b * by + ly) + n_c * (b * bz + lz))
+
+
+@pytest.mark.parametrize("n_c", [3, 4, 5, 7, 8, 13, 32, 33, 44])
+def test_brick_order_closed_form(n_c):
+    """The closed-form brick order equals the direct enumeration of bricks
+    and is a permutation of the cells (every n_c mod 4, including n_c < 4)."""
+    from helpers import brick_order
+    want = brick_order(n_c)
+    got = np.array([_brick_cell(j, n_c) for j in range(n_c ** 3)])
+    assert np.array_equal(got, want)
+    assert np.array_equal(np.sort(got), np.arange(n_c ** 3))

@@ -15,7 +15,7 @@ import pytest
 
 from paper_2512_05516_amd import inputs
 
-from helpers import gpu_fields, max_rel, oracle_step, rel_max, rel_rmse, run_gpu
+from helpers import brick_order, gpu_fields, max_rel, oracle_step, rel_max, rel_rmse, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -211,20 +211,22 @@ def test_host_convert_matches_device(sph, kind):
 
 def _worklist_reference(start, n, n_c, ti):
     """Items and XCD range boundaries of the work list, rebuilt on the host
-    from the cell table: items (cell, first slot) in cell order; the cost of
-    a cell is ceil(count * min(count of its 27 cells, 27 * 64) / 4096),
-    clamped so the sum fits in int32; range q starts at the first item of the
-    first cell whose cost prefix reaches ceil(q * total / 8)."""
+    from the cell table: items (cell, first slot) with the cells in brick
+    order; the cost of a cell is ceil(count * min(count of its 27 cells,
+    27 * 64) / 4096), clamped so the sum fits in int32; range q starts at the
+    first item of the first cell (in brick order) whose cost prefix reaches
+    ceil(q * total / 8)."""
     C = n_c ** 3
+    order = brick_order(n_c)
     counts = np.diff(start).astype(np.int64)
-    items = [(c, f) for c in range(C) for f in range(start[c], start[c + 1], ti)]
+    items = [(c, f) for c in order for f in range(start[c], start[c + 1], ti)]
     grid = counts.reshape(n_c, n_c, n_c)
     nb = sum(np.roll(grid, (dz, dy, dx), axis=(0, 1, 2))
              for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)).reshape(-1)
     cap = (2 ** 31 - 1) // (C + 1)
-    cost = np.minimum((counts * np.minimum(nb, 27 * 64) + 4095) >> 12, cap)
+    cost = np.minimum((counts * np.minimum(nb, 27 * 64) + 4095) >> 12, cap)[order]
     prefix = np.concatenate([[0], np.cumsum(cost)])
-    pos = np.concatenate([[0], np.cumsum((counts + ti - 1) // ti)])
+    pos = np.concatenate([[0], np.cumsum((counts[order] + ti - 1) // ti)])
     total = len(items)
     bounds = [0]
     for q in range(1, 8):
