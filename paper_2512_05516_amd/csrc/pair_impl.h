@@ -183,24 +183,6 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return (b & 7) * per + (b >> 3);
 }
 
-template <int NT>
-__device__ __forceinline__ float block_max(float v, float* lds) {
-  constexpr int NW = NT / 64;
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-  __syncthreads();
-  float r = lds[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) r = fmaxf(r, lds[w]);
-  __syncthreads();
-  return r;
-}
-
-template <int NT>
-__device__ __forceinline__ float block_min(float v, float* lds) {
-  return -block_max<NT>(-v, lds);
-}
-
 template <int K>
 __device__ __forceinline__ float group_sum(float v) {
 #pragma unroll
@@ -512,15 +494,38 @@ struct ChunkBox {
 template <int NT>
 __device__ __forceinline__ ChunkBox chunk_box(bool vi, float xi, float yi, float zi, float H2,
                                               float* red) {
+  // the seven block maxima (minima as maxima of negated values) in one pass:
+  // per value a wave shuffle tree, then the wave results in wave order; two
+  // barriers
+  constexpr int NW = NT / 64;
   const float inf = __builtin_inff();
+  float v[7] = {vi ? -xi : -inf, vi ? -yi : -inf, vi ? -zi : -inf,
+                vi ? xi : -inf,  vi ? yi : -inf,  vi ? zi : -inf, H2};
+#pragma unroll
+  for (int k = 0; k < 7; ++k)
+    for (int o = 32; o > 0; o >>= 1) v[k] = fmaxf(v[k], __shfl_xor(v[k], o));
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) red[k * NW + wave] = v[k];
+  }
+  __syncthreads();
+  float r[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    r[k] = red[k * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r[k] = fmaxf(r[k], red[k * NW + w]);
+  }
+  __syncthreads();
   ChunkBox b;
-  b.lox = block_min<NT>(vi ? xi : inf, red);
-  b.loy = block_min<NT>(vi ? yi : inf, red);
-  b.loz = block_min<NT>(vi ? zi : inf, red);
-  b.hix = block_max<NT>(vi ? xi : -inf, red);
-  b.hiy = block_max<NT>(vi ? yi : -inf, red);
-  b.hiz = block_max<NT>(vi ? zi : -inf, red);
-  b.h2max = block_max<NT>(H2, red);
+  b.lox = -r[0];
+  b.loy = -r[1];
+  b.loz = -r[2];
+  b.hix = r[3];
+  b.hiy = r[4];
+  b.hiz = r[5];
+  b.h2max = r[6];
   return b;
 }
 
@@ -728,8 +733,18 @@ struct TaskItems {
 // --------------------------------------------------------------------------
 // Density
 // --------------------------------------------------------------------------
+// The second launch bound: the compiler reads it as waves per SIMD =
+// blocks x ceil(waves per block / 4). Three waves per SIMD (at most 168
+// VGPRs) for the density tiles of one or two waves and for every force
+// tile; four (128 VGPRs) for the four-wave density tiles, whose LDS allows
+// four workgroups per CU.
+template <int NT>
+constexpr int kDensityBlocks = NT <= 128 ? 3 : 4;
+template <int NT>
+constexpr int kForceBlocks = 3;
+
 template <int TI, int K, class Src, class Items, int KS>
-__global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, CellsDev cd, Phys ph,
+__global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src src, CellsDev cd, Phys ph,
                                                                     float s32, Items items) {
   using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
@@ -742,7 +757,7 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
   __shared__ NbrCells T;
   __shared__ RangeTab<NT> tab;
   __shared__ int wtot[2 * (NT / 64)];
-  __shared__ float red[NT / 64];
+  __shared__ float red[7 * (NT / 64)];
 
   const int n_c = cd.n_c;
   const int tid = threadIdx.x;
@@ -882,7 +897,7 @@ __global__ __launch_bounds__(TI* K, 1024 / (TI * K)) void k_density(Src src, Cel
 // Force
 // --------------------------------------------------------------------------
 template <int TI, int K, class Src, class Items, int KS>
-__global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsDev cd, Phys ph,
+__global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, CellsDev cd, Phys ph,
                                                                  float s32, Items items) {
   using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
@@ -898,7 +913,7 @@ __global__ __launch_bounds__(TI* K, 768 / (TI * K)) void k_force(Src src, CellsD
   __shared__ NbrCells T;
   __shared__ RangeTab<NT> tab;
   __shared__ int wtot[2 * (NT / 64)];
-  __shared__ float red[NT / 64];
+  __shared__ float red[7 * (NT / 64)];
 
   const int n_c = cd.n_c;
   const int tid = threadIdx.x;
