@@ -734,12 +734,11 @@ struct TaskItems {
 // Density
 // --------------------------------------------------------------------------
 // The second launch bound: the compiler reads it as waves per SIMD =
-// blocks x ceil(waves per block / 4). Three waves per SIMD (at most 168
-// VGPRs) for the density tiles of one or two waves and for every force
-// tile; four (128 VGPRs) for the four-wave density tiles, whose LDS allows
-// four workgroups per CU.
+// blocks x ceil(waves per block / 4). Four waves per SIMD (at most 128
+// VGPRs, a few spilled) for every density tile, three (168 VGPRs) for every
+// force tile.
 template <int NT>
-constexpr int kDensityBlocks = NT <= 128 ? 3 : 4;
+constexpr int kDensityBlocks = 4;
 template <int NT>
 constexpr int kForceBlocks = 3;
 
