@@ -747,7 +747,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
                                                                     float s32, Items items) {
   using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
-  constexpr int CAP = 4 * NT;
+  constexpr int CAP = 3 * NT;   // staged candidates (LDS for four waves per SIMD)
   constexpr int LCAP = 32;
   constexpr int kPad = K * kUnroll;
   __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, |x|^2
