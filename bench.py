@@ -96,13 +96,14 @@ def force_traffic(choice):
     the chunks) and the kernel's sources have not changed since; else
     (None, None)."""
     from paper_2512_05516_amd import prof_summary
-    t = prof_summary.read_traffic(os.path.join(ROOT, "profiles", "step_lattice128_f32.txt"))
     f = choice["force"]
     inst = f"sub_bits{choice['sub_bits']}/force{f['ti']}x{f['k']}"
-    if (not t or not t.get("tiling", "").startswith(inst)
-            or t.get("source_sha256") != prof_summary.source_hash()):
-        return None, None
-    return int(t["fetch_bytes"]) + int(t["write_bytes"]), t["tiling"]
+    src = prof_summary.source_hash()
+    for t in prof_summary.read_traffic_all(os.path.join(ROOT, "profiles",
+                                                        "step_lattice128_f32.txt")):
+        if t.get("tiling", "").startswith(inst) and t.get("source_sha256") == src:
+            return int(t["fetch_bytes"]) + int(t["write_bytes"]), t["tiling"]
+    return None, None
 
 
 def cpu_baseline(ps, gpu_records=None):
@@ -351,6 +352,9 @@ def main():
                     help="time only the clustered variant (profiling runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: tune afresh every run)")
+    ap.add_argument("--force-tile", default=None,
+                    help="TIxK[:schedule]: the force loop's tile for the lattice instead of the "
+                         "tuner's (counter runs of a given kernel instance)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size for counter calibration (and skip the "
                          "1 GiB copy-bandwidth measurement, so this copy is the largest)")
@@ -383,6 +387,14 @@ def main():
     # ---- tiling chosen by the autotuner (outside the timed region) ------------
     log("autotuning the pair loops")
     choice = tune.tune(rec, N_C, reps=3, cache_path=args.tune_cache, log=log)
+    if args.force_tile:
+        ti_k, _, sched = args.force_tile.partition(":")
+        ti, k = (int(v) for v in ti_k.split("x"))
+        iso = [r["ms"] for r in choice["table"] if r["sub_bits"] == choice["sub_bits"]
+               and r["loop"] == "force" and (r["ti"], r["k"], r["sched"]) == (ti, k, sched or None)]
+        if not iso:
+            raise SystemExit(f"--force-tile {args.force_tile}: not a tuner candidate")
+        choice = dict(choice, force={"ti": ti, "k": k, "sched": sched or None, "ms": iso[0]})
     kw = tune.pipeline_kwargs(choice)
     log("chosen:", tune.describe(choice))
 

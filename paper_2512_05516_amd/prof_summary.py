@@ -37,15 +37,23 @@ def source_hash() -> str:
 
 
 def read_traffic(path: str):
-    """The traffic line of a summary file as a dict, or None."""
+    """The first traffic line of a summary file as a dict, or None."""
+    lines = read_traffic_all(path)
+    return lines[0] if lines else None
+
+
+def read_traffic_all(path: str):
+    """Every traffic line of a summary file (one per profiled kernel
+    instance) as a list of dicts; empty if the file is missing."""
+    out = []
     try:
         with open(path) as fh:
             for line in fh:
                 if line.startswith("traffic "):
-                    return dict(kv.split("=", 1) for kv in line.split()[1:])
+                    out.append(dict(kv.split("=", 1) for kv in line.split()[1:]))
     except OSError:
-        return None
-    return None
+        pass
+    return out
 
 
 def short(name: str) -> str:
