@@ -38,10 +38,12 @@ N_C = 32
 SEED = 2
 DT = 1e-4
 
-# Algorithmic work per unit (counted from the pair expressions; FMA = 2 flops,
-# sqrt / reciprocal = 1): per in-support density pair and force pair.
-FLOP_DENSITY_PAIR = 34
-FLOP_FORCE_PAIR = 72
+# Algorithmic work per in-support pair, the method's flop counts: about 40
+# FP32 flops per density pair (distance, kernel value and slope, three
+# accumulations) and 100 per force pair (distance, two kernel slopes,
+# pressure and viscosity terms, four accumulations).
+FLOP_DENSITY_PAIR = 40
+FLOP_FORCE_PAIR = 100
 # Algorithmic bytes per particle (FP32 record, FP32 storage):
 BYTES_CONVERT_FULL = 56 + 8 + 76     # record fields x,v,m,h,u + perm,cell; SoA writes
 BYTES_KICK = 96                      # x(24) v(12) u(4) a(12) du(4) read; x v u written
@@ -106,30 +108,99 @@ def force_traffic(choice):
     return None, None
 
 
-def cpu_baseline(ps, gpu_records=None):
-    """FP64 oracle (cells mode, OpenMP) on a bounded sample of the workload:
-    density over all particles and force over every 8th particle. With
-    gpu_records ({storage: records of one GPU evaluation of the same
-    particles}) the same oracle values give each storage format's error
-    against FP64: max relative error of rho over all particles, relative
-    RMSE (normalised by the mean magnitude) and max normalised error of a
-    and du/dt over the force sample."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_timings(oracle, ps, n_c, stride, d_all, reps=3):
+    """Median of `reps` timed runs of the FP64 oracle (cell-list mode) on a
+    sample of ps (every `stride`-th particle): density, force (its inputs at
+    every particle from d_all, computed beforehand) and kick/drift over all
+    particles."""
+    import ctypes as C
+    sel = np.arange(0, ps.n, stride, dtype=np.int32)
+    x0 = np.ascontiguousarray(ps.x, np.float64)
+    v0 = np.ascontiguousarray(ps.v, np.float64)
+    u0 = np.ascontiguousarray(ps.u, np.float64)
+    a = np.zeros((ps.n, 3))
+    du = np.zeros(ps.n)
+    td, tf, tk, pairs = [], [], [], 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        d = oracle.density(ps, n_c=n_c, sel=sel)
+        t1 = time.perf_counter()
+        f = oracle.force(ps, d_all, n_c=n_c, sel=sel)
+        t2 = time.perf_counter()
+        x, v, u = x0.copy(), v0.copy(), u0.copy()
+        t3 = time.perf_counter()
+        oracle.lib().orc_kick_drift(ps.n, oracle._p(x, C.c_double), oracle._p(v, C.c_double),
+                                    oracle._p(u, C.c_double), oracle._p(a, C.c_double),
+                                    oracle._p(du, C.c_double), DT, DT)
+        t4 = time.perf_counter()
+        td.append(t1 - t0)
+        tf.append(t2 - t1)
+        tk.append(t4 - t3)
+        pairs = float(d["nngb"].sum() + f["nforce"].sum())
+    md, mf, mk = float(np.median(td)), float(np.median(tf)), float(np.median(tk))
+    return {"pair_interactions_per_s": pairs / (md + mf), "density_s": md, "force_s": mf,
+            "pairs": pairs, "sample_particles": int(len(sel)),
+            "kick_drift_particles_per_s": ps.n / mk,
+            # the oracle's FP64 arrays: x, v, u, a, du read (88 B), x, v, u written (56 B)
+            "kick_drift_gbs_fp64_arrays": 144.0 * ps.n / mk / 1e9}
+
+
+def cpu_baseline(sets, gpu_records=None, err_set=None):
+    """FP64 oracle (cell-list mode, OpenMP) timed on bounded samples of the
+    workloads, with all host threads and with one, median of 3 each.
+    sets: [(name, ParticleSet, n_c, stride)]; density and force over every
+    stride-th particle, kick/drift over all. The headline value is the
+    all-threads pair-interaction rate on the 128^3 set. With gpu_records
+    ({storage: records of one GPU evaluation of err_set's particles}) the
+    oracle's values give each storage format's error against FP64: max
+    relative error of rho over all particles, relative RMSE (normalised by
+    the mean magnitude) and max normalised error of a and du/dt over every
+    8th particle."""
     import oracle
     oracle.lib()
-    n = ps.n
-    t0 = time.perf_counter()
-    d = oracle.density(ps, n_c=N_C)
-    t1 = time.perf_counter()
-    sel = np.arange(0, n, 8, dtype=np.int32)
-    f = oracle.force(ps, d, n_c=N_C, sel=sel)
-    t2 = time.perf_counter()
-    pairs = float(d["nngb"].sum() + f["nforce"].sum())
-    out = {"value": pairs / (t2 - t0), "unit": "pair-interactions/s",
-           "cores": oracle.num_threads(), "kind": "oracle",
-           "sample": f"FP64 oracle, cell-list mode: density over all {n} particles "
-                     f"({t1 - t0:.2f} s) + force over {len(sel)} (every 8th) "
-                     f"({t2 - t1:.2f} s)"}
-    if gpu_records:
+    threads = oracle.num_threads()
+    out = {"unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+           "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "reps": 3, "statistic": "median",
+           "configs": {}}
+    dens_all = {}
+    for name, ps, n_c, stride in sets:
+        log(f"CPU oracle: {name} ({ps.n} particles, density at all of them for the force)")
+        oracle.set_threads(threads)
+        d_all = oracle.density(ps, n_c=n_c)
+        dens_all[name] = d_all
+        res = {"particles": ps.n, "n_c": n_c, "sample": f"density and force over every "
+                                                        f"{stride}-th particle, kick/drift "
+                                                        f"over all"}
+        for t in (threads, 1):
+            oracle.set_threads(t)
+            res[f"threads_{t}"] = _oracle_timings(oracle, ps, n_c, stride, d_all)
+        oracle.set_threads(threads)
+        out["configs"][name] = res
+    m = out["configs"]["medium_128cubed"][f"threads_{threads}"]
+    out["value"] = m["pair_interactions_per_s"]
+    out["sample"] = (f"FP64 oracle, cell-list mode, {threads} threads: density + force over "
+                     f"{m['sample_particles']} particles (every "
+                     f"{sets[1][3]}-th) of the 128^3 set, median of 3 "
+                     f"({m['density_s'] + m['force_s']:.2f} s); S, M, K and 1-thread "
+                     f"figures under configs")
+    if gpu_records and err_set is not None:
+        ps, n_c, key = err_set
+        d = dens_all[key]
+        sel = np.arange(0, ps.n, 8, dtype=np.int32)
+        f = oracle.force(ps, d, n_c=n_c, sel=sel)
+
         def rel_rmse(g, r):
             dn = np.linalg.norm(np.atleast_2d((g - r).T).T, axis=1)
             rn = np.linalg.norm(np.atleast_2d(r.T).T, axis=1)
@@ -145,10 +216,24 @@ def cpu_baseline(ps, gpu_records=None):
     return out
 
 
-SERVE_RATES = (5e3, 1e4, 2e4, 5e4)     # offered tasks per second
-SERVE_SECONDS = 1.0                    # arrivals per rate
+# offered tasks per second and seconds of arrivals: the configured rates,
+# then two beyond them that keep the device busy (continuous batching under
+# load: batches fill up while earlier ones run)
+SERVE_RATES = ((5e3, 3.0), (1e4, 3.0), (2e4, 3.0), (5e4, 3.0), (2e5, 1.0), (1e6, 0.5))
 KDK_STEPS = 10         # leapfrog steps of the multi-step run
-PREC16 = lambda sphmi: sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
+# reduced storage (positions as offsets from sub-cell centres of side 1/(4 n_c)):
+# the mixed format of the 128^3 reduced-precision configuration, all-FP16 and
+# all-BF16; m, h, u scales for FP16
+ANCHOR = 3     # SPH_ANCHOR_SUB(2)
+PREC16 = lambda sphmi, sm=21: sphmi.precision("f16", "bf16", "f16", scale_m=sm, scale_h=7,
+                                              scale_u=0, anchor=ANCHOR)
+PREC_ALL16 = lambda sphmi: sphmi.precision("f16", "f16", "f16", scale_m=21, scale_h=7, scale_u=0,
+                                           anchor=ANCHOR)
+PREC_ALLBF16 = lambda sphmi: sphmi.precision("bf16", "bf16", "bf16", anchor=ANCHOR)
+PREC_NAMES = {"fp16_store": "pos f16 offsets from sub-cell centres, v bf16, m/h/u f16 "
+                            "(scales 21/7/0)",
+              "fp16_all": "pos, v, m/h/u f16 (scales 21/7/0), sub-cell-centre offsets",
+              "bf16_all": "pos, v, m/h/u bf16, sub-cell-centre offsets"}
 PIPE_THREADS = 16      # host worker threads of the streaming arrangement
 H_ROOM = 1.6      # clustered set: cell size / background support radius while h iterates
 H_TOL = 1e-4      # relative h change that ends a particle's iteration
@@ -157,23 +242,24 @@ H_TOL = 1e-4      # relative h change that ends a particle's iteration
 def serving_variant(pipe, n_c, seed=4):
     """Continuous-batching server over the resident state of `pipe`: for
     each offered rate, a Poisson stream of cell-pair tasks (half density,
-    half force; both sides 16..512 particles) for SERVE_SECONDS; latency =
+    half force; both sides 16..512 particles) for the seconds SERVE_RATES gives; latency =
     completion - arrival per task."""
     from paper_2512_05516_amd import serve
     start = pipe.cells.cell_start.cpu().numpy()
-    nmax = int(max(SERVE_RATES) * SERVE_SECONDS)
+    nmax = int(max(r * t for r, t in SERVE_RATES))
     tasks_all = serve.make_tasks(start, n_c, nmax, seed)
     sizes = (tasks_all[:, 4] - tasks_all[:, 3]).astype(np.int64)
     buf = np.empty(int(sizes.sum()), serve.RESULT)
     buf.view(np.uint8).fill(0)        # fault the pages in before any task completes
     cfg = {"streams": 4, "max_batch": 256, "pool_bytes": 64 << 20}
     out = {"config": dict(cfg, tile="64x4", task_sides="16..512 particles",
-                          mix="50% density / 50% force", seconds_per_rate=SERVE_SECONDS)}
+                          mix="50% density / 50% force",
+                          seconds_per_rate={str(int(r)): t for r, t in SERVE_RATES})}
     with serve.Server(pipe, **cfg) as srv:
         warm, _ = serve.requests(tasks_all[:256], np.zeros(256, np.int64))
         srv.run(warm)
-        for rate in SERVE_RATES:
-            n = int(rate * SERVE_SECONDS)
+        for rate, seconds in SERVE_RATES:
+            n = int(rate * seconds)
             tasks = tasks_all[:n]
             t0 = serve.now_ns() + 2_000_000
             arr = serve.poisson_arrivals(n, rate, t0, seed + int(rate))
@@ -214,7 +300,7 @@ def pipeline_variant(torch, args, rec, choice, sphmi):
     from paper_2512_05516_amd import tune
     kw = tune.pipeline_kwargs(choice)
     kw.pop("sub_bits")
-    prec16 = sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
+    prec16 = PREC16(sphmi)
     steps = max(2, min(args.steps, 5))
     t, _ = pinned_records(rec)
     out = {"steps": steps, "host_threads": PIPE_THREADS,
@@ -268,45 +354,34 @@ def kdk_variant(torch, rec, kw, Pipeline, steps=KDK_STEPS):
     return out
 
 
-def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
+def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline, settle_h):
     """Clustered 4,194,304-particle set: tuned tiling, whole FP32 SoA steps
     and FP16-store steps (FP16 offsets, BF16 v, FP16 m/h/u)."""
     log("generating the clustered 4M set")
     ps = inputs.clustered_k_set(3)
-    gk = sphmi.params().gamma_k
     rec = inputs.pack_aos(ps, "f32")
     n = ps.n
     # h from the density iteration, on the GPU: start from the background h
     # in a cell list with room for h to grow, then take cells as small as the
     # largest iterated support radius allows
-    n_c0 = int(np.floor(1.0 / (H_ROOM * gk * ps.h.max())))
     del ps
-    log(f"clustered: smoothing-length iteration (n_c = {n_c0})")
-    p0 = Pipeline(rec, n_c0, sched="grid", til=sphmi.tile(32, 2), sub_bits=2)
-    p0.bin()
-    p0.convert("full")
+    log("clustered: smoothing-length iteration")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    passes, left = p0.smoothing_length(tol=H_TOL, max_iter=30)
-    torch.cuda.synchronize()
+    rec, n_c, info = settle_h(rec, tol=H_TOL, max_iter=30, room=H_ROOM)
     t_h = time.perf_counter() - t0
-    rec = p0.records()
-    del p0
-    torch.cuda.empty_cache()
     h = rec["h"].astype(np.float64)
-    n_c = int(np.floor(1.0 / (gk * h.max())))
-    h_iter = {"passes": passes, "not_converged": left, "ms": round(1e3 * t_h, 3), "tol": H_TOL,
-              "n_c_during": n_c0,
+    passes, left = info["passes"], info["not_converged"]
+    h_iter = {"passes": passes, "not_converged": left, "ms_incl_transfers": round(1e3 * t_h, 3),
+              "tol": H_TOL, "n_c_during": info["n_c_during"],
               "h": {"min": float(h.min()), "p50": float(np.median(h)), "max": float(h.max())}}
     log(f"clustered: {passes} passes, {left} not converged, {1e3 * t_h:.1f} ms; n_c = {n_c}")
     steps = max(1, min(args.steps, 10))
     warm = max(1, min(args.warmup, 2))
-    out = {"workload": f"clustered: {n} particles, 37% in 8 Gaussian blobs (sigma 0.03) over "
+    out = {"workload": f"clustered: {n} particles, 19% in 8 Gaussian blobs (sigma 0.03) over "
                        f"a uniform background, h from the density iteration, n_c = {n_c}",
            "particles": n, "n_c": n_c, "steps": steps, "h_iteration": h_iter}
-    for name, prec in (("fp32", sphmi.precision()),
-                       ("fp16_store", sphmi.precision("f16", "bf16", "f16", scale_m=22,
-                                                      scale_h=7, scale_u=0))):
+    for name, prec in (("fp32", sphmi.precision()), ("fp16_store", PREC16(sphmi, 22))):
         log(f"clustered {name}: autotuning")
         sub = (0, 1, 2, 3) if name == "fp32" else (out["fp32"]["sub_bits"],)
         ch = tune.tune(rec, n_c, prec=prec, sub_bits=sub, reps=2, cache_path=args.tune_cache,
@@ -331,7 +406,7 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline):
             out[name]["serving"] = serving_variant(pipe, n_c)
         del pipe
         torch.cuda.empty_cache()
-    return out
+    return out, (rec, n_c)
 
 
 def main():
@@ -368,7 +443,7 @@ def main():
 
     import torch
     from paper_2512_05516_amd import inputs, sphmi, tune
-    from paper_2512_05516_amd.pipeline import Pipeline
+    from paper_2512_05516_amd.pipeline import Pipeline, settle_h
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -376,7 +451,7 @@ def main():
     sphmi.lib()
     torch.cuda.set_device(0)
     if args.clustered_only:
-        out = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)
+        out, _ = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline, settle_h)
         print(json.dumps({"metric": METRIC, "clustered": out}), flush=True)
         return
     log("generating 128^3 jittered lattice")
@@ -450,33 +525,55 @@ def main():
     del pipe
     torch.cuda.empty_cache()
 
+    # ---- work counters of the pair loops (one extra step, not timed) ---------
+    pt = Pipeline(rec, N_C, tally=True, **kw)
+    pt.bin()
+    pt.convert("full")
+    pt.density()
+    torch.cuda.synchronize()
+    tl_d = pt.cells.tally.cpu().numpy().astype(np.float64)
+    pt.force()
+    torch.cuda.synchronize()
+    tl_f = pt.cells.tally.cpu().numpy().astype(np.float64) - tl_d
+    del pt
+    torch.cuda.empty_cache()
+    result["candidates"] = {
+        "note": "candidate tests = particles of a chunk x candidates staged for it (the "
+                "prefilter's evaluations); efficiency = in-support pairs / tests",
+        "density_tests": tl_d[0], "force_tests": tl_f[0],
+        "density_gathered": tl_d[1], "force_gathered": tl_f[1],
+        "density_tests_per_s": tl_d[0] / (per["density"] * 1e-3),
+        "force_tests_per_s": tl_f[0] / (per["force"] * 1e-3),
+        "density_efficiency": pairs_d / tl_d[0], "force_efficiency": pairs_f / tl_f[0]}
+
     if not args.no_variants:
         # ---- plain AoS step (Eq. gpu_native) ---------------------------------
         log("plain AoS step")
         pa = Pipeline(rec, N_C, **kw)
         s_aos, per_aos = timed_steps(torch, pa, "aos", args.steps, args.warmup)
         del pa
-        # ---- reduced-precision SoA step (FP16 offsets, BF16 v, FP16 m/h/u) -----
-        log("FP16-store SoA step")
-        prec = sphmi.precision("f16", "bf16", "f16", scale_m=21, scale_h=7, scale_u=0)
-        pr = Pipeline(rec, N_C, prec=prec, **kw)
-        s_r, per_r = timed_steps(torch, pr, "soa", args.steps, args.warmup)
-        del pr
-        torch.cuda.empty_cache()
         ms_aos = 1e3 * s_aos / args.steps
-        ms_r = 1e3 * s_r / args.steps
         result["aos_plain"] = {"ms_per_step": ms_aos, "value": pairs * args.steps / s_aos,
                                "kernels_ms": {k: round(v, 4) for k, v in per_aos.items()}}
-        result["fp16_store"] = {"ms_per_step": ms_r, "value": pairs * args.steps / s_r,
-                                "precision": "pos f16 offsets, v bf16, m/h/u f16 (scales 21/7/0)",
-                                "kernels_ms": {k: round(v, 4) for k, v in per_r.items()}}
-        result["speedup_vs_fp32_aos"] = {
-            "fp32_soa_step": round(ms_aos / ms_step, 3),
-            "fp16_store_step": round(ms_aos / ms_r, 3),
-            "density_fp16_store": round(per_aos["density"] / per_r["density"], 3),
-            "force_fp16_store": round(per_aos["force"] / per_r["force"], 3),
-            "kick_drift_fp16_store": round(per_aos["kick_drift"] / per_r["kick_drift"], 3),
-        }
+        sp = {"fp32_soa_step": round(ms_aos / ms_step, 3)}
+        # ---- reduced-precision SoA steps: the mixed format, all-FP16, all-BF16 --
+        for name, prec in (("fp16_store", PREC16(sphmi)), ("fp16_all", PREC_ALL16(sphmi)),
+                           ("bf16_all", PREC_ALLBF16(sphmi))):
+            log(f"{name} SoA step")
+            pr = Pipeline(rec, N_C, prec=prec, **kw)
+            s_r, per_r = timed_steps(torch, pr, "soa", args.steps, args.warmup)
+            st_r = pr.status()
+            del pr
+            torch.cuda.empty_cache()
+            ms_r = 1e3 * s_r / args.steps
+            result[name] = {"ms_per_step": ms_r, "value": pairs * args.steps / s_r,
+                            "precision": PREC_NAMES[name], "status_flags": st_r,
+                            "kernels_ms": {k: round(v, 4) for k, v in per_r.items()}}
+            sp.update({f"{name}_step": round(ms_aos / ms_r, 3),
+                       f"density_{name}": round(per_aos["density"] / per_r["density"], 3),
+                       f"force_{name}": round(per_aos["force"] / per_r["force"], 3),
+                       f"kick_drift_{name}": round(per_aos["kick_drift"] / per_r["kick_drift"], 3)})
+        result["speedup_vs_fp32_aos"] = sp
         # ---- host-side convert (CPU data management) vs GPU convert + copy ----
         log("host-convert variant")
         ph = Pipeline(rec, N_C)
@@ -528,8 +625,10 @@ def main():
         if not args.no_pipeline:
             result["pipeline"] = pipeline_variant(torch, args, rec, choice, sphmi)
 
+    k_state = None
     if not args.no_clustered:
-        result["clustered"] = clustered_variant(torch, args, inputs, sphmi, tune, Pipeline)
+        result["clustered"], k_state = clustered_variant(torch, args, inputs, sphmi, tune,
+                                                         Pipeline, settle_h)
 
     # practical HBM ceiling: a plain 1 GiB device-to-device copy (read + write);
     # left out of counter runs, whose calibration takes the largest device copy
@@ -559,7 +658,8 @@ def main():
     if not args.no_cpu_baseline:
         log("CPU oracle baseline")
         gpu_records = {}
-        for name, prec in (("fp32", sphmi.precision()), ("fp16_store", PREC16(sphmi))):
+        for name, prec in (("fp32", sphmi.precision()), ("fp16_store", PREC16(sphmi)),
+                           ("fp16_all", PREC_ALL16(sphmi)), ("bf16_all", PREC_ALLBF16(sphmi))):
             pe = Pipeline(rec, N_C, prec=prec, **kw)
             pe.bin()
             pe.convert("full")
@@ -569,7 +669,14 @@ def main():
             gpu_records[name] = pe.records()
             del pe
         torch.cuda.empty_cache()
-        result["cpu_baseline"] = cpu_baseline(ps, gpu_records)
+        sets = [("small_16cubed", inputs.small_set(1), 4, 1), ("medium_128cubed", ps, N_C, 128)]
+        if k_state is not None:
+            k_rec, k_nc = k_state
+            sets.append(("clustered_4m", inputs.unpack_aos(k_rec), k_nc, 256))
+        result["cpu_baseline"] = cpu_baseline(sets, gpu_records, (ps, N_C, "medium_128cubed"))
+        if k_state is not None:
+            result["cpu_baseline"]["configs"]["clustered_4m"]["note"] = (
+                "h of the records as the GPU density iteration left them (the workload's h)")
     print(json.dumps(result), flush=True)
 
 

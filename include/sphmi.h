@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 8
+#define SPH_ABI_VERSION 9
 
 typedef int32_t sph_status;
 enum {
@@ -123,6 +123,11 @@ typedef struct {
   float *hmax;            /* [n_c^3] largest h of each cell (written by   */
                           /* sph_bin when the layout has H; may be NULL)  */
   int32_t *status;        /* [1] optional (may be NULL) SPH_FLAG_* word   */
+  uint64_t *tally;        /* [2] optional (may be NULL) work counters of  */
+                          /* the pair loops: [0] += candidate pair tests  */
+                          /* (particles of a chunk times the candidates   */
+                          /* staged for it), [1] += candidates gathered   */
+                          /* from the candidate ranges                    */
 } sph_cells;
 
 /* Work list of the pair kernels for a launch over all cells of uneven
@@ -161,6 +166,8 @@ enum {
   SPH_S_RHO, SPH_S_WCOUNT, SPH_S_RHO_DH, SPH_S_F, SPH_S_P, SPH_S_C, SPH_S_NNGB,
   /* force outputs (float; NFORCE int32)                                  */
   SPH_S_A_X, SPH_S_A_Y, SPH_S_A_Z, SPH_S_DU, SPH_S_VSIG, SPH_S_NFORCE,
+  /* anchor sub-cell code of each slot (uint8; see sph_precision.pos_anchor) */
+  SPH_S_ANC,
   SPH_S_NFIELDS
 };
 
@@ -175,10 +182,30 @@ typedef struct {
  * normal range of FP16); Q rounds to nearest even for the IEEE formats and
  * cuts the mantissa for SPH_TRUNC_BITS. Truncated formats are written by
  * sph_convert only (records of at most 208 bytes), and read by the kernels'
- * run-time format path. */
+ * run-time format path.
+ *
+ * Positions are stored as offsets from an anchor that the kernels rebuild
+ * from the cell id (Sec. 3.2: a value kept as a quantised difference from an
+ * anchor). With x_w the wrapped position of a particle in cell c (per axis):
+ *   SPH_ANCHOR_CORNER:  anchor = c / n_c;
+ *   SPH_ANCHOR_SUB(b):  anchor = (c 2^b + a + 1/2) / (n_c 2^b), the centre
+ *     of the particle's sub-cell of side 1/(n_c 2^b), with the sub-cell
+ *     index a = floor(x_w n_c 2^b) - c 2^b clamped to [0, 2^b - 1]
+ *     (b = 0: the cell centre; 0 <= b <= 2);
+ * all in FP64; OFF = Q_pos(RNE32(x_w - anchor)). Every halving of the
+ * anchor's reach halves the largest stored offset and so the position
+ * error of a floating storage format. For b >= 1 the SoA field ANC holds
+ * each slot's code a_x + 4 a_y + 16 a_z (uint8), written with the offsets
+ * and required wherever they are read. The kernels read a position
+ * relative to the cell corner as fma(a + 1/2, s 2^-b, off) in FP32 with
+ * s = RNE32(1 / n_c). */
+#define SPH_ANCHOR_CORNER 0
+#define SPH_ANCHOR_SUB(b) (1 + (b))
 typedef struct {
   int32_t pos, vel, mhu;
   int32_t scale_m, scale_h, scale_u;
+  int32_t pos_anchor;     /* SPH_ANCHOR_CORNER or SPH_ANCHOR_SUB(0..2)    */
+  int32_t reserved;       /* must be 0                                    */
 } sph_precision;
 
 /* which fields a convert or writeback moves (operator N of Sec. 4.1) */
@@ -250,8 +277,9 @@ sph_status sph_bin(const void *aos, const sph_aos_layout *layout, const sph_cell
 
 /* AoS->SoA gather U o N o C (Sec. 4.1; Eq. gpu_soa_conversion): for every
  * sorted slot k, read record perm[k] and write the view's fields at k.
- * OFF = FP32(x_wrapped - c / n_c) (FP64 difference, one rounding), then
- * the pos format; VQ, M, H, U: RNE to FP32, scale, RNE to the format;
+ * OFF = FP32(x_wrapped - anchor) (FP64 difference, one rounding; anchor as
+ * in sph_precision), then the pos format, and ANC for anchors with b >= 1;
+ * VQ, M, H, U: RNE to FP32, scale, RNE to the format;
  * X: wrapped FP64 position; V, UK: FP32. */
 sph_status sph_convert(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
                        int32_t view, const sph_precision *prec, const sph_soa *out,
@@ -340,12 +368,13 @@ sph_status sph_worklist_occupancy(const sph_cells *cells, sph_work *work, int32_
  * around each particle's cell). For every slot i, over every j with
  * r_ij < H_i, the self pair included (support test in FP32:
  * r2 = fma(dz,dz,fma(dy,dy,dx*dx)) < (gamma_k h_i)^2 with d the difference
- * of the stored offsets shifted by the cell separation):
+ * of the stored positions relative to i's cell corner; a pair decided
+ * otherwise than in FP64 lies within FP32 rounding of the support radius):
  *   rho_i = sum m_j W(r_ij, h_i)      wcount_i = (4 pi/3) sum w(r_ij/H_i)
  *   rho_dh_i = sum m_j dW/dh          nngb_i = #j
  *   f_i = 1 / (1 + h_i rho_dh_i / (3 rho_i))   (1 if gradh = 0)
  *   P_i = (gamma-1) rho_i u_i         c_i = sqrt(gamma (gamma-1) u_i)
- * Reads OFF, M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB.
+ * Reads OFF (and ANC), M, H, U; writes RHO, WCOUNT, RHO_DH, F, P, C, NNGB.
  * work == NULL: one workgroup per cell; otherwise one launch over the work
  * list with schedule work->sched (work->ti must equal the tile's ti). Candidates come from
  * the sub-cells (or cells, sub_bits = 0) within the chunk's bounding box
@@ -363,7 +392,12 @@ sph_status sph_density(const sph_soa *soa, const sph_precision *prec, const sph_
  *   a_i   -= m_j (A_i g_i + A_j g_j + Pi gbar) e
  *   du_i  += m_j (A_i g_i + Pi gbar / 2) w
  *   vsig_i = max_j vsig_ij,  nforce_i = #j
- * Reads OFF, VQ, M, H and RHO, F, P, C; writes A_*, DU, VSIG, NFORCE.
+ * A pair at zero separation (coincident stored positions, j != i) has the
+ * zero vector as e: it counts, adds nothing to a and du, and has
+ * vsig_ij = c_i + c_j (the r -> 0 limit of the pair terms, which vanish
+ * with w'(0) = 0).
+ * Reads OFF (and ANC), VQ, M, H and RHO, F, P, C; writes A_*, DU, VSIG,
+ * NFORCE.
  * Needs cells->hmax (the neighbour bound of each cell); work as above. */
 sph_status sph_force(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
                      const sph_params *params, sph_tile tile, const sph_work *work,

@@ -97,9 +97,9 @@ def lib():
         L.orc_kick_drift.restype = None
         L.orc_reduce.argtypes = [C.c_int, d, d, d, d, d]
         L.orc_reduce.restype = None
-        L.orc_count32.argtypes = [C.c_int, d, d, C.c_int, C.c_double, C.c_int, C.c_int,
-                                  C.c_int, C.c_int, C.POINTER(C.c_uint8), i32, C.c_int,
-                                  i32, i32]
+        L.orc_near_support.argtypes = [C.c_int, d, d, C.c_double, C.c_int, C.c_int, i32, C.c_int,
+                                       C.c_double, C.c_double, i32, i32]
+        L.orc_pos_offsets.argtypes = [C.c_int, d, C.c_int, C.c_int, d, C.POINTER(C.c_uint8)]
         L.orc_f32_to_f16.restype = C.c_uint16
         L.orc_f32_to_f16.argtypes = [C.c_float]
         L.orc_f16_to_f32.restype = C.c_float
@@ -115,8 +115,10 @@ def lib():
         L.orc_roundtrip.restype = C.c_double
         L.orc_roundtrip.argtypes = [C.c_double, C.c_int, C.c_int]
         L.orc_dequantise_set.argtypes = [C.c_int, d, d, d, d, d, C.c_int, C.c_int, C.c_int,
-                                         C.c_int, i32, d, d, d, d, d]
+                                         C.c_int, i32, C.c_int, d, d, d, d, d]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         L.orc_bin_sub.argtypes = [C.c_int, d, C.c_int, C.c_int, i32, i32, i32]
         L.orc_smoothing_length.argtypes = [C.c_int, d, d, d, C.c_double, C.POINTER(Params),
                                            C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
@@ -127,6 +129,11 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following OpenMP regions (timing runs)."""
+    lib().orc_set_threads(int(n))
 
 
 def _p(a, t):
@@ -250,23 +257,49 @@ def reduce(m, v, a, du):
     return out
 
 
-def count32(ps, n_c, pos="f32", hdt="f32", h_scale=0, mode="cells", gamma_k=GAMMA_K,
-            jmask=None, sel=None):
-    """Neighbour counts with the support test in FP32 -> (n_density, n_force);
-    jmask restricts j as for density(); sel selects the i (outputs per entry)."""
+# Pairs this close to a support radius may be decided either way by a count
+# taken in FP32 on stored offsets (the kernels' rounding of the shifted
+# positions and of r^2 and H^2 stays well inside both terms).
+NEAR_EPS_REL = 1e-5
+NEAR_EPS_ABS_CELLS = 2.0 ** -18     # times the cell side
+
+
+def near_support(ps, n_c, gamma_k=GAMMA_K, mode="cells", sel=None, eps_rel=NEAR_EPS_REL,
+                 eps_abs=None):
+    """Per particle (or per entry of sel): the number of density-list pairs
+    with |r - H_i| < eps_rel H_i + eps_abs and of force-list pairs within
+    that distance of H_i or H_j (eps_abs: NEAR_EPS_ABS_CELLS / n_c by
+    default) -> (near_density, near_force)."""
     x, h = _f64(ps.x), _f64(ps.h)
     n = x.shape[0]
+    if eps_abs is None:
+        eps_abs = NEAR_EPS_ABS_CELLS / n_c
     if sel is not None:
         sel = np.ascontiguousarray(sel, dtype=np.int32)
     cnt = n if sel is None else sel.shape[0]
     nd = np.empty(cnt, np.int32)
     nf = np.empty(cnt, np.int32)
-    rc = lib().orc_count32(n, _p(x, C.c_double), _p(h, C.c_double), int(n_c), float(gamma_k),
-                           DTYPE_CODES[pos], DTYPE_CODES[hdt], int(h_scale),
-                           0 if mode == "brute" else 1, _p(_mask(jmask), C.c_uint8),
-                           _p(sel, C.c_int32), cnt, _p(nd, C.c_int32), _p(nf, C.c_int32))
-    assert rc == 0
+    rc = lib().orc_near_support(n, _p(x, C.c_double), _p(h, C.c_double), float(gamma_k),
+                                0 if mode == "brute" else 1, int(n_c), _p(sel, C.c_int32), cnt,
+                                float(eps_rel), float(eps_abs), _p(nd, C.c_int32),
+                                _p(nf, C.c_int32))
+    if rc != 0:
+        raise ValueError(f"orc_near_support failed ({rc})")
     return nd, nf
+
+
+def pos_offsets(x, n_c, anchor=0):
+    """(off[N, 3], code[N]): FP64 offsets of the wrapped positions from their
+    anchor (0: cell corner; 1 + b: centre of the sub-cell of side
+    1/(n_c 2^b)) and the anchor sub-cell code a_x + 4 a_y + 16 a_z."""
+    x = _f64(x)
+    n = x.shape[0]
+    off = np.empty((n, 3))
+    code = np.empty(n, np.uint8)
+    rc = lib().orc_pos_offsets(n, _p(x, C.c_double), int(n_c), int(anchor), _p(off, C.c_double),
+                               _p(code, C.c_uint8))
+    assert rc == 0
+    return off, code
 
 
 def quant(a32, dtype):
@@ -288,20 +321,23 @@ def roundtrip(v, dtype, scale=0):
     return lib().orc_roundtrip(float(v), DTYPE_CODES[dtype], int(scale))
 
 
-def dequantise_set(ps, n_c, pos="f32", vel="f32", mhu="f32", scales=(0, 0, 0)):
+def dequantise_set(ps, n_c, pos="f32", vel="f32", mhu="f32", scales=(0, 0, 0), anchor=0):
     """The particle set as an SoA view of the given storage formats holds it,
-    read back into FP64 (positions = cell origin + stored offset)."""
+    read back into FP64 (positions = anchor + stored offset; anchor as in
+    pos_offsets)."""
     from paper_2512_05516_amd.inputs import ParticleSet
     x, v, m, h, u = (_f64(ps.x), _f64(ps.v), _f64(ps.m), _f64(ps.h), _f64(ps.u))
     n = x.shape[0]
     xq, vq = np.empty_like(x), np.empty_like(v)
     mq, hq, uq = np.empty_like(m), np.empty_like(h), np.empty_like(u)
     sc = np.ascontiguousarray(scales, dtype=np.int32)
-    lib().orc_dequantise_set(n, _p(x, C.c_double), _p(v, C.c_double), _p(m, C.c_double),
-                             _p(h, C.c_double), _p(u, C.c_double), int(n_c), DTYPE_CODES[pos],
-                             DTYPE_CODES[vel], DTYPE_CODES[mhu], _p(sc, C.c_int32),
-                             _p(xq, C.c_double), _p(vq, C.c_double), _p(mq, C.c_double),
-                             _p(hq, C.c_double), _p(uq, C.c_double))
+    rc = lib().orc_dequantise_set(n, _p(x, C.c_double), _p(v, C.c_double), _p(m, C.c_double),
+                                  _p(h, C.c_double), _p(u, C.c_double), int(n_c),
+                                  DTYPE_CODES[pos], DTYPE_CODES[vel], DTYPE_CODES[mhu],
+                                  _p(sc, C.c_int32), int(anchor), _p(xq, C.c_double),
+                                  _p(vq, C.c_double), _p(mq, C.c_double), _p(hq, C.c_double),
+                                  _p(uq, C.c_double))
+    assert rc == 0
     return ParticleSet(xq, vq, mq, hq, uq, ps.name + "_dq")
 
 

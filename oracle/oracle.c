@@ -9,8 +9,8 @@
  * neighbour indices, so the brute-force and cell-list modes produce
  * bit-identical results (the cell list only restricts candidates).
  *
- * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math: the
- * FP32 support-test replica relies on unfused float arithmetic).
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math, no
+ * contraction: every expression rounds as written).
  *
  * Readings where the paper is silent (listed in the design notes):
  *  - kernel: cubic-spline M4 with support radius H = gamma_k h (Sec. 2.1
@@ -23,6 +23,9 @@
  *  - viscosity: signal-velocity artificial viscosity, no limiter.
  *  - the self pair is in the density sums and out of the force sums.
  *  - support test is strict: r < H.
+ *  - a pair at zero separation with j != i (coincident stored positions)
+ *    has the zero vector as its direction: it counts, exerts no force and
+ *    its signal velocity is c_i + c_j.
  */
 #include "oracle.h"
 
@@ -380,7 +383,13 @@ int orc_force(int n, const double *x, const double *v, const double *m,
       for (int t = 0; t < l.n; ++t) {
         int j = l.idx[t];
         double r = sqrt(sep2(x, i, j, d));
-        double e[3] = {d[0] / r, d[1] / r, d[2] / r};
+        /* coincident positions (j != i, r = 0): the pair direction is taken
+         * as the zero vector, the limit of the pair terms as r -> 0
+         * averaged over directions; the pair counts, exerts no force and
+         * does no work, and its signal velocity is c_i + c_j */
+        double e[3] = {0.0, 0.0, 0.0};
+        if (r > 0.0)
+          for (int k = 0; k < 3; ++k) e[k] = d[k] / r;
         double fj = p->gradh ? f[j] : 1.0;
         double Aj = fj * P[j] / (rho[j] * rho[j]);
         double gi = orc_gradW(p->kernel, r, h[i], p->gamma_k);
@@ -670,102 +679,126 @@ double orc_roundtrip(double v, int dtype, int scale) {
   return (double)roundtrip32(v, dtype, scale);
 }
 
+/* Offsets of the stored positions from their anchor (Sec. 3.2's anchor
+ * and delta: a value is kept as a quantised difference from an anchor the
+ * reader reconstructs). The anchor of a particle in cell c is
+ *   anchor 0:      the cell corner c / n_c, per axis;
+ *   anchor 1 + b:  the centre of its sub-cell of side 1 / (n_c 2^b),
+ *                  (c 2^b + a + 1/2) / (n_c 2^b), with the sub-cell index
+ *                  a = floor(x_w n_c 2^b) - c 2^b clamped to [0, 2^b - 1]
+ *                  (b = 0: the cell centre; b <= 2),
+ * all in FP64 on the wrapped position x_w. off = x_w - anchor in FP64;
+ * code = a_x + 4 a_y + 16 a_z (0 for anchor 0 and 1). Either output may be
+ * NULL. */
+static int anchor_of(double xw, int c, int n_c, int anchor, double *o) {
+  if (anchor == 0) {
+    *o = (double)c / (double)n_c;
+    return 0;
+  }
+  int R = 1 << (anchor - 1);
+  double t = floor(xw * (double)(n_c * R));
+  int a = (t != t) ? 0 : (int)(t - (double)c * R);
+  if (a < 0) a = 0;
+  if (a > R - 1) a = R - 1;
+  *o = ((double)c * R + a + 0.5) / ((double)n_c * R);
+  return a;
+}
+
+int orc_pos_offsets(int n, const double *x, int n_c, int anchor, double *off, uint8_t *code) {
+  if (n < 0 || n_c < 1 || anchor < 0 || anchor > 3) return -1;
+  for (int i = 0; i < n; ++i) {
+    int cc = 0;
+    for (int k = 0; k < 3; ++k) {
+      double xw = wrap01(x[3 * i + k]), o;
+      int a = anchor_of(xw, cell_axis(xw, n_c), n_c, anchor, &o);
+      if (off) off[3 * i + k] = xw - o;
+      cc |= a << (2 * k);
+    }
+    if (code) code[i] = (uint8_t)cc;
+  }
+  return 0;
+}
+
 int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
                        const double *h, const double *u, int n_c, int pos_dt,
-                       int vel_dt, int mhu_dt, const int32_t *scales,
+                       int vel_dt, int mhu_dt, const int32_t *scales, int pos_anchor,
                        double *xq, double *vq, double *mq, double *hq, double *uq) {
-  int32_t *cell = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-  double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-  orc_bin(n, x, n_c, cell, NULL, NULL, off);
+  if (pos_anchor < 0 || pos_anchor > 3) return -1;
   int s_m = scales ? scales[0] : 0, s_h = scales ? scales[1] : 0, s_u = scales ? scales[2] : 0;
   for (int i = 0; i < n; ++i) {
-    int c3[3] = {cell[i] % n_c, (cell[i] / n_c) % n_c, cell[i] / (n_c * n_c)};
     for (int k = 0; k < 3; ++k) {
-      xq[3 * i + k] = (double)c3[k] / (double)n_c + orc_roundtrip(off[3 * i + k], pos_dt, 0);
+      double xw = wrap01(x[3 * i + k]), o;
+      anchor_of(xw, cell_axis(xw, n_c), n_c, pos_anchor, &o);
+      xq[3 * i + k] = o + orc_roundtrip(xw - o, pos_dt, 0);
       vq[3 * i + k] = orc_roundtrip(v[3 * i + k], vel_dt, 0);
     }
     mq[i] = orc_roundtrip(m[i], mhu_dt, s_m);
     hq[i] = orc_roundtrip(h[i], mhu_dt, s_h);
     uq[i] = orc_roundtrip(u[i], mhu_dt, s_u);
   }
-  free(cell);
-  free(off);
   return 0;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Neighbour counts with the support test taken in FP32.                     */
-/* A floating-point decision that produces an integer is taken in the        */
-/* kernel's precision on both sides. The FP32 test for particle i in cell    */
-/* c_i and j in cell c_i + delta (delta in {-1,0,1}^3, periodic):            */
-/*   s      = FP32(1 / n_c)                                                  */
-/*   xr_k   = off_j,k + delta_k s          (one FP32 add; delta s exact)     */
-/*   d_k    = off_i,k - xr_k               (FP32)                            */
-/*   r2     = fma(d_z, d_z, fma(d_y, d_y, d_x * d_x))                        */
-/*   H_i    = FP32(gamma_k) * h_i, H2_i = H_i * H_i (FP32)                   */
-/* density: r2 < H2_i (self included); force: j != i and r2 < max(H2_i,H2_j) */
-/* off and h are the stored values (pos_dtype, h_dtype) read back as FP32.   */
-/* sel (nsel entries, NULL: all) selects the i; outputs are per entry of sel. */
+/* Pairs near the support boundary. A neighbour count taken in another        */
+/* precision (or with positions rounded differently) can differ from the     */
+/* FP64 count of this oracle only through pairs whose separation lies within */
+/* that precision's rounding of the support radius. For each selected i:      */
+/*   near_d = #{j : |r_ij - H_i| < eps_rel H_i + eps_abs}                      */
+/*   near_f = #{j != i : |r_ij - H_i| < tol_i or |r_ij - H_j| < tol_j}         */
+/* with tol_k = eps_rel H_k + eps_abs; r_ij is the FP64 minimum-image         */
+/* separation (the same expression as in the density and force sums).        */
+/* Pairs beyond the 27 cells around i's cell are not candidates of a cell    */
+/* list and are not counted (mode 1); brute force (mode 0) counts all.       */
 /* ------------------------------------------------------------------------ */
-
-int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
-                int pos_dtype, int h_dtype, int h_scale, int mode,
-                const uint8_t *jmask, const int32_t *sel, int nsel, int32_t *nd,
-                int32_t *nf) {
-  if (n_c < 3) return -1;
+int orc_near_support(int n, const double *x, const double *h, double gamma_k, int mode,
+                     int n_c, const int32_t *sel, int nsel, double eps_rel, double eps_abs,
+                     int32_t *near_d, int32_t *near_f) {
   cellgrid g;
-  double *off = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
-  float *o32 = (float *)malloc(sizeof(float) * 3 * (size_t)(n > 0 ? n : 1));
-  float *H2 = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
-  grid_build(&g, n, x, n_c);
-  orc_bin(n, x, n_c, NULL, NULL, NULL, off);
-  float gk = (float)gamma_k;
-  for (int i = 0; i < n; ++i) {
-    for (int k = 0; k < 3; ++k) o32[3 * i + k] = roundtrip32(off[3 * i + k], pos_dtype, 0);
-    float hi = roundtrip32(h[i], h_dtype, h_scale);
-    float Hi = gk * hi;
-    H2[i] = Hi * Hi;
+  memset(&g, 0, sizeof g);
+  if (mode == 1) {
+    if (!grid_ok(n, h, gamma_k, n_c)) return -2;
+    grid_build(&g, n, x, n_c);
   }
-  float s = (float)(1.0 / (double)n_c);
   int cnt = sel ? nsel : n;
 #pragma omp parallel for schedule(dynamic, 64)
-  for (int s_ = 0; s_ < cnt; ++s_) {
-    int i = sel ? sel[s_] : s_;
-    int ci = g.cell[i];
-    int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
-    int cnt_d = 0, cnt_f = 0;
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          int cn = ((cx + dx + n_c) % n_c) +
-                   n_c * (((cy + dy + n_c) % n_c) + n_c * ((cz + dz + n_c) % n_c));
-          float sh[3] = {dx < 0 ? -s : (dx > 0 ? s : 0.0f),
-                         dy < 0 ? -s : (dy > 0 ? s : 0.0f),
-                         dz < 0 ? -s : (dz > 0 ? s : 0.0f)};
-          int lo = 0, hi = n;
-          if (mode == 1) { lo = g.start[cn]; hi = g.start[cn + 1]; }
-          for (int t = lo; t < hi; ++t) {
-            int j = (mode == 1) ? g.perm[t] : t;
-            if (mode == 0 && g.cell[j] != cn) continue;
-            if (jmask && !jmask[j]) continue;
-            float dd[3];
-            for (int k = 0; k < 3; ++k) {
-              float xr = o32[3 * j + k] + sh[k];
-              dd[k] = o32[3 * i + k] - xr;
-            }
-            float r2 = fmaf(dd[2], dd[2], fmaf(dd[1], dd[1], dd[0] * dd[0]));
-            if (r2 < H2[i]) cnt_d++;
-            if (j != i && (r2 < H2[i] || r2 < H2[j])) cnt_f++;
-          }
-        }
-    if (nd) nd[s_] = cnt_d;
-    if (nf) nf[s_] = cnt_f;
+  for (int s = 0; s < cnt; ++s) {
+    int i = sel ? sel[s] : s;
+    double Hi = gamma_k * h[i], ti = eps_rel * Hi + eps_abs, d[3];
+    int nd = 0, nf = 0;
+    int lo = 0, hi = n, C = mode == 1 ? 27 : 1;
+    for (int q = 0; q < C; ++q) {
+      if (mode == 1) {
+        int ci = g.cell[i];
+        int cx = ci % n_c, cy = (ci / n_c) % n_c, cz = ci / (n_c * n_c);
+        int cn = ((cx + q % 3 - 1 + n_c) % n_c) +
+                 n_c * (((cy + (q / 3) % 3 - 1 + n_c) % n_c) + n_c * ((cz + q / 9 - 1 + n_c) % n_c));
+        lo = g.start[cn];
+        hi = g.start[cn + 1];
+      }
+      for (int t = lo; t < hi; ++t) {
+        int j = mode == 1 ? g.perm[t] : t;
+        double r = sqrt(sep2(x, i, j, d));
+        double Hj = gamma_k * h[j], tj = eps_rel * Hj + eps_abs;
+        int near_i = fabs(r - Hi) < ti;
+        if (near_i) nd++;
+        if (j != i && (near_i || fabs(r - Hj) < tj)) nf++;
+      }
+    }
+    if (near_d) near_d[s] = nd;
+    if (near_f) near_f[s] = nf;
   }
-  grid_free(&g);
-  free(off);
-  free(o32);
-  free(H2);
+  if (mode == 1) grid_free(&g);
   return 0;
+}
+
+/* threads the following OpenMP parallel regions use (n >= 1) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 /* threads an OpenMP parallel region of the oracle uses */

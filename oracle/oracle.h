@@ -84,17 +84,18 @@ void orc_kick_drift(int n, double *x, double *v, double *u, const double *a,
 void orc_reduce(int n, const double *m, const double *v, const double *a,
                 const double *du, double *out);
 
-/* neighbour counts with the support test taken in FP32, as the GPU takes it */
 /* smoothing lengths solving h = eta (m / rho(h))^(1/3) per particle */
 int orc_smoothing_length(int n, const double *x, const double *m, const double *h0,
                          double eta, const orc_params *p, int mode, int n_c, double h_max,
                          double tol, int max_iter, const int32_t *sel, int nsel,
                          double *h_out, int32_t *iters);
 
-int orc_count32(int n, const double *x, const double *h, int n_c, double gamma_k,
-                int pos_dtype, int h_dtype, int h_scale, int mode,
-                const uint8_t *jmask, const int32_t *sel, int nsel, int32_t *nd,
-                int32_t *nf);
+/* per selected i, pairs whose FP64 separation lies within
+ * eps_rel H + eps_abs of a support radius: near_d over the density list
+ * (H_i), near_f over the force list (H_i or H_j, j != i) */
+int orc_near_support(int n, const double *x, const double *h, double gamma_k, int mode,
+                     int n_c, const int32_t *sel, int nsel, double eps_rel, double eps_abs,
+                     int32_t *near_d, int32_t *near_f);
 
 /* quantisers (RNE), FP32 -> {FP16, BF16} bits and back */
 uint16_t orc_f32_to_f16(float v);
@@ -107,15 +108,20 @@ void orc_dequant_array(int64_t n, const uint16_t *in, float *out, int dtype);
 /* FP64 value -> stored value -> FP64 (the value a kernel reads back) */
 double orc_roundtrip(double v, int dtype, int scale);
 
+/* position offsets from their anchor (0: cell corner; 1 + b: centre of the
+ * sub-cell of side 1/(n_c 2^b)) and the anchor sub-cell code per particle */
+int orc_pos_offsets(int n, const double *x, int n_c, int anchor, double *off, uint8_t *code);
+
 /* Dequantised copy of a particle set as stored in an SoA view:
- * positions become cell origin + stored offset, other fields round-trip. */
+ * positions become anchor + stored offset, other fields round-trip. */
 int orc_dequantise_set(int n, const double *x, const double *v, const double *m,
                        const double *h, const double *u, int n_c, int pos_dt,
-                       int vel_dt, int mhu_dt, const int32_t *scales,
+                       int vel_dt, int mhu_dt, const int32_t *scales, int pos_anchor,
                        double *xq, double *vq, double *mq, double *hq, double *uq);
 
-/* threads the OpenMP regions use */
+/* threads the OpenMP regions use, and setting them */
 int orc_num_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

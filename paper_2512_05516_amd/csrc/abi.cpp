@@ -119,6 +119,7 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   out.sub_start = c->sub_bits > 0 ? c->sub_start : c->cell_start;
   out.hmax = c->hmax;
   out.status = c->status;
+  out.tally = reinterpret_cast<unsigned long long*>(c->tally);
   return SPH_OK;
 }
 
@@ -144,9 +145,14 @@ sph_status check_prec(const sph_precision* p, Prec& out) {
   const int32_t sc[3] = {p->scale_m, p->scale_h, p->scale_u};
   for (int q = 0; q < 3; ++q)
     if (sc[q] < -64 || sc[q] > 64) return fail(SPH_E_INVALID, "precision scale %d out of range", sc[q]);
+  if (p->pos_anchor < SPH_ANCHOR_CORNER || p->pos_anchor > SPH_ANCHOR_SUB(2))
+    return fail(SPH_E_INVALID, "precision pos_anchor %d is not SPH_ANCHOR_CORNER or SPH_ANCHOR_SUB(0..2)",
+                p->pos_anchor);
+  if (p->reserved != 0) return fail(SPH_E_INVALID, "precision reserved must be 0");
   out.pos = p->pos;
   out.vel = p->vel;
   out.mhu = p->mhu;
+  out.anchor = p->pos_anchor;
   out.store_m = std::ldexp(1.0f, p->scale_m);
   out.store_h = std::ldexp(1.0f, p->scale_h);
   out.store_u = std::ldexp(1.0f, p->scale_u);
@@ -177,6 +183,13 @@ sph_status check_soa(const sph_soa* s, const int* fields, int nf, const char* wh
   if (!s) return fail(SPH_E_INVALID, "%s: soa is NULL", what);
   for (int q = 0; q < nf; ++q)
     if (!s->f[fields[q]]) return fail(SPH_E_INVALID, "%s: soa field %d is NULL", what, fields[q]);
+  return SPH_OK;
+}
+
+// Positions anchored at sub-cell centres of depth b >= 1 need the ANC codes
+sph_status check_anchor(const sph_soa* s, const Prec& p, const char* what) {
+  if (p.anchor >= SPH_ANCHOR_SUB(1) && !s->f[SPH_S_ANC])
+    return fail(SPH_E_INVALID, "%s: soa field ANC is NULL (pos_anchor %d needs it)", what, p.anchor);
   return SPH_OK;
 }
 
@@ -326,6 +339,7 @@ sph_status sph_convert(const void* aos, const sph_aos_layout* layout, const sph_
   SPH_TRY(check_layout(layout, view_aos_fields(view), L));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
+  if (view != SPH_VIEW_KICK) SPH_TRY(check_anchor(out, p, "sph_convert"));
   SPH_TRY(check_aos_ptr(aos, c.n));
   if ((is_trunc(p.pos) || is_trunc(p.vel) || is_trunc(p.mhu)) && L.stride > kMaxPackedStride)
     return fail(SPH_E_UNSUPPORTED,
@@ -374,6 +388,7 @@ sph_status sph_density(const sph_soa* soa, const sph_precision* prec, const sph_
   SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_density"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_anchor(soa, p, "sph_density"));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
   SPH_TRY(check_work(work, c, ti, w, use_w));
@@ -393,6 +408,7 @@ sph_status sph_force(const sph_soa* soa, const sph_precision* prec, const sph_ce
   SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_force"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_anchor(soa, p, "sph_force"));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
   SPH_TRY(check_work(work, c, ti, w, use_w));
@@ -418,6 +434,7 @@ sph_status sph_tasks_run(const sph_soa* soa, const sph_precision* prec, const sp
   if (n_force > 0) SPH_TRY(check_soa(soa, kForceIn, len(kForceIn), "sph_tasks_run"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
+  if (n_dens + n_force > 0) SPH_TRY(check_anchor(soa, p, "sph_tasks_run"));
   SPH_TRY(check_params(params, ph));
   const int ti = tile.ti ? tile.ti : 64, k = tile.k ? tile.k : 4;
   if (!task_tile_supported(ti, k))
@@ -454,6 +471,7 @@ sph_status sph_smoothing_length(const sph_soa* soa, const sph_precision* prec,
   SPH_TRY(check_soa(soa, kDensIn, len(kDensIn), "sph_smoothing_length"));
   SPH_TRY(check_cells(cells, true, c));
   SPH_TRY(check_prec(prec, p));
+  SPH_TRY(check_anchor(soa, p, "sph_smoothing_length"));
   SPH_TRY(check_params(params, ph));
   SPH_TRY(resolve_tile(tile, ti, k));
   SPH_TRY(check_work(work, c, ti, w, use_w));

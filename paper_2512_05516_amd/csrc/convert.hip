@@ -15,6 +15,7 @@ constexpr int kThreads = 256;
 
 struct SoaOut {
   void* off[3];
+  uint8_t* anc;
   void* vq[3];
   void* m;
   void* h;
@@ -43,10 +44,15 @@ __global__ __launch_bounds__(kThreads) void k_convert_direct(const char* __restr
   }
   const double u = need_u ? rec_load(rec, L.off[SPH_A_U], L.dt[SPH_A_U]) : 0.0;
   if (pair_view) {
-    int c3[3];
+    int c3[3], code = 0;
     cell_coords(cd.cell[k], cd.n_c, c3[0], c3[1], c3[2]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) store_q32(o.off[a], p.pos, k, cell_offset(xw[a], c3[a], cd.n_c), 1.0f);
+    for (int a = 0; a < 3; ++a) {
+      int sa;
+      store_q32(o.off[a], p.pos, k, anchor_offset(xw[a], c3[a], cd.n_c, p.anchor, sa), 1.0f);
+      code |= sa << (2 * a);
+    }
+    if (p.anchor >= SPH_ANCHOR_SUB(1)) o.anc[k] = (uint8_t)code;
     store_q(o.m, p.mhu, k, rec_load(rec, L.off[SPH_A_M], L.dt[SPH_A_M]), p.store_m);
     store_q(o.h, p.mhu, k, rec_load(rec, L.off[SPH_A_H], L.dt[SPH_A_H]), p.store_h);
     if (view != SPH_VIEW_FORCE) store_q(o.u, p.mhu, k, u, p.store_u);
@@ -205,11 +211,15 @@ __global__ __launch_bounds__(kThreads) void k_convert_staged(const char* __restr
     }
     const double u = need_u ? rec_load(rec, L.off[SPH_A_U], L.dt[SPH_A_U]) : 0.0;
     if (pair_view) {
-      int c3[3];
+      int c3[3], code = 0;
       cell_coords(cd.cell[k], cd.n_c, c3[0], c3[1], c3[2]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        put(kF_OFF + a, o.off[a], p.pos, k, cell_offset(xw[a], c3[a], cd.n_c));
+      for (int a = 0; a < 3; ++a) {
+        int sa;
+        put(kF_OFF + a, o.off[a], p.pos, k, anchor_offset(xw[a], c3[a], cd.n_c, p.anchor, sa));
+        code |= sa << (2 * a);
+      }
+      if (p.anchor >= SPH_ANCHOR_SUB(1)) o.anc[k] = (uint8_t)code;
       put(kF_M, o.m, p.mhu, k, (float)rec_load(rec, L.off[SPH_A_M], L.dt[SPH_A_M]) * p.store_m);
       put(kF_H, o.h, p.mhu, k, (float)rec_load(rec, L.off[SPH_A_H], L.dt[SPH_A_H]) * p.store_h);
       if (view != SPH_VIEW_FORCE) put(kF_U, o.u, p.mhu, k, (float)u * p.store_u);
@@ -316,6 +326,7 @@ hipError_t launch_convert(const void* aos, const AosLayout& L, const CellsDev& c
   o.h = out.f[SPH_S_H];
   o.u = out.f[SPH_S_U];
   o.uk = static_cast<float*>(out.f[SPH_S_UK]);
+  o.anc = static_cast<uint8_t*>(out.f[SPH_S_ANC]);
   if (L.stride <= kMaxStagedStride) {
     const size_t lds = (size_t)kTileSlots * ((L.stride >> 3) + 1) * 8;
     const int G = (c.n + kTileSlots - 1) / kTileSlots;

@@ -28,10 +28,10 @@ int esz(int dt) { return (dt == SPH_F32) ? 4 : 2; }
 
 struct Plan {
   size_t off_start, off_perm, off_cell, off_hmax;
-  size_t off_pos[3], off_vq[3], off_m, off_h, off_u, off_x[3], off_v[3], off_uk;
+  size_t off_pos[3], off_vq[3], off_m, off_h, off_u, off_x[3], off_v[3], off_uk, off_anc;
   size_t off_dens[4], off_acc[4];   // FORCE_IN: rho, f, P, c; KICK_IN: a[3], du
   size_t total;
-  bool pair, kick, vq, u, dens_in, acc_in;
+  bool pair, kick, vq, u, dens_in, acc_in, anc;
 };
 
 Plan plan(int n, int n_c, int view, const sph_precision& p) {
@@ -61,6 +61,8 @@ Plan plan(int n, int n_c, int view, const sph_precision& p) {
     pl.off_x[a] = pl.kick ? take((size_t)n * 8) : 0;
     pl.off_v[a] = pl.kick ? take((size_t)n * 4) : 0;
   }
+  pl.anc = pl.pair && p.pos_anchor >= SPH_ANCHOR_SUB(1);
+  pl.off_anc = pl.anc ? take((size_t)n) : 0;
   pl.off_m = pl.pair ? take((size_t)n * esz(p.mhu)) : 0;
   pl.off_h = pl.pair ? take((size_t)n * esz(p.mhu)) : 0;
   pl.off_u = pl.u ? take((size_t)n * esz(p.mhu)) : 0;
@@ -74,6 +76,22 @@ Plan plan(int n, int n_c, int view, const sph_precision& p) {
 }
 
 bool known_view(int v) { return v >= SPH_VIEW_DENSITY && v <= SPH_VIEW_KICK_IN; }
+
+// FP32 offset of a wrapped coordinate from its anchor (the definition of
+// sph_precision.pos_anchor; the same FP64 expression as the device convert,
+// so host and device gathers store identical values) and the sub-cell
+// index a along the axis
+float anchor_offset(double xw, int c, int n_c, int anchor, int& a) {
+  if (anchor == SPH_ANCHOR_CORNER) {
+    a = 0;
+    return (float)(xw - (double)c / (double)n_c);
+  }
+  const int R = 1 << (anchor - 1);
+  const double t = std::floor(xw * (double)(n_c * R));
+  a = (t == t) ? (int)std::fmin(std::fmax(t - (double)c * R, 0.0), (double)(R - 1)) : 0;
+  const double o = ((double)c * R + a + 0.5) / ((double)n_c * R);
+  return (float)(xw - o);
+}
 
 double rec_d(const char* rec, uint32_t off, int dt, int c = 0) {
   if (dt == SPH_F64) {
@@ -201,10 +219,14 @@ void gather_host(const char* aos, const sph_aos_layout& L, int n, int n_c, const
       int c = cell[k];
       int c3[3] = {c % n_c, (c / n_c) % n_c, c / (n_c * n_c)};
       if (pl.pair) {
+        int code = 0;
         for (int a = 0; a < 3; ++a) {
-          float off = (float)(xw[a] - (double)c3[a] / (double)n_c);
+          int sa;
+          float off = anchor_offset(xw[a], c3[a], n_c, prec.pos_anchor, sa);
           put(st + pl.off_pos[a], prec.pos, (size_t)k, (double)off, 1.0f);
+          code |= sa << (2 * a);
         }
+        if (pl.anc) reinterpret_cast<uint8_t*>(st + pl.off_anc)[k] = (uint8_t)code;
         put(st + pl.off_m, prec.mhu, (size_t)k, rec_d(rec, L.offset[SPH_A_M], L.dtype[SPH_A_M]), sm);
         put(st + pl.off_h, prec.mhu, (size_t)k, rec_d(rec, L.offset[SPH_A_H], L.dtype[SPH_A_H]), sh);
       }
@@ -253,6 +275,7 @@ std::vector<Cp> view_copies(const Plan& pl, const sph_soa& out, int n, const sph
       cps.push_back({out.f[SPH_S_V_X + a], pl.off_v[a], (size_t)n * 4});
     }
   }
+  if (pl.anc) cps.push_back({out.f[SPH_S_ANC], pl.off_anc, (size_t)n});
   if (pl.pair) {
     cps.push_back({out.f[SPH_S_M], pl.off_m, (size_t)n * esz(prec.mhu)});
     cps.push_back({out.f[SPH_S_H], pl.off_h, (size_t)n * esz(prec.mhu)});
@@ -278,6 +301,9 @@ sph_status check_gather(const char* fn, const void* aos_host, const sph_aos_layo
   if (!known_view(view)) return host_fail(SPH_E_INVALID, (f + ": unknown view").c_str());
   if (n < 0 || n_c < 3 || n_c > 1290) return host_fail(SPH_E_RANGE, (f + ": bad n or n_c").c_str());
   if (n > 0 && !aos_host) return host_fail(SPH_E_INVALID, (f + ": aos_host is NULL").c_str());
+  if (prec->pos_anchor < SPH_ANCHOR_CORNER || prec->pos_anchor > SPH_ANCHOR_SUB(2) ||
+      prec->reserved != 0)
+    return host_fail(SPH_E_INVALID, (f + ": bad precision pos_anchor or reserved").c_str());
   const int fmt[3] = {prec->pos, prec->vel, prec->mhu};
   for (int q : fmt) {
     if (q >= SPH_TRUNC + 9 && q <= SPH_TRUNC + 32)

@@ -16,20 +16,20 @@ hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, 
                           int ti, int k, const WorkDev* w, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   if (p.pos == DT_F32 && p.vel == DT_F32 && p.mhu == DT_F32)
-    return run_density_dens_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p), c, ph, ti, k, w, s);
+    return run_density_dens_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p, c.n_c), c, ph, ti, k, w, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
-    return run_density_dens_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p), c, ph, ti, k, w, s);
-  return run_density_dens_gen(make_soa<-1, -1, -1>(soa, p), c, ph, ti, k, w, s);
+    return run_density_dens_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  return run_density_dens_gen(make_soa<-1, -1, -1>(soa, p, c.n_c), c, ph, ti, k, w, s);
 }
 
 hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
                         int ti, int k, const WorkDev* w, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   if (p.pos == DT_F32 && p.vel == DT_F32 && p.mhu == DT_F32)
-    return run_force_force_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p), c, ph, ti, k, w, s);
+    return run_force_force_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p, c.n_c), c, ph, ti, k, w, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
-    return run_force_force_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p), c, ph, ti, k, w, s);
-  return run_force_force_gen(make_soa<-1, -1, -1>(soa, p), c, ph, ti, k, w, s);
+    return run_force_force_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  return run_force_force_gen(make_soa<-1, -1, -1>(soa, p, c.n_c), c, ph, ti, k, w, s);
 }
 
 hipError_t launch_density_aos(void* aos, const AosLayout& L, const CellsDev& c, const Phys& ph,
@@ -59,10 +59,10 @@ hipError_t launch_tasks(const sph_soa& soa, const Prec& p, const CellsDev& c, co
   const TaskItems d{tasks, n_tasks, out_off, it, n_dens, out, n_out};
   const TaskItems f{tasks, n_tasks, out_off, it + n_dens, n_force, out, n_out};
   if (p.pos == DT_F32 && p.vel == DT_F32 && p.mhu == DT_F32)
-    return run_tasks_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p), c, ph, ti, k, d, f, s);
+    return run_tasks_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p, c.n_c), c, ph, ti, k, d, f, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
-    return run_tasks_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p), c, ph, ti, k, d, f, s);
-  return run_tasks_gen(make_soa<-1, -1, -1>(soa, p), c, ph, ti, k, d, f, s);
+    return run_tasks_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, d, f, s);
+  return run_tasks_gen(make_soa<-1, -1, -1>(soa, p, c.n_c), c, ph, ti, k, d, f, s);
 }
 
 }  // namespace sph

@@ -24,6 +24,8 @@
 // AoS records) are the only difference between the SoA kernels and the
 // plain-AoS kernels.
 #pragma once
+#include <cmath>
+
 #include "sph_device.h"
 
 namespace sph {
@@ -50,6 +52,9 @@ __device__ __forceinline__ float load_fmt(const void* p, int rt, int64_t k, floa
 template <int PT, int VT, int MT>
 struct SoaSrc {
   const void* off[3];
+  const uint8_t* anc;     // anchor sub-cell codes (anchor >= SPH_ANCHOR_SUB(1))
+  float anc_step;         // sub-cell side s 2^-b of the anchors
+  int anchor;             // SPH_ANCHOR_CORNER or SPH_ANCHOR_SUB(b)
   const void* vq[3];
   const void* m;
   const void* h;
@@ -62,6 +67,7 @@ struct SoaSrc {
   float *o_ax, *o_ay, *o_az, *o_du, *o_vsig;
   int32_t* o_nforce;
 
+  // position relative to the cell corner: the stored offset plus its anchor
   __device__ __forceinline__ void pos(int k, int cell, int n_c, float& x, float& y,
                                       float& z) const {
     (void)cell;
@@ -69,6 +75,12 @@ struct SoaSrc {
     x = load_fmt<PT>(off[0], pos_dt, k, 1.0f);
     y = load_fmt<PT>(off[1], pos_dt, k, 1.0f);
     z = load_fmt<PT>(off[2], pos_dt, k, 1.0f);
+    if (anchor != SPH_ANCHOR_CORNER) {          // uniform over the launch
+      const uint32_t c = anchor >= SPH_ANCHOR_SUB(1) ? (uint32_t)anc[k] : 0u;
+      x = __builtin_fmaf((float)(c & 3u) + 0.5f, anc_step, x);
+      y = __builtin_fmaf((float)((c >> 2) & 3u) + 0.5f, anc_step, y);
+      z = __builtin_fmaf((float)((c >> 4) & 3u) + 0.5f, anc_step, z);
+    }
   }
   __device__ __forceinline__ void vel(int k, float& x, float& y, float& z) const {
     x = load_fmt<VT>(vq[0], vel_dt, k, 1.0f);
@@ -787,8 +799,10 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
 
     float rho = 0.f, wsum = 0.f, dh = 0.f;
     int nn = 0;
+    int staged = 0, gathered = 0;     // uniform: work counters of the chunk
 
     auto pair_phase = [&](int nj) {
+      staged += nj;
       // pad [nj, roundup(nj, kPad)) with entries no particle accepts
       const int njp = (nj + kPad - 1) / kPad * kPad;
       if (tid < njp - nj) cand[nj + tid] = make_float4(0.f, 0.f, 0.f, 1e30f);
@@ -824,6 +838,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
         [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
+          gathered += total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
             float4 c[kRounds];
             int qq[kRounds];
@@ -869,6 +884,10 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
         });
     pair_phase(nj);
 
+    if (cd.tally && tid == 0) {
+      atomicAdd(cd.tally, (unsigned long long)(c1 - c0) * (unsigned long long)staged);
+      atomicAdd(cd.tally + 1, (unsigned long long)gathered);
+    }
     rho = group_sum<K>(rho);
     wsum = group_sum<K>(wsum);
     dh = group_sum<K>(dh);
@@ -963,6 +982,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
 
     float ax = 0.f, ay = 0.f, az = 0.f, du = 0.f, vsig = 0.f;
     int nf = 0;
+    int staged = 0, gathered = 0;     // uniform: work counters of the chunk
 
     // force-only fields of staged candidates [from, to), loaded cooperatively
     auto fill = [&](int from, int to) {
@@ -999,6 +1019,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
     };
 
     auto pair_phase = [&](int nj) {
+      staged += nj;
       const int njp = (nj + kPad - 1) / kPad * kPad;
       if (tid < njp - nj) {
         cp[nj + tid] = make_float4(0.f, 0.f, 0.f, 1e30f);
@@ -1059,6 +1080,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
         [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
         [&](const RangeTab<NT>& tb) {
           const int total = tb.total;
+          gathered += total;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
             float4 c[kRounds];
             int qq[kRounds], jj[kRounds];
@@ -1112,6 +1134,10 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
         });
     pair_phase(nj);
 
+    if (cd.tally && tid == 0) {
+      atomicAdd(cd.tally, (unsigned long long)(c1 - c0) * (unsigned long long)staged);
+      atomicAdd(cd.tally + 1, (unsigned long long)gathered);
+    }
     ax = group_sum<K>(ax);
     ay = group_sum<K>(ay);
     az = group_sum<K>(az);
@@ -1130,12 +1156,18 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
 }
 
 template <int PT, int VT, int MT>
-SoaSrc<PT, VT, MT> make_soa(const sph_soa& s, const Prec& p) {
+SoaSrc<PT, VT, MT> make_soa(const sph_soa& s, const Prec& p, int n_c) {
   SoaSrc<PT, VT, MT> r;
   for (int k = 0; k < 3; ++k) {
     r.off[k] = s.f[SPH_S_OFF_X + k];
     r.vq[k] = s.f[SPH_S_VQ_X + k];
   }
+  r.anchor = p.anchor;
+  r.anc = static_cast<const uint8_t*>(s.f[SPH_S_ANC]);
+  // s 2^-b, exact: the kernels' cell side scaled by a power of two
+  r.anc_step = p.anchor == SPH_ANCHOR_CORNER
+                   ? 0.0f
+                   : std::ldexp((float)(1.0 / (double)n_c), -(p.anchor - SPH_ANCHOR_SUB(0)));
   r.m = s.f[SPH_S_M];
   r.h = s.f[SPH_S_H];
   r.u = s.f[SPH_S_U];

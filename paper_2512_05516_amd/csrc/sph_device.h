@@ -143,6 +143,23 @@ __device__ __forceinline__ float cell_offset(double xw, int c_axis, int n_c) {
   return (float)(xw - (double)c_axis / (double)n_c);
 }
 
+// FP32 offset of a wrapped coordinate from its anchor, the FP64 difference
+// rounded once: SPH_ANCHOR_CORNER, the cell corner c / n_c (a = 0);
+// SPH_ANCHOR_SUB(b), the centre (c 2^b + a + 1/2) / (n_c 2^b) of its
+// sub-cell a = floor(xw n_c 2^b) - c 2^b, clamped to [0, 2^b - 1].
+__device__ __forceinline__ float anchor_offset(double xw, int c_axis, int n_c, int anchor,
+                                               int& a) {
+  if (anchor == SPH_ANCHOR_CORNER) {
+    a = 0;
+    return cell_offset(xw, c_axis, n_c);
+  }
+  const int R = 1 << (anchor - 1);
+  const double t = floor(xw * (double)(n_c * R));
+  a = (t == t) ? (int)fmin(fmax(t - (double)c_axis * R, 0.0), (double)(R - 1)) : 0;
+  const double o = ((double)c_axis * R + a + 0.5) / ((double)n_c * R);
+  return (float)(xw - o);
+}
+
 // ---------------------------------------------------------------------------
 // FP32 support test. With xr = off_j + shift (one FP32 add, shift in
 // {-s, 0, s}) and d = off_i - xr, the squared distance is

@@ -35,6 +35,7 @@ struct AosLayout {
 // Precision as passed to kernels: formats and exact power-of-two factors
 struct Prec {
   int pos, vel, mhu;
+  int anchor;                        // SPH_ANCHOR_CORNER or SPH_ANCHOR_SUB(b)
   float store_m, store_h, store_u;   // 2^scale (applied before storing)
   float load_m, load_h, load_u;      // 2^-scale (applied after loading)
 };
@@ -54,6 +55,7 @@ struct CellsDev {
   const int32_t* sub_start;
   const float* hmax;
   int32_t* status;
+  unsigned long long* tally;   // [0] candidate tests, [1] gathered (may be null)
 };
 
 // Work list of the pair kernels (device buffer layout): 8 queue counters,

@@ -208,8 +208,9 @@ def medium_set(seed: int = 2, order: str = "blocked") -> ParticleSet:
 
 
 def clustered_k_set(seed: int = 3) -> ParticleSet:
-    """4,194,304 particles, 37 % of them in 8 periodic Gaussian blobs
-    (sigma 0.03) over a uniform background. With cells as small as the
-    largest support radius allows (61 per axis) the occupancy spans 1 to
-    about 1,970 particles per cell."""
-    return clustered_set(1 << 22, seed, f_blob=0.37)
+    """4,194,304 particles, 19 % of them in 8 periodic Gaussian blobs
+    (sigma 0.03) over a uniform background. With h from the density
+    iteration and cells as small as the largest support radius allows
+    (48 per axis) the occupancy spans about 10 to 2,000 particles per cell
+    (median 30); the blob fraction is chosen for that upper end."""
+    return clustered_set(1 << 22, seed, f_blob=0.19)

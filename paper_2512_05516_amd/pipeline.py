@@ -15,7 +15,7 @@ from . import sphmi
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
                  prm=None, stream=None, sub_bits: int = 0, sched=None,
-                 til_force=None, split=None):
+                 til_force=None, split=None, tally=False):
         import torch
         self.torch = torch
         self.n = int(aos_np.shape[0])
@@ -29,7 +29,7 @@ class Pipeline:
         self.til = til or sphmi.tile()
         self.til_force = til_force or self.til
         self.stream = stream
-        self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits)
+        self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits, tally=tally)
         # sched: None (one workgroup per cell) or a work-list schedule, one
         # for both loops or a (density, force) pair
         sd, sf = sched if isinstance(sched, (tuple, list)) else (sched, sched)
@@ -211,3 +211,27 @@ class Pipeline:
     def status(self) -> int:
         self.torch.cuda.synchronize()
         return int(self.cells.status.item())
+
+
+def settle_h(rec: np.ndarray, tol=1e-4, max_iter=30, room=1.6, prm=None, stream=None):
+    """Smoothing lengths from the density iteration on the GPU
+    (sph_smoothing_length) for AoS records whose h is the start value: the
+    records are binned in a cell list `room` times roomier than the largest
+    start support radius (so h can grow), iterated, and read back. Returns
+    (records with the new h, the cells per axis of the new h, i.e.
+    floor(1 / max H), and a dict with the pass count, the particles not
+    converged and the start cell count)."""
+    import torch
+    prm = prm or sphmi.params()
+    gk = prm.gamma_k
+    n_c0 = int(np.floor(1.0 / (room * gk * float(rec["h"].max()))))
+    p0 = Pipeline(rec, n_c0, sched="grid", til=sphmi.tile(32, 2), sub_bits=2, prm=prm,
+                  stream=stream)
+    p0.bin()
+    p0.convert("full")
+    passes, left = p0.smoothing_length(tol=tol, max_iter=max_iter)
+    out = p0.records()
+    del p0
+    torch.cuda.empty_cache()
+    n_c = int(np.floor(1.0 / (gk * float(out["h"].max()))))
+    return out, n_c, {"passes": passes, "not_converged": left, "n_c_during": n_c0}

@@ -33,7 +33,7 @@ A = {name: i for i, name in enumerate(A_FIELDS)}
 S_FIELDS = ["OFF_X", "OFF_Y", "OFF_Z", "VQ_X", "VQ_Y", "VQ_Z", "M", "H", "U",
             "X_X", "X_Y", "X_Z", "V_X", "V_Y", "V_Z", "UK",
             "RHO", "WCOUNT", "RHO_DH", "F", "P", "C", "NNGB",
-            "A_X", "A_Y", "A_Z", "DU", "VSIG", "NFORCE"]
+            "A_X", "A_Y", "A_Z", "DU", "VSIG", "NFORCE", "ANC"]
 S = {name: i for i, name in enumerate(S_FIELDS)}
 
 VIEW_DENSITY, VIEW_FORCE, VIEW_KICK, VIEW_FULL = 0, 1, 2, 3
@@ -57,7 +57,7 @@ class Cells(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("sub_bits", C.c_int32),
                 ("reserved", C.c_int32), ("cell_start", C.c_void_p), ("perm", C.c_void_p),
                 ("cell", C.c_void_p), ("sub_start", C.c_void_p), ("hmax", C.c_void_p),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("tally", C.c_void_p)]
 
 
 class Work(C.Structure):
@@ -69,9 +69,18 @@ class Soa(C.Structure):
     _fields_ = [("f", C.c_void_p * len(S_FIELDS))]
 
 
+ANCHOR_CORNER = 0
+
+
+def ANCHOR_SUB(b: int) -> int:
+    """Position anchor at the centre of the sub-cell of side 1/(n_c 2^b)."""
+    return 1 + int(b)
+
+
 class Precision(C.Structure):
     _fields_ = [("pos", C.c_int32), ("vel", C.c_int32), ("mhu", C.c_int32),
-                ("scale_m", C.c_int32), ("scale_h", C.c_int32), ("scale_u", C.c_int32)]
+                ("scale_m", C.c_int32), ("scale_h", C.c_int32), ("scale_u", C.c_int32),
+                ("pos_anchor", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -222,8 +231,9 @@ def layout_from_dtype(dt: np.dtype) -> AosLayout:
     return lay
 
 
-def precision(pos="f32", vel="f32", mhu="f32", scale_m=0, scale_h=0, scale_u=0) -> Precision:
-    return Precision(DT[pos], DT[vel], DT[mhu], scale_m, scale_h, scale_u)
+def precision(pos="f32", vel="f32", mhu="f32", scale_m=0, scale_h=0, scale_u=0,
+              anchor=ANCHOR_CORNER) -> Precision:
+    return Precision(DT[pos], DT[vel], DT[mhu], scale_m, scale_h, scale_u, int(anchor), 0)
 
 
 def params(gamma_k=None, gamma=5.0 / 3.0, alpha=0.8, beta=3.0, gradh=True,
@@ -253,9 +263,10 @@ _TORCH_DT = {F32: "float32", F16: "float16", BF16: "bfloat16"}
 
 class DeviceCells:
     """Cell list arrays on the device: cell_start[C+1], perm[n], cell[n],
-    sub_start[C 8^sub_bits + 1] (sub_bits > 0), hmax[C], status[1]."""
+    sub_start[C 8^sub_bits + 1] (sub_bits > 0), hmax[C], status[1], and
+    with tally=True the pair loops' work counters tally[2] (int64)."""
 
-    def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0):
+    def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0, tally=False):
         import torch
         self.n, self.n_c, self.sub_bits = int(n), int(n_c), int(sub_bits)
         C_ = self.n_c ** 3
@@ -266,10 +277,12 @@ class DeviceCells:
                           if self.sub_bits else None)
         self.hmax = torch.zeros(C_, dtype=torch.float32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
+        self.tally = torch.zeros(2, dtype=torch.int64, device=device) if tally else None
         self._s = Cells(self.n, self.n_c, self.sub_bits, 0, self.cell_start.data_ptr(),
                         self.perm.data_ptr(), self.cell.data_ptr(),
                         self.sub_start.data_ptr() if self.sub_start is not None else None,
-                        self.hmax.data_ptr(), self.status.data_ptr())
+                        self.hmax.data_ptr(), self.status.data_ptr(),
+                        self.tally.data_ptr() if tally else None)
 
     @property
     def struct(self) -> Cells:
@@ -306,23 +319,9 @@ def storage_bytes(n: int, dtype: int) -> int:
     return out.value
 
 
-def unpack_trunc(words, T: int, n: int) -> np.ndarray:
-    """Host-side reading of n truncated codes of T bits from a packed field
-    (value k at bits [kT, kT + T) of little-endian 32-bit words), widened to
-    FP32 as the kernels read them."""
-    w = np.asarray(words).view(np.uint32).astype(np.uint64)
-    b = np.arange(n, dtype=np.uint64) * np.uint64(T)
-    i = (b >> np.uint64(5)).astype(np.int64)
-    v = w[i] | (w[i + 1] << np.uint64(32))
-    code = (v >> (b & np.uint64(31))) & np.uint64((1 << T) - 1)
-    if T > 16:
-        return (code << np.uint64(32 - T)).astype(np.uint32).view(np.float32)
-    return (code << np.uint64(16 - T)).astype(np.uint16).view(np.float16).astype(np.float32)
-
-
 class DeviceSoa:
     """SoA arrays (sorted-slot order) for the given storage precision
-    (truncated formats: packed 32-bit words, see unpack_trunc)."""
+    (truncated formats: packed 32-bit words, value k at bits [kT, kT + T))."""
 
     def __init__(self, n: int, prec: Precision, device="cuda", fields=None):
         import torch
@@ -343,6 +342,7 @@ class DeviceSoa:
             spec[k] = torch.float32
         spec["NNGB"] = torch.int32
         spec["NFORCE"] = torch.int32
+        spec["ANC"] = torch.uint8
         want = fields if fields is not None else S_FIELDS
         code = {}
         for a in ("X", "Y", "Z"):

@@ -47,7 +47,7 @@ def signature(pipe: Pipeline) -> dict:
         "occ_max": int(occ.max()) if occ.size else 0,
         "occ_p50": float(np.median(occ)) if occ.size else 0.0,
         "occ_p99": float(np.percentile(occ, 99)) if occ.size else 0.0,
-        "formats": [p.pos, p.vel, p.mhu, p.scale_m, p.scale_h, p.scale_u],
+        "formats": [p.pos, p.vel, p.mhu, p.scale_m, p.scale_h, p.scale_u, p.pos_anchor],
     }
 
 

@@ -10,6 +10,8 @@ import pytest
 
 from paper_2512_05516_amd import inputs
 
+from helpers import unpack_trunc
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -39,10 +41,54 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 8
+    assert sph.abi_version() == 9
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
+
+
+def test_position_anchor_validation(sph):
+    """pos_anchor must be SPH_ANCHOR_CORNER or SPH_ANCHOR_SUB(0..2) and the
+    reserved word 0; anchors at sub-cell centres of depth b >= 1 need the
+    ANC codes wherever the offsets are written or read."""
+    L = sph.lib()
+    cells = _fake_cells(sph)
+    lay = sph.layout_from_dtype(inputs.AOS_F32)
+    soa = sph.Soa()
+    for i in range(len(sph.S_FIELDS)):
+        soa.f[i] = 0x4000 + 256 * i
+    no_anc = sph.Soa()
+    for i in range(len(sph.S_FIELDS)):
+        no_anc.f[i] = 0x4000 + 256 * i
+    no_anc.f[sph.S["ANC"]] = None
+    assert sph.ANCHOR_SUB(2) == 3 and sph.S["ANC"] == len(sph.S_FIELDS) - 1
+    for bad in (sph.precision("f16", anchor=4), sph.precision("f16", anchor=-1),
+                sph.Precision(sph.F16, sph.F32, sph.F32, 0, 0, 0, 0, 1)):
+        assert L.sph_density(C.byref(soa), C.byref(bad), C.byref(cells), C.byref(sph.params()),
+                             sph.Tile(0, 0), None, None) == sph.SPH_E_INVALID
+    for anchor in (sph.ANCHOR_SUB(1), sph.ANCHOR_SUB(2)):
+        p = sph.precision("f16", anchor=anchor)
+        for fn in (L.sph_density, L.sph_force):
+            assert fn(C.byref(no_anc), C.byref(p), C.byref(cells), C.byref(sph.params()),
+                      sph.Tile(0, 0), None, None) == sph.SPH_E_INVALID
+            assert "ANC" in sph.last_error()
+        assert L.sph_convert(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), 3, C.byref(p),
+                             C.byref(no_anc), None) == sph.SPH_E_INVALID
+        # the kick view holds no offsets: no codes needed
+        assert L.sph_convert(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, 0)), 2,
+                             C.byref(p), C.byref(no_anc), None) == sph.SPH_OK
+        buf = np.zeros(1 << 16, np.uint8)
+        rec = np.zeros(16, dtype=inputs.AOS_F32)
+        assert L.sph_convert_host(C.c_void_p(rec.ctypes.data), C.byref(lay),
+                                  C.byref(_fake_cells(sph)), 3, C.byref(p), C.byref(no_anc),
+                                  C.c_void_p(buf.ctypes.data), buf.size, 1,
+                                  None) == sph.SPH_E_INVALID
+    # the cell centre (b = 0) has no codes to store
+    p = sph.precision("f16", anchor=sph.ANCHOR_SUB(0))
+    assert sph.host_staging_size(1000, 4, "density", p) == \
+        sph.host_staging_size(1000, 4, "density", sph.precision("f16"))
+    assert sph.host_staging_size(1000, 4, "density", sph.precision("f16", anchor=3)) >= \
+        sph.host_staging_size(1000, 4, "density", p) + 1000
 
 
 def test_workspace_size_validation(sph):
@@ -263,7 +309,7 @@ def test_truncated_storage_host_side(sph):
             for b in range(T):
                 bits[k * T + b] = (int(c) >> b) & 1
         words = np.packbits(bits.reshape(-1, 8)[:, ::-1]).view(np.uint32)
-        got = sph.unpack_trunc(words, T, n)
+        got = unpack_trunc(words, T, n)
         want = ((codes << np.uint64(32 - T)).astype(np.uint32).view(np.float32) if T > 16 else
                 (codes << np.uint64(16 - T)).astype(np.uint16).view(np.float16).astype(np.float32))
         assert np.array_equal(got.view(np.uint32), np.asarray(want, np.float32).view(np.uint32)), T

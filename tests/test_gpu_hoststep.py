@@ -9,7 +9,7 @@ import pytest
 
 from paper_2512_05516_amd import inputs
 
-from helpers import max_rel, oracle_step, rel_rmse
+from helpers import assert_counts, max_rel, oracle_step, rel_rmse
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,8 @@ def test_streaming_equals_inplace(sph, orc, store):
     n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
     rec = inputs.pack_aos(ps, "f32")
     prec = (sph.precision() if store == "fp32" else
-            sph.precision("f16", "bf16", "f16", scale_m=14, scale_h=5, scale_u=0))
+            sph.precision("f16", "bf16", "f16", scale_m=14, scale_h=5, scale_u=0,
+                          anchor=sph.ANCHOR_SUB(2)))
     til = sph.tile(32, 2)
     r_in, _ = _step(rec, n_c, "inplace", prec=prec, til=til, sched="grid")
     r_st, hs = _step(rec, n_c, "streaming", prec=prec, til=til, sched="grid", nthreads=5)
@@ -62,8 +63,8 @@ def test_streaming_equals_inplace(sph, orc, store):
     if store == "fp32":
         ref = inputs.unpack_aos(rec)
         d, f = oracle_step(orc, ref, n_c)
-        nd, nf = orc.count32(ref, n_c)
-        assert np.array_equal(r_st["nngb"], nd) and np.array_equal(r_st["nforce"], nf)
+        assert_counts(orc, r_st["nngb"], r_st["nforce"], d["nngb"], f["nforce"], ref, n_c,
+                      tag="streaming")
         assert max_rel(r_st["rho"].astype(np.float64), d["rho"]) < 1e-5
         assert rel_rmse(r_st["a"].astype(np.float64), f["a"]) < 1e-5
         assert rel_rmse(r_st["du"].astype(np.float64), f["du"]) < 1e-5
@@ -75,12 +76,20 @@ def test_streaming_equals_inplace(sph, orc, store):
 
 def test_aos_baseline_equals_inplace(sph, orc):
     """The plain-AoS kernels and the FP32 SoA kernels give the same records
-    (per-cell launches, default tile)."""
+    (per-cell launches, default tile), and both match the oracle: counts
+    against FP64 brute force, density and force at the FP32 bar."""
     ps = inputs.small_set(12)
     rec = inputs.pack_aos(ps, "f32")
     r_aos, _ = _step(rec, 4, "aos")
     r_in, _ = _step(rec, 4, "inplace")
     _same(r_aos, r_in, "aos")
+    ref = inputs.unpack_aos(rec)
+    d, f = oracle_step(orc, ref, 4)
+    assert_counts(orc, r_aos["nngb"], r_aos["nforce"], d["nngb"], f["nforce"], ref, 4,
+                  min_clear=0.98, tag="aos")
+    assert max_rel(r_aos["rho"].astype(np.float64), d["rho"]) < 1e-5
+    assert rel_rmse(r_aos["a"].astype(np.float64), f["a"]) < 1e-5
+    assert rel_rmse(r_aos["du"].astype(np.float64), f["du"]) < 1e-5
 
 
 def test_streaming_edge_cases(sph, orc):

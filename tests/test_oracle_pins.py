@@ -181,9 +181,10 @@ def test_brute_equals_cells(orc, small):
     fc = orc.force(small, dc, mode="cells", n_c=4)
     for k in fb:
         assert np.array_equal(fb[k], fc[k]), k
-    n1 = orc.count32(small, 4, mode="brute")
-    n2 = orc.count32(small, 4, mode="cells")
+    n1 = orc.near_support(small, 4, mode="brute", eps_rel=1e-3)
+    n2 = orc.near_support(small, 4, mode="cells", eps_rel=1e-3)
     assert np.array_equal(n1[0], n2[0]) and np.array_equal(n1[1], n2[1])
+    assert n1[1].sum() > 0
 
 
 def test_cell_list_rejects_small_cells(orc, small):
@@ -370,17 +371,66 @@ def test_binning_definition(orc):
     assert np.array_equal(off, xw - c3 / n_c)
 
 
-def test_count32_matches_fp64_counts_away_from_the_boundary(orc, small):
-    # FP32 decisions agree with the FP64 ones except for pairs within FP32
-    # rounding of the support radius; on the perfect lattice there are none.
+def test_near_support_closed_forms(orc):
+    """Pairs near a support radius: none on the perfect lattice (its shells
+    lie at sqrt(5) and sqrt(6) spacings, the support at 2.254); for two
+    particles at separation H (1 + t) the pair is near exactly when
+    |t| H < eps_rel H + eps_abs, in both lists; in the force list a pair is
+    near when it is near either particle's support."""
     lat = inputs.lattice_set(16, 0, perfect=True, order="shuffled")
-    nd, nf = orc.count32(lat, 4)
-    assert np.all(nd == 57) and np.all(nf == 56)
-    nd, nf = orc.count32(small, 4)
-    d = orc.density(small, n_c=4)
-    f = orc.force(small, d, n_c=4)
-    assert np.abs(nd - d["nngb"]).max() <= 1 and (nd != d["nngb"]).mean() < 0.01
-    assert np.abs(nf - f["nforce"]).max() <= 2
+    nd, nf = orc.near_support(lat, 4)
+    assert not nd.any() and not nf.any()
+    h = 0.05
+    H = orc.GAMMA_K * h
+    for t, want in ((1e-7, 1), (-4e-6, 1), (3e-5, 0), (-2e-3, 0)):
+        x = np.array([[0.5, 0.5, 0.5], [0.5 + H * (1 + t), 0.5, 0.5]])
+        ps = inputs.ParticleSet(x, np.zeros((2, 3)), np.ones(2), np.full(2, h), np.ones(2))
+        nd, nf = orc.near_support(ps, 3, mode="brute", eps_rel=1e-5, eps_abs=0.0)
+        assert nd.tolist() == [want, want] and nf.tolist() == [want, want], t
+    # H_j > H_i: the pair sits at H_j only, so it is near in the force list of
+    # both particles and in the density list of j alone
+    x = np.array([[0.5, 0.5, 0.5], [0.5 + 2 * H, 0.5, 0.5]])
+    ps = inputs.ParticleSet(x, np.zeros((2, 3)), np.ones(2), np.array([h, 2 * h]), np.ones(2))
+    nd, nf = orc.near_support(ps, 3, mode="brute", eps_rel=1e-5, eps_abs=0.0)
+    assert nd.tolist() == [0, 1] and nf.tolist() == [1, 1]
+
+
+def test_fp32_counts_equal_fp64_counts_away_from_the_boundary(orc):
+    """A neighbour count whose support test is taken in FP32 (here numpy's
+    plain float32 arithmetic on the FP32 cell offsets, an order unrelated to
+    the kernels') equals the FP64 brute-force count for every particle with
+    no pair near a support radius, and differs by at most the number of
+    such pairs for the others; those are a small fraction."""
+    for ps, n_c in ((inputs.small_set(1), 4), (inputs.clustered_set(4000, 7, f_blob=0.4,
+                                                                     sigma=0.05), None)):
+        ps = ps.rounded_to("f32")
+        if n_c is None:
+            n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+        d = orc.density(ps, mode="brute")
+        f = orc.force(ps, d, mode="brute")
+        near_d, near_f = orc.near_support(ps, n_c)
+        cell, _, _, off = orc.bin_cells(ps.x, n_c)
+        c3 = np.stack([cell % n_c, (cell // n_c) % n_c, cell // (n_c * n_c)], 1)
+        o32 = off.astype(np.float32)
+        s = np.float32(1.0 / n_c)
+        H32 = np.float32(orc.GAMMA_K) * ps.h.astype(np.float32)
+        nd = np.zeros(ps.n, np.int64)
+        nf = np.zeros(ps.n, np.int64)
+        for i in range(ps.n):
+            dc = c3 - c3[i]
+            dc -= n_c * np.rint(dc / n_c).astype(np.int64)       # periodic cell separation
+            ok = np.all(np.abs(dc) <= 1, axis=1)
+            rel = (o32[ok] + dc[ok].astype(np.float32) * s) - o32[i]
+            r2 = (rel * rel).sum(1, dtype=np.float32)
+            hi2, hj2 = H32[i] * H32[i], H32[ok] * H32[ok]
+            nd[i] = np.count_nonzero(r2 < hi2)
+            nf[i] = np.count_nonzero((r2 < np.maximum(hi2, hj2)) & (np.nonzero(ok)[0] != i))
+        clear_d, clear_f = near_d == 0, near_f == 0
+        assert np.array_equal(nd[clear_d], d["nngb"][clear_d])
+        assert np.array_equal(nf[clear_f], f["nforce"][clear_f])
+        assert np.all(np.abs(nd - d["nngb"]) <= near_d)
+        assert np.all(np.abs(nf - f["nforce"]) <= near_f)
+        assert clear_d.mean() > 0.99 and clear_f.mean() > 0.98
 
 
 # --------------------------------------------------------------------------
@@ -521,7 +571,6 @@ def test_cell_pair_partials_partition_the_full_sums(orc):
     assert n_c >= 3
     dens = orc.density(ps, mode="brute")
     full_f = orc.force(ps, dens, mode="brute")
-    nd32, nf32 = orc.count32(ps, n_c, mode="brute")
     cell, start, perm, _ = orc.bin_cells(ps.x, n_c)
     rng = np.random.default_rng(5)
     cells = rng.choice(np.nonzero(np.diff(start) > 0)[0], size=6, replace=False)
@@ -546,21 +595,16 @@ def test_cell_pair_partials_partition_the_full_sums(orc):
                                    atol=1e-12 * np.abs(full_f["du"]).max())
         vmax = np.max(np.stack([p["vsig"] for p in fp]), axis=0)
         assert np.array_equal(vmax, full_f["vsig"][idx])
-        # the FP32 replica splits the same way
-        jm_counts = np.zeros(len(idx), np.int64)
-        for cj in nbr:
-            ndj, _ = orc.count32(ps, n_c, mode="brute", jmask=(cell == cj))
-            jm_counts += ndj[idx]
-        assert np.array_equal(jm_counts, nd32[idx])
 
 
-def test_count32_selection_is_a_subset(orc):
-    """count32 over selected i returns exactly the full counts at those i."""
+def test_near_support_selection_is_a_subset(orc):
+    """near_support over selected i returns exactly the full counts at those i."""
     ps = inputs.clustered_set(5000, 3, f_blob=0.4, sigma=0.06)
     n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
-    nd, nf = orc.count32(ps, n_c)
+    nd, nf = orc.near_support(ps, n_c, eps_rel=1e-3)
+    assert nf.sum() > 0
     sel = np.random.default_rng(2).choice(ps.n, 300, replace=False).astype(np.int32)
-    a, b = orc.count32(ps, n_c, sel=sel)
+    a, b = orc.near_support(ps, n_c, sel=sel, eps_rel=1e-3)
     assert np.array_equal(a, nd[sel]) and np.array_equal(b, nf[sel])
 
 
@@ -747,3 +791,88 @@ def test_kdk_free_particles(orc):
     assert np.array_equal(out.v, ps.v) and np.array_equal(out.u, ps.u)
     f = orc.force(ps, orc.density(ps, n_c=4), n_c=4)
     assert np.all(f["vsig"] == 0.0) and orc.timestep(ps.h, f["vsig"])[1] == np.inf
+
+
+# --------------------------------------------------------------------------
+# Coincident positions and position anchors (reduced-precision storage)
+# --------------------------------------------------------------------------
+
+def test_coincident_pair_reading(orc):
+    """Two particles j != i at the same position (reachable once positions
+    are stored in FP16): the pair direction is the zero vector. The pair
+    counts in both lists, exerts no force, does no work and has signal
+    velocity c_i + c_j. This is the r -> 0 limit of the pair terms: the
+    kernel gradient vanishes linearly at the origin, so the force of a pair
+    at separation r falls to zero with r, and with v_i = v_j the signal
+    velocity is c_i + c_j at every r."""
+    h = 0.05
+    res = {}
+    for r in (0.0, 1e-9, 1e-7):
+        x = np.array([[0.4, 0.5, 0.6], [0.4 + r, 0.5, 0.6], [0.4, 0.5 + 0.7 * h, 0.6]])
+        v = np.array([[0.1, 0.0, 0.0], [0.1, 0.0, 0.0], [0.0, -0.2, 0.0]])
+        ps = inputs.ParticleSet(x, v, np.full(3, 0.01), np.full(3, h), np.array([1.0, 2.0, 1.5]))
+        d = orc.density(ps, mode="brute")
+        f = orc.force(ps, d, mode="brute")
+        assert np.all(np.isfinite(f["a"])) and np.all(np.isfinite(f["du"]))
+        res[r] = (d, f)
+    d0, f0 = res[0.0]
+    assert d0["nngb"].tolist() == [3, 3, 3] and f0["nforce"].tolist() == [2, 2, 2]
+    # continuity at r -> 0 of every output: the change is of order r / h (the
+    # third particle interacts normally, its pair terms move with r too)
+    for r in (1e-9, 1e-7):
+        d1, f1 = res[r]
+        for k in ("rho", "wcount", "rho_dh"):
+            np.testing.assert_allclose(d1[k], d0[k], rtol=1e-10)
+        scale = np.abs(f0["a"]).max()
+        np.testing.assert_allclose(f1["a"], f0["a"], rtol=0, atol=10 * r / h * scale + 1e-15)
+        np.testing.assert_allclose(f1["du"], f0["du"], rtol=0,
+                                   atol=10 * r / h * np.abs(f0["du"]).max() + 1e-15)
+        np.testing.assert_allclose(f1["vsig"], f0["vsig"], rtol=10 * r / h)
+    # the coincident pair alone: no force, no heating, vsig = c_0 + c_1
+    x = np.array([[0.4, 0.5, 0.6], [0.4, 0.5, 0.6]])
+    ps = inputs.ParticleSet(x, np.array([[0.1, 0, 0], [-0.3, 0.2, 0]]), np.full(2, 0.01),
+                            np.full(2, h), np.array([1.0, 2.0]))
+    d = orc.density(ps, mode="brute")
+    f = orc.force(ps, d, mode="brute")
+    assert np.all(f["a"] == 0.0) and np.all(f["du"] == 0.0)
+    c = np.sqrt(orc.GAMMA * (orc.GAMMA - 1) * ps.u)
+    np.testing.assert_allclose(f["vsig"], [c.sum(), c.sum()], rtol=1e-15)
+    assert f["nforce"].tolist() == [1, 1]
+
+
+@pytest.mark.parametrize("anchor", [0, 1, 2, 3])
+def test_position_anchors(orc, anchor):
+    """Stored positions are offsets from an anchor (Sec. 3.2): the cell
+    corner (0) or the centre of the particle's sub-cell of side
+    1/(n_c 2^b) (1 + b). The anchor plus the FP64 offset gives back the
+    wrapped position; the offset lies within half a sub-cell of the anchor
+    (within the cell for the corner); the code holds the sub-cell indices;
+    the FP16-stored position errs by at most half an FP16 ulp of that
+    bound, so each level of anchor halves the worst error."""
+    rng = np.random.default_rng(anchor + 40)
+    n, n_c = 5000, 7
+    x = rng.uniform(-0.3, 1.3, size=(n, 3))
+    x[:4] = [[0, 0, 0], [1 - 1e-17, 0.5, 3 / 7], [2 / 7, 1 / 14, 0.999], [1 / 28, 3 / 28, 5 / 28]]
+    off, code = orc.pos_offsets(x, n_c, anchor)
+    xw = x - np.floor(x)
+    c3 = np.minimum(np.floor(xw * n_c), n_c - 1)
+    if anchor == 0:
+        assert np.array_equal(off, orc.bin_cells(x, n_c)[3])
+        assert not code.any()
+        bound = 1.0 / n_c
+        assert np.all(off >= 0) and np.all(off <= bound)
+    else:
+        R = 2 ** (anchor - 1)
+        a3 = np.clip(np.floor(xw * n_c * R) - c3 * R, 0, R - 1)
+        assert np.array_equal(code, (a3[:, 0] + 4 * a3[:, 1] + 16 * a3[:, 2]).astype(np.uint8))
+        centre = (c3 * R + a3 + 0.5) / (n_c * R)
+        np.testing.assert_array_equal(off, xw - centre)
+        bound = 0.5 / (n_c * R)
+        assert np.all(np.abs(off) <= bound * (1 + 1e-12))
+    ps = inputs.ParticleSet(x, np.zeros((n, 3)), np.ones(n), np.ones(n), np.ones(n))
+    q32 = orc.dequantise_set(ps, n_c, "f32", anchor=anchor)
+    q16 = orc.dequantise_set(ps, n_c, "f16", anchor=anchor)
+    assert np.max(np.abs(q32.x - xw)) <= 2.0 ** -24 * bound * (1 + 1e-9)
+    e16 = np.max(np.abs(q16.x - xw))
+    assert e16 <= 2.0 ** -11 * bound * (1 + 1e-9)
+    assert e16 > 2.0 ** -13 * bound            # the bound is attained up to a factor 4
