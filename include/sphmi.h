@@ -420,6 +420,20 @@ sph_status sph_reduce_workspace_size(int32_t n, size_t *bytes);
 sph_status sph_reduce(const sph_soa *soa, const sph_precision *prec, const sph_cells *cells,
                       double *out, void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* sph_reduce without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the same kernels and the same results bit for
+ * bit, with the partial sums in a 64 KiB array the library holds on each
+ * device it runs on (kept until the process ends; its address is resolved
+ * on the first call on a device). The call allocates nothing. It runs on
+ * the current device, and stream must belong to it. Every partial sum is
+ * overwritten by each call, so nothing needs clearing; calls that overlap
+ * on one device (on different streams or threads) share the array and race.
+ * The scratch covers any slot count (SPH_E_NOMEM would report a count
+ * beyond it). */
+sph_status sph_reduce_static(const sph_soa *soa, const sph_precision *prec,
+                             const sph_cells *cells, double *out, hipStream_t stream);
+
 /* Leapfrog kick-drift-kick over several steps (the Kick and Drift kernels
  * of Sec. 6 arranged as the second-order integrator; the paper gives no
  * scheme). A step of size dt: sph_kick_drift(dt/2, dt) and the kick view

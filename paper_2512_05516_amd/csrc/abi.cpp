@@ -561,6 +561,22 @@ sph_status sph_reduce(const sph_soa* soa, const sph_precision* prec, const sph_c
   return hip_status(launch_reduce(*soa, p, c.n, out, workspace, stream), "sph_reduce");
 }
 
+sph_status sph_reduce_static(const sph_soa* soa, const sph_precision* prec,
+                             const sph_cells* cells, double* out, hipStream_t stream) {
+  CellsDev c;
+  Prec p;
+  SPH_TRY(check_soa(soa, kReduceIn, len(kReduceIn), "sph_reduce_static"));
+  SPH_TRY(check_cells(cells, false, c));
+  SPH_TRY(check_prec(prec, p));
+  if (!out) return fail(SPH_E_INVALID, "sph_reduce_static: out is NULL");
+  if (reduce_workspace_bytes(c.n) > reduce_scratch_bytes())
+    return fail(SPH_E_NOMEM, "sph_reduce_static: %d slots need %zu scratch bytes, the library "
+                "holds %zu", c.n, reduce_workspace_bytes(c.n), reduce_scratch_bytes());
+  void* ws = nullptr;
+  SPH_TRY(hip_status(reduce_scratch(&ws), "sph_reduce_static: scratch address"));
+  return hip_status(launch_reduce(*soa, p, c.n, out, ws, stream), "sph_reduce_static");
+}
+
 sph_status sph_predict(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
                        const void* aos, const sph_aos_layout* layout, double dt_half,
                        hipStream_t stream) {

@@ -1,5 +1,7 @@
 // Linear kernels (Alg. 1 CallLinear): kick and drift, streaming over slots
 // (SoA) or records (AoS), and the FP64 conservation reductions.
+#include <mutex>
+
 #include "sph_device.h"
 
 namespace sph {
@@ -351,6 +353,38 @@ hipError_t launch_kick_drift_aos(void* aos, const AosLayout& L, int n, int n_c, 
 size_t reduce_workspace_bytes(int n) {
   (void)n;
   return sizeof(double) * kReduceBlocks * kReduceVals;
+}
+
+// Scratch of the allocation-free reduction (sph_reduce_static): the
+// kReduceBlocks x kReduceVals partial sums, one copy on each device the
+// library runs on. Host code never passes the array's name to a kernel: it
+// resolves each device's address once, with that device current, and
+// passes that address.
+static __device__ __align__(256) double scratch[kReduceBlocks * kReduceVals];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+size_t reduce_scratch_bytes() { return sizeof(scratch); }
+
+hipError_t reduce_scratch(void** ptr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,

@@ -138,5 +138,9 @@ hipError_t launch_step_totals(const sph_soa& soa, const Prec& p, int n, double g
                               double c_cfl, double* out, void* ws, hipStream_t s);
 hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,
                          hipStream_t s);
+// the reduction's device-resident scratch on the current device (address
+// resolved once per device) and its size
+hipError_t reduce_scratch(void** ptr);
+size_t reduce_scratch_bytes();
 
 }  // namespace sph

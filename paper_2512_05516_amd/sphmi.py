@@ -123,6 +123,7 @@ EXPORTS = [
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
     "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
     "sph_writeback_host", "sph_predict", "sph_step_totals", "sph_worklist_occupancy",
+    "sph_reduce_static",
 ]
 
 _lib = None
@@ -166,6 +167,7 @@ def lib():
     L.sph_kick_drift.argtypes = [P(Soa), P(Cells), C.c_double, C.c_double, vp, vp]
     L.sph_reduce_workspace_size.argtypes = [i32, P(sz)]
     L.sph_reduce.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp, sz, vp]
+    L.sph_reduce_static.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp]
     L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
@@ -587,6 +589,13 @@ def reduce(soa: DeviceSoa, cells: DeviceCells, out, workspace, stream=None):
     _check(lib().sph_reduce(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
                             _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                             _stream(stream)))
+
+
+def reduce_static(soa: DeviceSoa, cells: DeviceCells, out, stream=None):
+    """sph_reduce_static: the reductions of reduce() with the library's own
+    device scratch (no workspace, nothing allocated)."""
+    _check(lib().sph_reduce_static(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
+                                   _ptr(out), _stream(stream)))
 
 
 def density_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None, work=None):
