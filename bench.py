@@ -45,7 +45,7 @@ DT = 1e-4
 FLOP_DENSITY_PAIR = 40
 FLOP_FORCE_PAIR = 100
 # Algorithmic bytes per particle (FP32 record, FP32 storage):
-BYTES_CONVERT_FULL = 56 + 8 + 76     # record fields x,v,m,h,u + perm,cell; SoA writes
+BYTES_CONVERT_FULL = 128 + 8 + 76    # the 128-B record + perm, cell read; SoA writes
 BYTES_KICK = 96                      # x(24) v(12) u(4) a(12) du(4) read; x v u written
 BYTES_WRITEBACK_FULL = 104 + 96      # SoA reads (incl. perm, cell); record field writes
 PEAK_FP32_TFLOPS = 157.3
@@ -120,13 +120,11 @@ def _cpu_model():
     return platform.processor() or "unknown"
 
 
-def _oracle_timings(oracle, ps, n_c, stride, d_all, reps=3):
-    """Median of `reps` timed runs of the FP64 oracle (cell-list mode) on a
-    sample of ps (every `stride`-th particle): density, force (its inputs at
-    every particle from d_all, computed beforehand) and kick/drift over all
-    particles."""
+def _oracle_timings(oracle, ps, n_c, sel, d_all, reps=3):
+    """Median of `reps` timed runs of the FP64 oracle (cell-list mode) on the
+    sample `sel` of ps: density, force (its inputs at every particle from
+    d_all, computed beforehand) and kick/drift over all particles."""
     import ctypes as C
-    sel = np.arange(0, ps.n, stride, dtype=np.int32)
     x0 = np.ascontiguousarray(ps.x, np.float64)
     v0 = np.ascontiguousarray(ps.v, np.float64)
     u0 = np.ascontiguousarray(ps.u, np.float64)
@@ -157,12 +155,23 @@ def _oracle_timings(oracle, ps, n_c, stride, d_all, reps=3):
             "kick_drift_gbs_fp64_arrays": 144.0 * ps.n / mk / 1e9}
 
 
+def _sample(n, spec):
+    """Particle indices of a timing sample: ("first", k) the first k
+    particles (the lattice is stored in blocks of co-located particles, so
+    they form a compact region), ("every", s) every s-th particle."""
+    kind, k = spec
+    if kind == "first":
+        return np.arange(0, min(k, n), dtype=np.int32)
+    return np.arange(0, n, k, dtype=np.int32)
+
+
 def cpu_baseline(sets, gpu_records=None, err_set=None):
     """FP64 oracle (cell-list mode, OpenMP) timed on bounded samples of the
     workloads, with all host threads and with one, median of 3 each.
-    sets: [(name, ParticleSet, n_c, stride)]; density and force over every
-    stride-th particle, kick/drift over all. The headline value is the
-    all-threads pair-interaction rate on the 128^3 set. With gpu_records
+    sets: [(name, ParticleSet, n_c, sample spec with all threads, sample
+    spec with one)]; density and force over the sample (see _sample),
+    kick/drift over all particles. The headline value is the all-threads
+    pair-interaction rate on the 128^3 set. With gpu_records
     ({storage: records of one GPU evaluation of err_set's particles}) the
     oracle's values give each storage format's error against FP64: max
     relative error of rho over all particles, relative RMSE (normalised by
@@ -175,26 +184,27 @@ def cpu_baseline(sets, gpu_records=None, err_set=None):
            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "reps": 3, "statistic": "median",
            "configs": {}}
     dens_all = {}
-    for name, ps, n_c, stride in sets:
+    for name, ps, n_c, spec_all, spec_one in sets:
         log(f"CPU oracle: {name} ({ps.n} particles, density at all of them for the force)")
         oracle.set_threads(threads)
         d_all = oracle.density(ps, n_c=n_c)
         dens_all[name] = d_all
-        res = {"particles": ps.n, "n_c": n_c, "sample": f"density and force over every "
-                                                        f"{stride}-th particle, kick/drift "
-                                                        f"over all"}
-        for t in (threads, 1):
+        res = {"particles": ps.n, "n_c": n_c}
+        for t, spec in ((threads, spec_all), (1, spec_one)):
             oracle.set_threads(t)
-            res[f"threads_{t}"] = _oracle_timings(oracle, ps, n_c, stride, d_all)
+            r = _oracle_timings(oracle, ps, n_c, _sample(ps.n, spec), d_all)
+            which = (f"the first {spec[1]}" if spec[0] == "first" else
+                     f"every {spec[1]}-th of the" if spec[1] > 1 else "all")
+            r["sample"] = f"density and force over {which} particles; kick/drift over all"
+            res[f"threads_{t}"] = r
         oracle.set_threads(threads)
         out["configs"][name] = res
     m = out["configs"]["medium_128cubed"][f"threads_{threads}"]
     out["value"] = m["pair_interactions_per_s"]
     out["sample"] = (f"FP64 oracle, cell-list mode, {threads} threads: density + force over "
-                     f"{m['sample_particles']} particles (every "
-                     f"{sets[1][3]}-th) of the 128^3 set, median of 3 "
-                     f"({m['density_s'] + m['force_s']:.2f} s); S, M, K and 1-thread "
-                     f"figures under configs")
+                     f"the first {m['sample_particles']} particles (a compact block) of the "
+                     f"128^3 set, median of 3 ({m['density_s'] + m['force_s']:.2f} s); S, M, K "
+                     f"and 1-thread figures under configs")
     if gpu_records and err_set is not None:
         ps, n_c, key = err_set
         d = dens_all[key]
@@ -407,6 +417,70 @@ def clustered_variant(torch, args, inputs, sphmi, tune, Pipeline, settle_h):
         del pipe
         torch.cuda.empty_cache()
     return out, (rec, n_c)
+
+
+def _median_ms(torch, fn, flush, reps=10, warm=2):
+    """Median of `reps` launches of fn, each after `flush` (a 1 GiB write that
+    evicts the Infinity Cache), timed with HIP events on the launch stream."""
+    ts = []
+    for r in range(reps + warm):
+        flush()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= warm:
+            ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def hbm_variant(torch, sphmi, Pipeline, k_state):
+    """Streaming kernels against the device's own streaming ceiling, on data
+    beyond the 256 MiB Infinity Cache with the cache flushed before every
+    launch: the library's copy / read / write probes on 1 GiB, and kick/drift,
+    convert (full view) and writeback (full view) on the clustered 4,194,304-
+    particle set (FP32 records and storage), GB/s at algorithmic bytes."""
+    nb = 1 << 30
+    a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    fl = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(4, dtype=torch.float32, device="cuda")
+    a.fill_(1)
+    flush = lambda: sphmi.hbm_probe("write", None, fl, nb)
+    out = {"note": "median of 10 launches, each after a 1 GiB write (Infinity Cache flushed); "
+                   "GB/s at algorithmic bytes"}
+    pr = {}
+    for mode, traffic in (("copy", 2 * nb), ("read", nb), ("write", nb)):
+        ms = _median_ms(torch, lambda: sphmi.hbm_probe(mode, a, sink if mode == "read" else b, nb),
+                        flush)
+        pr[mode] = round(traffic / (ms * 1e-3) / 1e9, 1)
+    out["probe_gbs"] = pr
+    ceiling = pr["copy"]
+    del a, b
+    torch.cuda.empty_cache()
+    rec, n_c = k_state
+    n = rec.shape[0]
+    pipe = Pipeline(rec, n_c)
+    pipe.bin()
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    torch.cuda.synchronize()
+    k = {}
+    for name, fn, per in (("kick_drift", lambda: pipe.kick_drift(DT, DT), BYTES_KICK),
+                          ("convert_full", lambda: pipe.convert("full"), BYTES_CONVERT_FULL),
+                          ("writeback_full", lambda: pipe.writeback("full"), BYTES_WRITEBACK_FULL)):
+        ms = _median_ms(torch, fn, flush)
+        gbs = per * n / (ms * 1e-3) / 1e9
+        k[name] = {"us": round(1e3 * ms, 2), "bytes_per_particle": per, "gbs": round(gbs, 1),
+                   "frac_of_8tbs": round(gbs / PEAK_HBM_GBS, 4),
+                   "frac_of_copy_probe": round(gbs / ceiling, 4)}
+    out["kernels_4m"] = k
+    out["particles"] = n
+    del pipe, fl
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -629,6 +703,9 @@ def main():
     if not args.no_clustered:
         result["clustered"], k_state = clustered_variant(torch, args, inputs, sphmi, tune,
                                                          Pipeline, settle_h)
+        if not args.no_variants:
+            log("HBM: probes and streaming kernels on the 4M set")
+            result["hbm_4m"] = hbm_variant(torch, sphmi, Pipeline, k_state)
 
     # practical HBM ceiling: a plain 1 GiB device-to-device copy (read + write);
     # left out of counter runs, whose calibration takes the largest device copy
@@ -669,10 +746,12 @@ def main():
             gpu_records[name] = pe.records()
             del pe
         torch.cuda.empty_cache()
-        sets = [("small_16cubed", inputs.small_set(1), 4, 1), ("medium_128cubed", ps, N_C, 128)]
+        sets = [("small_16cubed", inputs.small_set(1), 4, ("every", 1), ("every", 1)),
+                ("medium_128cubed", ps, N_C, ("first", 1 << 18), ("first", 1 << 15))]
         if k_state is not None:
             k_rec, k_nc = k_state
-            sets.append(("clustered_4m", inputs.unpack_aos(k_rec), k_nc, 256))
+            sets.append(("clustered_4m", inputs.unpack_aos(k_rec), k_nc, ("every", 16),
+                         ("every", 128)))
         result["cpu_baseline"] = cpu_baseline(sets, gpu_records, (ps, N_C, "medium_128cubed"))
         if k_state is not None:
             result["cpu_baseline"]["configs"]["clustered_4m"]["note"] = (

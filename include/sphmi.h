@@ -128,6 +128,19 @@ typedef struct {
                           /* (particles of a chunk times the candidates   */
                           /* staged for it), [1] += candidates gathered   */
                           /* from the candidate ranges                    */
+  int32_t *rebin;         /* [2] optional (may be NULL) validity of the    */
+                          /* cell list across steps: [0] counts particles */
+                          /* that left their cell or sub-cell since the   */
+                          /* list was built (pass &rebin[0] as moved to   */
+                          /* sph_kick_drift / _aos); sph_bin keeps the    */
+                          /* list when [0] == 0 and otherwise rebuilds it */
+                          /* and sets [0] = 0; it sets [1] = 1 when it    */
+                          /* rebuilt, 0 when it kept the list, and        */
+                          /* sph_worklist / _occupancy rebuild a work     */
+                          /* list only when [1] != 0. The caller sets [0] */
+                          /* nonzero before the first sph_bin and         */
+                          /* whenever the records change otherwise (new   */
+                          /* positions or h, another n_c or sub_bits).    */
 } sph_cells;
 
 /* Work list of the pair kernels for a launch over all cells of uneven
@@ -406,7 +419,9 @@ sph_status sph_force(const sph_soa *soa, const sph_precision *prec, const sph_ce
 /* Kick and drift (Alg. 1 CallLinear): v += a dt_kick, u += du dt_kick
  * (FP32), then x += v dt_drift in FP64 with the kicked v and wrap into
  * [0,1). Reads/writes X, V, UK; reads A_*, DU. If moved (device int32)
- * is non-NULL, adds the number of particles whose cell changed. */
+ * is non-NULL, adds the number of particles whose cell changed or, with
+ * cells->sub_bits > 0, whose sub-cell changed (the binning's definitions
+ * of both). */
 sph_status sph_kick_drift(const sph_soa *soa, const sph_cells *cells, double dt_kick,
                           double dt_drift, int32_t *moved, hipStream_t stream);
 
@@ -673,6 +688,19 @@ sph_status sph_smoothing_length(const sph_soa *soa, const sph_precision *prec,
                                 const sph_work *work, void *workspace, size_t workspace_bytes,
                                 void *aos, const sph_aos_layout *layout, int32_t *iterations,
                                 int32_t *unconverged, hipStream_t stream);
+
+/* Streaming probes of the device memory rate: the ceiling against which the
+ * streaming kernels (convert, writeback, kick/drift) are measured. One
+ * launch moves `bytes` (a multiple of 16, src and dst 16-byte aligned) with
+ * 16-byte non-temporal accesses: SPH_PROBE_COPY reads src and writes dst
+ * (2 x bytes of traffic), SPH_PROBE_READ reads src (dst: a device float
+ * that is written only in a case no finite input produces), SPH_PROBE_WRITE
+ * writes dst (src unused). No result beyond the traffic is defined. */
+#define SPH_PROBE_COPY 0
+#define SPH_PROBE_READ 1
+#define SPH_PROBE_WRITE 2
+sph_status sph_hbm_probe(int32_t mode, const void *src, void *dst, size_t bytes,
+                         hipStream_t stream);
 
 /* hipStreamSynchronize with the error mapped to sph_status */
 sph_status sph_sync(hipStream_t stream);

@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsphmi.so")
 SOURCES = ["abi.cpp", "host_convert.cpp", "tune.cpp", "serve.cpp", "bin.hip", "convert.hip", "pair.hip", "kick.hip",
            "worklist.hip", "pair_dens_f32.hip", "pair_dens_r.hip", "pair_dens_gen.hip",
-           "pair_dens_aos.hip", "pair_force_f32.hip", "pair_force_r.hip", "pair_force_gen.hip",
+           "pair_dens_aos.hip", "pair_dens_h.hip", "pair_dens_b.hip", "pair_force_f32.hip",
+           "pair_force_r.hip", "pair_force_gen.hip", "pair_force_h.hip", "pair_force_b.hip",
            "pair_force_aos.hip", "pair_task_f32.hip", "pair_task_r.hip", "pair_task_gen.hip", "hiter.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("SPH_OFFLOAD_ARCH", "gfx950")

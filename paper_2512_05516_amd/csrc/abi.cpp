@@ -120,6 +120,7 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   out.hmax = c->hmax;
   out.status = c->status;
   out.tally = reinterpret_cast<unsigned long long*>(c->tally);
+  out.rebin = c->rebin;
   return SPH_OK;
 }
 
@@ -309,7 +310,9 @@ sph_status sph_worklist_occupancy(const sph_cells* cells, sph_work* work, int32_
   if (occ_lo < 0 || occ_hi <= occ_lo)
     return fail(SPH_E_INVALID, "occupancy range [%d, %d) is empty or negative", occ_lo, occ_hi);
   WorkDev w = work_view(*work, c.n, c.n_c);
-  return hip_status(launch_worklist_range(c, w, nullptr, occ_lo, occ_hi, stream), "sph_worklist");
+  return hip_status(launch_worklist_range(c, w, nullptr, occ_lo, occ_hi, stream,
+                                          c.rebin ? c.rebin + 1 : nullptr),
+                    "sph_worklist");
 }
 
 sph_status sph_bin(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,
@@ -677,8 +680,23 @@ sph_status sph_kick_drift_aos(void* aos, const sph_aos_layout* layout, const sph
   if (!std::isfinite(dt_kick) || !std::isfinite(dt_drift))
     return fail(SPH_E_INVALID, "time steps must be finite");
   SPH_TRY(check_aos_ptr(aos, c.n));
-  return hip_status(launch_kick_drift_aos(aos, L, c.n, c.n_c, dt_kick, dt_drift, moved, stream),
+  return hip_status(launch_kick_drift_aos(aos, L, c.n, c.n_c, c.sub_bits, dt_kick, dt_drift, moved, stream),
                     "sph_kick_drift_aos");
+}
+
+sph_status sph_hbm_probe(int32_t mode, const void* src, void* dst, size_t bytes,
+                         hipStream_t stream) {
+  if (mode != SPH_PROBE_COPY && mode != SPH_PROBE_READ && mode != SPH_PROBE_WRITE)
+    return fail(SPH_E_INVALID, "sph_hbm_probe: unknown mode %d", mode);
+  if (bytes % 16 != 0) return fail(SPH_E_INVALID, "sph_hbm_probe: bytes must be a multiple of 16");
+  if (bytes == 0) return SPH_OK;
+  const bool need_src = mode != SPH_PROBE_WRITE;
+  if ((need_src && !src) || !dst) return fail(SPH_E_INVALID, "sph_hbm_probe: NULL buffer");
+  if ((need_src && (reinterpret_cast<uintptr_t>(src) & 15)) ||
+      (mode != SPH_PROBE_READ && (reinterpret_cast<uintptr_t>(dst) & 15)))
+    return fail(SPH_E_INVALID, "sph_hbm_probe: buffers must be 16-byte aligned");
+  if (bytes / 16 >= (size_t)1 << 38) return fail(SPH_E_RANGE, "sph_hbm_probe: too many bytes");
+  return hip_status(launch_hbm_probe(mode, src, dst, bytes, stream), "sph_hbm_probe");
 }
 
 sph_status sph_sync(hipStream_t stream) {

@@ -13,6 +13,12 @@ constexpr int kScanPer = 16;                  // elements per thread in scans
 constexpr int kScanTile = kThreads * kScanPer;
 constexpr int kMaxBuckets = 512;             // radix buckets of the widest digit (9 bits)
 
+// A gated launch does nothing when *gate == 0 (the cell list is kept: no
+// particle changed its cell or sub-cell since it was built). The word is
+// read at the start of each kernel; only the last kernel of the binning
+// changes it.
+__device__ __forceinline__ bool gated_off(const int32_t* gate) { return gate && *gate == 0; }
+
 // Morton code of a sub-cell (bit b of sx at 3b, sy at 3b+1, sz at 3b+2)
 __device__ __forceinline__ int morton3(int sx, int sy, int sz, int bits) {
   int m = 0;
@@ -38,8 +44,9 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
                                                         int32_t* __restrict__ keys,
                                                         int32_t* __restrict__ vals,
                                                         float* __restrict__ hin,
-                                                        int32_t* status) {
+                                                        int32_t* status, const int32_t* gate) {
   __shared__ uint2 span[kThreads * kSpanWords];
+  if (gated_off(gate)) return;                 // uniform over the grid
   const int i0 = blockIdx.x * kThreads;
   const int i = i0 + threadIdx.x;
   const bool valid = i < n;   // no early exit: the whole block stages the records
@@ -86,7 +93,9 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
   if (valid && bad && status) atomicOr(status, SPH_FLAG_BAD_POSITION);
 }
 
-__global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, int n, float v) {
+__global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, int n, float v,
+                                                        const int32_t* gate) {
+  if (gated_off(gate)) return;
   int i = blockIdx.x * kThreads + threadIdx.x;
   if (i < n) p[i] = v;
 }
@@ -96,9 +105,10 @@ __global__ __launch_bounds__(kThreads) void k_fill_f32(float* __restrict__ p, in
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restrict__ kin,
                                                           int32_t* __restrict__ hist, int n,
-                                                          int nblk, int shift) {
+                                                          int nblk, int shift, const int32_t* gate) {
   constexpr int NB = 1 << D;
   __shared__ int h[NB];
+  if (gated_off(gate)) return;
   const int tid = threadIdx.x;
   for (int d = tid; d < NB; d += kThreads) h[d] = 0;
   __syncthreads();
@@ -117,9 +127,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restri
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
-    int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift) {
+    int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift,
+    const int32_t* gate) {
   constexpr int NB = 1 << D;
   __shared__ int wcnt[kThreads / 64][NB];
+  if (gated_off(gate)) return;
   __shared__ int run[NB];
   __shared__ int base[NB];
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -187,8 +199,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_tiles(int32_t* __restrict__ data, int len,
-                                                          int32_t* __restrict__ partials) {
+                                                          int32_t* __restrict__ partials,
+                                                          const int32_t* gate) {
   __shared__ int lds[kThreads];
+  if (gated_off(gate)) return;
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
   int v[kScanPer];
   int s = 0;
@@ -208,8 +222,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_tiles(int32_t* __restrict__ d
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_partials(int32_t* __restrict__ partials,
-                                                             int np) {
+                                                             int np, const int32_t* gate) {
   __shared__ int lds[kThreads];
+  if (gated_off(gate)) return;
   int carry = 0;
   for (int base = 0; base < np; base += kThreads) {
     int i = base + threadIdx.x;
@@ -222,7 +237,9 @@ __global__ __launch_bounds__(kThreads) void k_scan_partials(int32_t* __restrict_
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_add(int32_t* __restrict__ data, int len,
-                                                        const int32_t* __restrict__ partials) {
+                                                        const int32_t* __restrict__ partials,
+                                                        const int32_t* gate) {
+  if (gated_off(gate)) return;
   int add = partials[blockIdx.x];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
 #pragma unroll
@@ -243,7 +260,9 @@ __global__ __launch_bounds__(kThreads) void k_cell_tables(const int32_t* __restr
                                                            int n, int sub_bits, int C,
                                                            int32_t* __restrict__ cell,
                                                            int32_t* __restrict__ cell_start,
-                                                           int32_t* __restrict__ sub_start) {
+                                                           int32_t* __restrict__ sub_start,
+                                                           const int32_t* gate) {
+  if (gated_off(gate)) return;
   const int k = blockIdx.x * kThreads + threadIdx.x;
   if (k > n) return;
   const int sh = 3 * sub_bits;
@@ -261,7 +280,9 @@ __global__ __launch_bounds__(kThreads) void k_cell_tables(const int32_t* __restr
 __global__ __launch_bounds__(kThreads) void k_cell_hmax_sorted(const int32_t* __restrict__ start,
                                                                 const int32_t* __restrict__ perm,
                                                                 const float* __restrict__ hin,
-                                                                int C, float* __restrict__ hmax) {
+                                                                int C, float* __restrict__ hmax,
+                                                                const int32_t* gate) {
+  if (gated_off(gate)) return;
   const int c = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
   if (c >= C) return;                          // uniform over the wave
   const int lane = threadIdx.x & 63;
@@ -269,6 +290,15 @@ __global__ __launch_bounds__(kThreads) void k_cell_hmax_sorted(const int32_t* __
   for (int k = start[c] + lane; k < start[c + 1]; k += 64) m = fmaxf(m, hin[perm[k]]);
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if (lane == 0) hmax[c] = m;
+}
+
+// Last kernel of a gated binning: [1] = whether this call rebuilt the list,
+// [0] = 0 (the list now matches the records).
+__global__ void k_rebin_done(int32_t* gate) {
+  if (threadIdx.x == 0) {
+    gate[1] = gate[0] != 0 ? 1 : 0;
+    gate[0] = 0;
+  }
 }
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -294,12 +324,13 @@ BinWs carve(void* ws, int n, int nblk) {
   return w;
 }
 
-hipError_t scan_local(int32_t* data, int len, int32_t* partials, hipStream_t s) {
+hipError_t scan_local(int32_t* data, int len, int32_t* partials, hipStream_t s,
+                      const int32_t* gate) {
   int nt = cdiv(len, kScanTile);
   if (nt == 0) return hipSuccess;
-  k_scan_tiles<<<nt, kThreads, 0, s>>>(data, len, partials);
-  k_scan_partials<<<1, kThreads, 0, s>>>(partials, nt);
-  k_scan_add<<<nt, kThreads, 0, s>>>(data, len, partials);
+  k_scan_tiles<<<nt, kThreads, 0, s>>>(data, len, partials, gate);
+  k_scan_partials<<<1, kThreads, 0, s>>>(partials, nt, gate);
+  k_scan_add<<<nt, kThreads, 0, s>>>(data, len, partials, gate);
   return hipGetLastError();
 }
 
@@ -307,8 +338,9 @@ hipError_t scan_local(int32_t* data, int len, int32_t* partials, hipStream_t s) 
 
 size_t scan_partials_count(int len) { return (size_t)cdiv(len, kScanTile) + 1; }
 
-hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s) {
-  return scan_local(data, len, partials, s);
+hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s,
+                    const int32_t* gate) {
+  return scan_local(data, len, partials, s, gate);
 }
 
 size_t bin_workspace_bytes(int n, int n_c, int sub_bits) {
@@ -329,6 +361,7 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
   const int S = C << (3 * sb);
   const int nblk = cdiv(n, kTile);
   BinWs w = carve(ws, n, nblk);
+  const int32_t* gate = c.rebin;         // kept when no particle moved (may be null)
   int32_t* skeys = cell;                 // sorted keys (cell ids when sb == 0)
   if (n > 0) {
     // span of the record bytes the keys need: x, and h when hmax is wanted
@@ -340,7 +373,7 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
     const int nw = (hi - lo) / 8 <= (uint32_t)kSpanWords ? (int)((hi - lo) / 8) : 0;
     k_bin_keys<<<cdiv(n, kThreads), kThreads, 0, s>>>(
         static_cast<const char*>(aos), L.stride, ox, oh, L.dt[SPH_A_H], lo, nw, n, n_c, sb, w.ka,
-        w.va, want_h ? w.hin : nullptr, c.status);
+        w.va, want_h ? w.hin : nullptr, c.status, gate);
     int bits = 1;
     while ((1 << bits) < S) ++bits;
     // 9-bit digits where they need fewer passes than 8-bit ones (keys of
@@ -358,16 +391,16 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
         vd = (vs == w.va) ? w.vb : w.va;
       }
       if (D == 8) {
-        k_radix_hist<8><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p);
+        k_radix_hist<8><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 8 * p, gate);
       } else {
-        k_radix_hist<9><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 9 * p);
+        k_radix_hist<9><<<nblk, kThreads, 0, s>>>(ks, w.hist, n, nblk, 9 * p, gate);
       }
-      hipError_t e = scan_local(w.hist, (1 << D) * nblk, w.partials, s);
+      hipError_t e = scan_local(w.hist, (1 << D) * nblk, w.partials, s, gate);
       if (e != hipSuccess) return e;
       if (D == 8) {
-        k_radix_scatter<8><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p);
+        k_radix_scatter<8><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p, gate);
       } else {
-        k_radix_scatter<9><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 9 * p);
+        k_radix_scatter<9><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 9 * p, gate);
       }
       ks = kd;
       vs = vd;
@@ -375,15 +408,16 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
     skeys = ks;
   }
   k_cell_tables<<<cdiv(n + 1, kThreads), kThreads, 0, s>>>(skeys, n, sb, C, cell, cell_start,
-                                                           sub_start);
+                                                           sub_start, gate);
   if (hmax) {
     if (n > 0 && L.off[SPH_A_H] != kAbsent) {
       k_cell_hmax_sorted<<<cdiv(C, kThreads / 64), kThreads, 0, s>>>(cell_start, perm, w.hin, C,
-                                                                      hmax);
+                                                                      hmax, gate);
     } else {
-      k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f);
+      k_fill_f32<<<cdiv(C, kThreads), kThreads, 0, s>>>(hmax, C, 0.0f, gate);
     }
   }
+  if (c.rebin) k_rebin_done<<<1, 64, 0, s>>>(c.rebin);
   return hipGetLastError();
 }
 

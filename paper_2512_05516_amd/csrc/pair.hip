@@ -10,8 +10,9 @@ bool tile_supported(int ti, int k) {
          (ti == 128 && k == 2) || (ti == 16 && (k == 16 || k == 4));
 }
 
-// Storage formats with compiled-in loaders; every other combination uses the
-// run-time loader.
+// Storage formats with compiled-in loaders (FP32; FP16 positions and m/h/u
+// with BF16 velocities; all FP16; all BF16); every other combination uses
+// the run-time loader.
 hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, const Phys& ph,
                           int ti, int k, const WorkDev* w, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
@@ -19,6 +20,10 @@ hipError_t launch_density(const sph_soa& soa, const Prec& p, const CellsDev& c, 
     return run_density_dens_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p, c.n_c), c, ph, ti, k, w, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
     return run_density_dens_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  if (p.pos == DT_F16 && p.vel == DT_F16 && p.mhu == DT_F16)
+    return run_density_dens_h(make_soa<DT_F16, DT_F16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  if (p.pos == DT_BF16 && p.vel == DT_BF16 && p.mhu == DT_BF16)
+    return run_density_dens_b(make_soa<DT_BF16, DT_BF16, DT_BF16>(soa, p, c.n_c), c, ph, ti, k, w, s);
   return run_density_dens_gen(make_soa<-1, -1, -1>(soa, p, c.n_c), c, ph, ti, k, w, s);
 }
 
@@ -29,6 +34,10 @@ hipError_t launch_force(const sph_soa& soa, const Prec& p, const CellsDev& c, co
     return run_force_force_f32(make_soa<DT_F32, DT_F32, DT_F32>(soa, p, c.n_c), c, ph, ti, k, w, s);
   if (p.pos == DT_F16 && p.vel == DT_BF16 && p.mhu == DT_F16)
     return run_force_force_r(make_soa<DT_F16, DT_BF16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  if (p.pos == DT_F16 && p.vel == DT_F16 && p.mhu == DT_F16)
+    return run_force_force_h(make_soa<DT_F16, DT_F16, DT_F16>(soa, p, c.n_c), c, ph, ti, k, w, s);
+  if (p.pos == DT_BF16 && p.vel == DT_BF16 && p.mhu == DT_BF16)
+    return run_force_force_b(make_soa<DT_BF16, DT_BF16, DT_BF16>(soa, p, c.n_c), c, ph, ti, k, w, s);
   return run_force_force_gen(make_soa<-1, -1, -1>(soa, p, c.n_c), c, ph, ti, k, w, s);
 }
 

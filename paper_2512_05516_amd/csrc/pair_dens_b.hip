@@ -1,0 +1,13 @@
+// Instantiation of the density kernel for one data source (SoaSrc<DT_BF16, DT_BF16, DT_BF16>).
+#include "pair_impl.h"
+
+namespace sph {
+namespace pairk {
+
+hipError_t run_density_dens_b(const SoaSrc<DT_BF16, DT_BF16, DT_BF16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s) {
+  return run_density(src, c, ph, ti, k, w, s);
+}
+
+}  // namespace pairk
+}  // namespace sph

@@ -1307,6 +1307,10 @@ hipError_t run_density_dens_f32(const SoaSrc<DT_F32, DT_F32, DT_F32>& src, const
                   const WorkDev* w, hipStream_t s);
 hipError_t run_density_dens_r(const SoaSrc<DT_F16, DT_BF16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);
+hipError_t run_density_dens_h(const SoaSrc<DT_F16, DT_F16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_density_dens_b(const SoaSrc<DT_BF16, DT_BF16, DT_BF16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
 hipError_t run_density_dens_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);
 hipError_t run_density_dens_aos(const AosSrc& src, const CellsDev& c, const Phys& ph, int ti, int k,
@@ -1314,6 +1318,10 @@ hipError_t run_density_dens_aos(const AosSrc& src, const CellsDev& c, const Phys
 hipError_t run_force_force_f32(const SoaSrc<DT_F32, DT_F32, DT_F32>& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);
 hipError_t run_force_force_r(const SoaSrc<DT_F16, DT_BF16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_h(const SoaSrc<DT_F16, DT_F16, DT_F16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
+                  const WorkDev* w, hipStream_t s);
+hipError_t run_force_force_b(const SoaSrc<DT_BF16, DT_BF16, DT_BF16>& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);
 hipError_t run_force_force_gen(const SoaSrc<-1, -1, -1>& src, const CellsDev& c, const Phys& ph, int ti, int k,
                   const WorkDev* w, hipStream_t s);

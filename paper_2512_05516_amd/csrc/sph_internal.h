@@ -56,6 +56,7 @@ struct CellsDev {
   const float* hmax;
   int32_t* status;
   unsigned long long* tally;   // [0] candidate tests, [1] gathered (may be null)
+  int32_t* rebin;              // [0] moved since the list was built, [1] rebuilt flag
 };
 
 // Work list of the pair kernels (device buffer layout): 8 queue counters,
@@ -78,15 +79,19 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
                       int32_t* perm, int32_t* cell, int32_t* sub_start, float* hmax, void* ws,
                       hipStream_t s);
 
-// exclusive scan of int32 in place; partials: scan_partials_count(len) ints
+// exclusive scan of int32 in place; partials: scan_partials_count(len) ints;
+// with gate non-null the kernels do nothing when *gate == 0
 size_t scan_partials_count(int len);
-hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s);
+hipError_t scan_i32(int32_t* data, int len, int32_t* partials, hipStream_t s,
+                    const int32_t* gate = nullptr);
 
 size_t worklist_bytes(int n, int n_c, int ti);
 int worklist_capacity(int n, int n_c, int ti);
 hipError_t launch_worklist(const CellsDev& c, const WorkDev& w, hipStream_t s);
+// gate non-null: the kernels do nothing when *gate == 0
 hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint8_t* active,
-                                 int occ_lo, int occ_hi, hipStream_t s);
+                                 int occ_lo, int occ_hi, hipStream_t s,
+                                 const int32_t* gate = nullptr);
 // work list of the cells that hold at least one slot with active[k] != 0
 hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uint8_t* active,
                                   hipStream_t s);
@@ -128,8 +133,8 @@ hipError_t launch_tasks(const sph_soa& soa, const Prec& p, const CellsDev& c, co
 
 hipError_t launch_kick_drift(const sph_soa& soa, const CellsDev& c, double dtk, double dtd,
                              int32_t* moved, hipStream_t s);
-hipError_t launch_kick_drift_aos(void* aos, const AosLayout& L, int n, int n_c, double dtk,
-                                 double dtd, int32_t* moved, hipStream_t s);
+hipError_t launch_kick_drift_aos(void* aos, const AosLayout& L, int n, int n_c, int sub_bits,
+                                 double dtk, double dtd, int32_t* moved, hipStream_t s);
 
 size_t reduce_workspace_bytes(int n);
 hipError_t launch_predict(const sph_soa& soa, const Prec& p, const CellsDev& c, const void* aos,
@@ -138,6 +143,7 @@ hipError_t launch_step_totals(const sph_soa& soa, const Prec& p, int n, double g
                               double c_cfl, double* out, void* ws, hipStream_t s);
 hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,
                          hipStream_t s);
+hipError_t launch_hbm_probe(int mode, const void* src, void* dst, size_t bytes, hipStream_t s);
 // the reduction's device-resident scratch on the current device (address
 // resolved once per device) and its size
 hipError_t reduce_scratch(void** ptr);

@@ -58,7 +58,9 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
                                                         const uint8_t* __restrict__ active,
                                                         int occ_lo, int occ_hi,
                                                         int32_t* __restrict__ pos,
-                                                        int32_t* __restrict__ cost) {
+                                                        int32_t* __restrict__ cost,
+                                                        const int32_t* gate) {
+  if (gate && *gate == 0) return;             // the cell list was kept: so is this list
   const int C = n_c * n_c * n_c;
   const int j = blockIdx.x * kThreads + threadIdx.x;   // position in brick order
   if (j > C) return;
@@ -101,7 +103,9 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
 __global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict__ start, int n_c,
                                                        int n, int ti, int capacity,
                                                        const int32_t* __restrict__ pos,
-                                                       int2* __restrict__ items) {
+                                                       int2* __restrict__ items,
+                                                       const int32_t* gate) {
+  if (gate && *gate == 0) return;
   const int C = n_c * n_c * n_c;
   const int j = blockIdx.x * kThreads + threadIdx.x;   // position in brick order
   if (j >= C) return;
@@ -116,7 +120,8 @@ __global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict_
 // brick order) whose cost prefix reaches q/8 of the total.
 __global__ void k_wl_meta(const int32_t* __restrict__ pos, const int32_t* __restrict__ cost,
                           int C, int capacity, int32_t* __restrict__ counters,
-                          int32_t* __restrict__ meta) {
+                          int32_t* __restrict__ meta, const int32_t* gate) {
+  if (gate && *gate == 0) return;
   const int q = threadIdx.x;
   const int total = min(pos[C], capacity);
   if (q == 0) meta[0] = total;
@@ -167,19 +172,20 @@ hipError_t launch_worklist_active(const CellsDev& c, const WorkDev& w, const uin
 }
 
 hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint8_t* active,
-                                 int occ_lo, int occ_hi, hipStream_t s) {
+                                 int occ_lo, int occ_hi, hipStream_t s, const int32_t* gate) {
   const int C = c.n_c * c.n_c * c.n_c;
   WlLayout L = wl_layout(reinterpret_cast<char*>(w.counters), C);
   const int cost_cap = (int)((((int64_t)1 << 31) - 1) / ((int64_t)C + 1));
   k_wl_count<<<cdiv(C + 1, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, cost_cap,
-                                                         active, occ_lo, occ_hi, L.pos, L.cost);
-  hipError_t e = scan_i32(L.pos, C + 1, L.partials, s);
+                                                         active, occ_lo, occ_hi, L.pos, L.cost,
+                                                         gate);
+  hipError_t e = scan_i32(L.pos, C + 1, L.partials, s, gate);
   if (e != hipSuccess) return e;
-  e = scan_i32(L.cost, C + 1, L.partials, s);
+  e = scan_i32(L.cost, C + 1, L.partials, s, gate);
   if (e != hipSuccess) return e;
   k_wl_fill<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, w.capacity, L.pos,
-                                                    w.items);
-  k_wl_meta<<<1, 64, 0, s>>>(L.pos, L.cost, C, w.capacity, w.counters, w.meta);
+                                                    w.items, gate);
+  k_wl_meta<<<1, 64, 0, s>>>(L.pos, L.cost, C, w.capacity, w.counters, w.meta, gate);
   return hipGetLastError();
 }
 

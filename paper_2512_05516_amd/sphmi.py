@@ -57,7 +57,7 @@ class Cells(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_c", C.c_int32), ("sub_bits", C.c_int32),
                 ("reserved", C.c_int32), ("cell_start", C.c_void_p), ("perm", C.c_void_p),
                 ("cell", C.c_void_p), ("sub_start", C.c_void_p), ("hmax", C.c_void_p),
-                ("status", C.c_void_p), ("tally", C.c_void_p)]
+                ("status", C.c_void_p), ("tally", C.c_void_p), ("rebin", C.c_void_p)]
 
 
 class Work(C.Structure):
@@ -123,7 +123,7 @@ EXPORTS = [
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
     "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
     "sph_writeback_host", "sph_predict", "sph_step_totals", "sph_worklist_occupancy",
-    "sph_reduce_static",
+    "sph_reduce_static", "sph_hbm_probe",
 ]
 
 _lib = None
@@ -168,6 +168,7 @@ def lib():
     L.sph_reduce_workspace_size.argtypes = [i32, P(sz)]
     L.sph_reduce.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp, sz, vp]
     L.sph_reduce_static.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp]
+    L.sph_hbm_probe.argtypes = [i32, vp, vp, sz, vp]
     L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
@@ -613,6 +614,15 @@ def force_aos(aos, layout, cells: DeviceCells, prm=None, til=None, stream=None, 
 def kick_drift_aos(aos, layout, cells: DeviceCells, dt_kick, dt_drift, moved=None, stream=None):
     _check(lib().sph_kick_drift_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct),
                                     float(dt_kick), float(dt_drift), _ptr(moved), _stream(stream)))
+
+
+PROBES = {"copy": 0, "read": 1, "write": 2}
+
+
+def hbm_probe(mode: str, src, dst, nbytes: int, stream=None):
+    """sph_hbm_probe: one streaming launch over nbytes ('copy', 'read',
+    'write'); src/dst are torch device tensors (or None where unused)."""
+    _check(lib().sph_hbm_probe(PROBES[mode], _ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
 
 
 def sync(stream=None):
