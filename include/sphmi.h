@@ -360,7 +360,10 @@ sph_status sph_writeback(const sph_soa *soa, const sph_cells *cells, int32_t vie
                          void *aos, const sph_aos_layout *layout, hipStream_t stream);
 
 /* Work list for the pair kernels (Alg. 1 CallQuadratic over all cells of
- * uneven occupancy in one launch): one item per chunk of at most ti
+ * uneven occupancy in one launch; the relaxed neighbourhood-neighbourhood
+ * checks with interaction masking that Sec. 2.2 describes for
+ * accelerators, over chunks of co-located particles as the buffers of
+ * Sec. 6 are): one item per chunk of at most ti
  * consecutive slots of a cell, in cell order. The cost of an item is
  * estimated as its particle count times the particle count of the 27 cells
  * around its cell, capped at 27 x 64 (h follows the density, so the
@@ -425,7 +428,11 @@ sph_status sph_force(const sph_soa *soa, const sph_precision *prec, const sph_ce
 sph_status sph_kick_drift(const sph_soa *soa, const sph_cells *cells, double dt_kick,
                           double dt_drift, int32_t *moved, hipStream_t stream);
 
-/* FP64 reductions over the slots (deterministic order):
+/* FP64 reductions over the slots (deterministic order): the conservation
+ * checks of the discrete equations of Sec. 2.1 (Eq. momentum: the pair
+ * forces are antisymmetric, so sum m a vanishes up to rounding; Eq. energy:
+ * sum m (v.a + du/dt) vanishes for the same reason), with the magnitudes
+ * they are measured against:
  * out[0..2] = sum m a, out[3] = sum m (v.a + du), out[4] = sum m |a|,
  * out[5] = sum m (|v.a| + |du|), out[6] = sum nngb, out[7] = sum nforce.
  * Reads M (with its scale) or, if NULL, nothing for m (m = 1), V, A, DU,
@@ -494,7 +501,10 @@ sph_status sph_kick_drift_aos(void *aos, const sph_aos_layout *layout, const sph
                               hipStream_t stream);
 
 /* Autotuner of the pair loops' cell-to-workgroup tiling (the batched
- * launch over cells of uneven occupancy). One candidate is a tile and a
+ * launch over cells of uneven occupancy of Alg. 1 CallQuadratic; Sec. 2.2
+ * notes that the right offload granularity is a kernel- and
+ * architecture-specific decision, which the paper makes by hand and which
+ * this call makes by timing). One candidate is a tile and a
  * schedule: sched = -1 launches one workgroup per cell (no work list),
  * otherwise the work list is built for the tile's ti and taken with that
  * SPH_SCHED_* schedule. */
@@ -557,7 +567,10 @@ typedef struct {
 /* Tiles of the task kernels (ti particles per workgroup, k lanes each) */
 int32_t sph_task_tile_supported(sph_tile tile);
 
-/* One launch per kind over a batch of n_tasks tasks (device arrays): items are
+/* One launch per kind over a batch of n_tasks tasks (device arrays), each
+ * task one CallQuadratic of Alg. 1 over a cell pair, the unit the paper's
+ * host threads offload one loop invocation at a time (Sec. 5, GPU data
+ * handling; Sec. 6 gives 16 host cores to offloading): items are
  * (task index, first slot) pairs, one per chunk of at most tile.ti slots
  * of a task, density items first (n_dens of them), then force items
  * (n_force); out_off[t] is the index in `out` of task t's first result;

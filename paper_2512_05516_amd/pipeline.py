@@ -15,7 +15,7 @@ from . import sphmi
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
                  prm=None, stream=None, sub_bits: int = 0, sched=None,
-                 til_force=None, split=None, tally=False):
+                 til_force=None, split=None, tally=False, keep_cells=False):
         import torch
         self.torch = torch
         self.n = int(aos_np.shape[0])
@@ -29,7 +29,11 @@ class Pipeline:
         self.til = til or sphmi.tile()
         self.til_force = til_force or self.til
         self.stream = stream
-        self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits, tally=tally)
+        # keep_cells: the binning keeps the cell list (and the work lists)
+        # while no particle has left its cell or sub-cell since it was built;
+        # the kicks count such particles into cells.rebin[0]
+        self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits, tally=tally,
+                                       rebin=keep_cells)
         # sched: None (one workgroup per cell) or a work-list schedule, one
         # for both loops or a (density, force) pair
         sd, sf = sched if isinstance(sched, (tuple, list)) else (sched, sched)
@@ -69,7 +73,8 @@ class Pipeline:
         self.red_ws = torch.empty(sphmi.reduce_workspace_size(self.n), dtype=torch.uint8,
                                   device=device)
         self.red_out = torch.zeros(8, dtype=torch.float64, device=device)
-        self.moved = torch.zeros(1, dtype=torch.int32, device=device)
+        self.moved = (self.cells.rebin[:1] if keep_cells else
+                      torch.zeros(1, dtype=torch.int32, device=device))
 
     # --- individual stages -------------------------------------------------
     def bin(self):
@@ -97,6 +102,7 @@ class Pipeline:
                                      self.til, self.work, None,
                                      self.aos if write_back else None,
                                      self.layout if write_back else None, self.stream)
+        self.cells.invalidate()        # h changed; rebuild the lists now
         self.build_lists()             # the passes leave a filtered list behind
         return out
 

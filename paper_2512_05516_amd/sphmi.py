@@ -269,7 +269,8 @@ class DeviceCells:
     sub_start[C 8^sub_bits + 1] (sub_bits > 0), hmax[C], status[1], and
     with tally=True the pair loops' work counters tally[2] (int64)."""
 
-    def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0, tally=False):
+    def __init__(self, n: int, n_c: int, device="cuda", sub_bits: int = 0, tally=False,
+                 rebin=False):
         import torch
         self.n, self.n_c, self.sub_bits = int(n), int(n_c), int(sub_bits)
         C_ = self.n_c ** 3
@@ -281,11 +282,21 @@ class DeviceCells:
         self.hmax = torch.zeros(C_, dtype=torch.float32, device=device)
         self.status = torch.zeros(1, dtype=torch.int32, device=device)
         self.tally = torch.zeros(2, dtype=torch.int64, device=device) if tally else None
+        # rebin = [moved since the list was built, rebuilt by the last bin]:
+        # starts "stale" so the first bin builds the list
+        self.rebin = torch.ones(2, dtype=torch.int32, device=device) if rebin else None
         self._s = Cells(self.n, self.n_c, self.sub_bits, 0, self.cell_start.data_ptr(),
                         self.perm.data_ptr(), self.cell.data_ptr(),
                         self.sub_start.data_ptr() if self.sub_start is not None else None,
                         self.hmax.data_ptr(), self.status.data_ptr(),
-                        self.tally.data_ptr() if tally else None)
+                        self.tally.data_ptr() if tally else None,
+                        self.rebin.data_ptr() if rebin else None)
+
+    def invalidate(self):
+        """Mark the cell list stale (records changed other than by a kick):
+        the next bin rebuilds it, and work lists are rebuilt now."""
+        if self.rebin is not None:
+            self.rebin.fill_(1)
 
     @property
     def struct(self) -> Cells:

@@ -742,21 +742,27 @@ def test_truncated_storage_parity(sph, orc, pos, vel, mhu, scales):
 
 def test_truncation_error_curve_gpu(sph, orc):
     """Acceleration error of the FP32 kernels on T-bit storage (every field)
-    against FP64 on the unrounded inputs: at 32 bits the FP32 floor; growing
-    as bits are cut within the single and half layouts; lower at exactly 16
-    bits than at 17 (the switch to the half layout)."""
-    ps = inputs.small_set(1)
-    n_c = 4
+    against FP64 on the unrounded inputs, at the size of the paper's
+    experiment (a jittered 40^3 lattice, 64,000 particles, one force
+    evaluation): at 32 bits the FP32 floor; growing as bits are cut within
+    the single and half layouts, about doubling per bit; lower at exactly
+    16 bits than at 17 (the switch to the half layout)."""
+    ps = inputs.lattice_set(40, 1, order="shuffled")
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
     d0, f0 = oracle_step(orc, ps, n_c)
     e = {}
-    for T in (32, 28, 24, 20, 18, 17, 16, 14, 12, 10):
+    for T in (32, 30, 28, 26, 24, 22, 20, 18, 17, 16, 14, 12, 10):
         t = f"t{T}"
-        pipe = run_gpu(ps, n_c, "f32", prec=sph.precision(t, t, t, 12, 3, 0))
+        pipe = run_gpu(ps, n_c, "f32", prec=sph.precision(t, t, t, 16, 5, 0))
+        assert pipe.status() == 0
         e[T] = rel_rmse(gpu_fields(pipe)["a"], f0["a"])
-    print("RMSE(a) vs bits:", {T: f"{v:.2e}" for T, v in e.items()})
+    print("RMSE(a) vs bits, 64,000 particles:", {T: f"{v:.2e}" for T, v in e.items()})
     assert e[32] < 1e-5
-    for a, b in ((28, 32), (24, 28), (20, 24), (18, 20), (17, 18), (14, 16), (12, 14), (10, 12)):
+    for a, b in ((30, 32), (28, 30), (26, 28), (24, 26), (22, 24), (20, 22), (18, 20), (17, 18),
+                 (14, 16), (12, 14), (10, 12)):
         assert e[a] > e[b], (a, b)
+    for a, b in ((24, 26), (22, 24), (20, 22), (18, 20), (12, 14)):
+        assert 2.5 < e[a] / e[b] < 6.0, (a, b, e[a] / e[b])      # about 4x per two bits cut
     assert e[16] < e[17]
 
 
@@ -969,3 +975,49 @@ def test_occupancy_split_launches(sph, orc):
     d, f = oracle_step(orc, ref, n_c)
     assert_counts(orc, got["nngb"], got["nforce"], d["nngb"], f["nforce"], ref, n_c, tag="split")
     check_fp32(got, d, f, tag="split")
+
+
+# ---------------------------------------------------------------------------
+# keeping the cell list while no particle leaves its cell or sub-cell
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sub_bits,sched", [(0, None), (1, "grid"), (2, "dynamic")])
+def test_keep_cells_equals_rebinning(sph, sub_bits, sched):
+    """A pipeline that keeps its cell list (and work lists) while the kicks
+    count no particle leaving its cell or sub-cell gives records identical
+    bit for bit to one that rebins every step: over kick-only steps (no
+    drift) the list is kept after the first binning; once particles move
+    across cells it is rebuilt, and the moved count equals the number of
+    particles whose cell or sub-cell changed."""
+    import torch
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(20000, 5, f_blob=0.4, sigma=0.05)
+    n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
+    rec = inputs.pack_aos(ps, "f32")
+    kw = dict(sub_bits=sub_bits, sched=sched)
+    keep = Pipeline(rec, n_c, keep_cells=True, **kw)
+    full = Pipeline(rec, n_c, **kw)
+    rebuilt = []
+    for dt_drift in (0.0, 0.0, 0.0, 2e-3, 2e-3, 0.0):
+        for p in (keep, full):
+            p.soa_step(1e-4, dt_drift)
+        torch.cuda.synchronize()
+        rebuilt.append(int(keep.cells.rebin[1].item()))
+        assert keep.records().tobytes() == full.records().tobytes(), (dt_drift, rebuilt)
+    # built once, kept over the kick-only steps, rebuilt after the moves
+    assert rebuilt[:4] == [1, 0, 0, 0] and rebuilt[4] == 1, rebuilt
+    # the count of the last drifting kick: particles whose cell or sub-cell changed
+    x0 = full.records()["x"]
+    keep.bin()
+    keep.convert("full")
+    keep.density()
+    keep.force()
+    keep.kick_drift(0.0, 5e-3)
+    keep.writeback("kick")
+    torch.cuda.synchronize()
+    x1 = keep.records()["x"]
+    R = 1 << sub_bits
+    k0 = np.minimum(np.floor(x0 * n_c * R), n_c * R - 1).astype(np.int64)
+    k1 = np.minimum(np.floor(x1 * n_c * R), n_c * R - 1).astype(np.int64)
+    assert int(keep.cells.rebin[0].item()) == int(np.any(k0 != k1, axis=1).sum()) > 0
+    assert keep.status() == 0
