@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 9
+#define SPH_ABI_VERSION 10
 
 typedef int32_t sph_status;
 enum {
@@ -149,7 +149,10 @@ typedef struct {
  * XCD) of about equal estimated cost. The caller allocates `buf` with at
  * least sph_worklist_size(n, n_c, ti) bytes. A work list describes the cell
  * list it was built from: rebuild it after every sph_bin. `sched` picks how
- * workgroups take items; it changes only the timing, never a result. */
+ * workgroups take items; it changes only the timing, never a result.
+ * max_cells > 1 (merged items) changes the frame in which the positions of
+ * a merged cell's particles are taken (the group's first cell): results
+ * then differ from those of an unmerged list by FP32 rounding only. */
 enum {
   SPH_SCHED_GRID = 0,     /* one workgroup per item, dispatched by the hardware */
   SPH_SCHED_STATIC = 1,   /* persistent grid, items of an XCD's range in turn  */
@@ -160,6 +163,15 @@ typedef struct {
   int32_t sched;          /* SPH_SCHED_*                                  */
   void *buf;              /* device buffer: queues, item count, items     */
   size_t bytes;           /* size of buf                                  */
+  int32_t max_cells;      /* 0 or 1: an item holds slots of one cell; 2..4: */
+                          /* an item may hold all slots of up to that many */
+                          /* x-adjacent cells of one row of a 4x4x4 brick  */
+                          /* (in the same occupancy class) whose particles */
+                          /* fit the tile, so sparse cells share full      */
+                          /* tiles and one candidate neighbourhood; needs  */
+                          /* n_c^3 < 2^29; only sph_worklist /             */
+                          /* _occupancy build merged items                 */
+  int32_t reserved;       /* must be 0                                      */
 } sph_work;
 
 /* ------------------------------------------------------------------ */

@@ -124,6 +124,17 @@ sph_status check_cells(const sph_cells* c, bool need_lists, CellsDev& out) {
   return SPH_OK;
 }
 
+// Merged work items (several sparse cells per item) need the cell ids to fit
+// below the item's cell-count bits
+sph_status check_merge(const sph_work* w, const CellsDev& c) {
+  if (w->reserved != 0) return fail(SPH_E_INVALID, "work->reserved must be 0");
+  if (w->max_cells < 0 || w->max_cells > kMaxMerge)
+    return fail(SPH_E_INVALID, "work->max_cells = %d must be in [0, %d]", w->max_cells, kMaxMerge);
+  if (w->max_cells > 1 && (int64_t)c.n_c * c.n_c * c.n_c >= ((int64_t)1 << kMergeShift))
+    return fail(SPH_E_RANGE, "work->max_cells > 1 needs n_c^3 < 2^%d", kMergeShift);
+  return SPH_OK;
+}
+
 // Work list of a launch over items with tile ti (NULL: one workgroup per cell)
 sph_status check_work(const sph_work* w, const CellsDev& c, int ti, WorkDev& out, bool& use) {
   use = w != nullptr;
@@ -134,6 +145,8 @@ sph_status check_work(const sph_work* w, const CellsDev& c, int ti, WorkDev& out
     return fail(SPH_E_INVALID, "work->sched = %d is not an SPH_SCHED_* value", w->sched);
   if (w->bytes < worklist_bytes(c.n, c.n_c, w->ti))
     return fail(SPH_E_NOMEM, "work->bytes %zu < %zu", w->bytes, worklist_bytes(c.n, c.n_c, w->ti));
+  const sph_status st = check_merge(w, c);
+  if (st != SPH_OK) return st;
   out = work_view(*w, c.n, c.n_c);
   return SPH_OK;
 }
@@ -309,6 +322,7 @@ sph_status sph_worklist_occupancy(const sph_cells* cells, sph_work* work, int32_
                 worklist_bytes(c.n, c.n_c, work->ti));
   if (occ_lo < 0 || occ_hi <= occ_lo)
     return fail(SPH_E_INVALID, "occupancy range [%d, %d) is empty or negative", occ_lo, occ_hi);
+  SPH_TRY(check_merge(work, c));
   WorkDev w = work_view(*work, c.n, c.n_c);
   return hip_status(launch_worklist_range(c, w, nullptr, occ_lo, occ_hi, stream,
                                           c.rebin ? c.rebin + 1 : nullptr),

@@ -3,8 +3,10 @@
 // (Alg. 1 CallQuadratic; Eq. density, Eq. momentum, Eq. energy).
 //
 // One workgroup per (cell, chunk of TI particles): the chunk's particles i
-// are held in registers, K lanes per particle. The workgroup walks the
-// candidates j of the 27 surrounding cells as one flattened index space and
+// are held in registers, K lanes per particle (a chunk may also hold the
+// particles of up to four sparse cells along x, with the cells around all of
+// them as its neighbourhood). The workgroup walks the
+// candidates j of the surrounding cells as one flattened index space and
 // stages into LDS those whose distance to the chunk's bounding box is below
 // the largest support radius (a conservative prune: every operation of the
 // box distance is monotone in the same inputs as the pair test, so no
@@ -214,17 +216,28 @@ __device__ __forceinline__ float group_max(float v) {
   return v;
 }
 
-__device__ __forceinline__ void neighbour_cell(int nb, int cx, int cy, int cz, int n_c, float s,
-                                               int& cn, float& shx, float& shy, float& shz) {
-  int dx = nb % 3 - 1, dy = (nb / 3) % 3 - 1, dz = nb / 9 - 1;
+// Position shift of the cell d cells away along an axis, relative to the
+// chunk's cell: d * s (-s, 0, s exactly; FP32 products beyond, the same
+// value wherever a position is shifted by d cells)
+__device__ __forceinline__ float cell_shift(int d, float s) {
+  return d == 0 ? 0.0f : (d == 1 ? s : (d == -1 ? -s : (float)d * s));
+}
+
+// Neighbour entry nb of a chunk of w - 2 cells along x (w = 3 for a single
+// cell): offsets dx in [-1, w - 2], dy, dz in [-1, 1], nb = (dx + 1) +
+// w ((dy + 1) + 3 (dz + 1)); periodic cell id and the shift of its frame.
+__device__ __forceinline__ void neighbour_cell(int nb, int w, int cx, int cy, int cz, int n_c,
+                                               float s, int& cn, float& shx, float& shy,
+                                               float& shz) {
+  int dx = nb % w - 1, dy = (nb / w) % 3 - 1, dz = nb / (3 * w) - 1;
   int nx = cx + dx, ny = cy + dy, nz = cz + dz;
   nx += (nx < 0) ? n_c : ((nx >= n_c) ? -n_c : 0);
   ny += (ny < 0) ? n_c : ((ny >= n_c) ? -n_c : 0);
   nz += (nz < 0) ? n_c : ((nz >= n_c) ? -n_c : 0);
   cn = nx + n_c * (ny + n_c * nz);
-  shx = dx < 0 ? -s : (dx > 0 ? s : 0.0f);
-  shy = dy < 0 ? -s : (dy > 0 ? s : 0.0f);
-  shz = dz < 0 ? -s : (dz > 0 ? s : 0.0f);
+  shx = cell_shift(dx, s);
+  shy = cell_shift(dy, s);
+  shz = cell_shift(dz, s);
 }
 
 __device__ __forceinline__ float box_dist2(float x, float y, float z, float lox, float loy,
@@ -238,26 +251,35 @@ __device__ __forceinline__ float box_dist2(float x, float y, float z, float lox,
 }
 
 // --------------------------------------------------------------------------
-// Neighbour cells of a chunk's cell: ids, the position shift of each relative
-// to the chunk's cell (delta * s, delta in {-1, 0, 1}), and the support-radius
-// bound of each (gamma_k * max h * (1 + 2^-8), covering storage rounding of h;
-// the cell side when no bound table is given).
+// Neighbour cells of a chunk's cells (m cells along x from the chunk's first
+// cell, m = 1 unless the work list merges sparse cells): ids, the position
+// shift of each relative to the chunk's first cell (delta * s), and the
+// support-radius bound of each (gamma_k * max h * (1 + 2^-8), covering
+// storage rounding of h; the cell side when no bound table is given).
 // --------------------------------------------------------------------------
+constexpr int kMaxNbr = 9 * (kMaxMerge + 2);   // neighbour cells of a merged chunk
 struct NbrCells {
-  int cell[27];
-  float sh[27][3];
-  float hb[27];
-  float hbmax;   // largest hb over the 27 cells
+  int cell[kMaxNbr];
+  float sh[kMaxNbr][3];
+  float hb[kMaxNbr];
+  float hbmax;   // largest hb over the nq cells
+  int nq;       // neighbour cells: 9 (m + 2)
+  signed char d[kMaxNbr][3];   // offsets dx, dy, dz of each cell from the chunk's first cell
 };
 
 __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int cx, int cy,
-                                          int cz, float s32, float gk) {
+                                          int cz, int m, float s32, float gk) {
   const int tid = threadIdx.x;
+  const int w = m + 2, nq = 9 * w;
   float hbv = 0.0f;
-  if (tid < 27) {
+  if (tid == 0) T.nq = nq;
+  if (tid < nq) {
     int cn;
     float shx, shy, shz;
-    neighbour_cell(tid, cx, cy, cz, cd.n_c, s32, cn, shx, shy, shz);
+    neighbour_cell(tid, w, cx, cy, cz, cd.n_c, s32, cn, shx, shy, shz);
+    T.d[tid][0] = (signed char)(tid % w - 1);
+    T.d[tid][1] = (signed char)((tid / w) % 3 - 1);
+    T.d[tid][2] = (signed char)(tid / (3 * w) - 1);
     T.cell[tid] = cn;
     T.sh[tid][0] = shx;
     T.sh[tid][1] = shy;
@@ -265,13 +287,14 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
     hbv = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
     T.hb[tid] = hbv;
   }
-  if (tid < 64) {   // first wave: the largest bound
-    float m = hbv;
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (tid == 0) T.hbmax = m;
+  if (tid < 64) {   // first wave (kMaxNbr <= 64): the largest bound
+    float mx = hbv;
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (tid == 0) T.hbmax = mx;
   }
   __syncthreads();
 }
+static_assert(kMaxNbr <= 64, "the neighbour table is reduced by one wave");
 
 // Block-wide exclusive scan of two ints in thread order; returns the block
 // totals. Two barriers.
@@ -320,10 +343,10 @@ struct RangeTab {
   unsigned char q[NT];
   int scan[2 * (NT / 64)];
   int ntab, total;
-  int qn[27];                   // entries of cell q (0: skipped)
-  int qpre[28];                 // prefix of qn
-  unsigned char qw[27];         // 1: whole cell, 0: sub-cells qr
-  unsigned char qr[27][6];      // local sub-cell ranges x0, x1, y0, y1, z0, z1
+  int qn[kMaxNbr];              // entries of cell q (0: skipped)
+  int qpre[kMaxNbr + 1];        // prefix of qn
+  unsigned char qw[kMaxNbr];    // 1: whole cell, 0: sub-cells qr
+  unsigned char qr[kMaxNbr][6]; // local sub-cell ranges x0, x1, y0, y1, z0, z1
 };
 
 // A neighbour cell is split into its R^3 sub-cells only when it holds more
@@ -331,7 +354,7 @@ struct RangeTab {
 // cell costs less than the table work of its sub-cells.
 constexpr int kSplitFactor = 2;
 
-// The candidate ranges of a chunk: for each of the 27 neighbour cells q
+// The candidate ranges of a chunk: for each of the nq neighbour cells q
 // with bound(q) > 0, the sub-cells (R = 2^sub_bits per axis) of q whose
 // boxes lie within bound(q) of the chunk box [lo, hi], or the whole of q
 // (a superset) when q is sparse. Entries are processed in
@@ -347,9 +370,10 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
   const float inv = (float)R / s32;
   const int* sstart = sb ? cd.sub_start : cd.start;
   const int tid = threadIdx.x;
-  if (tid < 27) {
+  const int nq = T.nq;
+  if (tid < nq) {
     const int q = tid;
-    const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+    const int dx = T.d[q][0], dy = T.d[q][1], dz = T.d[q][2];
     const float bq = bound(q);
     int n = 0;
     if (bq > 0.0f) {
@@ -381,20 +405,20 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
   __syncthreads();
   if (tid == 0) {
     int acc = 0;
-    for (int q = 0; q < 27; ++q) {
+    for (int q = 0; q < nq; ++q) {
       tab.qpre[q] = acc;
       acc += tab.qn[q];
     }
-    tab.qpre[27] = acc;
+    tab.qpre[nq] = acc;
   }
   __syncthreads();
-  const int NQ = tab.qpre[27];
+  const int NQ = tab.qpre[nq];
   for (int b0 = 0; b0 < NQ; b0 += NT) {
     const int t = b0 + tid;
     bool ok = t < NQ;
     int st = 0, cnt = 0, q = 0;
     if (ok) {
-      int lo = 0, hi = 26;   // last q with qpre[q] <= t
+      int lo = 0, hi = nq - 1;   // last q with qpre[q] <= t
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tab.qpre[mid] <= t) lo = mid;
@@ -403,7 +427,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
       q = lo;
       const int e = t - tab.qpre[q];
       const int c = T.cell[q];
-      const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+      const int dx = T.d[q][0], dy = T.d[q][1], dz = T.d[q][2];
       float bx0, bx1, by0, by1, bz0, bz1;
       if (tab.qw[q]) {
         const float mg = s32 * 0x1p-8f;       // rounding margin of stored offsets
@@ -628,10 +652,27 @@ __device__ __forceinline__ float dist2_m2(float m2x, float m2y, float m2z, float
 //     atomic counter and then steal from the other queues; the counter of
 //     the next item is bumped while the current one is processed, so the
 //     atomic's latency overlaps the work.
-// The chunk callback takes (cell, c0, c1, only_q, out, obase): slots
-// [c0, c1) of `cell`, the neighbour cell index q (0..26) the j particles are
-// restricted to (-1: all 27), and the task result records (out == nullptr:
-// the full loop's outputs) with slot i's record at out[obase + i].
+// A merged item (the work list's max_cells > 1) packs m - 1 into the bits
+// of the cell id from kMergeShift up: its slots are those of the m cells
+// cell, cell + 1, ... of one brick row, at most TI of them.
+// The chunk callback takes (cell, m, c0, c1, only_q, out, obase): slots
+// [c0, c1) of the m cells from `cell` along x, the neighbour cell index q
+// (0..26) the j particles are restricted to (-1: all of them; only with
+// m = 1), and the task result records (out == nullptr: the full loop's
+// outputs) with slot i's record at out[obase + i].
+// Position of slot i of a chunk over the m cells from `cell` along x,
+// relative to `cell`: the stored offset in i's own cell, shifted by that
+// cell's distance from `cell` with the same expression as the candidates'
+// shifts, so that i meets its own candidate copy at r = 0 exactly.
+template <class Src>
+__device__ __forceinline__ void chunk_pos(const Src& src, const CellsDev& cd, int i, int cell,
+                                          int m, float s32, float& x, float& y, float& z) {
+  int d = 0;
+  for (int k = 1; k < m; ++k) d += i >= clamp_slot(cd.start[cell + k], cd.n) ? 1 : 0;
+  src.pos(i, cell + d, cd.n_c, x, y, z);
+  x = shifted(x, cell_shift(d, s32));
+}
+
 struct LoopItems {
   WorkDev wk;
 
@@ -642,16 +683,26 @@ struct LoopItems {
     const int cs = clamp_slot(cd.start[cell], cd.n);
     const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), cs);
     for (int base = cs; base < ce; base += TI)
-      chunk(cell, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
+      chunk(cell, 1, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
     return;
   }
   const int C = cd.n_c * cd.n_c * cd.n_c;
   auto item = [&](int it) {
     const int2 v = wk.items[it];
-    const int cell = min(max(v.x, 0), C - 1);
-    const int ce = max(clamp_slot(cd.start[cell + 1], cd.n), 0);
+    int cell = v.x, m = 1;
+    if (wk.merge > 1) {
+      cell = v.x & ((1 << kMergeShift) - 1);
+      m = (int)((unsigned)v.x >> kMergeShift) + 1;
+    }
+    cell = min(max(cell, 0), C - 1);
+    if (m > 1) {   // stay within the row (the list builder guarantees it)
+      int cx, cy, cz;
+      cell_coords(cell, cd.n_c, cx, cy, cz);
+      m = min(min(m, kMaxMerge), cd.n_c - cx);
+    }
+    const int ce = max(clamp_slot(cd.start[cell + m], cd.n), 0);
     const int base = clamp_slot(v.y, ce);
-    chunk(cell, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
+    chunk(cell, m, base, min(base + TI, ce), -1, (sph_task_result*)nullptr, 0);
   };
   const int x = blockIdx.x & (kQueues - 1);
   const int total = min(wk.meta[0], wk.capacity);
@@ -738,7 +789,7 @@ struct TaskItems {
     const int o = min(max(out_off[ti_], 0), n_out);
     // records past n_out are dropped: clamp the range to what fits
     const int c1o = min(c1, c0 + max(n_out - (o + (c0 - ib)), 0));
-    chunk(ci, c0, c1o, nbr_index(ci, cj, cd.n_c), out, o - ib);
+    chunk(ci, 1, c0, c1o, nbr_index(ci, cj, cd.n_c), out, o - ib);
   }
 };
 
@@ -775,16 +826,16 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
   const int gi = tid / K, kk = tid % K;
   const float gk = ph.gamma_k;
 
-  items.run(cd, TI, [&](int cell, int c0, int c1, int only_q, sph_task_result* tout,
+  items.run(cd, TI, [&](int cell, int m, int c0, int c1, int only_q, sph_task_result* tout,
                         int tbase) {
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
-    build_nbr(T, cd, cx, cy, cz, s32, gk);
+    build_nbr(T, cd, cx, cy, cz, m, s32, gk);
     const int i = c0 + gi;
     const bool vi = i < c1;
     float xi = 0.f, yi = 0.f, zi = 0.f, hi = 0.f, ui = 0.f;
     if (vi) {
-      src.pos(i, cell, n_c, xi, yi, zi);
+      chunk_pos(src, cd, i, cell, m, s32, xi, yi, zi);
       hi = src.hsml(i);
       ui = src.uint(i);
     }
@@ -939,18 +990,18 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
   const float gk = ph.gamma_k;
   const float alpha = ph.alpha, beta = ph.beta;
 
-  items.run(cd, TI, [&](int cell, int c0, int c1, int only_q, sph_task_result* tout,
+  items.run(cd, TI, [&](int cell, int m, int c0, int c1, int only_q, sph_task_result* tout,
                         int tbase) {
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
-    build_nbr(T, cd, cx, cy, cz, s32, gk);
+    build_nbr(T, cd, cx, cy, cz, m, s32, gk);
     const int i = c0 + gi;
     const bool vi = i < c1;
     // lanes without a particle sit far outside the box and accept nothing
     float xi = 1e30f, yi = 1e30f, zi = 1e30f, hi = 1.f, vxi = 0.f, vyi = 0.f, vzi = 0.f;
     float rhoi = 1.f, fi = 1.f, Pi_ = 0.f, ci = 0.f;
     if (vi) {
-      src.pos(i, cell, n_c, xi, yi, zi);
+      chunk_pos(src, cd, i, cell, m, s32, xi, yi, zi);
       src.vel(i, vxi, vyi, vzi);
       hi = src.hsml(i);
       src.dens_in(i, rhoi, fi, Pi_, ci);

@@ -66,12 +66,15 @@ struct WorkDev {
   int ti;
   int sched;
   int capacity;
+  int merge;           // > 1: items may span that many cells (cell | (m - 1) << 29)
   int32_t* counters;   // [8] next item index of each queue
   int32_t* meta;       // [0] item count, [1..9] range boundaries
   int2* items;         // [capacity]
 };
 constexpr int kQueues = 8;
 constexpr size_t kWorkHeader = 256;   // bytes before the items
+constexpr int kMaxMerge = 4;          // cells per merged work item
+constexpr int kMergeShift = 29;       // item.x = cell | (cells - 1) << kMergeShift
 
 // --- launchers (return hipError_t of the launch) ---
 size_t bin_workspace_bytes(int n, int n_c, int sub_bits);

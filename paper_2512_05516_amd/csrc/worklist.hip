@@ -51,12 +51,50 @@ __device__ __forceinline__ int cell_count(const int32_t* __restrict__ start, int
   return max(min(max(start[c + 1], 0), n) - a, 0);
 }
 
+// Merged items: in a launch over an occupancy class, consecutive non-empty
+// cells of the class along x within one row of a brick (bricks are 4 cells
+// wide) are grouped greedily from the row's first cell, up to `merge` cells
+// whose particles fit one tile; a cell outside the class, an empty cell or
+// a cell with more than ti particles ends a group and is not merged. The
+// group's first cell carries one item for all of its slots (a contiguous
+// slot range: cells of a row are consecutive in id order); the others carry
+// none. Returns the group size m of cell c's group if c starts one (1 for an
+// unmerged cell), 0 if c is inside a group started by another cell.
+__device__ __forceinline__ int merge_group(const int32_t* __restrict__ start, int n, int n_c,
+                                           int ti, int merge, int occ_lo, int occ_hi, int c) {
+  int cx, cy, cz;
+  cell_coords(c, n_c, cx, cy, cz);
+  const int x0 = cx - cx % kBrick, tx = min(kBrick, n_c - x0);
+  int rc[kBrick];
+#pragma unroll
+  for (int l = 0; l < kBrick; ++l) {
+    int k = -1;
+    if (l < tx) {
+      k = cell_count(start, (x0 + l) + n_c * (cy + n_c * cz), n);
+      if (k <= 0 || k < occ_lo || k >= occ_hi || k > ti) k = -1;   // not mergeable
+    }
+    rc[l] = k;
+  }
+  int l = 0;
+  while (l < tx) {
+    int m = 1;
+    if (rc[l] > 0) {
+      int sum = rc[l];
+      while (l + m < tx && m < merge && rc[l + m] > 0 && sum + rc[l + m] <= ti) sum += rc[l + m++];
+    }
+    if (cx - x0 == l) return m;
+    if (cx - x0 < l + m) return 0;
+    l += m;
+  }
+  return 1;
+}
+
 // Items per cell and the cell's cost estimate, clamped so that the sum over
 // all cells fits in int32.
 __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict__ start, int n_c,
                                                         int n, int ti, int cost_cap,
                                                         const uint8_t* __restrict__ active,
-                                                        int occ_lo, int occ_hi,
+                                                        int occ_lo, int occ_hi, int merge,
                                                         int32_t* __restrict__ pos,
                                                         int32_t* __restrict__ cost,
                                                         const int32_t* gate) {
@@ -78,7 +116,12 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
     for (int k = a; k < a + cnt && !any; ++k) any = active[k] != 0;
     if (!any) cnt = 0;
   }
-  pos[j] = (cnt + ti - 1) / ti;
+  if (merge > 1 && cnt > 0 && cnt <= ti) {
+    const int m = merge_group(start, n, n_c, ti, merge, occ_lo, occ_hi, c);
+    pos[j] = m > 0 ? 1 : 0;          // the group's first cell holds its one item
+  } else {
+    pos[j] = (cnt + ti - 1) / ti;
+  }
   int cx, cy, cz;
   cell_coords(c, n_c, cx, cy, cz);
   int64_t nb = 0;
@@ -101,7 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_wl_count(const int32_t* __restrict
 }
 
 __global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict__ start, int n_c,
-                                                       int n, int ti, int capacity,
+                                                       int n, int ti, int capacity, int merge,
+                                                       int occ_lo, int occ_hi,
                                                        const int32_t* __restrict__ pos,
                                                        int2* __restrict__ items,
                                                        const int32_t* gate) {
@@ -113,6 +157,11 @@ __global__ __launch_bounds__(kThreads) void k_wl_fill(const int32_t* __restrict_
   const int a = min(max(start[c], 0), n), b = min(max(start[c + 1], a), n);
   int o = pos[j];
   const int end = min(pos[j + 1], capacity);   // this cell's items (none if filtered out)
+  if (merge > 1 && o < end && b - a <= ti) {   // one item: the cell or its merged group
+    const int m = max(merge_group(start, n, n_c, ti, merge, occ_lo, occ_hi, c), 1);
+    items[o] = make_int2(c | ((m - 1) << kMergeShift), a);
+    return;
+  }
   for (int f = a; f < b && o < end; f += ti, ++o) items[o] = make_int2(c, f);
 }
 
@@ -176,15 +225,17 @@ hipError_t launch_worklist_range(const CellsDev& c, const WorkDev& w, const uint
   const int C = c.n_c * c.n_c * c.n_c;
   WlLayout L = wl_layout(reinterpret_cast<char*>(w.counters), C);
   const int cost_cap = (int)((((int64_t)1 << 31) - 1) / ((int64_t)C + 1));
+  // merged items only for plain lists (the h iteration's lists filter cells)
+  const int merge = active ? 1 : w.merge;
   k_wl_count<<<cdiv(C + 1, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, cost_cap,
-                                                         active, occ_lo, occ_hi, L.pos, L.cost,
-                                                         gate);
+                                                         active, occ_lo, occ_hi, merge, L.pos,
+                                                         L.cost, gate);
   hipError_t e = scan_i32(L.pos, C + 1, L.partials, s, gate);
   if (e != hipSuccess) return e;
   e = scan_i32(L.cost, C + 1, L.partials, s, gate);
   if (e != hipSuccess) return e;
-  k_wl_fill<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, w.capacity, L.pos,
-                                                    w.items, gate);
+  k_wl_fill<<<cdiv(C, kThreads), kThreads, 0, s>>>(c.start, c.n_c, c.n, w.ti, w.capacity, merge,
+                                                    occ_lo, occ_hi, L.pos, w.items, gate);
   k_wl_meta<<<1, 64, 0, s>>>(L.pos, L.cost, C, w.capacity, w.counters, w.meta, gate);
   return hipGetLastError();
 }
@@ -194,6 +245,7 @@ WorkDev work_view(const sph_work& w, int n, int n_c) {
   d.ti = w.ti;
   d.sched = w.sched;
   d.capacity = worklist_capacity(n, n_c, w.ti);
+  d.merge = w.max_cells > 1 ? min(w.max_cells, kMaxMerge) : 1;
   char* base = static_cast<char*>(w.buf);
   d.counters = reinterpret_cast<int32_t*>(base);
   d.meta = reinterpret_cast<int32_t*>(base + 64);

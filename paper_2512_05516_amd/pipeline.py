@@ -15,7 +15,7 @@ from . import sphmi
 class Pipeline:
     def __init__(self, aos_np: np.ndarray, n_c: int, prec=None, device="cuda", til=None,
                  prm=None, stream=None, sub_bits: int = 0, sched=None,
-                 til_force=None, split=None, tally=False, keep_cells=False):
+                 til_force=None, split=None, tally=False, keep_cells=False, max_cells=1):
         import torch
         self.torch = torch
         self.n = int(aos_np.shape[0])
@@ -35,7 +35,8 @@ class Pipeline:
         self.cells = sphmi.DeviceCells(self.n, self.n_c, device, sub_bits, tally=tally,
                                        rebin=keep_cells)
         # sched: None (one workgroup per cell) or a work-list schedule, one
-        # for both loops or a (density, force) pair
+        # for both loops or a (density, force) pair; max_cells > 1: the work
+        # lists merge up to that many sparse cells along x into one item
         sd, sf = sched if isinstance(sched, (tuple, list)) else (sched, sched)
         self.sched = (sd, sf)
         self.work = self.work_force = None
@@ -43,27 +44,30 @@ class Pipeline:
         ti_d = self.til.ti or 64
         ti_f = self.til_force.ti or 64
         if sd:
-            self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device, sd)
+            self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device, sd, max_cells=max_cells)
             self._lists.append(self.work)
         if sf:
             if self.work is not None and ti_f == ti_d:
                 self.work_force = self.work.with_sched(sf)
             else:
-                self.work_force = sphmi.DeviceWork(self.n, self.n_c, ti_f, device, sf)
+                self.work_force = sphmi.DeviceWork(self.n, self.n_c, ti_f, device, sf,
+                                                   max_cells=max_cells)
                 self._lists.append(self.work_force)
-        # split: per loop ("density" / "force") None or (T, (ti, k), sched):
-        # cells with fewer than T particles run as a launch of their own with
-        # that tile and schedule, the other cells with the loop's own tile and
-        # schedule (which must then be a work-list schedule)
+        # split: per loop ("density" / "force") None or (T, (ti, k), sched)
+        # or (T, (ti, k), sched, max_cells): cells with fewer than T
+        # particles run as a launch of their own with that tile and schedule
+        # (with max_cells > 1, up to that many such cells along x share a
+        # work item), the other cells with the loop's own tile and schedule
         self.split = dict(split or {})
         self._parts = {}
         for loop, main_til, main_sched in (("density", self.til, sd), ("force", self.til_force, sf)):
             sp = self.split.get(loop)
             if not sp:
                 continue
-            T, (ti, k), small_sched = sp
+            T, (ti, k), small_sched = sp[:3]
+            merge = int(sp[3]) if len(sp) > 3 else 1
             big_sched = main_sched or "grid"
-            ws = sphmi.DeviceWork(self.n, self.n_c, ti, device, small_sched)
+            ws = sphmi.DeviceWork(self.n, self.n_c, ti, device, small_sched, max_cells=merge)
             wl = sphmi.DeviceWork(self.n, self.n_c, main_til.ti or 64, device, big_sched)
             self._parts[loop] = [(sphmi.tile(ti, k), ws, (0, int(T))),
                                  (main_til, wl, (int(T), 2 ** 31 - 1))]

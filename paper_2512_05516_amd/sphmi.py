@@ -62,7 +62,7 @@ class Cells(C.Structure):
 
 class Work(C.Structure):
     _fields_ = [("ti", C.c_int32), ("sched", C.c_int32), ("buf", C.c_void_p),
-                ("bytes", C.c_size_t)]
+                ("bytes", C.c_size_t), ("max_cells", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Soa(C.Structure):
@@ -309,18 +309,22 @@ SCHEDS = {"grid": 0, "static": 1, "dynamic": 2}
 class DeviceWork:
     """Work-list buffer of the pair kernels for tile size ti, taken with
     schedule `sched` ("grid", "static" or "dynamic"); with_sched() gives a
-    view of the same list under another schedule."""
+    view of the same list under another schedule. max_cells > 1 lets an
+    item hold the slots of up to that many (<= 4) sparse cells along x."""
 
-    def __init__(self, n: int, n_c: int, ti: int, device="cuda", sched="grid", _buf=None):
+    def __init__(self, n: int, n_c: int, ti: int, device="cuda", sched="grid", _buf=None,
+                 max_cells: int = 1):
         import torch
         nbytes = worklist_size(n, n_c, ti)
         self.n, self.n_c, self.ti, self.sched = n, n_c, int(ti), sched
+        self.max_cells = int(max_cells)
         self.buf = (_buf if _buf is not None else
                     torch.empty(nbytes, dtype=torch.uint8, device=device))
-        self._s = Work(int(ti), SCHEDS[sched], self.buf.data_ptr(), nbytes)
+        self._s = Work(int(ti), SCHEDS[sched], self.buf.data_ptr(), nbytes, self.max_cells, 0)
 
     def with_sched(self, sched: str) -> "DeviceWork":
-        return DeviceWork(self.n, self.n_c, self.ti, sched=sched, _buf=self.buf)
+        return DeviceWork(self.n, self.n_c, self.ti, sched=sched, _buf=self.buf,
+                          max_cells=self.max_cells)
 
     @property
     def struct(self) -> Work:

@@ -12,7 +12,8 @@ fastest candidate of each loop, and keeps the result in a JSON cache keyed
 by the workload's signature (particle count, cells, occupancy statistics,
 storage formats, device). On cells of very uneven occupancy it then tries
 splitting each loop into two launches by an occupancy threshold T: the
-cells with fewer than T particles with a tile of their own, the others with
+cells with fewer than T particles with a tile of their own (optionally with
+up to four such cells along x merged into one work item), the others with
 the loop's tile, and keeps a split that is faster than the single launch.
 Before that, the fastest few candidates of each loop (timed back to back on
 their own) are timed again where the loop runs in a step, right after the
@@ -20,7 +21,8 @@ kernel that precedes it (bin, convert, density, force), and the fastest
 there is kept: a schedule that partitions a resident grid statically can
 lose several per cent in that position while leading in isolation.
 The choice changes only timings: every candidate computes the same
-interactions.
+interactions (merged items take a merged cell's positions relative to the
+group's first cell, which changes FP32 rounding only).
 """
 import json
 import os
@@ -72,8 +74,16 @@ def _store(path, cache):
 
 
 SPLIT_THRESHOLDS = (32, 48, 64)
-SPLIT_SMALL = ((32, 2, "grid"), (32, 8, "grid"), (16, 4, "grid"), (64, 1, "grid"))
+# small-cell launches: (ti, k, sched, cells merged per work item at most)
+SPLIT_SMALL = ((32, 2, "grid", 1), (32, 8, "grid", 1), (16, 4, "grid", 1), (64, 1, "grid", 1),
+               (32, 2, "grid", 4), (64, 1, "grid", 4), (64, 2, "grid", 4))
 SPLIT_LARGE = ((64, 4, "dynamic"), (32, 2, "grid"), (64, 4, "static"))
+
+
+def _small_str(sm) -> str:
+    """'ti x k sched' of a small-cell launch, '+ merge m' when items merge cells."""
+    out = f"{sm[0]}x{sm[1]} {sm[2]}"
+    return out + (f" merge {sm[3]}" if len(sm) > 3 and sm[3] > 1 else "")
 
 
 def _time_parts(pipe, loop, parts, reps):
@@ -102,10 +112,10 @@ def tune_split(pipe, single: dict, reps: int = 3, log=None) -> dict:
     out = {}
     works = {}
 
-    def work(ti, sched, rng):
-        key = (ti, sched, rng)
+    def work(ti, sched, rng, merge=1):
+        key = (ti, sched, rng, merge)
         if key not in works:
-            w = sphmi.DeviceWork(pipe.n, pipe.n_c, ti, pipe.aos.device, sched)
+            w = sphmi.DeviceWork(pipe.n, pipe.n_c, ti, pipe.aos.device, sched, max_cells=merge)
             sphmi.worklist(pipe.cells, w, None, rng)
             works[key] = w
         return works[key]
@@ -118,18 +128,18 @@ def tune_split(pipe, single: dict, reps: int = 3, log=None) -> dict:
             frac = occ[occ < T].sum() / max(occ.sum(), 1)
             if not 0.05 < frac < 0.95:
                 continue
-            for (ts, ks, ss) in SPLIT_SMALL:
+            for (ts, ks, ss, ms_) in SPLIT_SMALL:
                 for (tl, kl, sl) in sorted(large):
-                    parts = [(sphmi.tile(ts, ks), work(ts, ss, (0, T))),
+                    parts = [(sphmi.tile(ts, ks), work(ts, ss, (0, T), ms_)),
                              (sphmi.tile(tl, kl), work(tl, sl, (T, 2 ** 31 - 1)))]
                     ms = _time_parts(pipe, loop, parts, reps)
                     if best is None or ms < best[0]:
-                        best = (ms, T, (ts, ks, ss), (tl, kl, sl))
+                        best = (ms, T, (ts, ks, ss, ms_), (tl, kl, sl))
         if best is not None and best[0] < 0.97 * s["ms"]:
             ms, T, sm, lg = best
             out[loop] = {"threshold": T, "small": list(sm), "large": list(lg), "ms": ms}
             if log:
-                log(f"tune split {loop}: cells < {T} {sm[0]}x{sm[1]} {sm[2]}, others "
+                log(f"tune split {loop}: cells < {T} {_small_str(sm)}, others "
                     f"{lg[0]}x{lg[1]} {lg[2]}: {ms:.3f} ms (single {s['ms']:.3f} ms)")
     del works
     return out
@@ -274,7 +284,8 @@ def pipeline_kwargs(choice: dict) -> dict:
         if loop in sp:
             s = sp[loop]
             c["ti"], c["k"], c["sched"] = s["large"]
-            split[loop] = (s["threshold"], (s["small"][0], s["small"][1]), s["small"][2])
+            sm = list(s["small"]) + [1] * (4 - len(s["small"]))
+            split[loop] = (s["threshold"], (sm[0], sm[1]), sm[2], sm[3])
     return {"sub_bits": choice["sub_bits"], "til": sphmi.tile(d["ti"], d["k"]),
             "til_force": sphmi.tile(f["ti"], f["k"]), "sched": (d["sched"], f["sched"]),
             "split": split}
@@ -286,8 +297,8 @@ def describe(choice: dict) -> str:
     for loop in ("density", "force"):
         if loop in sp:
             s = sp[loop]
-            out.append(f"{loop} cells < {s['threshold']}: {s['small'][0]}x{s['small'][1]} "
-                       f"{s['small'][2]}, others {s['large'][0]}x{s['large'][1]} {s['large'][2]}")
+            out.append(f"{loop} cells < {s['threshold']}: {_small_str(s['small'])}, "
+                       f"others {s['large'][0]}x{s['large'][1]} {s['large'][2]}")
         else:
             c = choice[loop]
             out.append(f"{loop} {c['ti']}x{c['k']} {c['sched'] or 'per-cell'}")

@@ -41,7 +41,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 9
+    assert sph.abi_version() == 10
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)
@@ -169,6 +169,15 @@ def test_host_side_validation(sph):
                              C.byref(sph.params()), sph.Tile(64, 4), C.byref(wk),
                              None) == sph.SPH_E_INVALID
         assert "sched" in sph.last_error()
+    # merged work items: max_cells in [0, 4], reserved 0
+    for mc, rs in ((5, 0), (-1, 0), (4, 1)):
+        wk = sph.Work(64, 0, C.c_void_p(0x7000), 1 << 30, mc, rs)
+        assert L.sph_worklist(C.byref(cells), C.byref(wk), None) == sph.SPH_E_INVALID
+        assert L.sph_density(C.byref(soa), C.byref(sph.precision()), C.byref(cells),
+                             C.byref(sph.params()), sph.Tile(64, 4), C.byref(wk),
+                             None) == sph.SPH_E_INVALID
+    wk = sph.Work(64, 0, C.c_void_p(0x7000), 1 << 44, 2, 0)   # cell ids need n_c^3 < 2^29
+    assert L.sph_worklist(C.byref(_fake_cells(sph, 16, 820)), C.byref(wk), None) == sph.SPH_E_RANGE
     # sub-cells: range and the required sub_start table
     assert L.sph_bin(C.c_void_p(0x3000), C.byref(lay), C.byref(_fake_cells(sph, sub_bits=4)), ws,
                      1 << 30, None) == sph.SPH_E_RANGE

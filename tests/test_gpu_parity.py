@@ -219,24 +219,64 @@ def test_host_convert_matches_device(sph, kind):
             assert torch.equal(a.view(torch.uint8), b.view(torch.uint8)), name
 
 
-def _worklist_reference(start, n, n_c, ti):
+def _merge_group(counts, n_c, ti, merge, occ, c):
+    """Size of the merged group cell c starts (0 inside another cell's
+    group): cells of one 4-cell brick row along x, grouped greedily from the
+    row's first cell; a cell joins when it is non-empty, in the occupancy
+    class, holds at most ti particles, and the group stays within `merge`
+    cells and ti particles."""
+    cx, cy, cz = c % n_c, (c // n_c) % n_c, c // (n_c * n_c)
+    x0 = cx - cx % 4
+    row = [int(counts[x + n_c * (cy + n_c * cz)]) for x in range(x0, min(x0 + 4, n_c))]
+    ok = [0 < k <= ti and occ[0] <= k < occ[1] for k in row]
+    l = 0
+    while l < len(row):
+        m = 1
+        if ok[l]:
+            tot = row[l]
+            while l + m < len(row) and m < merge and ok[l + m] and tot + row[l + m] <= ti:
+                tot += row[l + m]
+                m += 1
+        if cx - x0 == l:
+            return m
+        if cx - x0 < l + m:
+            return 0
+        l += m
+    return 1
+
+
+def _worklist_reference(start, n, n_c, ti, merge=1, occ=(0, 2 ** 31 - 1)):
     """Items and XCD range boundaries of the work list, rebuilt on the host
-    from the cell table: items (cell, first slot) with the cells in brick
-    order; the cost of a cell is ceil(count * min(count of its 27 cells,
-    27 * 64) / 4096), clamped so the sum fits in int32; range q starts at the
-    first item of the first cell (in brick order) whose cost prefix reaches
+    from the cell table: items (cell, first slot) with the cells of the
+    occupancy class in brick order; with merge > 1 a cell of at most ti
+    particles instead carries one item (cell | (m - 1) << 29, its first
+    slot) if it starts a merged group of m cells and none inside one. The
+    cost of a cell is ceil(count * min(count of its 27 cells, 27 * 64) /
+    4096), clamped so the sum fits in int32; range q starts at the first
+    item of the first cell (in brick order) whose cost prefix reaches
     ceil(q * total / 8)."""
     C = n_c ** 3
     order = brick_order(n_c)
     counts = np.diff(start).astype(np.int64)
-    items = [(c, f) for c in order for f in range(start[c], start[c + 1], ti)]
+    cls = np.where((counts >= occ[0]) & (counts < occ[1]), counts, 0)
+    items, npos = [], []
+    for c in order:
+        k = int(cls[c])
+        if merge > 1 and 0 < k <= ti:
+            m = _merge_group(counts, n_c, ti, merge, occ, int(c))
+            if m > 0:
+                items.append((int(c) | ((m - 1) << 29), int(start[c])))
+            npos.append(1 if m > 0 else 0)
+        else:
+            items += [(int(c), f) for f in range(start[c], start[c] + k, ti)]
+            npos.append((k + ti - 1) // ti)
     grid = counts.reshape(n_c, n_c, n_c)
     nb = sum(np.roll(grid, (dz, dy, dx), axis=(0, 1, 2))
              for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)).reshape(-1)
     cap = (2 ** 31 - 1) // (C + 1)
-    cost = np.minimum((counts * np.minimum(nb, 27 * 64) + 4095) >> 12, cap)[order]
+    cost = np.minimum((cls * np.minimum(nb, 27 * 64) + 4095) >> 12, cap)[order]
     prefix = np.concatenate([[0], np.cumsum(cost)])
-    pos = np.concatenate([[0], np.cumsum((counts[order] + ti - 1) // ti)])
+    pos = np.concatenate([[0], np.cumsum(npos)])
     total = len(items)
     bounds = [0]
     for q in range(1, 8):
@@ -245,6 +285,14 @@ def _worklist_reference(start, n, n_c, ti):
         bounds.append(min(int(pos[c]), total))
     bounds.append(total)
     return np.array(items, np.int32).reshape(-1, 2), np.array(bounds, np.int32)
+
+
+def _read_worklist(w, n, n_c):
+    buf = w.buf.cpu().numpy()
+    meta = buf[64:104].view(np.int32)
+    cap = (n + (w.ti - 1) * min(n_c ** 3, n)) // w.ti + 1
+    items = buf[len(buf) - 8 * cap:].view(np.int32).reshape(-1, 2)[:meta[0]]
+    return items, meta, cap
 
 
 @pytest.mark.parametrize("ti", [16, 64, 128])
@@ -259,16 +307,52 @@ def test_worklist_bit_exact(sph, ti):
     torch.cuda.synchronize()
     start = pipe.cells.cell_start.cpu().numpy()
     items_ref, bounds_ref = _worklist_reference(start, ps.n, n_c, ti)
-    buf = pipe.work.buf.cpu().numpy()
-    meta = buf[64:104].view(np.int32)
-    C = n_c ** 3
-    cap = (ps.n + (ti - 1) * min(C, ps.n)) // ti + 1
+    items, meta, cap = _read_worklist(pipe.work, ps.n, n_c)
     assert len(items_ref) <= cap
     assert meta[0] == len(items_ref)
-    items = buf[len(buf) - 8 * cap:].view(np.int32).reshape(-1, 2)[:meta[0]]
     assert np.array_equal(items, items_ref)
     assert np.array_equal(meta[1:10], bounds_ref)
     assert np.all(np.diff(bounds_ref) >= 0)
+
+
+@pytest.mark.parametrize("ti,merge,occ", [(64, 4, (0, 2 ** 31 - 1)), (32, 4, (0, 24)),
+                                          (64, 2, (0, 2 ** 31 - 1)), (16, 3, (0, 48))])
+def test_worklist_merged_bit_exact(sph, ti, merge, occ):
+    """Merged work items (max_cells > 1) against the host rebuild, bit for
+    bit, and as a partition: every slot of the class's cells lies in exactly
+    one item, an item covers at most ti slots, and a merged item's cells are
+    consecutive along x within one brick row."""
+    import torch
+    ps = inputs.clustered_set(30000, 5, f_blob=0.5, sigma=0.05)
+    keep = ~((ps.x[:, 0] > 0.30) & (ps.x[:, 0] < 0.52))
+    ps = ps.subset(np.nonzero(keep)[0])
+    n_c = 13                      # partial bricks at the upper box edge
+    cells = sph.DeviceCells(ps.n, n_c, "cuda")
+    aos = torch.from_numpy(inputs.pack_aos(ps, "f32").view(np.uint8).reshape(-1).copy()).cuda()
+    ws = torch.empty(sph.bin_workspace_size(ps.n, n_c), dtype=torch.uint8, device="cuda")
+    sph.bin(aos, sph.layout_from_dtype(inputs.AOS_F32), cells, ws)
+    w = sph.DeviceWork(ps.n, n_c, ti, "cuda", "grid", max_cells=merge)
+    sph.worklist(cells, w, None, occ)
+    torch.cuda.synchronize()
+    start = cells.cell_start.cpu().numpy()
+    items_ref, bounds_ref = _worklist_reference(start, ps.n, n_c, ti, merge, occ)
+    items, meta, cap = _read_worklist(w, ps.n, n_c)
+    assert (items_ref[:, 0] >> 29).max() > 0          # some items do merge
+    assert meta[0] == len(items_ref)
+    assert np.array_equal(items, items_ref)
+    assert np.array_equal(meta[1:10], bounds_ref)
+    counts = np.diff(start)
+    covered = np.zeros(ps.n, np.int32)
+    for v, f in items:
+        c, m = int(v) & ((1 << 29) - 1), (int(v) >> 29) + 1
+        if m > 1:
+            assert c % n_c + m - 1 < n_c and (c % n_c) // 4 == (c % n_c + m - 1) // 4
+            assert f == start[c] and start[c + m] - f <= ti
+            covered[f:start[c + m]] += 1
+        else:
+            covered[f:min(f + ti, start[c + 1])] += 1
+    in_cls = np.repeat((counts >= occ[0]) & (counts < occ[1]), counts)
+    assert np.array_equal(covered, in_cls.astype(np.int32))
 
 
 # ---------------------------------------------------------------------------
@@ -442,7 +526,10 @@ def test_coincident_positions(sph, orc):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("mode", [{}, {"sub_bits": 2, "sched": "dynamic"},
-                                  {"sub_bits": 1, "sched": ("grid", "static")}])
+                                  {"sub_bits": 1, "sched": ("grid", "static")},
+                                  {"sub_bits": 1, "sched": "grid",
+                                   "split": {"density": (32, (32, 2), "grid", 4),
+                                             "force": (32, (64, 1), "grid", 4)}}])
 def test_aos_equals_soa_bitwise(sph, mode):
     from paper_2512_05516_amd.pipeline import Pipeline
     ps = inputs.clustered_set(20000, 9, f_blob=0.4, sigma=0.05)
@@ -975,6 +1062,59 @@ def test_occupancy_split_launches(sph, orc):
     d, f = oracle_step(orc, ref, n_c)
     assert_counts(orc, got["nngb"], got["nforce"], d["nngb"], f["nforce"], ref, n_c, tag="split")
     check_fp32(got, d, f, tag="split")
+
+
+@pytest.mark.parametrize("case", ["list64x1", "split32x2", "split64x2/sub2", "f16/split32x2",
+                                  "list32x8/sub1"])
+def test_merged_items_parity(sph, orc, ragged, case):
+    """Work items merging up to four sparse cells along x (one chunk, one
+    merged candidate neighbourhood): counts against FP64 brute force and
+    values at the FP32 bar on the ragged clustered set (empty cells, partial
+    bricks, crowded cells beside sparse ones), over the whole list, over
+    the sparse class of a split launch, with sub-cells, and with FP16
+    positions anchored at sub-cell centres (against the oracle on the same
+    stored values)."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps, ref, n_c, d, f = ragged
+    rec = inputs.pack_aos(ps, "f32")
+    prec, sub = None, 0
+    if case.startswith("f16"):
+        prec = sph.precision("f16", "bf16", "f16", 12, 3, 0, anchor=SUB2)
+    if "sub" in case:
+        sub = int(case[-1])
+    if case.startswith("list"):
+        ti, k = (64, 1) if "64x1" in case else (32, 8)
+        pipe = Pipeline(rec, n_c, prec=prec, sub_bits=sub, til=sph.tile(ti, k), sched="grid",
+                        max_cells=4)
+    else:
+        ti, k = (32, 2) if "32x2" in case else (64, 2)
+        pipe = Pipeline(rec, n_c, prec=prec, sub_bits=sub, til=sph.tile(64, 4),
+                        sched=("grid", "dynamic"),
+                        split={"density": (32, (ti, k), "grid", 4),
+                               "force": (32, (ti, k), "grid", 4)})
+    pipe.bin()
+    ws = pipe._parts["force"][0][1] if pipe._parts else pipe.work
+    items, _, _ = _read_worklist(ws, ps.n, n_c)
+    assert (items[:, 0] >> 29).max() > 0                 # some items do merge
+    pipe.soa["RHO"].fill_(float("nan"))
+    pipe.soa["A_X"].fill_(float("nan"))
+    pipe.convert("full")
+    pipe.density()
+    pipe.force()
+    pipe.writeback("full")
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    if prec is None:
+        got["h"] = ref.h
+        dd, ff, q, tol = d, f, ref, FP32_TOL
+    else:
+        q = orc.dequantise_set(ref, n_c, "f16", "bf16", "f16", (12, 3, 0), anchor=SUB2)
+        got["h"] = q.h
+        dd, ff = oracle_step(orc, q, n_c)
+        tol = 2e-5
+    assert_counts(orc, got["nngb"], got["nforce"], dd["nngb"], ff["nforce"], q, n_c,
+                  tag=f"merged/{case}")
+    check_fp32(got, dd, ff, tol=tol, tag=f"merged/{case}")
 
 
 # ---------------------------------------------------------------------------
