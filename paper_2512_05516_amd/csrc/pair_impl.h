@@ -217,27 +217,23 @@ __device__ __forceinline__ float group_max(float v) {
 }
 
 // Position shift of the cell d cells away along an axis, relative to the
-// chunk's cell: d * s (-s, 0, s exactly; FP32 products beyond, the same
-// value wherever a position is shifted by d cells)
-__device__ __forceinline__ float cell_shift(int d, float s) {
-  return d == 0 ? 0.0f : (d == 1 ? s : (d == -1 ? -s : (float)d * s));
-}
+// chunk's cell: d * s in FP32 (-s, 0, s exactly), one expression wherever a
+// position is shifted by d cells
+__device__ __forceinline__ float cell_shift(int d, float s) { return (float)d * s; }
 
 // Neighbour entry nb of a chunk of w - 2 cells along x (w = 3 for a single
 // cell): offsets dx in [-1, w - 2], dy, dz in [-1, 1], nb = (dx + 1) +
-// w ((dy + 1) + 3 (dz + 1)); periodic cell id and the shift of its frame.
-__device__ __forceinline__ void neighbour_cell(int nb, int w, int cx, int cy, int cz, int n_c,
-                                               float s, int& cn, float& shx, float& shy,
-                                               float& shz) {
-  int dx = nb % w - 1, dy = (nb / w) % 3 - 1, dz = nb / (3 * w) - 1;
+// w ((dy + 1) + 3 (dz + 1)), and the periodic cell id.
+__device__ __forceinline__ int neighbour_cell(int nb, int w, int cx, int cy, int cz, int n_c,
+                                              int& dx, int& dy, int& dz) {
+  dx = nb % w - 1;
+  dy = (nb / w) % 3 - 1;
+  dz = nb / (3 * w) - 1;
   int nx = cx + dx, ny = cy + dy, nz = cz + dz;
   nx += (nx < 0) ? n_c : ((nx >= n_c) ? -n_c : 0);
   ny += (ny < 0) ? n_c : ((ny >= n_c) ? -n_c : 0);
   nz += (nz < 0) ? n_c : ((nz >= n_c) ? -n_c : 0);
-  cn = nx + n_c * (ny + n_c * nz);
-  shx = cell_shift(dx, s);
-  shy = cell_shift(dy, s);
-  shz = cell_shift(dz, s);
+  return nx + n_c * (ny + n_c * nz);
 }
 
 __device__ __forceinline__ float box_dist2(float x, float y, float z, float lox, float loy,
@@ -252,20 +248,30 @@ __device__ __forceinline__ float box_dist2(float x, float y, float z, float lox,
 
 // --------------------------------------------------------------------------
 // Neighbour cells of a chunk's cells (m cells along x from the chunk's first
-// cell, m = 1 unless the work list merges sparse cells): ids, the position
-// shift of each relative to the chunk's first cell (delta * s), and the
-// support-radius bound of each (gamma_k * max h * (1 + 2^-8), covering
-// storage rounding of h; the cell side when no bound table is given).
+// cell, m = 1 unless the work list merges sparse cells): ids, the offsets
+// (dx, dy, dz) of each from the chunk's first cell (its frame is shifted by
+// cell_shift(delta, s) per axis), the support-radius bound of each (gamma_k * max h * (1 + 2^-8), covering
+// storage rounding of h; the cell side when no bound table is given), and
+// each cell's slot range. build_nbr issues all of its loads at once and
+// ends without a barrier: the caller's next barrier (the chunk box's)
+// publishes the table, so the chunk's own loads overlap these.
 // --------------------------------------------------------------------------
 constexpr int kMaxNbr = 9 * (kMaxMerge + 2);   // neighbour cells of a merged chunk
 struct NbrCells {
   int cell[kMaxNbr];
-  float sh[kMaxNbr][3];
   float hb[kMaxNbr];
-  float hbmax;   // largest hb over the nq cells
-  int nq;       // neighbour cells: 9 (m + 2)
-  signed char d[kMaxNbr][3];   // offsets dx, dy, dz of each cell from the chunk's first cell
+  int st[kMaxNbr], cnt[kMaxNbr];   // first slot and particle count of each cell
+  int d[kMaxNbr];   // offsets: (dx + 1) | (dy + 1) << 8 | (dz + 1) << 16
+  float hbmax;      // largest hb over the nq cells
+  int nq;           // neighbour cells: 9 (m + 2)
 };
+
+__device__ __forceinline__ void nbr_offsets(const NbrCells& T, int q, int& dx, int& dy, int& dz) {
+  const int v = T.d[q];
+  dx = (v & 0xff) - 1;
+  dy = ((v >> 8) & 0xff) - 1;
+  dz = (v >> 16) - 1;
+}
 
 __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int cx, int cy,
                                           int cz, int m, float s32, float gk) {
@@ -274,43 +280,40 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
   float hbv = 0.0f;
   if (tid == 0) T.nq = nq;
   if (tid < nq) {
-    int cn;
-    float shx, shy, shz;
-    neighbour_cell(tid, w, cx, cy, cz, cd.n_c, s32, cn, shx, shy, shz);
-    T.d[tid][0] = (signed char)(tid % w - 1);
-    T.d[tid][1] = (signed char)((tid / w) % 3 - 1);
-    T.d[tid][2] = (signed char)(tid / (3 * w) - 1);
+    int dx, dy, dz;
+    const int cn = neighbour_cell(tid, w, cx, cy, cz, cd.n_c, dx, dy, dz);
+    T.d[tid] = (dx + 1) | ((dy + 1) << 8) | ((dz + 1) << 16);
     T.cell[tid] = cn;
-    T.sh[tid][0] = shx;
-    T.sh[tid][1] = shy;
-    T.sh[tid][2] = shz;
+    const int a = clamp_slot(cd.start[cn], cd.n);
+    const int b = clamp_slot(cd.start[cn + 1], cd.n);
     hbv = cd.hmax ? gk * cd.hmax[cn] * (1.0f + 0x1p-8f) : s32;
     T.hb[tid] = hbv;
+    T.st[tid] = a;
+    T.cnt[tid] = max(b - a, 0);
   }
   if (tid < 64) {   // first wave (kMaxNbr <= 64): the largest bound
     float mx = hbv;
     for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
     if (tid == 0) T.hbmax = mx;
   }
-  __syncthreads();
 }
 static_assert(kMaxNbr <= 64, "the neighbour table is reduced by one wave");
 
-// Block-wide exclusive scan of two ints in thread order; returns the block
-// totals. Two barriers.
+// Block-wide exclusive scan, in thread order, of a flag (0/1) and of an
+// int; returns the block totals. One barrier: the caller must pass another
+// barrier before `lds` is written again.
 template <int NT>
-__device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int& ta, int& tb,
+__device__ __forceinline__ void block_scan2(bool flag, int b, int& ea, int& eb, int& ta, int& tb,
                                             int* lds) {
   constexpr int NW = NT / 64;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int ia = a, ib = b;
+  const uint64_t bal = __ballot(flag);
+  const int a = flag ? 1 : 0;
+  int ia = __popcll(bal & lanemask_lt()) + a, ib = b;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    const int xa = __shfl_up(ia, o), xb = __shfl_up(ib, o);
-    if (lane >= o) {
-      ia += xa;
-      ib += xb;
-    }
+    const int xb = __shfl_up(ib, o);
+    if (lane >= o) ib += xb;
   }
   if (lane == 63) {
     lds[wave] = ia;
@@ -330,7 +333,6 @@ __device__ __forceinline__ void block_scan2(int a, int b, int& ea, int& eb, int&
   }
   ea = pa + ia - a;
   eb = pb + ib - b;
-  __syncthreads();
 }
 
 // Range table of one batch of candidate ranges: slot ranges, prefix of
@@ -343,10 +345,10 @@ struct RangeTab {
   unsigned char q[NT];
   int scan[2 * (NT / 64)];
   int ntab, total;
-  int qn[kMaxNbr];              // entries of cell q (0: skipped)
-  int qpre[kMaxNbr + 1];        // prefix of qn
+  int qpre[kMaxNbr + 1];        // prefix of the entry counts of the cells
   unsigned char qw[kMaxNbr];    // 1: whole cell, 0: sub-cells qr
-  unsigned char qr[kMaxNbr][6]; // local sub-cell ranges x0, x1, y0, y1, z0, z1
+  unsigned char qny[kMaxNbr];   // sub-cell range width along y
+  alignas(4) unsigned char qr[kMaxNbr][4];   // local sub-cell range: x0, y0, z0, width nx
 };
 
 // A neighbour cell is split into its R^3 sub-cells only when it holds more
@@ -359,7 +361,10 @@ constexpr int kSplitFactor = 2;
 // boxes lie within bound(q) of the chunk box [lo, hi], or the whole of q
 // (a superset) when q is sparse. Entries are processed in
 // batches of at most NT: for each batch, `batch(tab)` gathers the
-// particles of the batch's ranges.
+// particles of the batch's ranges. The per-cell index ranges are widened by
+// 2^-7 of a sub-cell (twice the 2^-8 margin of the per-entry box test, which
+// covers the rounding of stored offsets), so every entry that test keeps is
+// enumerated.
 template <int NT, class Bound, class Batch>
 __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells& T,
                                               RangeTab<NT>& tab, float s32, float lox, float loy,
@@ -371,45 +376,45 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
   const int* sstart = sb ? cd.sub_start : cd.start;
   const int tid = threadIdx.x;
   const int nq = T.nq;
-  if (tid < nq) {
-    const int q = tid;
-    const int dx = T.d[q][0], dy = T.d[q][1], dz = T.d[q][2];
-    const float bq = bound(q);
+  if (tid < 64) {   // first wave (nq <= 64): entry counts per cell, then their prefix
     int n = 0;
-    if (bq > 0.0f) {
-      auto lo_i = [&](float v, int d) { return max((int)floorf((v - bq) * inv) - 1 - d * R, 0); };
-      auto hi_i = [&](float v, int d) {
-        return min((int)floorf((v + bq) * inv) + 1 - d * R, R - 1);
-      };
-      const int x0 = lo_i(lox, dx), x1 = hi_i(hix, dx);
-      const int y0 = lo_i(loy, dy), y1 = hi_i(hiy, dy);
-      const int z0 = lo_i(loz, dz), z1 = hi_i(hiz, dz);
-      if (x0 <= x1 && y0 <= y1 && z0 <= z1) {
-        const int c = T.cell[q];
-        const int a0 = clamp_slot(cd.start[c], cd.n);
-        const int cnt = max(clamp_slot(cd.start[c + 1], cd.n) - a0, 0);
-        const bool whole = sb == 0 || cnt <= kSplitFactor * R * R * R;
-        if (cnt > 0) n = whole ? 1 : (x1 - x0 + 1) * (y1 - y0 + 1) * (z1 - z0 + 1);
-        tab.qw[q] = whole ? 1 : 0;
-        unsigned char* r = tab.qr[q];
-        r[0] = (unsigned char)x0;
-        r[1] = (unsigned char)x1;
-        r[2] = (unsigned char)y0;
-        r[3] = (unsigned char)y1;
-        r[4] = (unsigned char)z0;
-        r[5] = (unsigned char)z1;
+    if (tid < nq) {
+      const int q = tid;
+      int dx, dy, dz;
+      nbr_offsets(T, q, dx, dy, dz);
+      const float bq = bound(q);
+      const int cnt = T.cnt[q];
+      if (bq > 0.0f && cnt > 0) {
+        auto lo_i = [&](float v, int d) {
+          return max((int)floorf((v - bq) * inv - 0x1p-7f) - d * R, 0);
+        };
+        auto hi_i = [&](float v, int d) {
+          return min((int)floorf((v + bq) * inv + 0x1p-7f) - d * R, R - 1);
+        };
+        const int x0 = lo_i(lox, dx), x1 = hi_i(hix, dx);
+        const int y0 = lo_i(loy, dy), y1 = hi_i(hiy, dy);
+        const int z0 = lo_i(loz, dz), z1 = hi_i(hiz, dz);
+        if (x0 <= x1 && y0 <= y1 && z0 <= z1) {
+          const bool whole = sb == 0 || cnt <= kSplitFactor * R * R * R;
+          const int nx = x1 - x0 + 1;
+          n = whole ? 1 : nx * (y1 - y0 + 1) * (z1 - z0 + 1);
+          tab.qw[q] = whole ? 1 : 0;
+          tab.qny[q] = (unsigned char)(y1 - y0 + 1);
+          unsigned char* r = tab.qr[q];
+          r[0] = (unsigned char)x0;
+          r[1] = (unsigned char)y0;
+          r[2] = (unsigned char)z0;
+          r[3] = (unsigned char)nx;
+        }
       }
     }
-    tab.qn[q] = n;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int q = 0; q < nq; ++q) {
-      tab.qpre[q] = acc;
-      acc += tab.qn[q];
+    int inc = n;   // inclusive wave scan
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int x = __shfl_up(inc, o);
+      if (tid >= o) inc += x;
     }
-    tab.qpre[nq] = acc;
+    if (tid <= nq) tab.qpre[tid] = inc - n;   // lane nq holds the total
   }
   __syncthreads();
   const int NQ = tab.qpre[nq];
@@ -426,20 +431,26 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
       }
       q = lo;
       const int e = t - tab.qpre[q];
-      const int c = T.cell[q];
-      const int dx = T.d[q][0], dy = T.d[q][1], dz = T.d[q][2];
+      int dx, dy, dz;
+      nbr_offsets(T, q, dx, dy, dz);
       float bx0, bx1, by0, by1, bz0, bz1;
       if (tab.qw[q]) {
         const float mg = s32 * 0x1p-8f;       // rounding margin of stored offsets
         bx0 = dx * s32 - mg, bx1 = (dx + 1) * s32 + mg;
         by0 = dy * s32 - mg, by1 = (dy + 1) * s32 + mg;
         bz0 = dz * s32 - mg, bz1 = (dz + 1) * s32 + mg;
-        st = clamp_slot(cd.start[c], cd.n);
-        cnt = max(clamp_slot(cd.start[c + 1], cd.n) - st, 0);
+        st = T.st[q];
+        cnt = T.cnt[q];
       } else {
-        const unsigned char* r = tab.qr[q];
-        const int nx = r[1] - r[0] + 1, ny = r[3] - r[2] + 1;
-        const int sx = r[0] + e % nx, sy = r[2] + (e / nx) % ny, sz = r[4] + e / (nx * ny);
+        const uchar4 r = *reinterpret_cast<const uchar4*>(tab.qr[q]);
+        // e = ex + nx (ey + ny ez), split through FP32 reciprocals (v_rcp,
+        // 1 ulp): exact, as e < 2^9 and (e + 1/2) / w lies at least
+        // 1 / (2 w) >= 2^-7 from an integer
+        const int nx = r.w, nxy = nx * tab.qny[q];
+        const int ez = (int)(((float)e + 0.5f) * __builtin_amdgcn_rcpf((float)nxy));
+        const int rem = e - ez * nxy;
+        const int ey = (int)(((float)rem + 0.5f) * __builtin_amdgcn_rcpf((float)nx));
+        const int sx = r.x + (rem - ey * nx), sy = r.y + ey, sz = r.z + ez;
         const float mg = ss * 0x1p-8f;
         const int gx = dx * R + sx, gy = dy * R + sy, gz = dz * R + sz;
         bx0 = gx * ss - mg, bx1 = (gx + 1) * ss + mg;
@@ -449,7 +460,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         for (int b = 0; b < sb; ++b)
           m |= (((sx >> b) & 1) << (3 * b)) | (((sy >> b) & 1) << (3 * b + 1)) |
                (((sz >> b) & 1) << (3 * b + 2));
-        const int key = (c << (3 * sb)) + m;
+        const int key = (T.cell[q] << (3 * sb)) + m;
         st = clamp_slot(sstart[key], cd.n);
         cnt = max(clamp_slot(sstart[key + 1], cd.n) - st, 0);
       }
@@ -460,7 +471,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
       ok = cnt > 0 && ex * ex + ey * ey + ez * ez < bq * bq * (1.0f + 0x1p-10f);
     }
     int e_idx, e_pre, ntab, total;
-    block_scan2<NT>(ok ? 1 : 0, ok ? cnt : 0, e_idx, e_pre, ntab, total, tab.scan);
+    block_scan2<NT>(ok, ok ? cnt : 0, e_idx, e_pre, ntab, total, tab.scan);
     if (ok) {
       tab.start[e_idx] = st;
       tab.pre[e_idx] = e_pre;
@@ -912,9 +923,11 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
               const int idx = sbase + r * NT + tid;
               bool ok = idx < total;
               if (ok) {
-                c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
-                c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
-                c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+                int ox, oy, oz;
+                nbr_offsets(T, qq[r], ox, oy, oz);
+                c[r].x = shifted(c[r].x, cell_shift(ox, s32));
+                c[r].y = shifted(c[r].y, cell_shift(oy, s32));
+                c[r].z = shifted(c[r].z, cell_shift(oz, s32));
                 ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
                                bx.hiz) < bx.h2max;
               }
@@ -1155,9 +1168,11 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
               const int idx = sbase + r * NT + tid;
               bool ok = idx < total;
               if (ok) {
-                c[r].x = shifted(c[r].x, T.sh[qq[r]][0]);
-                c[r].y = shifted(c[r].y, T.sh[qq[r]][1]);
-                c[r].z = shifted(c[r].z, T.sh[qq[r]][2]);
+                int ox, oy, oz;
+                nbr_offsets(T, qq[r], ox, oy, oz);
+                c[r].x = shifted(c[r].x, cell_shift(ox, s32));
+                c[r].y = shifted(c[r].y, cell_shift(oy, s32));
+                c[r].z = shifted(c[r].z, cell_shift(oz, s32));
                 c[r].w = support2(gk, c[r].w);
                 ok = box_dist2(c[r].x, c[r].y, c[r].z, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy,
                                bx.hiz) < fmaxf(bx.h2max, c[r].w);
