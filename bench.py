@@ -5,8 +5,11 @@ Workload: 2,097,152 particles on a jittered 128^3 lattice in the periodic unit
 box (seeded), FP32 AoS records of 128 bytes (FP64 positions), resident in HBM.
 One step = bin -> AoS->SoA convert (GPU) -> density -> force -> FP64
 reductions -> kick/drift -> SoA->AoS writeback, all through the C ABI on one
-stream. The headline value is in-support pair interactions (density pairs
-incl. self + force pairs) per second over whole steps. The pair loops' tiling
+stream. The binning keeps its cell list while the kicks count no particle
+that left its cell or sub-cell (a rebuilt list would be identical); the same
+step rebinning every time is reported beside it. The headline value is
+in-support pair interactions (density pairs incl. self + force pairs) per
+second over whole steps. The pair loops' tiling
 (sub-cell depth, tile, schedule) is chosen by the autotuner before timing.
 
 Beside it: per-kernel times (HIP events on the launch stream), HBM GB/s of
@@ -88,6 +91,16 @@ def timed_steps(torch, pipe, kind, steps, warmup):
     for q, (name, _) in enumerate(stages):
         per[name] = float(np.mean([evs[s][q].elapsed_time(evs[s][q + 1]) for s in range(steps)]))
     return t1 - t0, per
+
+
+def cells_kept(pipe):
+    """State of a cell-list-keeping pipeline after its timed steps: the
+    particles the last kick counted as having left their cell or sub-cell
+    (0: the next binning keeps the list) and whether the last binning rebuilt
+    the list."""
+    r = pipe.cells.rebin.cpu().numpy()
+    return {"kept_while_no_particle_left_its_cell": True, "moved_in_last_step": int(r[0]),
+            "last_binning_rebuilt": bool(r[1])}
 
 
 def force_traffic(choice):
@@ -548,9 +561,13 @@ def main():
     log("chosen:", tune.describe(choice))
 
     # ---- headline: FP32 SoA step, GPU-side convert ---------------------------
+    # The binning keeps its cell list while the kicks count no particle that
+    # left its cell or sub-cell (the lists are then what a fresh binning would
+    # build, bit for bit); the same step rebinning every time is timed below.
     log("FP32 SoA step")
-    pipe = Pipeline(rec, N_C, **kw)
+    pipe = Pipeline(rec, N_C, keep_cells=True, **kw)
     secs, per = timed_steps(torch, pipe, "soa", args.steps, args.warmup)
+    kept = cells_kept(pipe)
     red = pipe.red_out.cpu().numpy()
     pairs_d, pairs_f = float(red[6]), float(red[7])
     pairs = pairs_d + pairs_f
@@ -583,6 +600,9 @@ def main():
                                "(128 B, FP64 x) resident in HBM, GPU-side AoS->SoA convert",
                    "particles": n, "n_c": N_C, "cells": N_C ** 3, "dt": DT,
                    "step": "bin+convert+density+force+reduce+kick_drift+writeback",
+                   "binning": "cell list kept while no particle left its cell or sub-cell "
+                              "(counted by the kick); rebin_every_step times the same step "
+                              "rebuilding it every time",
                    "tiling": tune.describe(choice)},
         "roofline": roofline,
         "pairs_per_step": {"density": pairs_d, "force": pairs_f},
@@ -591,6 +611,7 @@ def main():
         "hbm_gbs": hbm,
         "hbm_frac": {k: round(v / PEAK_HBM_GBS, 4) for k, v in hbm.items()},
         "status_flags": status,
+        "cell_list": kept,
         "autotune": {"choice": tune.describe(choice),
                      "density_ms": round(choice["density"]["ms"], 4),
                      "force_ms": round(choice["force"]["ms"], 4),
@@ -598,6 +619,14 @@ def main():
     }
     del pipe
     torch.cuda.empty_cache()
+    log("FP32 SoA step, rebinning every step")
+    pb = Pipeline(rec, N_C, **kw)
+    s_rb, per_rb = timed_steps(torch, pb, "soa", args.steps, args.warmup)
+    del pb
+    torch.cuda.empty_cache()
+    result["rebin_every_step"] = {"ms_per_step": 1e3 * s_rb / args.steps,
+                                  "value": pairs * args.steps / s_rb,
+                                  "kernels_ms": {k: round(v, 4) for k, v in per_rb.items()}}
 
     # ---- work counters of the pair loops (one extra step, not timed) ---------
     pt = Pipeline(rec, N_C, tally=True, **kw)
@@ -623,18 +652,20 @@ def main():
     if not args.no_variants:
         # ---- plain AoS step (Eq. gpu_native) ---------------------------------
         log("plain AoS step")
-        pa = Pipeline(rec, N_C, **kw)
+        pa = Pipeline(rec, N_C, keep_cells=True, **kw)
         s_aos, per_aos = timed_steps(torch, pa, "aos", args.steps, args.warmup)
-        del pa
+        kept_aos = cells_kept(pa)
         ms_aos = 1e3 * s_aos / args.steps
         result["aos_plain"] = {"ms_per_step": ms_aos, "value": pairs * args.steps / s_aos,
-                               "kernels_ms": {k: round(v, 4) for k, v in per_aos.items()}}
+                               "kernels_ms": {k: round(v, 4) for k, v in per_aos.items()},
+                               "cell_list": kept_aos}
+        del pa
         sp = {"fp32_soa_step": round(ms_aos / ms_step, 3)}
         # ---- reduced-precision SoA steps: the mixed format, all-FP16, all-BF16 --
         for name, prec in (("fp16_store", PREC16(sphmi)), ("fp16_all", PREC_ALL16(sphmi)),
                            ("bf16_all", PREC_ALLBF16(sphmi))):
             log(f"{name} SoA step")
-            pr = Pipeline(rec, N_C, prec=prec, **kw)
+            pr = Pipeline(rec, N_C, prec=prec, keep_cells=True, **kw)
             s_r, per_r = timed_steps(torch, pr, "soa", args.steps, args.warmup)
             st_r = pr.status()
             del pr
@@ -682,7 +713,8 @@ def main():
 
         # ---- Wendland C2 kernel variant, FP32 SoA step, same tiling ---------------
         log("Wendland C2 step")
-        pw = Pipeline(rec, N_C, prm=sphmi.params(kernel="wendland_c2"), **kw)
+        pw = Pipeline(rec, N_C, prm=sphmi.params(kernel="wendland_c2"), keep_cells=True,
+                      **kw)
         s_w, per_w = timed_steps(torch, pw, "soa", args.steps, args.warmup)
         red_w = pw.red_out.cpu().numpy()
         result["wendland_c2"] = {"ms_per_step": 1e3 * s_w / args.steps,
