@@ -335,11 +335,17 @@ __device__ __forceinline__ void block_scan2(bool flag, int b, int& ea, int& eb, 
   eb = pb + ib - b;
 }
 
+constexpr int kRounds = 4;      // gather rounds whose loads are issued together
+
 // Range table of one batch of candidate ranges: slot ranges, prefix of
 // counts and the neighbour index q of each; and, per neighbour cell q, its
-// entries: the whole cell, or its sub-cells inside the query box.
+// entries: the whole cell, or its sub-cells inside the query box. wbits
+// marks the ranges that start inside the current gather window (kRounds
+// rounds of NT flattened candidates); it is all zero between windows.
 template <int NT>
 struct RangeTab {
+  static constexpr int kWinWords = kRounds * NT / 32;
+  unsigned wbits[kWinWords];
   int start[NT];
   int pre[NT + 1];
   unsigned char q[NT];
@@ -488,16 +494,64 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
   }
 }
 
-// Entry e of the range table holding flattened candidate idx < total
+// Range lookup for a gather window [sbase, sbase + kRounds NT) of the
+// flattened candidates: a bit per window position where a range starts
+// (ranges are non-empty, so starts are distinct), a prefix of the bit counts
+// per 32-bit word, and the number of ranges that start before the window.
+// The range of candidate idx is then the number of starts at or before idx,
+// minus one: one LDS read and a popcount instead of a search.
+struct WinScan {
+  int excl;    // lane w < kWinWords: set bits in the words before word w
+  int total;   // set bits in the window
+};
+
+// Marks the starts inside the window (the bits are zero on entry); ends with
+// a barrier, after which every wave may scan.
 template <int NT>
-__device__ __forceinline__ int find_range(const RangeTab<NT>& tab, int idx) {
-  int lo = 0, hi = tab.ntab - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tab.pre[mid] <= idx) lo = mid;
-    else hi = mid - 1;
+__device__ __forceinline__ void mark_window(RangeTab<NT>& tab, int sbase) {
+  const int t = threadIdx.x;
+  if (t < tab.ntab) {
+    const int p = tab.pre[t] - sbase;
+    if (p >= 0 && p < kRounds * NT) atomicOr(&tab.wbits[p >> 5], 1u << (p & 31));
   }
-  return lo;
+  __syncthreads();
+}
+
+// Per-word prefix of the window's bit counts, in every wave (uniform
+// control flow: all lanes active).
+template <int NT>
+__device__ __forceinline__ WinScan scan_window(const RangeTab<NT>& tab) {
+  constexpr int NWD = RangeTab<NT>::kWinWords;
+  static_assert(NWD <= 64, "one wave scans the window words");
+  const int lane = threadIdx.x & 63;
+  const int pc = lane < NWD ? __popc(tab.wbits[lane]) : 0;
+  int inc = pc;
+#pragma unroll
+  for (int o = 1; o < NWD; o <<= 1) {
+    const int x = __shfl_up(inc, o);
+    if (lane >= o) inc += x;
+  }
+  return {inc - pc, __shfl(inc, NWD - 1)};
+}
+
+// Table entry holding flattened candidate idx (sbase <= idx < total, or
+// clamped into that range by the caller); nbefore = ranges starting before
+// sbase. Uniform control flow (the word prefix comes from another lane).
+template <int NT>
+__device__ __forceinline__ int window_entry(const RangeTab<NT>& tab, const WinScan& ws,
+                                            int nbefore, int sbase, int idx) {
+  const int x = idx - sbase;
+  const int w = x >> 5;
+  const unsigned m = tab.wbits[w] & ((2u << (x & 31)) - 1u);   // bits 0..x&31
+  const int e = nbefore + __shfl(ws.excl, w) + __popc(m) - 1;
+  return min(max(e, 0), tab.ntab - 1);   // a table entry whatever the bits hold
+}
+
+// Clears the window's bits once every thread has read them (callers do this
+// after the first barrier that follows the lookups).
+template <int NT>
+__device__ __forceinline__ void clear_window(RangeTab<NT>& tab) {
+  if ((int)threadIdx.x < RangeTab<NT>::kWinWords) tab.wbits[threadIdx.x] = 0u;
 }
 
 // Deterministic block-wide compaction with one barrier: wave totals are
@@ -529,7 +583,6 @@ __device__ __forceinline__ int compact_round(bool ok, int& nj, int* wtot2, int r
 // entries: the test phase stops for the whole wave once any lane could
 // overflow within the next kUnroll candidates.
 constexpr int kUnroll = 8;
-constexpr int kRounds = 4;      // gather rounds whose loads are issued together
 constexpr int kFillRounds = 4;  // force-only fields: rounds issued together
 constexpr float kFlatRatio = 1.02f;   // force: neighbour support bound^2 / chunk's largest H^2
 
@@ -842,6 +895,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
     build_nbr(T, cd, cx, cy, cz, m, s32, gk);
+    clear_window<NT>(tab);   // published by the chunk box's barriers
     const int i = c0 + gi;
     const bool vi = i < c1;
     float xi = 0.f, yi = 0.f, zi = 0.f, hi = 0.f, ui = 0.f;
@@ -898,21 +952,24 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
-        [&](const RangeTab<NT>& tb) {
+        [&](RangeTab<NT>& tb) {
           const int total = tb.total;
           gathered += total;
+          int nbefore = 0;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
+            mark_window<NT>(tb, sbase);
+            const WinScan ws = scan_window<NT>(tb);
             float4 c[kRounds];
             int qq[kRounds];
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) {
               const int idx = sbase + r * NT + tid;
+              const int e = window_entry<NT>(tb, ws, nbefore, sbase, min(idx, total - 1));
               c[r] = make_float4(0.f, 0.f, 0.f, 0.f);
               qq[r] = 0;
               if (idx < total) {
-                const int e = find_range<NT>(tb, idx);
                 qq[r] = tb.q[e];
-                const int j = tb.start[e] + (idx - tb.pre[e]);
+                const int j = min(max(tb.start[e] + (idx - tb.pre[e]), 0), cd.n - 1);
                 src.pos(j, T.cell[qq[r]], n_c, c[r].x, c[r].y, c[r].z);
                 c[r].w = src.mass(j);
               }
@@ -933,6 +990,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
               }
               int njn = nj;
               const int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+              if (r == 0) clear_window<NT>(tb);       // every lookup is done
               if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
                 pair_phase(nj);
                 njn -= nj;
@@ -944,6 +1002,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
               }
               nj = njn;
             }
+            nbefore += ws.total;
           }
         });
     pair_phase(nj);
@@ -1008,6 +1067,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
     int cx, cy, cz;
     cell_coords(cell, n_c, cx, cy, cz);
     build_nbr(T, cd, cx, cy, cz, m, s32, gk);
+    clear_window<NT>(tab);   // published by the chunk box's barriers
     const int i = c0 + gi;
     const bool vi = i < c1;
     // lanes without a particle sit far outside the box and accept nothing
@@ -1142,22 +1202,25 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
     for_sub_cells<NT>(
         cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
         [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
-        [&](const RangeTab<NT>& tb) {
+        [&](RangeTab<NT>& tb) {
           const int total = tb.total;
           gathered += total;
+          int nbefore = 0;
           for (int sbase = 0; sbase < total; sbase += kRounds * NT) {
+            mark_window<NT>(tb, sbase);
+            const WinScan ws = scan_window<NT>(tb);
             float4 c[kRounds];
             int qq[kRounds], jj[kRounds];
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) {
               const int idx = sbase + r * NT + tid;
+              const int e = window_entry<NT>(tb, ws, nbefore, sbase, min(idx, total - 1));
               c[r] = make_float4(0.f, 0.f, 0.f, 1.f);   // w: h_j, then H_j^2
               qq[r] = 0;
               jj[r] = 0;
               if (idx < total) {
-                const int e = find_range<NT>(tb, idx);
                 qq[r] = tb.q[e];
-                jj[r] = tb.start[e] + (idx - tb.pre[e]);
+                jj[r] = min(max(tb.start[e] + (idx - tb.pre[e]), 0), cd.n - 1);
                 src.pos(jj[r], T.cell[qq[r]], n_c, c[r].x, c[r].y, c[r].z);
                 c[r].w = src.hsml(jj[r]);
               }
@@ -1179,6 +1242,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
               }
               int njn = nj;
               const int slot = compact_round<NT>(ok, njn, wtot, rnd++);
+              if (r == 0) clear_window<NT>(tb);       // every lookup is done
               if (njn > CAP - kPad) {                 // uniform: consume the staged ones first
                 fill(filled, nj);
                 pair_phase(nj);
@@ -1196,6 +1260,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
             // force-only fields of this super-round's candidates, one batch
             fill(filled, nj);
             filled = nj;
+            nbefore += ws.total;
           }
         });
     pair_phase(nj);
