@@ -1050,6 +1050,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
   __shared__ float4 cv[CAP];      // v_j, m_j
   __shared__ float4 cs4[CAP];     // 1/H_j, A_j, c_j, rho_j
   __shared__ int cid[CAP];        // sorted slot of j
+  __shared__ int selfpos[TI];     // batch << 16 | staged index of particle c0 + k, or -1
   __shared__ uint16_t lst[LCAP * NT];
   __shared__ NbrCells T;
   __shared__ RangeTab<NT> tab;
@@ -1068,6 +1069,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
     cell_coords(cell, n_c, cx, cy, cz);
     build_nbr(T, cd, cx, cy, cz, m, s32, gk);
     clear_window<NT>(tab);   // published by the chunk box's barriers
+    if (tid < TI) selfpos[tid] = -1;
     const int i = c0 + gi;
     const bool vi = i < c1;
     // lanes without a particle sit far outside the box and accept nothing
@@ -1142,6 +1144,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
       }
     };
 
+    int nbatch = 0;   // uniform: LDS batches consumed so far in this chunk
     auto pair_phase = [&](int nj) {
       staged += nj;
       const int njp = (nj + kPad - 1) / kPad * kPad;
@@ -1151,16 +1154,19 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
         cid[nj + tid] = -1;
       }
       __syncthreads();
+      // i's own copy in this batch, or -1
+      const int sp = selfpos[gi];
+      const int tself = (sp >> 16) == nbatch ? (sp & 0xffff) : -1;
       auto consume = [&](int lo) {
             for (int e = tid; e < lo; e += NT) {
               const int t = lst[e];
               const float4 q0 = cp[t];
               float dx, dy, dz;
               const float r2 = dist2_m2(m2x, m2y, m2z, q0.x, q0.y, q0.z, dx, dy, dz);
-              // the exact support test; the self pair has r2 = 0 exactly, so
-              // may coincident stored positions, for which w'(0) = 0 makes the
-              // pair's terms vanish
-              if (!(r2 < fmaxf(H2i, ch2[t])) || (r2 == 0.0f && cid[t] == i)) continue;
+              // the exact support test, r2 < max(H_i^2, H_j^2), and not the
+              // self pair; coincident stored positions (r2 = 0, j != i) stay:
+              // w'(0) = 0 makes their terms vanish
+              if (!(r2 < H2i || r2 < ch2[t]) || t == tself) continue;
               const float4 q1 = cv[t];
               const float4 q2 = cs4[t];
               const float r = fast_sqrt(r2);
@@ -1179,7 +1185,8 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
               ay = fmaf(-kc, ey, ay);
               az = fmaf(-kc, ez, az);
               du = fmaf(q1.w * (Ai * gi_ + 0.5f * visc * gbar), w, du);
-              vsig = fmaxf(vsig, vs);
+              // vs >= 0: the larger float is the larger int
+              vsig = __int_as_float(max(__float_as_int(vsig), __float_as_int(vs)));
               ++nf;
             }
           };
@@ -1196,6 +1203,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
             },
             consume);
       __syncthreads();
+      ++nbatch;
     };
 
     int nj = 0, filled = 0, rnd = 0;
@@ -1254,6 +1262,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
                 cp[nj + slot] = make_float4(c[r].x, c[r].y, c[r].z, norm2(c[r].x, c[r].y, c[r].z));
                 ch2[nj + slot] = c[r].w;
                 cid[nj + slot] = jj[r];
+                if (jj[r] >= c0 && jj[r] < c1) selfpos[jj[r] - c0] = (nbatch << 16) | (nj + slot);
               }
               nj = njn;
             }
