@@ -496,6 +496,39 @@ def hbm_variant(torch, sphmi, Pipeline, k_state):
     return out
 
 
+def variants_head(torch, args, rec, kw, Pipeline, result, pairs, per):
+    """Beside the headline step: the same step rebinning every time, and the
+    work counters of the pair loops (one extra untimed step with tallies)."""
+    log("FP32 SoA step, rebinning every step")
+    pb = Pipeline(rec, N_C, **kw)
+    s_rb, per_rb = timed_steps(torch, pb, "soa", args.steps, args.warmup)
+    del pb
+    torch.cuda.empty_cache()
+    result["rebin_every_step"] = {"ms_per_step": 1e3 * s_rb / args.steps,
+                                  "value": pairs * args.steps / s_rb,
+                                  "kernels_ms": {k: round(v, 4) for k, v in per_rb.items()}}
+    pairs_d, pairs_f = result["pairs_per_step"]["density"], result["pairs_per_step"]["force"]
+    pt = Pipeline(rec, N_C, tally=True, **kw)
+    pt.bin()
+    pt.convert("full")
+    pt.density()
+    torch.cuda.synchronize()
+    tl_d = pt.cells.tally.cpu().numpy().astype(np.float64)
+    pt.force()
+    torch.cuda.synchronize()
+    tl_f = pt.cells.tally.cpu().numpy().astype(np.float64) - tl_d
+    del pt
+    torch.cuda.empty_cache()
+    result["candidates"] = {
+        "note": "candidate tests = particles of a chunk x candidates staged for it (the "
+                "prefilter's evaluations); efficiency = in-support pairs / tests",
+        "density_tests": tl_d[0], "force_tests": tl_f[0],
+        "density_gathered": tl_d[1], "force_gathered": tl_f[1],
+        "density_tests_per_s": tl_d[0] / (per["density"] * 1e-3),
+        "force_tests_per_s": tl_f[0] / (per["force"] * 1e-3),
+        "density_efficiency": pairs_d / tl_d[0], "force_efficiency": pairs_f / tl_f[0]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,7 +536,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="time only the FP32 SoA step (profiling runs)")
+                    help="time only the FP32 SoA step, without the rebin-every-step and work-counter steps (profiling runs)")
     ap.add_argument("--no-clustered", action="store_true",
                     help="skip the clustered 4M-particle variant")
     ap.add_argument("--no-serving", action="store_true",
@@ -619,37 +652,8 @@ def main():
     }
     del pipe
     torch.cuda.empty_cache()
-    log("FP32 SoA step, rebinning every step")
-    pb = Pipeline(rec, N_C, **kw)
-    s_rb, per_rb = timed_steps(torch, pb, "soa", args.steps, args.warmup)
-    del pb
-    torch.cuda.empty_cache()
-    result["rebin_every_step"] = {"ms_per_step": 1e3 * s_rb / args.steps,
-                                  "value": pairs * args.steps / s_rb,
-                                  "kernels_ms": {k: round(v, 4) for k, v in per_rb.items()}}
-
-    # ---- work counters of the pair loops (one extra step, not timed) ---------
-    pt = Pipeline(rec, N_C, tally=True, **kw)
-    pt.bin()
-    pt.convert("full")
-    pt.density()
-    torch.cuda.synchronize()
-    tl_d = pt.cells.tally.cpu().numpy().astype(np.float64)
-    pt.force()
-    torch.cuda.synchronize()
-    tl_f = pt.cells.tally.cpu().numpy().astype(np.float64) - tl_d
-    del pt
-    torch.cuda.empty_cache()
-    result["candidates"] = {
-        "note": "candidate tests = particles of a chunk x candidates staged for it (the "
-                "prefilter's evaluations); efficiency = in-support pairs / tests",
-        "density_tests": tl_d[0], "force_tests": tl_f[0],
-        "density_gathered": tl_d[1], "force_gathered": tl_f[1],
-        "density_tests_per_s": tl_d[0] / (per["density"] * 1e-3),
-        "force_tests_per_s": tl_f[0] / (per["force"] * 1e-3),
-        "density_efficiency": pairs_d / tl_d[0], "force_efficiency": pairs_f / tl_f[0]}
-
     if not args.no_variants:
+        variants_head(torch, args, rec, kw, Pipeline, result, pairs, per)
         # ---- plain AoS step (Eq. gpu_native) ---------------------------------
         log("plain AoS step")
         pa = Pipeline(rec, N_C, keep_cells=True, **kw)
