@@ -66,7 +66,7 @@ def stage_list(pipe, kind):
                 ("kick_drift", lambda: pipe.kick_drift(DT, DT)),
                 ("writeback", lambda: pipe.writeback("full"))]
     return [("bin", pipe.bin), ("density", pipe.density_aos), ("force", pipe.force_aos),
-            ("kick_drift", lambda: pipe.kick_drift_aos(DT, DT))]
+            ("reduce", pipe.reduce_aos), ("kick_drift", lambda: pipe.kick_drift_aos(DT, DT))]
 
 
 def timed_steps(torch, pipe, kind, steps, warmup):

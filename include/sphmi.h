@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SPH_ABI_VERSION 10
+#define SPH_ABI_VERSION 11
 
 typedef int32_t sph_status;
 enum {
@@ -511,6 +511,17 @@ sph_status sph_force_aos(void *aos, const sph_aos_layout *layout, const sph_cell
 sph_status sph_kick_drift_aos(void *aos, const sph_aos_layout *layout, const sph_cells *cells,
                               double dt_kick, double dt_drift, int32_t *moved,
                               hipStream_t stream);
+/* The FP64 reductions of sph_reduce (the conservation sums of Sec. 2.1,
+ * Eq. momentum and Eq. energy, and the neighbour-count totals) over the
+ * AoS records through the cell list: slot k reads record perm[k]'s M (1 if
+ * the layout has none), V, A, DU, NNGB and NFORCE (0 if absent), in the
+ * slot order and summation tree of sph_reduce, so FP32 records give the
+ * sums of sph_reduce over FP32 storage bit for bit. Needs the cell list of
+ * sph_bin; out: 8 doubles on the device; workspace: at least
+ * sph_reduce_workspace_size bytes (caller-owned device memory). */
+sph_status sph_reduce_aos(const void *aos, const sph_aos_layout *layout, const sph_cells *cells,
+                          double *out, void *workspace, size_t workspace_bytes,
+                          hipStream_t stream);
 
 /* Autotuner of the pair loops' cell-to-workgroup tiling (the batched
  * launch over cells of uneven occupancy of Alg. 1 CallQuadratic; Sec. 2.2

@@ -594,6 +594,22 @@ sph_status sph_reduce_static(const sph_soa* soa, const sph_precision* prec,
   return hip_status(launch_reduce(*soa, p, c.n, out, ws, stream), "sph_reduce_static");
 }
 
+sph_status sph_reduce_aos(const void* aos, const sph_aos_layout* layout, const sph_cells* cells,
+                          double* out, void* workspace, size_t workspace_bytes,
+                          hipStream_t stream) {
+  CellsDev c;
+  AosLayout L;
+  SPH_TRY(check_cells(cells, true, c));
+  SPH_TRY(check_layout(layout, bit(SPH_A_V) | bit(SPH_A_A) | bit(SPH_A_DU), L));
+  SPH_TRY(check_aos_ptr(aos, c.n));
+  if (!out) return fail(SPH_E_INVALID, "sph_reduce_aos: out is NULL");
+  if (!workspace) return fail(SPH_E_INVALID, "sph_reduce_aos: workspace is NULL");
+  if (workspace_bytes < reduce_workspace_bytes(c.n))
+    return fail(SPH_E_NOMEM, "sph_reduce_aos: workspace has %zu bytes, needs %zu",
+                workspace_bytes, reduce_workspace_bytes(c.n));
+  return hip_status(launch_reduce_aos(aos, L, c, out, workspace, stream), "sph_reduce_aos");
+}
+
 sph_status sph_predict(const sph_soa* soa, const sph_precision* prec, const sph_cells* cells,
                        const void* aos, const sph_aos_layout* layout, double dt_half,
                        hipStream_t stream) {

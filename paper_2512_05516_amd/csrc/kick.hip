@@ -124,6 +124,10 @@ __global__ __launch_bounds__(kThreads) void k_kick_drift_aos(char* __restrict__ 
   count_moved(mv, moved);
 }
 
+// Inputs of the reductions at slot k: the SoA arrays (m and v in their
+// storage formats), or the AoS records through the cell list (record
+// perm[k]), in the same slot order, so FP32 storage and FP32 records give
+// the same sums bit for bit.
 struct RedSoa {
   const void* m;
   int mhu_dt;
@@ -134,31 +138,73 @@ struct RedSoa {
   const float* du;
   const int32_t* nngb;
   const int32_t* nforce;
+
+  __device__ __forceinline__ double mass(int k) const {
+    return m ? (double)load_q(m, mhu_dt, k, lm) : 1.0;
+  }
+  __device__ __forceinline__ double vel(int k, int c) const {
+    return load_q(v[c], vel_dt, k, 1.0f);
+  }
+  __device__ __forceinline__ double acc(int k, int c) const { return a[c][k]; }
+  __device__ __forceinline__ double dudt(int k) const { return du[k]; }
+  __device__ __forceinline__ double ngb(int k) const { return nngb ? (double)nngb[k] : 0.0; }
+  __device__ __forceinline__ double nfrc(int k) const { return nforce ? (double)nforce[k] : 0.0; }
 };
 
-__global__ __launch_bounds__(kThreads) void k_reduce_partial(RedSoa s, int n,
+struct RedAos {
+  const char* aos;
+  AosLayout L;
+  const int32_t* perm;
+  int n;
+
+  __device__ __forceinline__ const char* rec(int k) const {
+    return aos + (size_t)min(max(perm[k], 0), n - 1) * L.stride;
+  }
+  __device__ __forceinline__ double mass(int k) const {
+    return L.off[SPH_A_M] != kAbsent ? (double)rec_load32(rec(k), L.off[SPH_A_M], L.dt[SPH_A_M])
+                                     : 1.0;
+  }
+  __device__ __forceinline__ double vel(int k, int c) const {
+    return rec_load32(rec(k), L.off[SPH_A_V], L.dt[SPH_A_V], c);
+  }
+  __device__ __forceinline__ double acc(int k, int c) const {
+    return rec_load32(rec(k), L.off[SPH_A_A], L.dt[SPH_A_A], c);
+  }
+  __device__ __forceinline__ double dudt(int k) const {
+    return rec_load32(rec(k), L.off[SPH_A_DU], L.dt[SPH_A_DU]);
+  }
+  __device__ __forceinline__ double count(int k, int f) const {
+    return L.off[f] != kAbsent ? (double)*reinterpret_cast<const int32_t*>(rec(k) + L.off[f])
+                               : 0.0;
+  }
+  __device__ __forceinline__ double ngb(int k) const { return count(k, SPH_A_NNGB); }
+  __device__ __forceinline__ double nfrc(int k) const { return count(k, SPH_A_NFORCE); }
+};
+
+template <class R>
+__global__ __launch_bounds__(kThreads) void k_reduce_partial(R s, int n,
                                                               double* __restrict__ part) {
   __shared__ double lds[kThreads / 64][kReduceVals];
   double acc[kReduceVals];
 #pragma unroll
   for (int q = 0; q < kReduceVals; ++q) acc[q] = 0.0;
   for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) {
-    const double m = s.m ? (double)load_q(s.m, s.mhu_dt, k, s.lm) : 1.0;
+    const double m = s.mass(k);
     double va = 0.0, an = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double a = s.a[c][k];
-      const double v = load_q(s.v[c], s.vel_dt, k, 1.0f);
+      const double a = s.acc(k, c);
+      const double v = s.vel(k, c);
       acc[c] += m * a;
       va += v * a;
       an += a * a;
     }
-    const double du = s.du[k];
+    const double du = s.dudt(k);
     acc[3] += m * (va + du);
     acc[4] += m * sqrt(an);
     acc[5] += m * (fabs(va) + fabs(du));
-    acc[6] += s.nngb ? (double)s.nngb[k] : 0.0;
-    acc[7] += s.nforce ? (double)s.nforce[k] : 0.0;
+    acc[6] += s.ngb(k);
+    acc[7] += s.nfrc(k);
   }
 #pragma unroll
   for (int q = 0; q < kReduceVals; ++q) {
@@ -490,6 +536,15 @@ hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, 
   r.nforce = static_cast<const int32_t*>(soa.f[SPH_S_NFORCE]);
   double* part = static_cast<double*>(ws);
   k_reduce_partial<<<kReduceBlocks, kThreads, 0, s>>>(r, n, part);
+  k_reduce_final<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_aos(const void* aos, const AosLayout& L, const CellsDev& c, double* out,
+                             void* ws, hipStream_t s) {
+  const RedAos r{static_cast<const char*>(aos), L, c.perm, c.n};
+  double* part = static_cast<double*>(ws);
+  k_reduce_partial<<<kReduceBlocks, kThreads, 0, s>>>(r, c.n, part);
   k_reduce_final<<<1, kThreads, 0, s>>>(part, kReduceBlocks, out);
   return hipGetLastError();
 }

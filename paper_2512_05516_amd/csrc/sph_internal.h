@@ -146,6 +146,8 @@ hipError_t launch_step_totals(const sph_soa& soa, const Prec& p, int n, double g
                               double c_cfl, double* out, void* ws, hipStream_t s);
 hipError_t launch_reduce(const sph_soa& soa, const Prec& p, int n, double* out, void* ws,
                          hipStream_t s);
+hipError_t launch_reduce_aos(const void* aos, const AosLayout& L, const CellsDev& c, double* out,
+                             void* ws, hipStream_t s);
 hipError_t launch_hbm_probe(int mode, const void* src, void* dst, size_t bytes, hipStream_t s);
 // the reduction's device-resident scratch on the current device (address
 // resolved once per device) and its size

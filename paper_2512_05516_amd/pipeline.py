@@ -133,6 +133,9 @@ class Pipeline:
     def writeback(self, view="full"):
         sphmi.writeback(self.soa, self.cells, view, self.aos, self.layout, self.stream)
 
+    def reduce_aos(self):
+        sphmi.reduce_aos(self.aos, self.layout, self.cells, self.red_out, self.red_ws, self.stream)
+
     def density_aos(self):
         for til, w, _ in self._parts.get("density", [(self.til, self.work, None)]):
             sphmi.density_aos(self.aos, self.layout, self.cells, self.prm, til, self.stream, w)
@@ -157,10 +160,11 @@ class Pipeline:
         self.writeback("full")
 
     def aos_step(self, dt_kick=1e-4, dt_drift=1e-4):
-        """bin -> density (AoS) -> force (AoS) -> kick/drift (AoS)"""
+        """bin -> density (AoS) -> force (AoS) -> reduce (AoS) -> kick/drift (AoS)"""
         self.bin()
         self.density_aos()
         self.force_aos()
+        self.reduce_aos()
         self.kick_drift_aos(dt_kick, dt_drift)
 
     def kdk_run(self, steps, dt=None, c_cfl=sphmi.C_CFL, dt_max=float("inf")):

@@ -123,7 +123,7 @@ EXPORTS = [
     "sph_server_destroy", "sph_storage_bytes", "sph_smoothing_length_workspace_size",
     "sph_smoothing_length", "sph_bin_host", "sph_gather_host", "sph_writeback_host_size",
     "sph_writeback_host", "sph_predict", "sph_step_totals", "sph_worklist_occupancy",
-    "sph_reduce_static", "sph_hbm_probe",
+    "sph_reduce_static", "sph_hbm_probe", "sph_reduce_aos",
 ]
 
 _lib = None
@@ -169,6 +169,7 @@ def lib():
     L.sph_reduce.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp, sz, vp]
     L.sph_reduce_static.argtypes = [P(Soa), P(Precision), P(Cells), vp, vp]
     L.sph_hbm_probe.argtypes = [i32, vp, vp, sz, vp]
+    L.sph_reduce_aos.argtypes = [vp, P(AosLayout), P(Cells), vp, vp, sz, vp]
     L.sph_density_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_force_aos.argtypes = [vp, P(AosLayout), P(Cells), P(Params), Tile, P(Work), vp]
     L.sph_kick_drift_aos.argtypes = [vp, P(AosLayout), P(Cells), C.c_double, C.c_double, vp, vp]
@@ -605,6 +606,14 @@ def reduce(soa: DeviceSoa, cells: DeviceCells, out, workspace, stream=None):
     _check(lib().sph_reduce(C.byref(soa.struct), C.byref(soa.prec), C.byref(cells.struct),
                             _ptr(out), _ptr(workspace), workspace.numel() * workspace.element_size(),
                             _stream(stream)))
+
+
+def reduce_aos(aos, layout, cells: DeviceCells, out, workspace, stream=None):
+    """sph_reduce_aos: the reductions of reduce() over the AoS records in
+    slot order."""
+    _check(lib().sph_reduce_aos(_ptr(aos), C.byref(layout), C.byref(cells.struct), _ptr(out),
+                                _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream(stream)))
 
 
 def reduce_static(soa: DeviceSoa, cells: DeviceCells, out, stream=None):

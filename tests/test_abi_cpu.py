@@ -41,7 +41,7 @@ def test_exports_every_header_symbol(sph):
 
 
 def test_abi_version_and_tiles(sph):
-    assert sph.abi_version() == 10
+    assert sph.abi_version() == 11
     assert sph.tile_supported(64, 4)
     assert sph.tile_supported(16, 4) and sph.tile_supported(32, 2)
     assert not sph.tile_supported(48, 3)

@@ -544,6 +544,10 @@ def test_aos_equals_soa_bitwise(sph, mode):
     for k in ("x", "v", "u", "a", "du", "rho", "wcount", "rho_dh", "f", "P", "c", "vsig",
               "nngb", "nforce"):
         assert np.ascontiguousarray(ra[k]).tobytes() == np.ascontiguousarray(rb[k]).tobytes(), k
+    # the FP64 reductions of the last step: over the records (sph_reduce_aos)
+    # the same sums as over the FP32 SoA (sph_reduce), bit for bit
+    assert a.red_out.cpu().numpy().tobytes() == b.red_out.cpu().numpy().tobytes()
+    assert b.red_out.cpu().numpy()[6] == rb["nngb"].sum()
 
 
 @pytest.mark.parametrize("mode", [{}, {"sub_bits": 1, "sched": "dynamic"}])
