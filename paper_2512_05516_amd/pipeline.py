@@ -39,27 +39,44 @@ class Pipeline:
         # lists merge up to that many sparse cells along x into one item
         sd, sf = sched if isinstance(sched, (tuple, list)) else (sched, sched)
         self.sched = (sd, sf)
+        self.split = dict(split or {})
         self.work = self.work_force = None
-        self._lists = []
+        self._lists = []        # (list, occupancy range or None) rebuilt with the cell list
         ti_d = self.til.ti or 64
         ti_f = self.til_force.ti or 64
+        # a loop that runs split takes its own lists below; its single-launch
+        # list is then built only on demand (smoothing_length)
         if sd:
             self.work = sphmi.DeviceWork(self.n, self.n_c, ti_d, device, sd, max_cells=max_cells)
-            self._lists.append(self.work)
+            if "density" not in self.split:
+                self._lists.append((self.work, None))
         if sf:
             if self.work is not None and ti_f == ti_d:
                 self.work_force = self.work.with_sched(sf)
+                if "force" not in self.split and "density" in self.split:
+                    self._lists.append((self.work, None))
             else:
                 self.work_force = sphmi.DeviceWork(self.n, self.n_c, ti_f, device, sf,
                                                    max_cells=max_cells)
-                self._lists.append(self.work_force)
+                if "force" not in self.split:
+                    self._lists.append((self.work_force, None))
         # split: per loop ("density" / "force") None or (T, (ti, k), sched)
         # or (T, (ti, k), sched, max_cells): cells with fewer than T
         # particles run as a launch of their own with that tile and schedule
         # (with max_cells > 1, up to that many such cells along x share a
         # work item), the other cells with the loop's own tile and schedule
-        self.split = dict(split or {})
         self._parts = {}
+        shared = {}   # (ti, occupancy range, max_cells) -> list: the two loops may share one
+
+        def part_list(ti, occ, merge, sch):
+            key = (ti, occ, merge)
+            if key in shared:
+                return shared[key].with_sched(sch)
+            w = sphmi.DeviceWork(self.n, self.n_c, ti, device, sch, max_cells=merge)
+            shared[key] = w
+            self._lists.append((w, occ))
+            return w
+
         for loop, main_til, main_sched in (("density", self.til, sd), ("force", self.til_force, sf)):
             sp = self.split.get(loop)
             if not sp:
@@ -67,10 +84,10 @@ class Pipeline:
             T, (ti, k), small_sched = sp[:3]
             merge = int(sp[3]) if len(sp) > 3 else 1
             big_sched = main_sched or "grid"
-            ws = sphmi.DeviceWork(self.n, self.n_c, ti, device, small_sched, max_cells=merge)
-            wl = sphmi.DeviceWork(self.n, self.n_c, main_til.ti or 64, device, big_sched)
-            self._parts[loop] = [(sphmi.tile(ti, k), ws, (0, int(T))),
-                                 (main_til, wl, (int(T), 2 ** 31 - 1))]
+            small, big = (0, int(T)), (int(T), 2 ** 31 - 1)
+            ws = part_list(ti, small, merge, small_sched)
+            wl = part_list(main_til.ti or 64, big, 1, big_sched)
+            self._parts[loop] = [(sphmi.tile(ti, k), ws, small), (main_til, wl, big)]
         self.bin_ws = torch.empty(sphmi.bin_workspace_size(self.n, self.n_c), dtype=torch.uint8,
                                   device=device)
         self.soa = sphmi.DeviceSoa(self.n, self.prec, device)
@@ -86,11 +103,12 @@ class Pipeline:
         self.build_lists()
 
     def build_lists(self):
-        """(Re)build every work list from the current cell list."""
-        for w in self._lists:
-            sphmi.worklist(self.cells, w, self.stream)
-        for parts in self._parts.values():
-            for _, w, occ in parts:
+        """(Re)build every work list the step's loops take from the current
+        cell list (each list once, also where both loops share it)."""
+        for w, occ in self._lists:
+            if occ is None:
+                sphmi.worklist(self.cells, w, self.stream)
+            else:
                 sphmi.worklist(self.cells, w, self.stream, occ)
 
     def convert(self, view="full"):
