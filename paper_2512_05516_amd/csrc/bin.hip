@@ -121,11 +121,31 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const int32_t* __restri
   for (int d = tid; d < NB; d += kThreads) hist[d * nblk + b] = h[d];
 }
 
-// Stable scatter: in round r the block ranks keys b*kTile + r*256 + tid in
-// index order. Lanes with equal digits are found with D ballots; earlier
-// waves and earlier rounds are counted in LDS.
+// --- exclusive scan of int32 (three kernels: tile scan, partials, add) ---
+__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total) {
+  // Hillis-Steele over 256 threads in LDS
+  int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < kThreads; off <<= 1) {
+    int t = tid >= off ? lds[tid - off] : 0;
+    __syncthreads();
+    lds[tid] += t;
+    __syncthreads();
+  }
+  int incl = lds[tid];
+  total = lds[kThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// Stable scatter straight to global memory (9-bit digits: with 512 buckets a
+// tile's digit runs are too short for the local reorder below to pay): in
+// round r the block ranks keys b*kTile + r*256 + tid in index order. Lanes
+// with equal digits are found with D ballots; earlier waves and earlier
+// rounds are counted in LDS.
 template <int D>
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+__global__ __launch_bounds__(kThreads) void k_radix_scatter_direct(
     const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
     int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift,
     const int32_t* gate) {
@@ -180,22 +200,103 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
   }
 }
 
-// --- exclusive scan of int32 (three kernels: tile scan, partials, add) ---
-__device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total) {
-  // Hillis-Steele over 256 threads in LDS
-  int tid = threadIdx.x;
-  lds[tid] = v;
+// Stable scatter of one block's tile of kTile keys: the keys are ranked in
+// index order (round r holds keys b*kTile + r*256 + tid; lanes with equal
+// digits are found with D ballots, earlier waves and rounds are counted in
+// LDS) into a block-local order sorted by digit in LDS, and then written out
+// digit run by digit run, so consecutive threads store consecutive
+// addresses. The block's count of each digit is the difference of two
+// consecutive entries of the scanned digit-major histogram.
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    const int32_t* __restrict__ kin, const int32_t* __restrict__ vin, int32_t* __restrict__ kout,
+    int32_t* __restrict__ vout, const int32_t* __restrict__ offsets, int n, int nblk, int shift,
+    const int32_t* gate) {
+  constexpr int NB = 1 << D;
+  constexpr int PER = NB / kThreads;           // digits per thread in the local scan
+  static_assert(NB % kThreads == 0, "whole digits per thread");
+  __shared__ int wcnt[kThreads / 64][NB];
+  __shared__ int run[NB];
+  __shared__ int lstart[NB];                   // first local position of each digit
+  __shared__ int gbase[NB];                    // global position of the block's first key of each digit
+  __shared__ int2 tile[kTile];                 // (key, value) in local digit order
+  __shared__ int scan_lds[kThreads];
+  if (gated_off(gate)) return;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int b = blockIdx.x;
+  const int t0 = b * kTile;
+  const int ntile = min(kTile, n - t0);
+  // every load of the tile in flight before the ranking
+  int key[kRounds], val[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int idx = t0 + r * kThreads + tid;
+    key[r] = idx < n ? kin[idx] : 0;
+    val[r] = idx < n ? vin[idx] : 0;
+  }
+  int cnt[PER];
+  int csum = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int d = tid * PER + q;
+    const int e = d * nblk + b;
+    const int o = offsets[e];
+    const int o1 = e + 1 < NB * nblk ? offsets[e + 1] : n;
+    gbase[d] = o;
+    cnt[q] = o1 - o;
+    csum += cnt[q];
+    run[d] = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) wcnt[w][d] = 0;
+  }
+  int total;
+  int ex = block_exclusive_scan(csum, scan_lds, total);   // barriers inside
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    lstart[tid * PER + q] = ex;
+    ex += cnt[q];
+  }
   __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    int t = tid >= off ? lds[tid - off] : 0;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    if (t0 + r * kThreads >= n) break;         // uniform over the block
+    const int idx = t0 + r * kThreads + tid;
+    const bool valid = idx < n;
+    const int d = (key[r] >> shift) & (NB - 1);
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < D; ++bit) {
+      const uint64_t bl = __ballot((d >> bit) & 1);
+      m &= ((d >> bit) & 1) ? bl : ~bl;
+    }
+    const int rank = __popcll(m & lanemask_lt());
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(m);
     __syncthreads();
-    lds[tid] += t;
+    if (valid) {
+      int pre = run[d];
+      for (int w = 0; w < wave; ++w) pre += wcnt[w][d];
+      const int lp = min(max(lstart[d] + pre + rank, 0), kTile - 1);
+      tile[lp] = make_int2(key[r], val[r]);
+    }
+    __syncthreads();
+    for (int dd = tid; dd < NB; dd += kThreads) {
+      int tot = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) {
+        tot += wcnt[w][dd];
+        wcnt[w][dd] = 0;
+      }
+      run[dd] += tot;
+    }
     __syncthreads();
   }
-  int incl = lds[tid];
-  total = lds[kThreads - 1];
-  __syncthreads();
-  return incl - v;
+  for (int t = tid; t < ntile; t += kThreads) {
+    const int2 kv = tile[t];
+    const int d = (kv.x >> shift) & (NB - 1);
+    const int pos = min(max(gbase[d] + (t - lstart[d]), 0), n - 1);
+    kout[pos] = kv.x;
+    vout[pos] = kv.y;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_scan_tiles(int32_t* __restrict__ data, int len,
@@ -400,7 +501,8 @@ hipError_t launch_bin(const void* aos, const AosLayout& L, const CellsDev& c, in
       if (D == 8) {
         k_radix_scatter<8><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 8 * p, gate);
       } else {
-        k_radix_scatter<9><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 9 * p, gate);
+        k_radix_scatter_direct<9><<<nblk, kThreads, 0, s>>>(ks, vs, kd, vd, w.hist, n, nblk, 9 * p,
+                                                          gate);
       }
       ks = kd;
       vs = vd;
