@@ -191,6 +191,18 @@ def test_host_side_validation(sph):
     big_scale = sph.precision("f16", "f16", "f16", scale_m=100)
     assert L.sph_reduce(C.byref(soa), C.byref(big_scale), C.byref(cells), C.c_void_p(0x5000),
                         C.c_void_p(0x6000), 1 << 20, None) == sph.SPH_E_INVALID
+    # plain-AoS reductions: the cell list, V/A/DU in the layout, out and a large enough workspace
+    out, w6 = C.c_void_p(0x5000), C.c_void_p(0x6000)
+    assert L.sph_reduce_aos(C.c_void_p(0x3000), C.byref(lay), C.byref(nolists), out, w6, 1 << 20,
+                            None) == sph.SPH_E_INVALID
+    bad = sph.layout_from_dtype(inputs.AOS_F32)
+    bad.offset[sph.A["A"]] = sph.ABSENT
+    assert L.sph_reduce_aos(C.c_void_p(0x3000), C.byref(bad), C.byref(cells), out, w6, 1 << 20,
+                            None) == sph.SPH_E_INVALID
+    assert L.sph_reduce_aos(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), None, w6, 1 << 20,
+                            None) == sph.SPH_E_INVALID
+    assert L.sph_reduce_aos(C.c_void_p(0x3000), C.byref(lay), C.byref(cells), out, w6, 16,
+                            None) == sph.SPH_E_NOMEM
 
 
 def test_tuner_host_side(sph):
