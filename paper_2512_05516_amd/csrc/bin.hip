@@ -53,10 +53,24 @@ __global__ __launch_bounds__(kThreads) void k_bin_keys(const char* __restrict__ 
   const char* rec;            // record bytes as seen at offsets offx, offh
   uint32_t rx = offx, rh = offh;
   if (nw > 0) {
+    // every word of the block's spans: a thread's loads (at most
+    // kSpanWords) are all issued before the first is stored to LDS
     const int nrec = min(kThreads, n - i0);
-    for (int w = threadIdx.x; w < nrec * nw; w += kThreads) {
-      const int r = w / nw, j = w - r * nw;
-      span[w] = *reinterpret_cast<const uint2*>(aos + (size_t)(i0 + r) * stride + lo + 8 * j);
+    const int nwords = nrec * nw;
+    uint2 buf[kSpanWords];
+#pragma unroll
+    for (int q = 0; q < kSpanWords; ++q) {
+      const int w = threadIdx.x + q * kThreads;
+      buf[q] = make_uint2(0u, 0u);
+      if (w < nwords) {
+        const int r = w / nw, j = w - r * nw;
+        buf[q] = *reinterpret_cast<const uint2*>(aos + (size_t)(i0 + r) * stride + lo + 8 * j);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSpanWords; ++q) {
+      const int w = threadIdx.x + q * kThreads;
+      if (w < nwords) span[w] = buf[q];
     }
     __syncthreads();
     rec = reinterpret_cast<const char*>(span + (valid ? threadIdx.x : 0) * nw);
