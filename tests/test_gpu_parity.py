@@ -550,6 +550,38 @@ def test_aos_equals_soa_bitwise(sph, mode):
     assert b.red_out.cpu().numpy()[6] == rb["nngb"].sum()
 
 
+@pytest.mark.parametrize("kind", ["f32", "f64"])
+def test_aos_steps_records_kinds_and_kept_cells(sph, kind):
+    """Plain-AoS steps on FP32 and FP64 records (the latter the small
+    configuration's record): the records and the FP64 sums equal those of
+    the SoA path bit for bit, and keeping the cell list between AoS steps
+    (the records' kick/drift counting particles that leave their cell or
+    sub-cell) gives the records of rebinning every step; the list is kept
+    over kick-only steps and rebuilt after a drift."""
+    from paper_2512_05516_amd.pipeline import Pipeline
+    ps = inputs.clustered_set(20000, 6, f_blob=0.4, sigma=0.05)
+    rec = inputs.pack_aos(ps, kind)
+    n_c = int(np.floor(1.0 / (1.825742 * ps.h.max())))
+    kw = dict(sub_bits=1, sched="grid")
+    soa, aos = Pipeline(rec, n_c, **kw), Pipeline(rec, n_c, **kw)
+    keep = Pipeline(rec, n_c, keep_cells=True, **kw)
+    rebuilt = []
+    for dt_drift in (0.0, 0.0, 2e-3, 0.0):
+        soa.soa_step(1e-4, dt_drift)
+        aos.aos_step(1e-4, dt_drift)
+        keep.aos_step(1e-4, dt_drift)
+        rebuilt.append(int(keep.cells.rebin[1].item()))
+        ra, rb, rk = soa.records(), aos.records(), keep.records()
+        for k in ("x", "v", "u", "a", "du", "rho", "wcount", "rho_dh", "f", "P", "c", "vsig",
+                  "nngb", "nforce"):
+            assert np.ascontiguousarray(ra[k]).tobytes() == np.ascontiguousarray(rb[k]).tobytes(), k
+        assert rb.tobytes() == rk.tobytes(), (dt_drift, rebuilt)
+        assert soa.red_out.cpu().numpy().tobytes() == aos.red_out.cpu().numpy().tobytes()
+    # built by the first step, kept after kick-only steps, rebuilt after the drift
+    assert rebuilt == [1, 0, 0, 1], rebuilt
+    assert aos.status() == 0 and keep.status() == 0
+
+
 @pytest.mark.parametrize("mode", [{}, {"sub_bits": 1, "sched": "dynamic"}])
 def test_deterministic(sph, mode):
     ps = inputs.clustered_set(30000, 4, f_blob=0.5, sigma=0.05)
