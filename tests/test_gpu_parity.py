@@ -712,6 +712,55 @@ def test_full_size_medium(sph, orc):
 
 
 @pytest.fixture(scope="module")
+def m_tiling(sph):
+    """The benchmark's tiling of the 128^3 set (autotuned on FP32 storage,
+    used for every storage format of that set)."""
+    from paper_2512_05516_amd import tune
+    rec = inputs.pack_aos(inputs.medium_set(2), "f32")
+    return tune.pipeline_kwargs(tune.tune(rec, 32, reps=2, cache_path=None))
+
+
+@pytest.mark.parametrize("fmt", [("f16", "bf16", "f16", (21, 7, 0)), ("f16", "f16", "f16", (21, 7, 0)),
+                                 ("bf16", "bf16", "bf16", (0, 0, 0))],
+                         ids=["fp16_store", "fp16_all", "bf16_all"])
+def test_full_size_reduced(sph, orc, m_tiling, fmt):
+    """The 128^3 set with reduced-precision storage as the benchmark runs it
+    (positions as offsets from sub-cell centres; the mixed FP16/BF16 format,
+    all-FP16 and all-BF16), in the benchmark's tiling: on a seeded sample of
+    8,192 particles, counts against FP64 brute force and values against the
+    oracle on the dequantised inputs at the kernels' bar, and the storage
+    error against FP64 on the unrounded inputs within the stated tolerances
+    (FP16 positions: rho and a 2e-3; du/dt 2e-3, or 8e-3 with BF16
+    velocities; all-BF16 8e-3)."""
+    pos, vel, mhu, scales = fmt
+    ps = inputs.medium_set(2)
+    n_c = 32
+    prec = sph.precision(pos, vel, mhu, *scales, anchor=SUB2)
+    pipe = run_gpu(ps, n_c, "f32", prec=prec, **m_tiling)
+    assert pipe.status() == 0
+    got = gpu_fields(pipe)
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    q = orc.dequantise_set(ref, n_c, pos, vel, mhu, scales, anchor=SUB2)
+    sel = np.sort(np.random.default_rng(21).choice(ps.n, 8192, replace=False)).astype(np.int32)
+    d, f = _oracle_at(orc, q, n_c, sel)
+    tag = "/".join((pos, vel, mhu))
+    assert_counts(orc, got["nngb"][sel], got["nforce"][sel], d["nngb"], f["nforce"], q, n_c,
+                  sel=sel, min_clear=0.98, tag=f"R/{tag}")
+    sub = {k: v[sel] for k, v in got.items()}
+    sub["h"] = q.h[sel]
+    check_fp32(sub, d, f, tol=2e-5, tag=f"R/{tag} vs dequantised")
+    d0, f0 = _oracle_at(orc, ref, n_c, sel)
+    e = {"rho": max_rel(sub["rho"], d0["rho"]), "a": rel_rmse(sub["a"], f0["a"]),
+         "du": rel_rmse(sub["du"], f0["du"])}
+    print(f"R/{tag} storage error vs FP64:", {k: f"{v:.2e}" for k, v in e.items()})
+    if pos == "f16":
+        assert e["rho"] <= 2e-3 and e["a"] <= 2e-3, e
+        assert e["du"] <= (8e-3 if vel == "bf16" else 2e-3), e
+    else:
+        assert e["rho"] <= 8e-3 and e["a"] <= 8e-3 and e["du"] <= 8e-3, e
+
+
+@pytest.fixture(scope="module")
 def k_state(sph):
     """The clustered 4,194,304-particle set as the benchmark times it: h from
     the density iteration on the GPU (settle_h, tol 1e-4), then cells as
