@@ -299,9 +299,35 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
 }
 static_assert(kMaxNbr <= 64, "the neighbour table is reduced by one wave");
 
+// Block-wide exclusive scan of an int in thread order; returns the block
+// total. One barrier: the caller must pass another barrier before `lds`
+// (NT / 64 ints) is written again.
+template <int NT>
+__device__ __forceinline__ int block_scan(int b, int& tb, int* lds) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int ib = b;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int xb = __shfl_up(ib, o);
+    if (lane >= o) ib += xb;
+  }
+  if (lane == 63) lds[wave] = ib;
+  __syncthreads();
+  int pb = 0;
+  tb = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int wb = lds[w];
+    pb += (w < wave) ? wb : 0;
+    tb += wb;
+  }
+  return pb + ib - b;
+}
+
 // Block-wide exclusive scan, in thread order, of a flag (0/1) and of an
 // int; returns the block totals. One barrier: the caller must pass another
-// barrier before `lds` is written again.
+// barrier before `lds` (2 NT / 64 ints) is written again.
 template <int NT>
 __device__ __forceinline__ void block_scan2(bool flag, int b, int& ea, int& eb, int& ta, int& tb,
                                             int* lds) {
@@ -333,6 +359,38 @@ __device__ __forceinline__ void block_scan2(bool flag, int b, int& ea, int& eb, 
   }
   ea = pa + ia - a;
   eb = pb + ib - b;
+}
+
+// Position of each flagged thread when the flagged threads are ordered by
+// class (0..3) and, within a class, by thread. One barrier: the caller must
+// pass another barrier before `lds` (2 NT / 64 ints: a wave's four class
+// counts, at most 64 each, as 16-bit halves) is written again.
+template <int NT>
+__device__ __forceinline__ int class_rank(bool flag, int cls, int* lds) {
+  constexpr int NW = NT / 64;
+  const int wave = threadIdx.x >> 6;
+  uint64_t mine = 0;
+  int cnt[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t bal = __ballot(flag && cls == c);
+    cnt[c] = __popcll(bal);
+    mine = (cls == c) ? bal : mine;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    lds[wave] = cnt[0] | (cnt[1] << 16);
+    lds[NW + wave] = cnt[2] | (cnt[3] << 16);
+  }
+  __syncthreads();
+  int off = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int a = lds[w], b = lds[NW + w];
+    const int v[4] = {a & 0xffff, a >> 16, b & 0xffff, b >> 16};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) off += (c < cls || (c == cls && w < wave)) ? v[c] : 0;
+  }
+  return off + __popcll(mine & lanemask_lt());
 }
 
 constexpr int kRounds = 4;      // gather rounds whose loads are issued together
@@ -371,11 +429,21 @@ constexpr int kSplitFactor = 2;
 // 2^-7 of a sub-cell (twice the 2^-8 margin of the per-entry box test, which
 // covers the rounding of stored offsets), so every entry that test keeps is
 // enumerated.
+// When a batch's ranges hold more than `spread` candidates (more than one
+// LDS batch of the caller), they are placed class by class. The class of a
+// sub-cell at sub-cell coordinates (gx, gy, gz) from the chunk's cell is its
+// parity pattern (gx, gy, gz) & 1 taken together with the complementary
+// pattern, ((gx ^ gz) & 1) | ((gy ^ gz) & 1) << 1 (a whole cell: the same of
+// its cell offsets). Each class is spread evenly over the neighbourhood, so
+// when the staged candidates fill several LDS batches every batch holds a
+// similar share of each particle's neighbours, and the per-lane lists of a
+// batch are of similar length (in enumeration order a batch covers one side
+// of the neighbourhood, and particles on that side hold most of its pairs).
 template <int NT, class Bound, class Batch>
 __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells& T,
                                               RangeTab<NT>& tab, float s32, float lox, float loy,
                                               float loz, float hix, float hiy, float hiz,
-                                              Bound bound, Batch batch) {
+                                              int spread, Bound bound, Batch batch) {
   const int sb = cd.sub_bits, R = 1 << sb;
   const float ss = s32 / (float)R;
   const float inv = (float)R / s32;
@@ -427,7 +495,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
   for (int b0 = 0; b0 < NQ; b0 += NT) {
     const int t = b0 + tid;
     bool ok = t < NQ;
-    int st = 0, cnt = 0, q = 0;
+    int st = 0, cnt = 0, q = 0, cls = 0;
     if (ok) {
       int lo = 0, hi = nq - 1;   // last q with qpre[q] <= t
       while (lo < hi) {
@@ -447,6 +515,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         bz0 = dz * s32 - mg, bz1 = (dz + 1) * s32 + mg;
         st = T.st[q];
         cnt = T.cnt[q];
+        cls = ((dx ^ dz) & 1) | (((dy ^ dz) & 1) << 1);
       } else {
         const uchar4 r = *reinterpret_cast<const uchar4*>(tab.qr[q]);
         // e = ex + nx (ey + ny ez), split through FP32 reciprocals (v_rcp,
@@ -459,6 +528,7 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
         const int sx = r.x + (rem - ey * nx), sy = r.y + ey, sz = r.z + ez;
         const float mg = ss * 0x1p-8f;
         const int gx = dx * R + sx, gy = dy * R + sy, gz = dz * R + sz;
+        cls = ((gx ^ gz) & 1) | (((gy ^ gz) & 1) << 1);
         bx0 = gx * ss - mg, bx1 = (gx + 1) * ss + mg;
         by0 = gy * ss - mg, by1 = (gy + 1) * ss + mg;
         bz0 = gz * ss - mg, bz1 = (gz + 1) * ss + mg;
@@ -478,9 +548,19 @@ __device__ __forceinline__ void for_sub_cells(const CellsDev& cd, const NbrCells
     }
     int e_idx, e_pre, ntab, total;
     block_scan2<NT>(ok, ok ? cnt : 0, e_idx, e_pre, ntab, total, tab.scan);
+    if (total > spread) {   // uniform: more than one LDS batch, order by class
+      __syncthreads();
+      e_idx = class_rank<NT>(ok, cls, tab.scan);
+      if (ok) tab.pre[e_idx] = cnt;
+      __syncthreads();
+      const int c_t = tid < ntab ? tab.pre[tid] : 0;
+      e_pre = block_scan<NT>(c_t, total, tab.scan);
+      if (tid < ntab) tab.pre[tid] = e_pre;
+    } else if (ok) {
+      tab.pre[e_idx] = e_pre;
+    }
     if (ok) {
       tab.start[e_idx] = st;
-      tab.pre[e_idx] = e_pre;
       tab.q[e_idx] = (unsigned char)q;
     }
     if (tid == 0) {
@@ -927,9 +1007,13 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
           cand, lst, njp, kk,
           [&](const float4& q, int) { return prefilter_t(m2x, m2y, m2z, q) < cpre; },
           [&](int lo) {
+            // list entry e + NT is read while entry e is processed
+            int tn = tid < lo ? lst[tid] : 0;
             for (int e = tid; e < lo; e += NT) {
-              const int t = lst[e];
+              const int t = tn;
               const float4 q = cand[t];
+              const float mj = cmass[t];
+              tn = lst[e + NT < lo ? e + NT : e];
               float dx, dy, dz;
               const float r2 = dist2_m2(m2x, m2y, m2z, q.x, q.y, q.z, dx, dy, dz);
               const bool in = r2 < H2;       // the exact support test
@@ -938,7 +1022,6 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
               Shape::w_dw(u, w, dw);
               w = in ? w : 0.0f;
               dw = in ? dw : 0.0f;
-              const float mj = cmass[t];
               rho = fmaf(mj, w, rho);
               wsum += w;
               dh = fmaf(mj, fmaf(u, dw, 3.0f * w), dh);
@@ -950,7 +1033,7 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
 
     int nj = 0, rnd = 0;
     for_sub_cells<NT>(
-        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, CAP - kPad,
         [&](int q) { return (only_q == -1 || q == only_q) ? bext : 0.0f; },
         [&](RangeTab<NT>& tb) {
           const int total = tb.total;
@@ -1157,18 +1240,27 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
       // i's own copy in this batch, or -1
       const int sp = selfpos[gi];
       const int tself = (sp >> 16) == nbatch ? (sp & 0xffff) : -1;
+      // list entry e + NT is read while entry e is processed, and all fields
+      // of an entry are read at once (one LDS round trip per entry)
       auto consume = [&](int lo) {
+            int tn = tid < lo ? lst[tid] : 0;
             for (int e = tid; e < lo; e += NT) {
-              const int t = lst[e];
+              const int t = tn;
               const float4 q0 = cp[t];
+              const float h2j = ch2[t];
+              const float4 q1 = cv[t];
+              const float4 q2 = cs4[t];
+              tn = lst[e + NT < lo ? e + NT : e];
               float dx, dy, dz;
               const float r2 = dist2_m2(m2x, m2y, m2z, q0.x, q0.y, q0.z, dx, dy, dz);
               // the exact support test, r2 < max(H_i^2, H_j^2), and not the
               // self pair; coincident stored positions (r2 = 0, j != i) stay:
               // w'(0) = 0 makes their terms vanish
-              if (!(r2 < H2i || r2 < ch2[t]) || t == tself) continue;
-              const float4 q1 = cv[t];
-              const float4 q2 = cs4[t];
+              // (the empty asm keeps the force-only loads ahead of the branch,
+              // where they overlap the position load)
+              asm volatile("" ::"v"(q1.x), "v"(q1.y), "v"(q1.z), "v"(q1.w), "v"(q2.x),
+                           "v"(q2.y), "v"(q2.z), "v"(q2.w));
+              if (!((r2 < H2i) | (r2 < h2j)) | (t == tself)) continue;
               const float r = fast_sqrt(r2);
               const float rinv = r2 > 0.0f ? fast_rcp(r) : 0.0f;
               const float ex = dx * rinv, ey = dy * rinv, ez = dz * rinv;
@@ -1208,7 +1300,7 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
 
     int nj = 0, filled = 0, rnd = 0;
     for_sub_cells<NT>(
-        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz,
+        cd, T, tab, s32, bx.lox, bx.loy, bx.loz, bx.hix, bx.hiy, bx.hiz, CAP - kPad,
         [&](int q) { return (only_q == -1 || q == only_q) ? fmaxf(bi, T.hb[q]) : 0.0f; },
         [&](RangeTab<NT>& tb) {
           const int total = tb.total;
