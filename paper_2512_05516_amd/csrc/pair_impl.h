@@ -954,7 +954,10 @@ __global__ __launch_bounds__(TI* K, kDensityBlocks<TI * K>) void k_density(Src s
                                                                     float s32, Items items) {
   using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
-  constexpr int CAP = 3 * NT;   // staged candidates (LDS for four waves per SIMD)
+  // staged candidates (LDS for four waves per SIMD); with one lane per
+  // particle a batch of 2 NT: a chunk of one lattice cell then fills four
+  // batches, one per range class, where three batches would cut a class
+  constexpr int CAP = (K == 1 ? 2 : 3) * NT;
   constexpr int LCAP = 32;
   constexpr int kPad = K * kUnroll;
   __shared__ float4 cand[CAP];                 // x, y, z relative to this cell, |x|^2
@@ -1126,7 +1129,9 @@ __global__ __launch_bounds__(TI* K, kForceBlocks<TI * K>) void k_force(Src src, 
   using Shape = KernelShape<KS>;
   constexpr int NT = TI * K;
   constexpr int CAP = 2 * NT;
-  constexpr int LCAP = 32;
+  // one lane per particle: the lists of a batch of 2 NT stay short, and 24
+  // entries keep the block's LDS within 1/12 of the CU's (three waves per SIMD)
+  constexpr int LCAP = K == 1 ? 24 : 32;
   constexpr int kPad = K * kUnroll;
   __shared__ float4 cp[CAP];      // x, y, z (relative to this cell), |x|^2
   __shared__ float ch2[CAP];      // H_j^2
