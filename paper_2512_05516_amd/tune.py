@@ -77,7 +77,7 @@ SPLIT_THRESHOLDS = (32, 48, 64)
 # small-cell launches: (ti, k, sched, cells merged per work item at most)
 SPLIT_SMALL = ((32, 2, "grid", 1), (32, 8, "grid", 1), (16, 4, "grid", 1), (64, 1, "grid", 1),
                (32, 2, "grid", 4), (64, 1, "grid", 4), (64, 2, "grid", 4))
-SPLIT_LARGE = ((64, 4, "dynamic"), (32, 2, "grid"), (64, 4, "static"))
+SPLIT_LARGE = ((64, 4, "dynamic"), (32, 2, "grid"), (64, 4, "static"), (64, 1, "grid"))
 
 
 def _small_str(sm) -> str:
