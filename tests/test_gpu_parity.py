@@ -379,6 +379,21 @@ def test_small_lattice_parity(sph, orc, kind, mode):
 
 
 @pytest.fixture(scope="module")
+def dense_blobs(orc):
+    # compact blobs (sigma 0.01, 80 % of 40,000 particles) in cells sized by the
+    # background h: a dozen cells above 1,024 particles, split at sub-cell
+    # depth 3 (more than 2 x 8^3), whose chunks reach hundreds of sub-cell
+    # ranges (several range-table batches per chunk) and, for the force, whose
+    # neighbour cells hold background h, thousands of candidates (many LDS
+    # batches, so the ranges are placed by class)
+    ps = inputs.clustered_set(40000, 11, f_blob=0.8, sigma=0.01)
+    n_c = int(np.floor(1.0 / (orc.GAMMA_K * ps.h.max())))
+    ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
+    d, f = oracle_step(orc, ref, n_c)
+    return ps, ref, n_c, d, f
+
+
+@pytest.fixture(scope="module")
 def ragged(orc):
     # clustered set with a slab cut out: empty cells, nearly empty cells, cells
     # spanning several chunks (ragged tails), uneven h
@@ -389,6 +404,22 @@ def ragged(orc):
     ref = inputs.unpack_aos(inputs.pack_aos(ps, "f32"))
     d, f = oracle_step(orc, ref, n_c)
     return ps, ref, n_c, d, f
+
+
+@pytest.mark.parametrize("ti,k,bits,sched", [(16, 4, 3, "static"), (64, 1, 3, "grid"),
+                                             (32, 2, 3, None), (128, 2, 3, "dynamic"),
+                                             (64, 2, 2, "grid")])
+def test_dense_blob_sub_cells_parity(sph, orc, dense_blobs, ti, k, bits, sched):
+    ps, ref, n_c, d, f = dense_blobs
+    pipe = run_gpu(ps, n_c, "f32", til=sph.tile(ti, k), sub_bits=bits, sched=sched)
+    assert pipe.status() == 0
+    counts = np.diff(pipe.cells.cell_start.cpu().numpy())
+    assert (counts > 2 * 8 ** bits).sum() >= 5         # cells split into sub-cell ranges
+    got = gpu_fields(pipe)
+    got["h"] = ref.h
+    assert_counts(orc, got["nngb"], got["nforce"], d["nngb"], f["nforce"], ref, n_c,
+                  tag=f"dense/{ti}x{k}")
+    check_fp32(got, d, f, tag=f"dense/{ti}x{k}/sub{bits}/{sched or 'cells'}")
 
 
 @pytest.mark.parametrize("ti,k,bits,sched", [(64, 4, 0, None), (32, 8, 0, None),
