@@ -299,9 +299,9 @@ __device__ __forceinline__ void build_nbr(NbrCells& T, const CellsDev& cd, int c
 }
 static_assert(kMaxNbr <= 64, "the neighbour table is reduced by one wave");
 
-// Block-wide exclusive scan of an int in thread order; returns the block
-// total. One barrier: the caller must pass another barrier before `lds`
-// (NT / 64 ints) is written again.
+// Block-wide exclusive scan of an int in thread order: returns this
+// thread's prefix and sets tb to the block total. One barrier: the caller
+// must pass another barrier before `lds` (NT / 64 ints) is written again.
 template <int NT>
 __device__ __forceinline__ int block_scan(int b, int& tb, int* lds) {
   constexpr int NW = NT / 64;
